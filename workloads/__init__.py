@@ -1,0 +1,115 @@
+"""Seeded synthetic block collections (low-rank-plus-noise), shared by the oracle
+tests, the GPU parity tests and the benchmark.
+
+This module holds only random data generation; none of the estimator's arithmetic.
+Every generator draws from ``numpy.random.default_rng(seed)`` (PCG64) in the order
+written in its body, builds the data in FP64, and casts once to the storage dtype.
+Orthonormal bases are the Q factor of a Householder QR of a Gaussian matrix with
+the column signs fixed so that diag(R) > 0.
+
+Workloads (the paper's datasets are not available; these stand in for them):
+
+* ``tiny_groups``     -- 16 FP64 blocks 64x32 in 4 groups sharing a 64x8 basis,
+                         noise sigma 0.01, rank 8 (all-pairs + full-chain check).
+* ``rotated_groups``  -- 256 FP32 blocks 1024x256 in 16 groups; each group shares a
+                         1024x32 basis rotated per block by principal angles
+                         theta_l ~ U(0, 0.3) rad; coefficient row l scaled by
+                         l^-0.5; noise sigma 1e-3; rank 64 (all 32,640 pairs).
+* ``latent_uneven``   -- 512 FP32 blocks with 4096 rows and n_i ~ U{64..1024}
+                         columns from 32 latent 4096x48 subspaces, noise 1e-2.
+* ``shared_chain``    -- 64 FP32 blocks 2048x512 sharing a 2048x96 subspace,
+                         noise sigma 0.05 (long chain).
+Each accepts size overrides so tests can run scaled-down versions of the same recipe.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def orthonormal(rng: np.random.Generator, m: int, p: int) -> np.ndarray:
+    """m x p matrix with orthonormal columns (QR of a Gaussian, sign-fixed)."""
+    q, r = np.linalg.qr(rng.standard_normal((m, p)))
+    return q * np.sign(np.diag(r))[None, :]
+
+
+def tiny_groups(seed: int = 0, m: int = 64, n: int = 32, d: int = 8, groups: int = 4,
+                per_group: int = 4, noise: float = 0.01, dtype=np.float64):
+    """Block b = per_group*g + i is Q_g G + noise; draw order: all Q_g, then per block G then noise."""
+    rng = np.random.default_rng(seed)
+    Q = [orthonormal(rng, m, d) for _ in range(groups)]
+    blocks = []
+    for g in range(groups):
+        for _ in range(per_group):
+            G = rng.standard_normal((d, n))
+            E = rng.standard_normal((m, n)) * noise
+            blocks.append((Q[g] @ G + E).astype(dtype))
+    return blocks
+
+
+def rotated_groups(seed: int = 0, m: int = 1024, n: int = 256, d: int = 32, groups: int = 16,
+                   per_group: int = 16, max_angle: float = 0.3, noise: float = 1e-3,
+                   dtype=np.float32):
+    """Draw order: all group bases Q_g; then per block: angles theta (d), a Gaussian
+    m x d completing block W (projected off Q_g, orthonormalised), coefficients C
+    (d x n, row l scaled l^-0.5), noise (m x n)."""
+    rng = np.random.default_rng(seed)
+    Q = [orthonormal(rng, m, d) for _ in range(groups)]
+    scale = (np.arange(1, d + 1, dtype=np.float64) ** -0.5)[:, None]
+    blocks = []
+    for g in range(groups):
+        Qg = Q[g]
+        for _ in range(per_group):
+            theta = rng.uniform(0.0, max_angle, d)
+            W = rng.standard_normal((m, d))
+            W -= Qg @ (Qg.T @ W)
+            W -= Qg @ (Qg.T @ W)
+            q, rr = np.linalg.qr(W)
+            W = q * np.sign(np.diag(rr))[None, :]
+            Qi = Qg * np.cos(theta)[None, :] + W * np.sin(theta)[None, :]
+            C = rng.standard_normal((d, n)) * scale
+            E = rng.standard_normal((m, n)) * noise
+            blocks.append((Qi @ C + E).astype(dtype))
+    return blocks
+
+
+def latent_uneven(seed: int = 0, m: int = 4096, nblocks: int = 512, latents: int = 32, d: int = 48,
+                  nmin: int = 64, nmax: int = 1024, noise: float = 1e-2, dtype=np.float32):
+    """Draw order: all latent bases L_s; all column counts n_i ~ U{nmin..nmax}; then per
+    block (block i uses latent i mod latents): C_i (d x n_i), noise (m x n_i)."""
+    rng = np.random.default_rng(seed)
+    L = [orthonormal(rng, m, d) for _ in range(latents)]
+    ns = rng.integers(nmin, nmax + 1, size=nblocks)
+    blocks = []
+    for i in range(nblocks):
+        C = rng.standard_normal((d, int(ns[i])))
+        E = rng.standard_normal((m, int(ns[i]))) * noise
+        blocks.append((L[i % latents] @ C + E).astype(dtype))
+    return blocks
+
+
+def shared_chain(seed: int = 0, m: int = 2048, n: int = 512, d: int = 96, nblocks: int = 64,
+                 noise: float = 0.05, dtype=np.float32):
+    """Draw order: shared basis S (m x d, Gaussian entries), then per block C_i, noise."""
+    rng = np.random.default_rng(seed)
+    S = rng.standard_normal((m, d))
+    blocks = []
+    for _ in range(nblocks):
+        C = rng.standard_normal((d, n))
+        E = rng.standard_normal((m, n)) * noise
+        blocks.append((S @ C + E).astype(dtype))
+    return blocks
+
+
+def anchor_ordered_pairs(blocks) -> np.ndarray:
+    """All unordered pairs {i, j}, i < j, oriented anchor-first: the block with the
+    larger Frobenius norm heads the pair (ties: the lower index)."""
+    n2 = np.array([float(np.sum(np.asarray(b, dtype=np.float64) ** 2)) for b in blocks])
+    out = []
+    N = len(blocks)
+    for i in range(N):
+        for j in range(i + 1, N):
+            if n2[j] > n2[i]:
+                out.append((j, i))
+            else:
+                out.append((i, j))
+    return np.array(out, dtype=np.int32).reshape(-1, 2)
