@@ -1,0 +1,154 @@
+/*
+ * cmsvd -- incremental concatenated-SVD merge-error engine for MI355X (gfx950).
+ *
+ * C ABI of the HIP library libcmsvd.so.  It evaluates the incremental truncated-SVD
+ * estimate of the optimal rank-r error of a horizontal concatenation
+ * [A_1 ... A_K] (Lemma 1 and Corollary 3 of Shamrai, "Concatenated Matrix SVD:
+ * Compression Bounds, Incremental Approximation, and Error-Constrained Clustering",
+ * TMLR 2026, Section 3.3 and Appendix B) and the plug-in error of Corollary 2,
+ * for single updates, for all requested candidate pairs, and inside the greedy
+ * error-constrained clustering of Algorithm 3 (Appendix E).
+ *
+ * Conventions shared by every call
+ *   - Blocks A_i are real m x n_i matrices with a common row count m (Section 2,
+ *     problem formulation).  They are passed as cmsvd_block: a DEVICE pointer to a
+ *     row-major matrix (element (i, c) at ptr[i * ld + c]), ld >= cols, dtype
+ *     CMSVD_F32 or CMSVD_F64.  FP32 data is promoted to FP64 exactly; all
+ *     arithmetic is FP64.
+ *   - A state of rank r (Algorithm 3, "what is maintained") is a DEVICE basis U
+ *     (m x r, row-major FP64, orthonormal or zero columns), DEVICE singular values
+ *     S (r FP64, descending, zero-padded), and DEVICE accumulators
+ *     acc[4] = {E_tot hi, E_tot lo, D hi, D lo}: the block energy sum_i ||A_i||_F^2
+ *     and the energy discarded by truncation, each as a double-double.
+ *   - The caller owns every input and output buffer; the handle owns only its
+ *     workspace (grown on demand with hipMalloc, freed by cmsvd_destroy).
+ *   - All calls are ordered on the handle's HIP stream.  cmsvd_update and
+ *     cmsvd_merge_errors return once their work is enqueued (the host may block
+ *     briefly while descriptor tables are uploaded); results are valid after a
+ *     stream synchronisation.  cmsvd_cluster is synchronous (its outputs are host
+ *     memory).
+ *   - Argument validation happens before any launch.  A non-OK status means no
+ *     kernel was launched by that call, except CMSVD_EHIP, which reports a HIP
+ *     runtime failure.  cmsvd_last_error() gives a thread-local message.
+ *   - NaN/Inf in the data propagate into the affected results; they are not errors.
+ *     A rank-deficient residual is not an error either: its numerically absent
+ *     directions are dropped (their energy stays in the error estimate).
+ */
+#ifndef CMSVD_H
+#define CMSVD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cmsvd_ctx* cmsvd_handle;
+
+typedef enum { CMSVD_F32 = 0, CMSVD_F64 = 2 } cmsvd_dtype;
+
+typedef enum {
+    CMSVD_OK = 0,
+    CMSVD_EINVAL = 1,      /* bad argument value (null pointer, r < 1, index out of range, ...) */
+    CMSVD_ESHAPE = 2,      /* inconsistent shapes (row counts differ, ld < cols, r > m, ...)   */
+    CMSVD_ENOMEM = 3,      /* workspace allocation failed                                      */
+    CMSVD_EHIP = 4,        /* a HIP runtime call failed                                        */
+    CMSVD_EUNSUPPORTED = 5 /* dtype or size not supported by this build                        */
+} cmsvd_status;
+
+typedef struct {
+    const void* ptr; /* device pointer, row-major                      */
+    int64_t rows;    /* m                                               */
+    int64_t cols;    /* n_i >= 1                                        */
+    int64_t ld;      /* row stride in elements, >= cols                 */
+    int32_t dtype;   /* cmsvd_dtype                                     */
+} cmsvd_block;
+
+/* Creates a handle bound to a HIP stream (NULL = the default stream).  The current
+   HIP device at creation time is the device used by every call on the handle. */
+cmsvd_status cmsvd_create(cmsvd_handle* handle, void* hip_stream);
+cmsvd_status cmsvd_destroy(cmsvd_handle handle);
+cmsvd_status cmsvd_set_stream(cmsvd_handle handle, void* hip_stream);
+const char* cmsvd_last_error(void);
+
+/* One incremental step: Lemma 1 (projection Y = U^T B, residual R = B - U Y, thin
+   QR of R) and Corollary 3 (eigendecomposition of the enlarged Gram S_{t+1},
+   truncation to the top r pairs), then the plug-in of Corollary 2.
+     m            row count of the state and of B
+     U, ldu       current basis, m x r_in row-major FP64 (ignored when r_in == 0)
+     S            current singular values, r_in FP64 (ignored when r_in == 0)
+     r_in         current state width (0 = empty state: the update then computes the
+                  rank-r truncated SVD of B, Algorithm 3 step 1)
+     B            the appended block (rows == m)
+     r            target rank, 1 <= r <= m
+     U_out, ldu_out  new basis, m x r row-major FP64 (must not alias U)
+     S_out        new singular values, r FP64 (must not alias S)
+     acc          state accumulators (see above), updated in place
+     est          optional (may be NULL): est[0] = plug-in error sqrt(E_tot -
+                  sum S_out^2) after the step, est[1] = sqrt(D) (the same quantity
+                  from the discarded-energy tally; they agree to rounding).
+   Directions whose eigenvalue is at rounding level get S_out = 0 and a zero column. */
+cmsvd_status cmsvd_update(cmsvd_handle handle, int64_t m, const double* U, int64_t ldu, const double* S,
+                          int64_t r_in, const cmsvd_block* B, int64_t r, double* U_out, int64_t ldu_out,
+                          double* S_out, double* acc, double* est);
+
+/* Merge errors for ordered candidate pairs (Corollary 2 applied to [A_i, A_j]: the
+   anchor A_i is truncated to rank r first, then A_j is appended; order matters,
+   Remark 3).
+     blocks, nblocks   the collection (host array of descriptors of device data)
+     pairs             HOST int32 array npairs x 2, (i, j) with 0 <= i, j < nblocks
+     r                 target rank, 1 <= r <= m
+     err               DEVICE npairs FP64: plug-in error sqrt(||A_i||^2 + ||A_j||^2 -
+                       sum_{l<=r} sigma_l^2)
+     rel               DEVICE npairs FP64 (may be NULL): err / ||[A_i, A_j]||_F */
+cmsvd_status cmsvd_merge_errors(cmsvd_handle handle, const cmsvd_block* blocks, int64_t nblocks,
+                                const int32_t* pairs, int64_t npairs, int64_t r, double* err, double* rel);
+
+/* Algorithm 3 (approximate clustering via incremental truncated SVD), pass-based:
+   anchor = largest remaining block (ties: lower index); a pass orders the
+   remaining candidates once (sort_mode 0: increasing ||A_j||_F; 1: increasing
+   ||(I - Q_C Q_C^T) A_j||_F against the state at the pass start; ties: lower index)
+   and scans them, accepting a candidate iff err / ||M_{C+j}||_F <= eps and then
+   continuing the scan against the new state; passes repeat until one accepts
+   nothing.
+     labels       HOST nblocks int32: cluster id per block, ids in creation order
+     nclusters    HOST out
+     cluster_rel  HOST nblocks FP64 (may be NULL): final err/||M_C||_F per cluster
+                  (first *nclusters entries) */
+cmsvd_status cmsvd_cluster(cmsvd_handle handle, const cmsvd_block* blocks, int64_t nblocks, int64_t r,
+                           double eps, int32_t sort_mode, int32_t* labels, int64_t* nclusters,
+                           double* cluster_rel);
+
+/* Building block exposed for testing and reuse: the largest nkeep eigenvalues of
+   count symmetric matrices, each n x n column-major FP64 on the device (A + i*stride_a,
+   lower triangle read, both triangles assumed equal), written descending to
+   lam + i*nkeep (device).  Same kernel as the core step of the two calls above. */
+cmsvd_status cmsvd_sym_eigvals(cmsvd_handle handle, const double* A, int64_t n, int64_t lda, int64_t stride_a,
+                               int64_t count, int64_t nkeep, double* lam);
+
+/* Stage timing for measurement (off by default).  When enabled, every pipeline stage
+   launched on the handle's stream is bracketed by HIP events recorded on that same
+   stream.  Stages: 0 = block norms and Grams B^T B, 1 = commit pipeline (anchor
+   initialisation and state updates), 2 = projection GEMM Y = U^T B of candidate
+   evaluation, 3 = core eigenvalue kernel of candidate evaluation (tridiagonalisation,
+   bisection, plug-in error; one launch per evaluation chunk).
+   cmsvd_profile_read synchronises the handle's stream, writes for each of the 4
+   stages the summed milliseconds and the number of bracketed launches, and resets
+   the counters.  ms and count are HOST arrays of 4 entries. */
+cmsvd_status cmsvd_profile(cmsvd_handle handle, int32_t enable);
+cmsvd_status cmsvd_profile_read(cmsvd_handle handle, double* ms, int64_t* count);
+
+/* Building block exposed for testing and reuse: one FP64 GEMM on the matrix cores,
+   C = alpha op(A) op(B) + beta C, all column-major on the device.  op(A) is M x K,
+   op(B) is K x N; trans_a / trans_b = 1 selects the transpose.  A and B may be FP32
+   or FP64 (a_dtype / b_dtype); C is FP64.  Same kernel as the projections, Grams and
+   rotations of the update (step (a) P = U^T B is trans_a = 0, trans_b = 1 on the
+   column-major views of the row-major U and B). */
+cmsvd_status cmsvd_gemm_f64(cmsvd_handle handle, int32_t trans_a, int32_t trans_b, int64_t M, int64_t N, int64_t K,
+                            double alpha, const void* A, int64_t lda, int32_t a_dtype, const void* B, int64_t ldb,
+                            int32_t b_dtype, double beta, double* C, int64_t ldc);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CMSVD_H */

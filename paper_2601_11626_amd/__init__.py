@@ -1,0 +1,262 @@
+"""cmsvd: incremental concatenated-SVD merge-error engine for MI355X (gfx950).
+
+Thin ctypes binding over ``libcmsvd.so`` (built from ``csrc/`` by ``build.py``).  The
+functions mirror the C ABI in ``include/cmsvd.h``; they only marshal torch tensors
+(device memory and the current HIP stream) into the C calls.  Every step of the
+computation runs in the HIP kernels of the library; there is no CPU fallback, and
+importing this package raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcmsvd.so")
+
+CMSVD_F32 = 0
+CMSVD_F64 = 2
+_STATUS = {0: "OK", 1: "EINVAL", 2: "ESHAPE", 3: "ENOMEM", 4: "EHIP", 5: "EUNSUPPORTED"}
+
+
+class CmsvdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"cmsvd {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Block(ctypes.Structure):
+    _fields_ = [("ptr", ctypes.c_void_p), ("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
+                ("ld", ctypes.c_int64), ("dtype", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2601_11626_amd/build.py`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    lib.cmsvd_create.argtypes = [ctypes.POINTER(vp), vp]
+    lib.cmsvd_destroy.argtypes = [vp]
+    lib.cmsvd_set_stream.argtypes = [vp, vp]
+    lib.cmsvd_last_error.restype = ctypes.c_char_p
+    lib.cmsvd_update.argtypes = [vp, i64, vp, i64, vp, i64, ctypes.POINTER(Block), i64, vp, i64, vp, vp, vp]
+    lib.cmsvd_merge_errors.argtypes = [vp, ctypes.POINTER(Block), i64, vp, i64, i64, vp, vp]
+    lib.cmsvd_cluster.argtypes = [vp, ctypes.POINTER(Block), i64, i64, d, i32, vp, ctypes.POINTER(i64), vp]
+    lib.cmsvd_sym_eigvals.argtypes = [vp, vp, i64, i64, i64, i64, i64, vp]
+    lib.cmsvd_gemm_f64.argtypes = [vp, i32, i32, i64, i64, i64, d, vp, i64, i32, vp, i64, i32, d, vp, i64]
+    lib.cmsvd_profile.argtypes = [vp, i32]
+    lib.cmsvd_profile_read.argtypes = [vp, vp, vp]
+    for f in ("cmsvd_create", "cmsvd_destroy", "cmsvd_set_stream", "cmsvd_update", "cmsvd_merge_errors",
+              "cmsvd_cluster", "cmsvd_sym_eigvals", "cmsvd_gemm_f64", "cmsvd_profile", "cmsvd_profile_read"):
+        getattr(lib, f).restype = ctypes.c_int
+    return lib
+
+
+_lib = _load()
+
+EXPORTS = ("cmsvd_create", "cmsvd_destroy", "cmsvd_set_stream", "cmsvd_last_error", "cmsvd_update",
+           "cmsvd_merge_errors", "cmsvd_cluster", "cmsvd_sym_eigvals", "cmsvd_gemm_f64", "cmsvd_profile",
+           "cmsvd_profile_read")
+
+STAGES = ("norms_grams", "commit", "projection", "core_eig")
+
+
+def _check(status: int):
+    if status != 0:
+        raise CmsvdError(status, _lib.cmsvd_last_error().decode(errors="replace"))
+
+
+def _stream_ptr(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Handle:
+    """Owns a cmsvd handle bound to the current torch stream of ``device``."""
+
+    def __init__(self, device=None):
+        self._h = ctypes.c_void_p()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else torch.device(device).index)
+        with torch.cuda.device(self.device):
+            _check(_lib.cmsvd_create(ctypes.byref(self._h), _stream_ptr(self.device)))
+
+    def sync_stream(self):
+        _check(_lib.cmsvd_set_stream(self._h, _stream_ptr(self.device)))
+
+    def close(self):
+        if self._h:
+            _lib.cmsvd_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def profile(self, enable: bool = True):
+        _check(_lib.cmsvd_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """Per-stage (milliseconds, launches) since the last read; synchronises the stream."""
+        ms = (ctypes.c_double * 4)()
+        cnt = (ctypes.c_int64 * 4)()
+        _check(_lib.cmsvd_profile_read(self._h, ms, cnt))
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(STAGES)}
+
+
+_default: dict = {}
+
+
+def default_handle(device=None) -> Handle:
+    dev = torch.cuda.current_device() if device is None else torch.device(device).index
+    h = _default.get(dev)
+    if h is None:
+        h = _default[dev] = Handle(dev)
+    h.sync_stream()
+    return h
+
+
+def _block(t: torch.Tensor) -> Block:
+    if not t.is_cuda:
+        raise ValueError("blocks must be device tensors")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("blocks must be 2-D with unit column stride (row-major)")
+    if t.dtype == torch.float32:
+        dt = CMSVD_F32
+    elif t.dtype == torch.float64:
+        dt = CMSVD_F64
+    else:
+        raise ValueError(f"unsupported dtype {t.dtype}")
+    return Block(t.data_ptr(), t.shape[0], t.shape[1], t.stride(0), dt)
+
+
+def _blocks(ts: Sequence[torch.Tensor]):
+    arr = (Block * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = _block(t)
+    return arr
+
+
+class State:
+    """Device state of the estimator: basis U (m x r, FP64), singular values S (r),
+    accumulators acc = [E_tot hi, E_tot lo, D hi, D lo] and est = [Etilde, sqrt(D)]."""
+
+    def __init__(self, m: int, r: int, device):
+        self.m, self.r = m, r
+        self.U = torch.zeros((m, r), dtype=torch.float64, device=device)
+        self.S = torch.zeros(r, dtype=torch.float64, device=device)
+        self.acc = torch.zeros(4, dtype=torch.float64, device=device)
+        self.est = torch.zeros(2, dtype=torch.float64, device=device)
+        self.width = 0  # 0 = empty state
+
+
+def cmsvd_update(state: State, B: torch.Tensor, r: int | None = None, handle: Handle | None = None) -> State:
+    """One incremental step; returns a new State (the input state is not modified)."""
+    h = handle or default_handle(B.device)
+    r = state.r if r is None else r
+    out = State(state.m, r, B.device)
+    out.acc.copy_(state.acc)
+    blk = _block(B)
+    U = state.U if state.width else None
+    _check(_lib.cmsvd_update(
+        h.ptr, state.m,
+        ctypes.c_void_p(U.data_ptr() if U is not None else 0), state.U.stride(0),
+        ctypes.c_void_p(state.S.data_ptr() if U is not None else 0), state.width,
+        ctypes.byref(blk), r,
+        ctypes.c_void_p(out.U.data_ptr()), out.U.stride(0), ctypes.c_void_p(out.S.data_ptr()),
+        ctypes.c_void_p(out.acc.data_ptr()), ctypes.c_void_p(out.est.data_ptr())))
+    out.width = r
+    return out
+
+
+def cmsvd_merge_errors(blocks: Sequence[torch.Tensor], pairs, r: int, handle: Handle | None = None):
+    """Returns (err, rel) device FP64 tensors for the ordered pairs (i, j)."""
+    dev = blocks[0].device
+    h = handle or default_handle(dev)
+    if isinstance(pairs, torch.Tensor):
+        pr = pairs.detach().to("cpu", torch.int32).contiguous()
+    else:
+        import numpy as np
+
+        pr = torch.from_numpy(np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2)))
+    npairs = pr.shape[0]
+    err = torch.empty(npairs, dtype=torch.float64, device=dev)
+    rel = torch.empty(npairs, dtype=torch.float64, device=dev)
+    arr = _blocks(blocks)
+    _check(_lib.cmsvd_merge_errors(h.ptr, arr, len(blocks), ctypes.c_void_p(pr.data_ptr()), npairs, r,
+                                   ctypes.c_void_p(err.data_ptr()), ctypes.c_void_p(rel.data_ptr())))
+    return err, rel
+
+
+def cmsvd_cluster(blocks: Sequence[torch.Tensor], r: int, eps: float, sort_mode: str = "frobenius",
+                  handle: Handle | None = None):
+    """Algorithm 3 on the device.  Returns (labels list, clusters list, cluster_rel list)."""
+    dev = blocks[0].device
+    h = handle or default_handle(dev)
+    mode = {"frobenius": 0, "residual": 1}[sort_mode]
+    n = len(blocks)
+    labels = (ctypes.c_int32 * n)()
+    ncl = ctypes.c_int64(0)
+    crel = (ctypes.c_double * n)()
+    arr = _blocks(blocks)
+    _check(_lib.cmsvd_cluster(h.ptr, arr, n, r, float(eps), mode, labels, ctypes.byref(ncl), crel))
+    lab = list(labels)
+    clusters = [[] for _ in range(ncl.value)]
+    for i, c in enumerate(lab):
+        clusters[c].append(i)
+    return lab, clusters, list(crel)[: ncl.value]
+
+
+def cmsvd_sym_eigvals(A: torch.Tensor, nkeep: int, handle: Handle | None = None) -> torch.Tensor:
+    """Largest nkeep eigenvalues (descending) of a batch of symmetric FP64 matrices (..., n, n)."""
+    if A.dtype != torch.float64 or not A.is_cuda:
+        raise ValueError("A must be a CUDA float64 tensor")
+    h = handle or default_handle(A.device)
+    n = A.shape[-1]
+    batch = A.reshape(-1, n, n).contiguous()
+    lam = torch.empty((batch.shape[0], nkeep), dtype=torch.float64, device=A.device)
+    # column-major view of each matrix: symmetric, so the row-major buffer serves as is
+    _check(_lib.cmsvd_sym_eigvals(h.ptr, ctypes.c_void_p(batch.data_ptr()), n, n, n * n, batch.shape[0], nkeep,
+                                  ctypes.c_void_p(lam.data_ptr())))
+    return lam.reshape(*A.shape[:-2], nkeep)
+
+
+def cmsvd_gemm_f64(opA: torch.Tensor, opB: torch.Tensor, C: torch.Tensor | None = None, alpha: float = 1.0,
+                   beta: float = 0.0, handle: Handle | None = None) -> torch.Tensor:
+    """C = alpha opA @ opB + beta C on the matrix cores.  opA (M x K) and opB (K x N) may be
+    transposed views of contiguous FP32/FP64 tensors; C is FP64."""
+    h = handle or default_handle(opA.device)
+
+    def desc(t):
+        # column-major (ld, trans) description of a 2-D view
+        if t.stride(0) == 1 and t.stride(1) >= max(t.shape[0], 1):
+            return t, 0, t.stride(1)
+        if t.stride(1) == 1 and t.stride(0) >= max(t.shape[1], 1):
+            return t, 1, t.stride(0)
+        t = t.contiguous()
+        return t, 1, t.stride(0)
+
+    M, K = opA.shape
+    K2, N = opB.shape
+    assert K == K2
+    a, ta, lda = desc(opA)
+    b, tb, ldb = desc(opB)
+    if C is None:
+        C = torch.zeros((N, M), dtype=torch.float64, device=opA.device).t()
+    assert C.stride(0) == 1
+    dt = {torch.float32: CMSVD_F32, torch.float64: CMSVD_F64}
+    _check(_lib.cmsvd_gemm_f64(h.ptr, ta, tb, M, N, K, float(alpha), ctypes.c_void_p(a.data_ptr()), lda,
+                               dt[a.dtype], ctypes.c_void_p(b.data_ptr()), ldb, dt[b.dtype], float(beta),
+                               ctypes.c_void_p(C.data_ptr()), C.stride(1)))
+    return C
+
+
+__all__ = ["cmsvd_gemm_f64", "Handle", "State", "Block", "CmsvdError", "cmsvd_update", "cmsvd_merge_errors", "cmsvd_cluster",
+           "cmsvd_sym_eigvals", "default_handle", "LIB_PATH", "EXPORTS"]

@@ -1,0 +1,153 @@
+// Internal kernel descriptors and launchers of the cmsvd HIP library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cmsvd {
+
+// One GEMM problem: C = alpha op(A) op(B) + beta C, column-major, FP64 accumulate.
+struct GemmDesc {
+    const void* A;
+    const void* B;
+    double* C;
+    int M, N, K;
+    long lda, ldb, ldc;
+};
+
+void gemm_f64_batched(const GemmDesc* d_descs, int count, int maxM, int maxN, bool transA, bool transB,
+                      bool a_f32, bool b_f32, double alpha, double beta, hipStream_t s);
+
+// One symmetric eigenvalue problem of order n, given in block-arrow form
+//     H = [[ diag(s)^2        , diag(s) P ],
+//          [ P^T diag(s)      , Y         ]]
+// with s of length n1, P n1 x (n-n1) (column-major, ldp) and Y (n-n1) x (n-n1)
+// symmetric (column-major, ldy, both triangles valid).  n1 = 0 gives a dense Y.
+struct EigDesc {
+    int n, n1, nkeep;
+    const double* s;
+    const double* P;
+    long ldp;
+    const double* Y;
+    long ldy;
+    // evaluation mode: plug-in error from the total energy E_tot = *na + *nb, each a
+    // double-double (hi, lo) in device memory (nb may be null)
+    const double* na;
+    const double* nb;
+    double* out_err;
+    double* out_rel;
+    // vector mode
+    double* lam;      // nkeep eigenvalues, descending
+    double* d;        // n   (tridiagonal diagonal)
+    double* e;        // n-1 (tridiagonal off-diagonal)
+    double* V;        // n x n column-major Householder vectors (column j holds v_j, v_j[j+1] = 1 implicit)
+    long ldv;
+    double* tau;      // n
+    double* sum_top;  // 2 doubles: (hi, lo) of the sum of the kept eigenvalues
+};
+
+// Tridiagonalisation + bisection.  mode 0: evaluation (writes out_err/out_rel);
+// mode 1: vectors wanted (writes lam, d, e, V, tau, sum_top).
+void sym_eig_batched(const EigDesc* d_descs, int count, int nmax, int mode, double* gws, int nslots,
+                     hipStream_t s);
+size_t sym_eig_workspace_doubles(int nmax, int nslots);
+
+// Inverse iteration on the tridiagonal (lam, d, e) for the nkeep top eigenvectors,
+// orthonormalised, then back-transformed by the stored Householder vectors.  Z is
+// n x nkeep column-major (ldz).  scratch: per problem 4 * n * nkeep doubles.
+struct VecDesc {
+    int n, nkeep;
+    const double* lam;
+    const double* d;
+    const double* e;
+    const double* V;
+    long ldv;
+    const double* tau;
+    double* Z;
+    long ldz;
+    double* scratch;
+};
+void sym_vectors_batched(const VecDesc* d_descs, int count, hipStream_t s);
+
+// Semidefinite Cholesky with a pivot threshold, in place on the lower triangle
+// of G (column-major, ldg).  A pivot <= thresh zeroes its column of L.  Then
+// writes Linv = L^{-1} restricted to the kept pivots (zero rows/cols elsewhere).
+struct CholDesc {
+    int k;
+    double* G;
+    long ldg;
+    double* Linv;
+    long ldi;
+    double thresh_scale;        // pivot threshold = thresh_scale * (thresh_ref ? thresh_ref[0] : 1)
+    const double* thresh_ref;   // device scalar (e.g. the block energy), may be null
+    int* dropped;               // number of dropped pivots (output, may be null)
+};
+void chol_semidef_batched(const CholDesc* d_descs, int count, hipStream_t s);
+
+// Frobenius norm squared of a row-major m x n block (FP32 or FP64), double-double.
+struct NormDesc {
+    const void* A;
+    int rows, cols;
+    long ld;
+    int f32;
+    double* out;  // 2 doubles (hi, lo)
+};
+void sumsq_batched(const NormDesc* d_descs, int count, hipStream_t s);
+
+// Copy a row-major block (FP32/FP64) into FP64 storage with a new row stride.
+struct CopyDesc {
+    const void* A;
+    int rows, cols;
+    long lda;
+    int f32;
+    double* B;
+    long ldb;
+};
+void copy_f64_batched(const CopyDesc* d_descs, int count, int maxrows, hipStream_t s);
+
+// KT = [[diag(s), 0], [P^T, F]] ((r+k) x (r+k), column-major, ldk), F lower k x k.
+struct KtDesc {
+    int r, k;
+    const double* s;
+    const double* P;
+    long ldp;
+    const double* F;
+    long ldf;
+    double* KT;
+    long ldk;
+};
+void assemble_kt_batched(const KtDesc* d_descs, int count, int nmax, hipStream_t s);
+
+// Commit a state: s_out[q] = sqrt(lam[q]) (0 when lam[q] <= cut or q >= nkeep), the
+// matching columns of the row-major m x r basis are zeroed; energies updated:
+//   acc[0..1] += ||B||^2 (nb), acc[2..3] += (sum s_in^2 + ||B||^2) - sum_top,
+//   est[0] = sqrt(max(0, E_tot - sum s_out^2)), est[1] = sqrt(D).
+struct FinDesc {
+    int r_in, r, nkeep, m, nc;
+    const double* s_in;
+    const double* lam;
+    const double* sum_top;
+    const double* nb;
+    double* s_out;
+    double* U_out;
+    long ldu;
+    double* acc;
+    double* est;
+};
+void finalize_state_batched(const FinDesc* d_descs, int count, hipStream_t s);
+
+// y[i] += x[i]
+void add_f64(const double* x, double* y, long n, hipStream_t s);
+// zero the strictly upper triangle of a k x k column-major matrix
+void zero_upper(double* A, int k, long lda, hipStream_t s);
+// index of the first i < n with rel[i] <= eps (n if none), written to *out (device int)
+void first_feasible(const double* rel, int n, double eps, int* out, hipStream_t s);
+// ||P||_F^2 per column block: out[b] = sum over the r x k_b block (column-major, ld) -- plain FP64
+struct ColNormDesc {
+    const double* P;
+    int r, k;
+    long ld;
+    double* out;
+};
+void colblock_sumsq_batched(const ColNormDesc* d_descs, int count, hipStream_t s);
+
+}  // namespace cmsvd

@@ -1,0 +1,162 @@
+// Small glue kernels of the update and the clustering decision.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace cmsvd {
+
+__global__ void assemble_kt_kernel(const KtDesc* __restrict__ descs) {
+    const KtDesc D = descs[blockIdx.y];
+    const int n = D.r + D.k;
+    const long tot = (long)n * n;
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < tot; e += (long)gridDim.x * 256) {
+        const int i = (int)(e % n), c = (int)(e / n);
+        double v = 0.0;
+        if (c < D.r) {
+            if (i < D.r) v = (i == c) ? D.s[i] : 0.0;
+            else v = D.P[(long)c + (long)(i - D.r) * D.ldp];  // (P^T)[i-r][c]
+        } else if (i >= D.r) {
+            const int a = i - D.r, b = c - D.r;
+            v = (a >= b) ? D.F[(long)a + (long)b * D.ldf] : 0.0;
+        }
+        D.KT[(long)i + (long)c * D.ldk] = v;
+    }
+}
+
+void assemble_kt_batched(const KtDesc* d_descs, int count, int nmax, hipStream_t s) {
+    if (count <= 0) return;
+    const long tot = (long)nmax * nmax;
+    int gx = (int)((tot + 255) / 256);
+    gx = gx > 512 ? 512 : gx;
+    for (int base = 0; base < count; base += 65535) {
+        const int n = count - base < 65535 ? count - base : 65535;
+        hipLaunchKernelGGL(assemble_kt_kernel, dim3(gx, n), dim3(256), 0, s, d_descs + base);
+    }
+}
+
+__global__ void __launch_bounds__(256) finalize_state_kernel(const FinDesc* __restrict__ descs) {
+    const FinDesc D = descs[blockIdx.x];
+    __shared__ double sq[1024];
+    __shared__ int keep[1024];
+    const int t = threadIdx.x;
+    double lmax = 0.0;
+    for (int q = 0; q < D.nkeep; ++q) lmax = fmax(lmax, D.lam[q]);
+    // eigenvalues at the eigensolver's rounding level (n eps ||S||) are numerically zero
+    const double cut = (double)D.nc * 8.0 * 2.220446049250313e-16 * lmax;
+    for (int q = t; q < D.r; q += 256) {
+        const double l = q < D.nkeep ? D.lam[q] : 0.0;
+        const int k = (q < D.nkeep && l > cut) ? 1 : 0;
+        const double sv = k ? sqrt(l) : 0.0;
+        D.s_out[q] = sv;
+        if (q < 1024) {
+            sq[q] = sv * sv;
+            keep[q] = k;
+        }
+    }
+    __syncthreads();
+    // zero the basis columns of dropped directions (row-major m x r)
+    for (long e = t; e < (long)D.m * D.r; e += 256) {
+        const int q = (int)(e % D.r);
+        const long row = e / D.r;
+        const int k = q < 1024 ? keep[q] : (q < D.nkeep);
+        if (!k) D.U_out[row * D.ldu + q] = 0.0;
+    }
+    if (t == 0) {
+        // energies (double-double)
+        double eh = D.acc[0], el = D.acc[1];
+        dd_add(eh, el, D.nb[0]);
+        el += D.nb[1];
+        double sin_h = 0.0, sin_l = 0.0;
+        for (int q = 0; q < D.r_in; ++q) dd_add(sin_h, sin_l, D.s_in[q] * D.s_in[q]);
+        // core energy = sum s_in^2 + ||B||^2; discarded = core energy - kept
+        double ch = sin_h, cl = sin_l;
+        dd_add(ch, cl, D.nb[0]);
+        cl += D.nb[1];
+        double dh = D.acc[2], dl = D.acc[3];
+        dd_add(dh, dl, ch);
+        dl += cl;
+        dd_add(dh, dl, -D.sum_top[0]);
+        dl -= D.sum_top[1];
+        D.acc[0] = eh;
+        D.acc[1] = el;
+        D.acc[2] = dh;
+        D.acc[3] = dl;
+        if (D.est) {
+            double kh = 0.0, kl = 0.0;
+            for (int q = 0; q < D.r && q < 1024; ++q) dd_add(kh, kl, sq[q]);
+            double s, e;
+            two_sum(eh, -kh, s, e);
+            double tail = s + (e + el - kl);
+            D.est[0] = sqrt(tail < 0.0 ? 0.0 : tail);
+            const double dtot = dh + dl;
+            D.est[1] = sqrt(dtot < 0.0 ? 0.0 : dtot);
+        }
+    }
+}
+
+void finalize_state_batched(const FinDesc* d_descs, int count, hipStream_t s) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(finalize_state_kernel, dim3(count), dim3(256), 0, s, d_descs);
+}
+
+__global__ void add_f64_kernel(const double* __restrict__ x, double* __restrict__ y, long n) {
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) y[i] += x[i];
+}
+
+void add_f64(const double* x, double* y, long n, hipStream_t s) {
+    if (n <= 0) return;
+    long g = (n + 255) / 256;
+    hipLaunchKernelGGL(add_f64_kernel, dim3((int)(g > 1024 ? 1024 : g)), dim3(256), 0, s, x, y, n);
+}
+
+__global__ void zero_upper_kernel(double* A, int k, long lda) {
+    const long tot = (long)k * k;
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < tot; e += (long)gridDim.x * 256) {
+        const int i = (int)(e % k), c = (int)(e / k);
+        if (i < c) A[(long)i + (long)c * lda] = 0.0;
+    }
+}
+
+void zero_upper(double* A, int k, long lda, hipStream_t s) {
+    if (k <= 0) return;
+    long g = ((long)k * k + 255) / 256;
+    hipLaunchKernelGGL(zero_upper_kernel, dim3((int)(g > 1024 ? 1024 : g)), dim3(256), 0, s, A, k, lda);
+}
+
+__global__ void __launch_bounds__(256) first_feasible_kernel(const double* __restrict__ rel, int n, double eps,
+                                                             int* out) {
+    __shared__ int red[256];
+    int best = n;
+    for (int i = threadIdx.x; i < n; i += 256)
+        if (rel[i] <= eps && i < best) best = i;
+    red[threadIdx.x] = best;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] = min(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+void first_feasible(const double* rel, int n, double eps, int* out, hipStream_t s) {
+    hipLaunchKernelGGL(first_feasible_kernel, dim3(1), dim3(256), 0, s, rel, n, eps, out);
+}
+
+__global__ void __launch_bounds__(256) colblock_sumsq_kernel(const ColNormDesc* __restrict__ descs) {
+    const ColNormDesc D = descs[blockIdx.x];
+    double part = 0.0;
+    for (long e = threadIdx.x; e < (long)D.r * D.k; e += 256) {
+        const int i = (int)(e % D.r), c = (int)(e / D.r);
+        const double v = D.P[(long)i + (long)c * D.ld];
+        part += v * v;
+    }
+    __shared__ double red[4];
+    const double s = block_sum(part, red);
+    if (threadIdx.x == 0) *D.out = s;
+}
+
+void colblock_sumsq_batched(const ColNormDesc* d_descs, int count, hipStream_t s) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(colblock_sumsq_kernel, dim3(count), dim3(256), 0, s, d_descs);
+}
+
+}  // namespace cmsvd
