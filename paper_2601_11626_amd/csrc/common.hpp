@@ -14,11 +14,48 @@ __device__ __forceinline__ double shfl_xor_d(double v, int mask) {
     return __shfl_xor(v, mask, CMSVD_WAVE);
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += shfl_xor_d(v, o);
+// Cross-lane moves that stay on the VALU (no LDS round trip): DPP within rows of
+// 16 lanes and the gfx950 permlane16/32 swaps across rows.  Lane semantics were
+// checked on the device: quad_perm 0xB1 = lane^1, 0x4E = lane^2, row_half_mirror
+// pairs the two quads of every 8-lane group, row_ror:8 = lane^8 within 16 lanes.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// v + v(lane ^ 16) and v + v(lane ^ 32) via the row / half swaps.
+__device__ __forceinline__ double add_swap16(double v) {
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+__device__ __forceinline__ double add_swap32(double v) {
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+
+// Sum over each group of 8 consecutive lanes (every lane of the group gets it).
+__device__ __forceinline__ double sum_lanes8(double v) {
+    v += dpp_move<0xB1>(v);
+    v += dpp_move<0x4E>(v);
+    v += dpp_move<0x141>(v);
     return v;
 }
+
+// Sum over the 8 lanes sharing lane % 8 (every lane of the set gets it).
+__device__ __forceinline__ double sum_stride8(double v) {
+    v += dpp_move<0x128>(v);
+    v = add_swap16(v);
+    return add_swap32(v);
+}
+
+__device__ __forceinline__ double wave_sum(double v) { return sum_stride8(sum_lanes8(v)); }
 
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll

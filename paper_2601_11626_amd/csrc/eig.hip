@@ -27,6 +27,16 @@ constexpr int TILE = 32;         // tile edge
 constexpr int TILE_EL = TILE * TILE;
 constexpr int LDS_BYTES = 163840;  // gfx950: 160 KiB per workgroup
 
+// Tiles are stored in "plane" order: the 4x4 sub-block held by lane (ly, lx) of a
+// wave is spread over 16 planes of 64 doubles, element (4ly+s, 4lx+q) at
+// (s*4+q)*64 + ly*8 + lx.  Every per-element access of a wave then touches 64
+// consecutive doubles (no LDS bank conflicts, fully coalesced in global memory).
+__device__ __forceinline__ int tile_off(int r, int c) {
+    return ((((r & 3) << 2) | (c & 3)) << 6) + ((r >> 2) << 3) + (c >> 2);
+}
+__device__ __forceinline__ int plane_row(int el) { return (((el & 63) >> 3) << 2) + ((el >> 8) & 3); }
+__device__ __forceinline__ int plane_col(int el) { return ((el & 7) << 2) + ((el >> 6) & 3); }
+
 __device__ __forceinline__ double* tile_ptr(int R, int C, int T, int c0, int TL, double* gt, double* lt) {
     if (C >= c0) {
         const int cc = C - c0, rr = R - c0;
@@ -46,15 +56,35 @@ __device__ __forceinline__ double hval(const EigDesc& D, int i, int c) {
     return D.Y[(long)(i - n1) + (long)(c - n1) * D.ldy];
 }
 
-// Number of eigenvalues of the tridiagonal (dd, e2 = off-diagonal squared) below x.
+// Number of eigenvalues of the tridiagonal (dd, e2 = off-diagonal squared) below x,
+// from the signs of the LDL^T pivots of T - x I (Sturm sequence).  The reciprocal
+// is v_rcp_f64 refined by one Newton step; pivots below pivmin in magnitude are
+// replaced by -pivmin.  Loads are issued 8 at a time ahead of the dependent chain.
+__device__ __forceinline__ double rcp_refined(double q) {
+    double r = __builtin_amdgcn_rcp(q);
+    const double e = fma(-q, r, 1.0);
+    return fma(r, e, r);
+}
+
 __device__ __forceinline__ int sturm_count(const double* dd, const double* e2, int n, double x, double pivmin) {
     double q = dd[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
     int cnt = q < 0.0;
-    for (int i = 1; i < n; ++i) {
-        q = (dd[i] - x) - e2[i - 1] / q;
-        if (fabs(q) < pivmin) q = -pivmin;
-        cnt += q < 0.0;
+    for (int i0 = 1; i0 < n; i0 += 8) {
+        double dl[8], el[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            dl[k] = dd[i0 + k];
+            el[k] = e2[i0 + k - 1];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (i0 + k < n) {
+                q = (dl[k] - x) - el[k] * rcp_refined(q);
+                if (fabs(q) < pivmin) q = -pivmin;
+                cnt += q < 0.0;
+            }
+        }
     }
     return cnt;
 }
@@ -65,6 +95,10 @@ static int tl_for(int npad, int T) {
     while (tl + 1 <= T && vec_bytes + (long)(tl + 1) * (tl + 2) / 2 * TILE_EL * 8 <= LDS_BYTES) ++tl;
     return tl;
 }
+
+__device__ __forceinline__ void tile_step(double (&a)[16], int R, int C, const double* __restrict__ vc,
+                                          const double* __restrict__ vp, const double* __restrict__ wp,
+                                          double* pww, int ly, int lx);
 
 template <int MODE>
 __global__ void __launch_bounds__(ET) sym_eig_kernel(const EigDesc* __restrict__ descs, int count, int NP,
@@ -95,10 +129,7 @@ __global__ void __launch_bounds__(ET) sym_eig_kernel(const EigDesc* __restrict__
         for (int C = 0; C < T; ++C)
             for (int R = C; R < T; ++R) {
                 double* tp = tile_ptr(R, C, T, c0, TL, gt, lt);
-                for (int el = t; el < TILE_EL; el += ET) {
-                    const int li = el & 31, lc = el >> 5;
-                    tp[el] = hval(D, R * TILE + li, C * TILE + lc);
-                }
+                for (int el = t; el < TILE_EL; el += ET) tp[el] = hval(D, R * TILE + plane_row(el), C * TILE + plane_col(el));
             }
         for (int i = t; i < npad; i += ET) {
             vc[i] = vp[i] = wp[i] = xv[i] = 0.0;
@@ -115,7 +146,7 @@ __global__ void __launch_bounds__(ET) sym_eig_kernel(const EigDesc* __restrict__
             double part = 0.0;
             for (int i = j + t; i < n; i += ET) {
                 const double* tp = tile_ptr(i >> 5, Cj, T, c0, TL, gt, lt);
-                const double val = tp[cj * TILE + (i & 31)] - (vp[i] * wpj + wp[i] * vpj);
+                const double val = tp[tile_off(i & 31, cj)] - (vp[i] * wpj + wp[i] * vpj);
                 if (i == j) dd[j] = val;
                 else {
                     xv[i] = val;
@@ -157,63 +188,12 @@ __global__ void __launch_bounds__(ET) sym_eig_kernel(const EigDesc* __restrict__
                 for (int R = C; R < T; ++R, ++f) {
                     if ((f & 3) != w) continue;
                     double* tp = tile_ptr(R, C, T, c0, TL, gt, lt);
-                    const int gi0 = R * TILE + 4 * ly, gc0 = C * TILE + 4 * lx;
-                    double a[4][4];
+                    double a[16];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
+                    for (int e = 0; e < 16; ++e) a[e] = tp[(e << 6) + lane];
+                    tile_step(a, R, C, vc, vp, wp, pw + w * NP, ly, lx);
 #pragma unroll
-                        for (int s = 0; s < 4; ++s) a[s][q] = tp[(4 * lx + q) * TILE + 4 * ly + s];
-                    double vr[4], wr[4], cr[4], vq[4], wq[4], cq[4];
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        vr[s] = vp[gi0 + s];
-                        wr[s] = wp[gi0 + s];
-                        cr[s] = vc[gi0 + s];
-                        vq[s] = vp[gc0 + s];
-                        wq[s] = wp[gc0 + s];
-                        cq[s] = vc[gc0 + s];
-                    }
-                    const bool any_active = (gi0 + 3 >= j + 1) && (gc0 + 3 >= j + 1);
-                    if (any_active) {
-#pragma unroll
-                        for (int s = 0; s < 4; ++s)
-#pragma unroll
-                            for (int q = 0; q < 4; ++q)
-                                if (gi0 + s >= j + 1 && gc0 + q >= j + 1)
-                                    a[s][q] -= vr[s] * wq[q] + wr[s] * vq[q];
-#pragma unroll
-                        for (int q = 0; q < 4; ++q)
-#pragma unroll
-                            for (int s = 0; s < 4; ++s) tp[(4 * lx + q) * TILE + 4 * ly + s] = a[s][q];
-                    }
-                    double rp[4], cp[4];
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) rp[s] = a[s][0] * cq[0] + a[s][1] * cq[1] + a[s][2] * cq[2] + a[s][3] * cq[3];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) cp[q] = a[0][q] * cr[0] + a[1][q] * cr[1] + a[2][q] * cr[2] + a[3][q] * cr[3];
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        rp[s] += shfl_xor_d(rp[s], 1);
-                        rp[s] += shfl_xor_d(rp[s], 2);
-                        rp[s] += shfl_xor_d(rp[s], 4);
-                    }
-                    if (R != C) {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            cp[q] += shfl_xor_d(cp[q], 8);
-                            cp[q] += shfl_xor_d(cp[q], 16);
-                            cp[q] += shfl_xor_d(cp[q], 32);
-                        }
-                    }
-                    double* pww = pw + w * NP;
-                    if (lx == 0) {
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) pww[gi0 + s] += rp[s];
-                    }
-                    if (R != C && ly == 0) {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) pww[gc0 + q] += cp[q];
-                    }
+                    for (int e = 0; e < 16; ++e) tp[(e << 6) + lane] = a[e];
                 }
             }
             __syncthreads();
@@ -301,6 +281,333 @@ __global__ void __launch_bounds__(ET) sym_eig_kernel(const EigDesc* __restrict__
     }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident variant for n <= 320 (at most 10 tile rows).
+//
+// 512 threads (8 waves, two per SIMD).  The trailing (up to) 5 tile columns live in
+// LDS as above; every other lower tile (at most 40) lives permanently in the VGPRs
+// of one wave (wave w owns tiles w, w+8, ... in column-major tile order, 5 slots), so
+// the reduction never touches global memory.  One column step costs three barriers:
+// the Householder scalars are recomputed redundantly by every wave, and each wave
+// contracts its own partial A v with v before the cross-wave combine.
+// Bisection is a multisection with 512 / nkeep probes per eigenvalue.
+// ---------------------------------------------------------------------------
+constexpr int RT = 512;
+constexpr int RW = RT / 64;
+constexpr int NSLOT = 5;
+constexpr int REG_TMAX = 10;
+constexpr int RTL = 5;
+
+__device__ __forceinline__ double pick4(const double (&a)[16], int s, int q) {
+    const double x0 = a[s * 4 + 0], x1 = a[s * 4 + 1], x2 = a[s * 4 + 2], x3 = a[s * 4 + 3];
+    return q == 0 ? x0 : (q == 1 ? x1 : (q == 2 ? x2 : x3));
+}
+
+// One tile of the fused pass, for a tile held as a 4x4 sub-block per lane
+// (a[s*4+q] = element (4ly+s, 4lx+q)): applies the pending rank-2 update of step
+// j-1 and accumulates the partial products of A v into this wave's buffer pww.
+// The update is applied unmasked: vp and wp vanish below index j, and the only
+// extra elements it touches (row and column j) are never read again.  vc holds v
+// (zero outside [j+1, n)), so the products need no masking either.
+__device__ __forceinline__ void tile_step(double (&a)[16], int R, int C, const double* __restrict__ vc,
+                                          const double* __restrict__ vp, const double* __restrict__ wp,
+                                          double* pww, int ly, int lx) {
+    const int gi0 = R * TILE + 4 * ly, gc0 = C * TILE + 4 * lx;
+    double vq[4], wq[4], cq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        vq[q] = vp[gc0 + q];
+        wq[q] = wp[gc0 + q];
+        cq[q] = vc[gc0 + q];
+    }
+    double cp0 = 0.0, cp1 = 0.0, cp2 = 0.0, cp3 = 0.0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int i = gi0 + s;
+        const double vr = vp[i], wr = wp[i], cr = vc[i];
+        double rp = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double x = a[s * 4 + q] - (vr * wq[q] + wr * vq[q]);
+            a[s * 4 + q] = x;
+            rp += x * cq[q];
+        }
+        cp0 += a[s * 4 + 0] * cr;
+        cp1 += a[s * 4 + 1] * cr;
+        cp2 += a[s * 4 + 2] * cr;
+        cp3 += a[s * 4 + 3] * cr;
+        rp = sum_lanes8(rp);
+        if (lx == 0) pww[i] += rp;
+    }
+    if (R != C) {
+        cp0 = sum_stride8(cp0);
+        cp1 = sum_stride8(cp1);
+        cp2 = sum_stride8(cp2);
+        cp3 = sum_stride8(cp3);
+        if (ly == 0) {
+            pww[gc0 + 0] += cp0;
+            pww[gc0 + 1] += cp1;
+            pww[gc0 + 2] += cp2;
+            pww[gc0 + 3] += cp3;
+        }
+    }
+}
+
+__device__ __forceinline__ int lds_tile_index(int R, int C, int c0, int TL) {
+    const int cc = C - c0, rr = R - c0;
+    return cc * TL - (cc * (cc - 1)) / 2 + (rr - cc);
+}
+
+constexpr int REG_NP = REG_TMAX * TILE;                                  // vector stride (fixed layout)
+constexpr int REG_PWL = RW * REG_NP;                                     // per-wave partials
+constexpr int REG_LDS_DOUBLES = 6 * REG_NP + REG_PWL + 16 + RTL * (RTL + 1) / 2 * TILE_EL + RW * NSLOT;
+
+template <int MODE>
+__global__ void __launch_bounds__(RT) sym_eig_reg_kernel(const EigDesc* __restrict__ descs, int count) {
+    constexpr int NP = REG_NP, PWL = REG_PWL;
+    extern __shared__ double lds[];
+    double* xv = lds;           // column j, later e^2
+    double* vp = xv + NP;       // previous v
+    double* wp = vp + NP;       // previous w
+    double* pw = wp + NP;       // RW per-wave partials of A v (PWL doubles)
+    double* dd = pw + PWL;
+    double* ee = dd + NP;
+    double* vc = ee + NP;       // current Householder vector (zero outside [j+1, n))
+    double* red = vc + NP;      // 16
+    double* lt = red + 16;      // LDS tiles
+    // register-slot geometry (R << 8 | C, or -1), re-read every step so that no
+    // per-slot scalar state stays live across the column loop
+    int* geo = reinterpret_cast<int*>(lt + RTL * (RTL + 1) / 2 * TILE_EL);
+    const int t = threadIdx.x, lane = t & 63, ly = lane >> 3, lx = lane & 7;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+
+    for (int prob = blockIdx.x; prob < count; prob += gridDim.x) {
+        const EigDesc D = descs[prob];
+        const int n = D.n, T = (n + TILE - 1) / TILE, npad = T * TILE;
+        const int TL = T < RTL ? T : RTL, c0 = T - TL;
+        const int ngl = c0 * T - (c0 * (c0 - 1)) / 2;
+        if (t < RW * NSLOT) {
+            int g = (t % RW) + RW * (t / RW);  // wave t%RW, slot t/RW
+            int code = -1;
+            if (g < ngl) {
+                int C = 0;
+                while (g >= T - C) {
+                    g -= T - C;
+                    ++C;
+                }
+                code = ((C + g) << 8) | C;
+            }
+            geo[(t % RW) * NSLOT + t / RW] = code;
+        }
+        __syncthreads();
+        double rt[NSLOT][16];
+#pragma unroll
+        for (int sl = 0; sl < NSLOT; ++sl) {
+            const int code = __builtin_amdgcn_readfirstlane(geo[w * NSLOT + sl]);
+            const int R = code >> 8, C = code & 255;
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    rt[sl][s * 4 + q] = code >= 0 ? hval(D, R * TILE + 4 * ly + s, C * TILE + 4 * lx + q) : 0.0;
+        }
+        for (int C = c0; C < T; ++C)
+            for (int R = C; R < T; ++R) {
+                double* tp = lt + (size_t)lds_tile_index(R, C, c0, TL) * TILE_EL;
+                for (int el = t; el < TILE_EL; el += RT) tp[el] = hval(D, R * TILE + plane_row(el), C * TILE + plane_col(el));
+            }
+        for (int i = t; i < NP; i += RT) {
+            xv[i] = vp[i] = wp[i] = dd[i] = ee[i] = vc[i] = 0.0;
+        }
+        for (int i = t; i < PWL; i += RT) pw[i] = 0.0;
+        __syncthreads();
+
+        for (int j = 0; j < n; ++j) {
+            const int Cj = j >> 5, cj = j & 31;
+            const double vpj = vp[j], wpj = wp[j];
+            // (A) column j with the pending update of step j-1
+#pragma unroll
+            for (int sl = 0; sl < NSLOT; ++sl) {
+                const int code = __builtin_amdgcn_readfirstlane(geo[w * NSLOT + sl]);
+                if (code >= 0 && (code & 255) == Cj && lx == (cj >> 2)) {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const int i = (code >> 8) * TILE + 4 * ly + s;
+                        if (i >= j && i < n) {
+                            const double val = pick4(rt[sl], s, cj & 3) - (vp[i] * wpj + wp[i] * vpj);
+                            if (i == j) dd[j] = val;
+                            else xv[i] = val;
+                        }
+                    }
+                }
+            }
+            if (Cj >= c0) {
+                for (int i = j + t; i < n; i += RT) {
+                    const double* tp = lt + (size_t)lds_tile_index(i >> 5, Cj, c0, TL) * TILE_EL;
+                    const double val = tp[tile_off(i & 31, cj)] - (vp[i] * wpj + wp[i] * vpj);
+                    if (i == j) dd[j] = val;
+                    else xv[i] = val;
+                }
+            }
+            if (j == n - 1) break;
+            __syncthreads();  // #1
+            // (B) Householder vector of the column (redundantly in every wave)
+            double part = 0.0;
+            for (int i = j + 2 + lane; i < n; i += 64) part += xv[i] * xv[i];
+            const double xn2 = wave_sum(part);
+            const double alpha = xv[j + 1];
+            double tau = 0.0, beta = alpha, scale = 0.0;
+            if (xn2 > 0.0) {
+                beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+                tau = (beta - alpha) / beta;
+                scale = 1.0 / (alpha - beta);
+            }
+            if (t == 0) {
+                ee[j] = beta;
+                if (MODE == 1 && D.tau) D.tau[j] = tau;
+            }
+            if (MODE == 1 && D.V)
+                for (int i = j + 2 + t; i < n; i += RT) D.V[(long)i + (long)j * D.ldv] = tau != 0.0 ? xv[i] * scale : 0.0;
+            for (int i = t; i < npad; i += RT)
+                vc[i] = (tau == 0.0 || i <= j || i >= n) ? 0.0 : (i == j + 1 ? 1.0 : xv[i] * scale);
+            __syncthreads();  // #1b
+            // (C) fused pass: registers tiles, then this wave's share of the LDS tiles
+            double* pww = pw + w * NP;
+#pragma unroll
+            for (int sl = 0; sl < NSLOT; ++sl) {
+                const int code = __builtin_amdgcn_readfirstlane(geo[w * NSLOT + sl]);
+                if (code >= 0 && (code & 255) >= Cj) tile_step(rt[sl], code >> 8, code & 255, vc, vp, wp, pww, ly, lx);
+            }
+            {
+                int f = 0;
+                for (int C = (Cj > c0 ? Cj : c0); C < T; ++C)
+                    for (int R = C; R < T; ++R, ++f) {
+                        if ((f & (RW - 1)) != w) continue;
+                        double* tp = lt + (size_t)lds_tile_index(R, C, c0, TL) * TILE_EL;
+                        double a[16];
+#pragma unroll
+                        for (int e = 0; e < 16; ++e) a[e] = tp[(e << 6) + lane];
+                        tile_step(a, R, C, vc, vp, wp, pww, ly, lx);
+#pragma unroll
+                        for (int e = 0; e < 16; ++e) tp[(e << 6) + lane] = a[e];
+                    }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            double dp = 0.0;
+            for (int i = j + 1 + lane; i < n; i += 64) dp += pww[i] * vc[i];
+            dp = wave_sum(dp);
+            if (lane == 0) red[w] = dp;
+            __syncthreads();  // #2
+            // (D) p = tau A v, w = p - (tau/2)(p.v) v, reset the partials
+            double dsum = 0.0;
+#pragma unroll
+            for (int q = 0; q < RW; ++q) dsum += red[q];
+            const double K = -0.5 * tau * tau * dsum;
+            for (int i = t; i < npad; i += RT) {
+                double acc = 0.0;
+#pragma unroll
+                for (int q = 0; q < RW; ++q) {
+                    acc += pw[q * NP + i];
+                    pw[q * NP + i] = 0.0;
+                }
+                const double vi = vc[i];
+                wp[i] = (i >= j + 1 && i < n) ? tau * acc + K * vi : 0.0;
+                vp[i] = vi;
+            }
+            __syncthreads();  // #3
+        }
+        __syncthreads();
+
+        // ---- multisection bisection for the nkeep largest eigenvalues ----
+        for (int i = t; i < npad; i += RT) xv[i] = (i < n - 1) ? ee[i] * ee[i] : 0.0;
+        double glo = INFINITY, ghi = -INFINITY, em = 0.0;
+        for (int i = t; i < n; i += RT) {
+            const double rad = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i < n - 1 ? fabs(ee[i]) : 0.0);
+            glo = fmin(glo, dd[i] - rad);
+            ghi = fmax(ghi, dd[i] + rad);
+            if (i < n - 1) em = fmax(em, ee[i] * ee[i]);
+        }
+        glo = -block_max(-glo, red);
+        ghi = block_max(ghi, red);
+        em = block_max(em, red);
+        const double tnorm = fmax(fabs(glo), fabs(ghi));
+        const double pivmin = DBL_MIN * fmax(1.0, em);
+        const double tol = 4.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
+        glo -= tol;
+        ghi += tol;
+        const int nk = D.nkeep;
+        int P = 1;
+        while (2 * P * nk <= RT) P *= 2;
+        double* blo = pw;
+        double* bhi = pw + NP;
+        double* flag = pw + 2 * NP;
+        for (int q = t; q < nk; q += RT) {
+            blo[q] = glo;
+            bhi[q] = ghi;
+        }
+        const double width = ghi - glo;
+        int iters = 1;
+        if (width > tol) iters = (int)ceil(log(width / tol) / log((double)(P + 1))) + 2;
+        __syncthreads();
+        for (int it = 0; it < iters; ++it) {
+            for (int base = 0; base < nk * P; base += RT) {
+                const int u = base + t;
+                if (u < nk * P) {
+                    const int q = u / P, pi = u % P;
+                    const double lo = blo[q], hi = bhi[q];
+                    const double x = lo + (hi - lo) * (double)(pi + 1) / (double)(P + 1);
+                    flag[u - base] = (sturm_count(dd, xv, n, x, pivmin) >= n - q) ? 1.0 : 0.0;
+                }
+                __syncthreads();
+                if (u < nk * P && (u % P) == 0) {
+                    const int q = u / P;
+                    const double lo = blo[q], hi = bhi[q];
+                    int first = P;
+                    for (int pi = P - 1; pi >= 0; --pi)
+                        if (flag[u - base + pi] != 0.0) first = pi;
+                    const double nhi = first < P ? lo + (hi - lo) * (double)(first + 1) / (double)(P + 1) : hi;
+                    const double nlo = first > 0 ? lo + (hi - lo) * (double)first / (double)(P + 1) : lo;
+                    blo[q] = nlo;
+                    bhi[q] = nhi;
+                }
+                __syncthreads();
+            }
+        }
+        if (t == 0) {
+            double hi = 0.0, lo = 0.0;
+            for (int q = 0; q < nk; ++q) dd_add(hi, lo, 0.5 * (blo[q] + bhi[q]));
+            if (MODE == 0) {
+                double eh = D.na[0], el = D.na[1];
+                if (D.nb) {
+                    dd_add(eh, el, D.nb[0]);
+                    el += D.nb[1];
+                }
+                double s2, e2;
+                two_sum(eh, -hi, s2, e2);
+                double tail = s2 + (e2 + el - lo);
+                if (tail < 0.0) tail = 0.0;  // clamp rounding below zero; NaN propagates
+                const double err = sqrt(tail);
+                const double etot = eh + el;
+                *D.out_err = err;
+                if (D.out_rel) *D.out_rel = etot != 0.0 ? err / sqrt(etot) : 0.0;
+            } else if (D.sum_top) {
+                D.sum_top[0] = hi;
+                D.sum_top[1] = lo;
+            }
+        }
+        if (MODE == 1) {
+            for (int q = t; q < nk; q += RT) D.lam[q] = 0.5 * (blo[q] + bhi[q]);
+            if (D.d)
+                for (int i = t; i < n; i += RT) {
+                    D.d[i] = dd[i];
+                    if (i < n - 1) D.e[i] = ee[i];
+                }
+        }
+        __syncthreads();
+    }
+}
+
 size_t sym_eig_workspace_doubles(int nmax, int nslots) {
     const int T = (nmax + TILE - 1) / TILE;
     return (size_t)nslots * (size_t)T * (size_t)(T + 1) / 2 * TILE_EL;
@@ -310,6 +617,18 @@ void sym_eig_batched(const EigDesc* d_descs, int count, int nmax, int mode, doub
                      hipStream_t s) {
     if (count <= 0) return;
     const int T = (nmax + TILE - 1) / TILE, npad = T * TILE;
+    if (T <= REG_TMAX) {
+        const size_t lds = (size_t)REG_LDS_DOUBLES * 8;
+        const int grid = count < nslots ? count : nslots;
+        if (mode == 0) {
+            (void)hipFuncSetAttribute((const void*)sym_eig_reg_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(sym_eig_reg_kernel<0>, dim3(grid), dim3(RT), lds, s, d_descs, count);
+        } else {
+            (void)hipFuncSetAttribute((const void*)sym_eig_reg_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(sym_eig_reg_kernel<1>, dim3(grid), dim3(RT), lds, s, d_descs, count);
+        }
+        return;
+    }
     const int TL = tl_for(npad, T);
     const size_t lds = (size_t)(10L * npad + 32) * 8 + (size_t)TL * (TL + 1) / 2 * TILE_EL * 8;
     const long slot = (long)T * (T + 1) / 2 * TILE_EL;
