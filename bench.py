@@ -36,23 +36,104 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def kernel_source_hash():
+    import hashlib
+
+    hs = hashlib.sha256()
+    for name in ("eig.hip", "common.hpp", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2601_11626_amd", "csrc", name), "rb") as f:
+            hs.update(f.read())
+    return hs.hexdigest()[:16]
+
+
+def measured_traffic(kernel, npairs):
+    """HBM bytes per launch of `kernel` from the committed counter summary (FETCH_SIZE +
+    WRITE_SIZE, scaled by a plain copy of known size), or None when the summary is missing
+    or was taken on different kernel sources or another launch size."""
+    path = os.path.join(ROOT, "profiles", "traffic_sym_eig_rotated_groups_256x1024x256_r64.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel") != kernel or rec.get("source_hash") != kernel_source_hash() or rec.get("pairs") != npairs:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def _pmc_rows(path):
+    import csv
+
+    rows = {}
+    with open(path, newline="") as f:
+        for rec in csv.DictReader(f):
+            low = {k.lower(): v for k, v in rec.items()}
+            key = (low.get("dispatch_id"), low.get("kernel_name"))
+            rows[key] = rows.get(key, 0.0) + float(low.get("counter_value", 0.0))
+    return rows  # (dispatch, kernel) -> counter summed over its instances (KiB)
+
+
+def pmc_summary(fetch_csv, write_csv, copy_mib, kernel="sym_eig_reg_kernel<0>"):
+    """Per-launch HBM bytes of `kernel` from FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
+    each scaled by what the same counter reads for the reference copy of copy_mib MiB."""
+    out = {"kernel": kernel, "copy_mib": copy_mib}
+    for tag, path in (("fetch", fetch_csv), ("write", write_csv)):
+        rows = _pmc_rows(path)
+        cal = [v for (d, k), v in rows.items() if "MulFunctor" in (k or "")]
+        ker = [v for (d, k), v in rows.items() if kernel in (k or "")]
+        if not cal or not ker:
+            raise SystemExit(f"{path}: calibration dispatches {len(cal)}, {kernel} dispatches {len(ker)}")
+        scale = (copy_mib << 20) / (sum(cal) / len(cal) * 1024.0)
+        out[tag] = {"kib_per_launch": sum(ker) / len(ker), "launches": len(ker),
+                    "copy_kib": sum(cal) / len(cal), "scale": scale,
+                    "bytes_per_launch": sum(ker) / len(ker) * 1024.0 * scale}
+    out["bytes_per_launch"] = out["fetch"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]
+    out["source_hash"] = kernel_source_hash()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--plain-pairs", type=int, default=48)
-    ap.add_argument("--cpu-pairs", type=int, default=24)
+    ap.add_argument("--plain-pairs", type=int, default=48, help="0 skips the plain per-pair leg")
+    ap.add_argument("--cpu-pairs", type=int, default=448, help="oracle sample size (about 17 s on 16 cores)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--groups", type=int, default=16)
     ap.add_argument("--per-group", type=int, default=16)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run a plain copy of MIB MiB (FP64) three times, the reference "
+                         "dispatch for scaling the HBM traffic counters")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, "
+                         "WRITE_SIZE) of a run with --calibrate-copy, then exit")
+    ap.add_argument("--pmc-mib", type=int, default=1024, help="copy size used with --pmc-summary")
     args = ap.parse_args()
+    if args.pmc_summary:
+        nb = args.groups * args.per_group
+        rec = pmc_summary(*args.pmc_summary, copy_mib=args.pmc_mib)
+        rec["pairs"] = nb * (nb - 1) // 2
+        print(json.dumps(rec, indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "layout is a design note, not part of this build.", file=sys.stderr)
         sys.exit(2)
 
     import torch
+
+    if args.calibrate_copy > 0:
+        # reference dispatches for the traffic counters: dst = 1.0 * src reads and writes
+        # exactly MIB MiB each; the kernel name carries "MulFunctor"
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"copy calibration: 3 dispatches of {nbytes} bytes read + written")
 
     import paper_2601_11626_amd as cm
     import workloads
@@ -93,18 +174,22 @@ def main():
 
     # plain per-pair method on a sample of the same pairs
     rng = np.random.default_rng(1)
-    sample = rng.choice(npairs, size=min(args.plain_pairs, npairs), replace=False)
-    torch.cuda.synchronize()
-    tp = time.perf_counter()
-    plain_err = []
-    for p in sample:
-        e, _ = cm.cmsvd_merge_errors(blocks, pairs[p:p + 1], r, handle=h)
-        plain_err.append(e)
-    torch.cuda.synchronize()
-    plain_rate = len(sample) / (time.perf_counter() - tp)
-    plain_err = torch.cat(plain_err).cpu().numpy()
-    plain_dev = float(np.max(np.abs(plain_err - err_h[sample]) / np.maximum(err_h[sample], 1e-300)))
-    log(f"plain: {plain_rate:.1f} merges/s over {len(sample)} pairs")
+    plain = None
+    if args.plain_pairs > 0:
+        sample = rng.choice(npairs, size=min(args.plain_pairs, npairs), replace=False)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        plain_err = []
+        for p in sample:
+            e, _ = cm.cmsvd_merge_errors(blocks, pairs[p:p + 1], r, handle=h)
+            plain_err.append(e)
+        torch.cuda.synchronize()
+        plain_rate = len(sample) / (time.perf_counter() - tp)
+        plain_err = torch.cat(plain_err).cpu().numpy()
+        plain_dev = float(np.max(np.abs(plain_err - err_h[sample]) / np.maximum(err_h[sample], 1e-300)))
+        plain = {"value": round(plain_rate, 3), "unit": "merges/s", "pairs": int(len(sample)),
+                 "max_rel_diff_vs_batched": plain_dev}
+        log(f"plain: {plain_rate:.1f} merges/s over {len(sample)} pairs")
 
     # dominant stage and its roofline position
     flops = {
@@ -117,7 +202,7 @@ def main():
     if dom in flops and timed[dom] > 0:
         ach = flops[dom] / (timed[dom] * 1e-3) / 1e12
         roof = {
-            "kernel": "sym_eig_kernel<0> (tridiagonalisation + bisection)" if dom == "core_eig" else "gemm_f64_kernel (Y = U^T B)",
+            "kernel": "sym_eig_reg_kernel<0> (tridiagonalisation + bisection)" if dom == "core_eig" else "gemm_f64_kernel (Y = U^T B)",
             "bound": "alu" if dom == "core_eig" else "mfma",
             "achieved": round(ach, 3),
             "peak": PEAK_FP64_TFLOPS,
@@ -130,6 +215,9 @@ def main():
     else:
         roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": None, "traffic": None}
+
+    if roof.get("achieved") is not None:
+        roof["traffic"] = measured_traffic(roof["kernel"].split(" ")[0], npairs)
 
     cpu = None
     parity = None
@@ -179,9 +267,8 @@ def main():
                         f"pairs per step (anchor init included)",
             "blocks": len(blocks_np), "m": int(m), "k": int(k), "r": r, "pairs": npairs,
         },
-        "plain": {"value": round(plain_rate, 3), "unit": "merges/s", "pairs": int(len(sample)),
-                  "max_rel_diff_vs_batched": plain_dev},
-        "speedup_vs_plain": round(value / plain_rate, 2),
+        "plain": plain,
+        "speedup_vs_plain": round(value / plain["value"], 2) if plain else None,
         "stages_ms_per_step": {n: round(stages[n][0] / args.steps, 3) for n in stages},
         "roofline": roof,
         "cpu_baseline": cpu,

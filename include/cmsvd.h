@@ -5,17 +5,17 @@
  * estimate of the optimal rank-r error of a horizontal concatenation
  * [A_1 ... A_K] (Lemma 1 and Corollary 3 of Shamrai, "Concatenated Matrix SVD:
  * Compression Bounds, Incremental Approximation, and Error-Constrained Clustering",
- * TMLR 2026, Section 3.3 and Appendix B) and the plug-in error of Corollary 2,
- * for single updates, for all requested candidate pairs, and inside the greedy
- * error-constrained clustering of Algorithm 3 (Appendix E).
+ * TMLR 2026: Methodology, incremental truncated SVD, and Appendix B) and the plug-in
+ * error of Corollary 2, for single updates, for all requested candidate pairs, and
+ * inside the greedy error-constrained clustering of Algorithm 3 (Appendix E).
  *
  * Conventions shared by every call
- *   - Blocks A_i are real m x n_i matrices with a common row count m (Section 2,
- *     problem formulation).  They are passed as cmsvd_block: a DEVICE pointer to a
+ *   - Blocks A_i are real m x n_i matrices with a common row count m (Problem
+ *     Formulation).  They are passed as cmsvd_block: a DEVICE pointer to a
  *     row-major matrix (element (i, c) at ptr[i * ld + c]), ld >= cols, dtype
  *     CMSVD_F32 or CMSVD_F64.  FP32 data is promoted to FP64 exactly; all
  *     arithmetic is FP64.
- *   - A state of rank r (Algorithm 3, "what is maintained") is a DEVICE basis U
+ *   - A state of rank r (the state Algorithm 3 maintains) is a DEVICE basis U
  *     (m x r, row-major FP64, orthonormal or zero columns), DEVICE singular values
  *     S (r FP64, descending, zero-padded), and DEVICE accumulators
  *     acc[4] = {E_tot hi, E_tot lo, D hi, D lo}: the block energy sum_i ||A_i||_F^2
