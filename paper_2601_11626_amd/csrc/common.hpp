@@ -18,27 +18,29 @@ __device__ __forceinline__ double shfl_xor_d(double v, int mask) {
 // 16 lanes and the gfx950 permlane16/32 swaps across rows.  Lane semantics were
 // checked on the device: quad_perm 0xB1 = lane^1, 0x4E = lane^2, row_half_mirror
 // pairs the two quads of every 8-lane group, row_ror:8 = lane^8 within 16 lanes.
+// Every control used here reads a valid lane, so the moves need no "old" operand.
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v) {
-    int lo = __double2loint(v), hi = __double2hiint(v);
-    lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
-    hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 
-// v + v(lane ^ 16) and v + v(lane ^ 32) via the row / half swaps.
-__device__ __forceinline__ double add_swap16(double v) {
-    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
-    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+// Pairwise reductions through the swaps: lanes 0..31 receive x(l) + x(l^32) and
+// lanes 32..63 receive y(l) + y(l^32); with x == y this is the sum over lane^32.
+__device__ __forceinline__ double add_swap32(double x, double y) {
+    const auto a = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(x), (unsigned)__double2loint(y), false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(x), (unsigned)__double2hiint(y), false, false);
     return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
 }
-__device__ __forceinline__ double add_swap32(double v) {
-    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
-    const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-    const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+// Rows of 16 lanes: even rows receive x(l) + x(l^16), odd rows y(l) + y(l^16).
+__device__ __forceinline__ double add_swap16(double x, double y) {
+    const auto a = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(x), (unsigned)__double2loint(y), false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(x), (unsigned)__double2hiint(y), false, false);
     return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
 }
+__device__ __forceinline__ double add_swap32(double v) { return add_swap32(v, v); }
+__device__ __forceinline__ double add_swap16(double v) { return add_swap16(v, v); }
 
 // Sum over each group of 8 consecutive lanes (every lane of the group gets it).
 __device__ __forceinline__ double sum_lanes8(double v) {

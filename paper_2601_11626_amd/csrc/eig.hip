@@ -89,6 +89,39 @@ __device__ __forceinline__ int sturm_count(const double* dd, const double* e2, i
     return cnt;
 }
 
+// KP Sturm counts at once (independent shifts x[k]); the recurrences are
+// interleaved so that their dependent chains overlap.
+template <int KP>
+__device__ __forceinline__ void sturm_count_k(const double* dd, const double* e2, int n, const double (&x)[KP],
+                                              double pivmin, int (&cnt)[KP]) {
+    double q[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        q[k] = dd[0] - x[k];
+        if (fabs(q[k]) < pivmin) q[k] = -pivmin;
+        cnt[k] = q[k] < 0.0;
+    }
+    for (int i0 = 1; i0 < n; i0 += 8) {
+        double dl[8], el[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            dl[m] = dd[i0 + m];
+            el[m] = e2[i0 + m - 1];
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            if (i0 + m < n) {
+#pragma unroll
+                for (int k = 0; k < KP; ++k) {
+                    q[k] = (dl[m] - x[k]) - el[m] * rcp_refined(q[k]);
+                    if (fabs(q[k]) < pivmin) q[k] = -pivmin;
+                    cnt[k] += q[k] < 0.0;
+                }
+            }
+        }
+    }
+}
+
 static int tl_for(int npad, int T) {
     const long vec_bytes = (10L * npad + 32) * 8;
     int tl = 0;
@@ -290,7 +323,7 @@ __global__ void __launch_bounds__(ET) sym_eig_kernel(const EigDesc* __restrict__
 // the reduction never touches global memory.  One column step costs three barriers:
 // the Householder scalars are recomputed redundantly by every wave, and each wave
 // contracts its own partial A v with v before the cross-wave combine.
-// Bisection is a multisection with 512 / nkeep probes per eigenvalue.
+// Bisection is a multisection with 512 / nkeep probes per eigenvalue per round.
 // ---------------------------------------------------------------------------
 constexpr int RT = 512;
 constexpr int RW = RT / 64;
@@ -309,6 +342,12 @@ __device__ __forceinline__ double pick4(const double (&a)[16], int s, int q) {
 // The update is applied unmasked: vp and wp vanish below index j, and the only
 // extra elements it touches (row and column j) are never read again.  vc holds v
 // (zero outside [j+1, n)), so the products need no masking either.
+//
+// Row sums are reduced over the 8 lanes of a row group (lx) with DPP; lane lx < 4
+// then adds row 4ly+lx.  Column sums (off-diagonal tiles only; diagonal tiles hold
+// both triangles) are reduce-scattered over ly: the two swap stages pair different
+// columns, so after the last DPP stage the lanes with even ly hold column
+// 4lx + q, q = (ly>>2) + 2((ly>>1)&1), each summed over all eight row groups.
 __device__ __forceinline__ void tile_step(double (&a)[16], int R, int C, const double* __restrict__ vc,
                                           const double* __restrict__ vp, const double* __restrict__ wp,
                                           double* pww, int ly, int lx) {
@@ -320,36 +359,73 @@ __device__ __forceinline__ void tile_step(double (&a)[16], int R, int C, const d
         wq[q] = wp[gc0 + q];
         cq[q] = vc[gc0 + q];
     }
-    double cp0 = 0.0, cp1 = 0.0, cp2 = 0.0, cp3 = 0.0;
+    double cp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        const int i = gi0 + s;
-        const double vr = vp[i], wr = wp[i], cr = vc[i];
+        const double vr = vp[gi0 + s], wr = wp[gi0 + s], cr = vc[gi0 + s];
         double rp = 0.0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const double x = a[s * 4 + q] - (vr * wq[q] + wr * vq[q]);
+            double x = fma(-vr, wq[q], a[s * 4 + q]);
+            x = fma(-wr, vq[q], x);
             a[s * 4 + q] = x;
-            rp += x * cq[q];
+            rp = fma(x, cq[q], rp);
+            cp[q] = fma(x, cr, cp[q]);
         }
-        cp0 += a[s * 4 + 0] * cr;
-        cp1 += a[s * 4 + 1] * cr;
-        cp2 += a[s * 4 + 2] * cr;
-        cp3 += a[s * 4 + 3] * cr;
         rp = sum_lanes8(rp);
-        if (lx == 0) pww[i] += rp;
+        if (lx == s) unsafeAtomicAdd(&pww[gi0 + s], rp);
     }
     if (R != C) {
-        cp0 = sum_stride8(cp0);
-        cp1 = sum_stride8(cp1);
-        cp2 = sum_stride8(cp2);
-        cp3 = sum_stride8(cp3);
-        if (ly == 0) {
-            pww[gc0 + 0] += cp0;
-            pww[gc0 + 1] += cp1;
-            pww[gc0 + 2] += cp2;
-            pww[gc0 + 3] += cp3;
+        const double s01 = add_swap32(cp[0], cp[1]);
+        const double s23 = add_swap32(cp[2], cp[3]);
+        double t = add_swap16(s01, s23);
+        t += dpp_move<0x128>(t);
+        if ((ly & 1) == 0) unsafeAtomicAdd(&pww[gc0 + (ly >> 2) + 2 * ((ly >> 1) & 1)], t);
+    }
+}
+
+// The same tile update for row-owned passes: the row partials are accumulated into
+// racc (per lane, rows 4ly..4ly+3 of the tile row) instead of being reduced per tile;
+// flush_rows reduces and publishes them once per tile row.
+__device__ __forceinline__ void tile_step_racc(double (&a)[16], int R, int C, const double* __restrict__ vc,
+                                               const double* __restrict__ vp, const double* __restrict__ wp,
+                                               double* pww, int ly, int lx, double (&racc)[4]) {
+    const int gi0 = R * TILE + 4 * ly, gc0 = C * TILE + 4 * lx;
+    double vq[4], wq[4], cq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        vq[q] = vp[gc0 + q];
+        wq[q] = wp[gc0 + q];
+        cq[q] = vc[gc0 + q];
+    }
+    double cp[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const double vr = vp[gi0 + s], wr = wp[gi0 + s], cr = vc[gi0 + s];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double x = fma(-vr, wq[q], a[s * 4 + q]);
+            x = fma(-wr, vq[q], x);
+            a[s * 4 + q] = x;
+            racc[s] = fma(x, cq[q], racc[s]);
+            cp[q] = fma(x, cr, cp[q]);
         }
+    }
+    if (R != C) {
+        const double s01 = add_swap32(cp[0], cp[1]);
+        const double s23 = add_swap32(cp[2], cp[3]);
+        double t = add_swap16(s01, s23);
+        t += dpp_move<0x128>(t);
+        if ((ly & 1) == 0) unsafeAtomicAdd(&pww[gc0 + (ly >> 2) + 2 * ((ly >> 1) & 1)], t);
+    }
+}
+
+__device__ __forceinline__ void flush_rows(int R, double (&racc)[4], double* pww, int ly, int lx) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const double v = sum_lanes8(racc[s]);
+        if (lx == s) unsafeAtomicAdd(&pww[R * TILE + 4 * ly + s], v);
+        racc[s] = 0.0;
     }
 }
 
@@ -360,20 +436,25 @@ __device__ __forceinline__ int lds_tile_index(int R, int C, int c0, int TL) {
 
 constexpr int REG_NP = REG_TMAX * TILE;                                  // vector stride (fixed layout)
 constexpr int REG_PWL = RW * REG_NP;                                     // per-wave partials
-constexpr int REG_LDS_DOUBLES = 6 * REG_NP + REG_PWL + 16 + RTL * (RTL + 1) / 2 * TILE_EL + RW * NSLOT;
+// geo: RW*NSLOT slot codes, then per tile column c the LDS-tile share of every wave
+// ((first << 8) | count, RW * REG_TMAX ints)
+constexpr int REG_GEO_INTS = RW * NSLOT + RW * REG_TMAX;
+constexpr int REG_LDS_DOUBLES = 7 * REG_NP + REG_PWL + 16 + RTL * (RTL + 1) / 2 * TILE_EL + REG_GEO_INTS / 2;
+static_assert(REG_LDS_DOUBLES * 8 <= LDS_BYTES, "register-resident eigen kernel exceeds the LDS");
 
 template <int MODE>
 __global__ void __launch_bounds__(RT) sym_eig_reg_kernel(const EigDesc* __restrict__ descs, int count) {
     constexpr int NP = REG_NP, PWL = REG_PWL;
     extern __shared__ double lds[];
-    double* xv = lds;           // column j, later e^2
-    double* vp = xv + NP;       // previous v
-    double* wp = vp + NP;       // previous w
-    double* pw = wp + NP;       // RW per-wave partials of A v (PWL doubles)
+    double* xv = lds;           // current column below the diagonal (later e^2)
+    double* vc = xv + NP;       // Householder vector v_j of the current step
+    double* vp = vc + NP;       // v of the previous step
+    double* wp = vp + NP;       // w of the previous step
+    double* xn = wp + NP;       // next column as held in the register tiles
+    double* pw = xn + NP;       // RW per-wave partials of A v (PWL doubles)
     double* dd = pw + PWL;
     double* ee = dd + NP;
-    double* vc = ee + NP;       // current Householder vector (zero outside [j+1, n))
-    double* red = vc + NP;      // 16
+    double* red = ee + NP;      // 16: per-wave dots (0..7), per-wave norm partials (8..15)
     double* lt = red + 16;      // LDS tiles
     // register-slot geometry (R << 8 | C, or -1), re-read every step so that no
     // per-slot scalar state stays live across the column loop
@@ -386,20 +467,41 @@ __global__ void __launch_bounds__(RT) sym_eig_reg_kernel(const EigDesc* __restri
         const int n = D.n, T = (n + TILE - 1) / TILE, npad = T * TILE;
         const int TL = T < RTL ? T : RTL, c0 = T - TL;
         const int ngl = c0 * T - (c0 * (c0 - 1)) / 2;
+        // Register tiles (columns below c0) in row-major order, split into contiguous
+        // chunks of at most NSLOT per wave, so that a wave's tiles share tile rows.
+        const int cs = (ngl + RW - 1) / RW;
         if (t < RW * NSLOT) {
-            int g = (t % RW) + RW * (t / RW);  // wave t%RW, slot t/RW
-            int code = -1;
-            if (g < ngl) {
-                int C = 0;
-                while (g >= T - C) {
-                    g -= T - C;
-                    ++C;
+            const int ww = t / NSLOT, sl = t % NSLOT;
+            int g = ww * cs + sl, code = -1;
+            if (sl < cs && g < ngl) {
+                int R = 0;
+                while (g >= (R + 1 < c0 ? R + 1 : c0)) {
+                    g -= (R + 1 < c0 ? R + 1 : c0);
+                    ++R;
                 }
-                code = ((C + g) << 8) | C;
+                code = (R << 8) | g;
             }
-            geo[(t % RW) * NSLOT + t / RW] = code;
+            geo[t] = code;
         }
         __syncthreads();
+        // For each tile column c (the step's leading column), the active LDS tiles
+        // (columns >= max(c, c0)) in row-major order, handed out so that every wave
+        // ends up with about the same number of active tiles.
+        if (t < T) {
+            const int c = t, cl = c > c0 ? c : c0, mL = T - cl, NL = mL * (mL + 1) / 2;
+            int tot = NL;
+            for (int g = 0; g < RW * NSLOT; ++g) tot += (geo[g] >= 0 && (geo[g] & 255) >= c) ? 1 : 0;
+            const int target = (tot + RW - 1) / RW;
+            int first = 0;
+            for (int ww = 0; ww < RW; ++ww) {
+                int rc = 0;
+                for (int sl = 0; sl < NSLOT; ++sl) rc += (geo[ww * NSLOT + sl] >= 0 && (geo[ww * NSLOT + sl] & 255) >= c) ? 1 : 0;
+                int k = target - rc;
+                k = k < 0 ? 0 : (k > NL - first ? NL - first : k);
+                geo[RW * NSLOT + c * RW + ww] = (first << 8) | k;
+                first += k;
+            }
+        }
         double rt[NSLOT][16];
 #pragma unroll
         for (int sl = 0; sl < NSLOT; ++sl) {
@@ -416,45 +518,31 @@ __global__ void __launch_bounds__(RT) sym_eig_reg_kernel(const EigDesc* __restri
                 double* tp = lt + (size_t)lds_tile_index(R, C, c0, TL) * TILE_EL;
                 for (int el = t; el < TILE_EL; el += RT) tp[el] = hval(D, R * TILE + plane_row(el), C * TILE + plane_col(el));
             }
+        // column 0 and the norm of its part below the subdiagonal
+        double part = 0.0;
         for (int i = t; i < NP; i += RT) {
-            xv[i] = vp[i] = wp[i] = dd[i] = ee[i] = vc[i] = 0.0;
+            const double x = i < n ? hval(D, i, 0) : 0.0;
+            xv[i] = i >= 1 ? x : 0.0;
+            dd[i] = i == 0 ? x : 0.0;
+            if (i >= 2) part += x * x;
+            vc[i] = vp[i] = wp[i] = xn[i] = ee[i] = 0.0;
         }
         for (int i = t; i < PWL; i += RT) pw[i] = 0.0;
+        part = wave_sum(part);
+        if (lane == 0) red[8 + w] = part;
         __syncthreads();
 
-        for (int j = 0; j < n; ++j) {
-            const int Cj = j >> 5, cj = j & 31;
-            const double vpj = vp[j], wpj = wp[j];
-            // (A) column j with the pending update of step j-1
+        // Step j: (H) Householder vector v_j of column j; (P) one pass over the
+        // trailing tiles applying the update of step j-1 and forming A v_j, while the
+        // owners of column j+1 publish it; (W) w_j, column j+1 with the update of
+        // step j, the norm partials for step j+1, and v_j kept as the previous
+        // vector.  Three barriers per step.
+        for (int j = 0; j + 1 < n; ++j) {
+            const int Cj = j >> 5;
+            // (H) redundantly in every wave
+            double xn2 = 0.0;
 #pragma unroll
-            for (int sl = 0; sl < NSLOT; ++sl) {
-                const int code = __builtin_amdgcn_readfirstlane(geo[w * NSLOT + sl]);
-                if (code >= 0 && (code & 255) == Cj && lx == (cj >> 2)) {
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        const int i = (code >> 8) * TILE + 4 * ly + s;
-                        if (i >= j && i < n) {
-                            const double val = pick4(rt[sl], s, cj & 3) - (vp[i] * wpj + wp[i] * vpj);
-                            if (i == j) dd[j] = val;
-                            else xv[i] = val;
-                        }
-                    }
-                }
-            }
-            if (Cj >= c0) {
-                for (int i = j + t; i < n; i += RT) {
-                    const double* tp = lt + (size_t)lds_tile_index(i >> 5, Cj, c0, TL) * TILE_EL;
-                    const double val = tp[tile_off(i & 31, cj)] - (vp[i] * wpj + wp[i] * vpj);
-                    if (i == j) dd[j] = val;
-                    else xv[i] = val;
-                }
-            }
-            if (j == n - 1) break;
-            __syncthreads();  // #1
-            // (B) Householder vector of the column (redundantly in every wave)
-            double part = 0.0;
-            for (int i = j + 2 + lane; i < n; i += 64) part += xv[i] * xv[i];
-            const double xn2 = wave_sum(part);
+            for (int q = 0; q < RW; ++q) xn2 += red[8 + q];
             const double alpha = xv[j + 1];
             double tau = 0.0, beta = alpha, scale = 0.0;
             if (xn2 > 0.0) {
@@ -470,28 +558,64 @@ __global__ void __launch_bounds__(RT) sym_eig_reg_kernel(const EigDesc* __restri
                 for (int i = j + 2 + t; i < n; i += RT) D.V[(long)i + (long)j * D.ldv] = tau != 0.0 ? xv[i] * scale : 0.0;
             for (int i = t; i < npad; i += RT)
                 vc[i] = (tau == 0.0 || i <= j || i >= n) ? 0.0 : (i == j + 1 ? 1.0 : xv[i] * scale);
-            __syncthreads();  // #1b
-            // (C) fused pass: registers tiles, then this wave's share of the LDS tiles
+            __syncthreads();  // #1
+            // (P) register tiles, then this wave's share of the LDS tiles.  Row
+            // partials accumulate while consecutive tiles stay in one tile row.
+            const int Cn = (j + 1) >> 5, cn = (j + 1) & 31;
             double* pww = pw + w * NP;
+            double racc[4] = {0.0, 0.0, 0.0, 0.0};
+            int curR = -1;
 #pragma unroll
             for (int sl = 0; sl < NSLOT; ++sl) {
                 const int code = __builtin_amdgcn_readfirstlane(geo[w * NSLOT + sl]);
-                if (code >= 0 && (code & 255) >= Cj) tile_step(rt[sl], code >> 8, code & 255, vc, vp, wp, pww, ly, lx);
+                if (code >= 0 && (code & 255) >= Cj) {
+                    const int R = code >> 8, C = code & 255;
+                    if (R != curR) {
+                        if (curR >= 0) flush_rows(curR, racc, pww, ly, lx);
+                        curR = R;
+                    }
+                    tile_step_racc(rt[sl], R, C, vc, vp, wp, pww, ly, lx, racc);
+                    if (C == Cn && lx == (cn >> 2)) {
+                        double* xo = xn + R * TILE + 4 * ly;
+                        switch (cn & 3) {  // uniform across the wave
+                            case 0: xo[0] = rt[sl][0]; xo[1] = rt[sl][4]; xo[2] = rt[sl][8]; xo[3] = rt[sl][12]; break;
+                            case 1: xo[0] = rt[sl][1]; xo[1] = rt[sl][5]; xo[2] = rt[sl][9]; xo[3] = rt[sl][13]; break;
+                            case 2: xo[0] = rt[sl][2]; xo[1] = rt[sl][6]; xo[2] = rt[sl][10]; xo[3] = rt[sl][14]; break;
+                            default: xo[0] = rt[sl][3]; xo[1] = rt[sl][7]; xo[2] = rt[sl][11]; xo[3] = rt[sl][15]; break;
+                        }
+                    }
+                }
             }
             {
-                int f = 0;
-                for (int C = (Cj > c0 ? Cj : c0); C < T; ++C)
-                    for (int R = C; R < T; ++R, ++f) {
-                        if ((f & (RW - 1)) != w) continue;
-                        double* tp = lt + (size_t)lds_tile_index(R, C, c0, TL) * TILE_EL;
-                        double a[16];
-#pragma unroll
-                        for (int e = 0; e < 16; ++e) a[e] = tp[(e << 6) + lane];
-                        tile_step(a, R, C, vc, vp, wp, pww, ly, lx);
-#pragma unroll
-                        for (int e = 0; e < 16; ++e) tp[(e << 6) + lane] = a[e];
+                const int al = __builtin_amdgcn_readfirstlane(geo[RW * NSLOT + Cj * RW + w]);
+                const int cl = Cj > c0 ? Cj : c0;
+                int f = al >> 8, k = al & 255;
+                // row-major position of the first tile of this wave's share
+                int R = cl, C = cl;
+                while (f > R - cl) {
+                    f -= R - cl + 1;
+                    ++R;
+                }
+                C = cl + f;
+                for (; k > 0; --k) {
+                    if (R != curR) {
+                        if (curR >= 0) flush_rows(curR, racc, pww, ly, lx);
+                        curR = R;
                     }
+                    double* tp = lt + (size_t)lds_tile_index(R, C, c0, TL) * TILE_EL;
+                    double a[16];
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) a[e] = tp[(e << 6) + lane];
+                    tile_step_racc(a, R, C, vc, vp, wp, pww, ly, lx, racc);
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) tp[(e << 6) + lane] = a[e];
+                    if (++C > R) {
+                        ++R;
+                        C = cl;
+                    }
+                }
             }
+            if (curR >= 0) flush_rows(curR, racc, pww, ly, lx);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             double dp = 0.0;
@@ -499,22 +623,45 @@ __global__ void __launch_bounds__(RT) sym_eig_reg_kernel(const EigDesc* __restri
             dp = wave_sum(dp);
             if (lane == 0) red[w] = dp;
             __syncthreads();  // #2
-            // (D) p = tau A v, w = p - (tau/2)(p.v) v, reset the partials
+            // (W) p = tau A v, w = p - (tau/2)(p.v) v; column j+1 of A - v w^T - w v^T.
+            // Every thread needs w_{j+1} and v_{j+1}, so it forms them from the partials
+            // itself; those partials are never cleared (row j+1 is dead from here on).
             double dsum = 0.0;
 #pragma unroll
             for (int q = 0; q < RW; ++q) dsum += red[q];
             const double K = -0.5 * tau * tau * dsum;
-            for (int i = t; i < npad; i += RT) {
-                double acc = 0.0;
+            double p1 = 0.0;
 #pragma unroll
-                for (int q = 0; q < RW; ++q) {
-                    acc += pw[q * NP + i];
-                    pw[q * NP + i] = 0.0;
+            for (int q = 0; q < RW; ++q) p1 += pw[q * NP + j + 1];
+            const double v1 = vc[j + 1];
+            const double w1 = tau * p1 + K * v1;
+            part = 0.0;
+            for (int i = t; i < npad; i += RT) {
+                double wi = 0.0;
+                if (i >= j + 1 && i < n) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int q = 0; q < RW; ++q) acc += pw[q * NP + i];
+                    wi = tau * acc + K * vc[i];
+                    const double base = Cn < c0 ? xn[i]
+                                                : lt[(size_t)lds_tile_index(i >> 5, Cn, c0, TL) * TILE_EL + tile_off(i & 31, cn)];
+                    double x = fma(-vc[i], w1, base);
+                    x = fma(-wi, v1, x);
+                    if (i == j + 1) dd[j + 1] = x;
+                    else {
+                        xv[i] = x;
+                        if (i >= j + 3) part += x * x;
+                    }
                 }
-                const double vi = vc[i];
-                wp[i] = (i >= j + 1 && i < n) ? tau * acc + K * vi : 0.0;
-                vp[i] = vi;
+                if (i >= j + 2) {
+#pragma unroll
+                    for (int q = 0; q < RW; ++q) pw[q * NP + i] = 0.0;
+                }
+                wp[i] = wi;
+                vp[i] = vc[i];
             }
+            part = wave_sum(part);
+            if (lane == 0) red[8 + w] = part;
             __syncthreads();  // #3
         }
         __syncthreads();
@@ -536,12 +683,15 @@ __global__ void __launch_bounds__(RT) sym_eig_reg_kernel(const EigDesc* __restri
         const double tol = 4.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
         glo -= tol;
         ghi += tol;
+        // One probe per thread (the Sturm recurrence already keeps the VALU busy);
+        // P probes per eigenvalue and round split its interval into P + 1 parts.
+        constexpr int KP = 1, NPROBE = KP * RT;
         const int nk = D.nkeep;
         int P = 1;
-        while (2 * P * nk <= RT) P *= 2;
+        while (2 * P * nk <= NPROBE) P *= 2;
         double* blo = pw;
         double* bhi = pw + NP;
-        double* flag = pw + 2 * NP;
+        int* flag = reinterpret_cast<int*>(pw + 2 * NP);  // NPROBE ints
         for (int q = t; q < nk; q += RT) {
             blo[q] = glo;
             bhi[q] = ghi;
@@ -551,21 +701,33 @@ __global__ void __launch_bounds__(RT) sym_eig_reg_kernel(const EigDesc* __restri
         if (width > tol) iters = (int)ceil(log(width / tol) / log((double)(P + 1))) + 2;
         __syncthreads();
         for (int it = 0; it < iters; ++it) {
-            for (int base = 0; base < nk * P; base += RT) {
-                const int u = base + t;
-                if (u < nk * P) {
-                    const int q = u / P, pi = u % P;
-                    const double lo = blo[q], hi = bhi[q];
-                    const double x = lo + (hi - lo) * (double)(pi + 1) / (double)(P + 1);
-                    flag[u - base] = (sturm_count(dd, xv, n, x, pivmin) >= n - q) ? 1.0 : 0.0;
+            for (int base = 0; base < nk * P; base += NPROBE) {
+                double x[KP];
+                int cnt[KP];
+#pragma unroll
+                for (int k = 0; k < KP; ++k) {
+                    const int u = base + t * KP + k;
+                    x[k] = 0.0;
+                    if (u < nk * P) {
+                        const int q = u / P, pi = u % P;
+                        const double lo = blo[q], hi = bhi[q];
+                        x[k] = lo + (hi - lo) * (double)(pi + 1) / (double)(P + 1);
+                    }
+                }
+                sturm_count_k<KP>(dd, xv, n, x, pivmin, cnt);
+#pragma unroll
+                for (int k = 0; k < KP; ++k) {
+                    const int u = base + t * KP + k;
+                    if (u < nk * P) flag[u - base] = cnt[k] >= n - u / P;
                 }
                 __syncthreads();
-                if (u < nk * P && (u % P) == 0) {
-                    const int q = u / P;
+                const int q = base / P + t;
+                if (t < NPROBE / P && q < nk) {
                     const double lo = blo[q], hi = bhi[q];
+                    const int* fq = flag + (q * P - base);
                     int first = P;
                     for (int pi = P - 1; pi >= 0; --pi)
-                        if (flag[u - base + pi] != 0.0) first = pi;
+                        if (fq[pi]) first = pi;
                     const double nhi = first < P ? lo + (hi - lo) * (double)(first + 1) / (double)(P + 1) : hi;
                     const double nlo = first > 0 ? lo + (hi - lo) * (double)first / (double)(P + 1) : lo;
                     blo[q] = nlo;
