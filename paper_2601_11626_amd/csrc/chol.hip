@@ -12,78 +12,111 @@
 
 namespace cmsvd {
 
-__global__ void __launch_bounds__(256) chol_semidef_kernel(const CholDesc* __restrict__ descs) {
+constexpr int CHT = 256;              // threads per problem
+constexpr int CH_LDS = 16384;         // doubles of LDS for panels (128 KiB)
+
+// Right-looking Cholesky by panels of up to 32 columns.  The panel (all rows from
+// its first column down) is factored in LDS; the trailing lower triangle is then
+// updated in global memory (L2-resident), one column at a time with the rows spread
+// over the threads.  Afterwards the inverse of L is formed by column blocks, each
+// block held in LDS while its rows are produced in order; every entry is a dot
+// product split over 8 lanes and reduced with DPP.
+__global__ void __launch_bounds__(CHT) chol_semidef_kernel(const CholDesc* __restrict__ descs) {
     const CholDesc D = descs[blockIdx.x];
     const int k = D.k, t = threadIdx.x;
     double* G = D.G;
     const long ld = D.ldg;
-    __shared__ double colj[4096];
-    __shared__ double piv;
-    __shared__ int ndrop;
-    if (t == 0) ndrop = 0;
+    extern __shared__ double sm[];
+    __shared__ double piv_s;
+    __shared__ int ndrop_s;
+    if (t == 0) ndrop_s = 0;
     const double thresh = D.thresh_scale * (D.thresh_ref ? D.thresh_ref[0] : 1.0);
-    for (int j = 0; j < k; ++j) {
-        if (t == 0) {
-            const double dj = G[j + j * ld];
-            if (dj > thresh) piv = sqrt(dj);
-            else {
-                piv = 0.0;
-                ++ndrop;
+    int pw = 32;
+    while (pw > 1 && (long)k * pw > CH_LDS) pw >>= 1;
+
+    for (int jb = 0; jb < k; jb += pw) {
+        const int w = pw < k - jb ? pw : k - jb, h = k - jb;
+        double* P = sm;  // h x w row-major: P[r * w + c] = G(jb + r, jb + c)
+        __syncthreads();
+        for (int r = t; r < h; r += CHT)
+            for (int c = 0; c < w; ++c) P[r * w + c] = r >= c ? G[(jb + r) + (long)(jb + c) * ld] : 0.0;
+        __syncthreads();
+        for (int c = 0; c < w; ++c) {
+            if (t == 0) {
+                const double d = P[c * w + c];
+                double pv = 0.0;
+                if (d > thresh) pv = sqrt(d);
+                else ++ndrop_s;
+                P[c * w + c] = pv;
+                piv_s = pv;
             }
-            G[j + j * ld] = piv;
+            __syncthreads();
+            const double pv = piv_s;
+            const double inv = pv > 0.0 ? 1.0 / pv : 0.0;
+            for (int r = c + 1 + t; r < h; r += CHT) P[r * w + c] *= inv;
+            __syncthreads();
+            for (int r = c + 1 + t; r < h; r += CHT) {
+                const double l = P[r * w + c];
+                const int cmax = r < w - 1 ? r : w - 1;
+                for (int c2 = c + 1; c2 <= cmax; ++c2) P[r * w + c2] -= l * P[c2 * w + c];
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        const double pj = piv;
-        for (int i = j + 1 + t; i < k; i += 256) {
-            const double v = pj > 0.0 ? G[i + j * ld] / pj : 0.0;
-            G[i + j * ld] = v;
-            if (i < 4096) colj[i] = v;
-        }
-        __syncthreads();
-        if (pj > 0.0) {
-            // trailing update of the lower triangle: G(i,l) -= L(i,j) L(l,j), j < l <= i
-            const int m = k - j - 1;
-            const long tot = (long)m * m;
-            for (long e = t; e < tot; e += 256) {
-                const int i = (int)(e % m), l = (int)(e / m);
-                if (i < l) continue;
-                const int gi = j + 1 + i, gl = j + 1 + l;
-                const double li = gi < 4096 ? colj[gi] : G[gi + j * ld];
-                const double ll = gl < 4096 ? colj[gl] : G[gl + j * ld];
-                G[gi + (long)gl * ld] -= li * ll;
+        for (int r = t; r < h; r += CHT)
+            for (int c = 0; c < w && c <= r; ++c) G[(jb + r) + (long)(jb + c) * ld] = P[r * w + c];
+        for (int l = jb + w; l < k; ++l) {
+            const double* Pl = P + (l - jb) * w;
+            for (int i = l + t; i < k; i += CHT) {
+                const double* Pi = P + (i - jb) * w;
+                double acc = 0.0;
+                for (int p = 0; p < w; ++p) acc = fma(Pi[p], Pl[p], acc);
+                G[i + (long)l * ld] -= acc;
             }
         }
         __syncthreads();
     }
-    // Linv: forward substitution, one column of the inverse per thread
-    for (int c = t; c < k; c += 256) {
-        double* X = D.Linv + (long)c * D.ldi;
-        for (int i = 0; i < c; ++i) X[i] = 0.0;
-        const double lcc = G[c + c * ld];
-        X[c] = lcc > 0.0 ? 1.0 / lcc : 0.0;
-        for (int i = c + 1; i < k; ++i) {
-            const double lii = G[i + i * ld];
-            if (lii > 0.0) {
-                double s = 0.0;
-                for (int b = c; b < i; ++b) s += G[i + (long)b * ld] * X[b];
-                X[i] = -s / lii;
-            } else {
-                X[i] = 0.0;
+
+    // Linv = L^{-1} on the kept pivots: column block [cb, cb + w) solves L X = I by
+    // forward substitution, rows in order; thread t works on column c = t / 8 with
+    // part t % 8 of every dot product.
+    int xw = 32;
+    while (xw > 1 && (long)k * xw > CH_LDS) xw >>= 1;
+    const int c = t >> 3, part = t & 7;
+    for (int cb = 0; cb < k; cb += xw) {
+        const int w = xw < k - cb ? xw : k - cb;
+        double* X = sm;  // (k - cb) x w row-major
+        __syncthreads();
+        for (int i = cb; i < k; ++i) {
+            const double lii = G[i + (long)i * ld];
+            double s = 0.0;
+            const int gc = cb + c;
+            if (c < w && gc < i)
+                for (int b = gc + part; b < i; b += 8) s = fma(G[i + (long)b * ld], X[(b - cb) * w + c], s);
+            s = sum_lanes8(s);
+            if (c < w && part == 0) {
+                double x = 0.0;
+                if (i >= gc && lii > 0.0) x = ((i == gc ? 1.0 : 0.0) - s) / lii;
+                X[(i - cb) * w + c] = x;
             }
+            __syncthreads();
+        }
+        for (int cc = 0; cc < w; ++cc) {
+            double* Xo = D.Linv + (long)(cb + cc) * D.ldi;
+            for (int i = t; i < k; i += CHT) Xo[i] = i >= cb ? X[(i - cb) * w + cc] : 0.0;
         }
     }
     __syncthreads();
     // leave L with a zero strict upper triangle
-    for (long e = t; e < (long)k * k; e += 256) {
-        const int i = (int)(e % k), c = (int)(e / k);
-        if (i < c) G[i + (long)c * ld] = 0.0;
-    }
-    if (t == 0 && D.dropped) *D.dropped = ndrop;
+    for (int cc = 1; cc < k; ++cc)
+        for (int i = t; i < cc; i += CHT) G[i + (long)cc * ld] = 0.0;
+    if (t == 0 && D.dropped) *D.dropped = ndrop_s;
 }
 
 void chol_semidef_batched(const CholDesc* d_descs, int count, hipStream_t s) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(chol_semidef_kernel, dim3(count), dim3(256), 0, s, d_descs);
+    (void)hipFuncSetAttribute((const void*)chol_semidef_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              CH_LDS * (int)sizeof(double));
+    hipLaunchKernelGGL(chol_semidef_kernel, dim3(count), dim3(CHT), CH_LDS * sizeof(double), s, d_descs);
 }
 
 // Frobenius norm squared (double-double) of row-major blocks.
