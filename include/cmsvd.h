@@ -119,6 +119,36 @@ cmsvd_status cmsvd_cluster(cmsvd_handle handle, const cmsvd_block* blocks, int64
                            double eps, int32_t sort_mode, int32_t* labels, int64_t* nclusters,
                            double* cluster_rel);
 
+/* Tail energy of a chain and its gradient with respect to every block.
+   The chain folds the blocks in order (the incremental state of Lemma 1 and
+   Corollary 3, starting from the empty state); the tail energy is Corollary 2's
+   plug-in f = E~_r^2 = sum_t ||A_t||_F^2 - sum_{l<=r} sigma_l^2 of the final state.
+   The paper gives no gradient; the one computed here is the reverse mode through
+   every truncation: with H_t the Gram of step t and W_t the derivative of the
+   retained energy with respect to H_t, W_T projects onto the kept eigenvectors and
+   W_t applies the Daleckii-Krein divided differences of the truncation to W_{t+1}
+   (1 between kept eigenvalues, 0 between dropped ones, lam_i / (lam_i - lam_j)
+   between a kept lam_i and a dropped lam_j); d f / d A_t = 2 A_t - 2 W_t A_t.  W_t is
+   carried in factored form (m x r and r x r factors), so the reverse sweep costs
+   GEMMs of the forward's sizes.
+     blocks, nblocks   the chain, in order (device data, common row count m)
+     r                 target rank, 1 <= r <= m
+     checkpoint        steps between stored states (>= 1).  The forward keeps only
+                       every checkpoint-th state; the backward recomputes the states
+                       in between, and each step's residual basis and core
+                       eigenvectors, instead of storing them.  Device memory:
+                       about (nblocks / checkpoint + checkpoint + 6) m r doubles.
+     f                 HOST out: the tail energy f
+     grads             HOST array of nblocks DEVICE pointers, or NULL for the
+                       forward only; grads[t] receives d f / d A_t as an m x n_t
+                       row-major FP64 matrix with row stride n_t
+     min_gap           HOST out (may be NULL): min over steps of
+                       (lam_r - lam_{r+1}) / lam_1 of the step's core spectrum; the
+                       gradient does not exist where this is 0 (a tie at the cut)
+   Synchronous.  The workspace for states and factors is allocated per call. */
+cmsvd_status cmsvd_tail_energy_grad(cmsvd_handle handle, const cmsvd_block* blocks, int64_t nblocks, int64_t r,
+                                    int64_t checkpoint, double* f, double* const* grads, double* min_gap);
+
 /* Building block exposed for testing and reuse: the largest nkeep eigenvalues of
    count symmetric matrices, each n x n column-major FP64 on the device (A + i*stride_a,
    lower triangle read, both triangles assumed equal), written descending to

@@ -49,8 +49,11 @@ def _load():
     lib.cmsvd_gemm_f64.argtypes = [vp, i32, i32, i64, i64, i64, d, vp, i64, i32, vp, i64, i32, d, vp, i64]
     lib.cmsvd_profile.argtypes = [vp, i32]
     lib.cmsvd_profile_read.argtypes = [vp, vp, vp]
+    lib.cmsvd_tail_energy_grad.argtypes = [vp, ctypes.POINTER(Block), i64, i64, i64, ctypes.POINTER(d), vp,
+                                           ctypes.POINTER(d)]
     for f in ("cmsvd_create", "cmsvd_destroy", "cmsvd_set_stream", "cmsvd_update", "cmsvd_merge_errors",
-              "cmsvd_cluster", "cmsvd_sym_eigvals", "cmsvd_gemm_f64", "cmsvd_profile", "cmsvd_profile_read"):
+              "cmsvd_cluster", "cmsvd_sym_eigvals", "cmsvd_gemm_f64", "cmsvd_profile", "cmsvd_profile_read",
+              "cmsvd_tail_energy_grad"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -59,7 +62,7 @@ _lib = _load()
 
 EXPORTS = ("cmsvd_create", "cmsvd_destroy", "cmsvd_set_stream", "cmsvd_last_error", "cmsvd_update",
            "cmsvd_merge_errors", "cmsvd_cluster", "cmsvd_sym_eigvals", "cmsvd_gemm_f64", "cmsvd_profile",
-           "cmsvd_profile_read")
+           "cmsvd_profile_read", "cmsvd_tail_energy_grad")
 
 STAGES = ("norms_grams", "commit", "projection", "core_eig")
 
@@ -214,6 +217,57 @@ def cmsvd_cluster(blocks: Sequence[torch.Tensor], r: int, eps: float, sort_mode:
     return lab, clusters, list(crel)[: ncl.value]
 
 
+def cmsvd_tail_energy_grad(blocks: Sequence[torch.Tensor], r: int, checkpoint: int | None = None,
+                           want_grad: bool = True, handle: Handle | None = None):
+    """Tail energy f = E~_r^2 of the chain ``blocks`` (in order) and, if ``want_grad``,
+    d f / d A_t for every block (FP64, the blocks' shapes).  ``checkpoint`` = steps between
+    stored states (default about sqrt(len(blocks))).  Returns (f, grads or None, min_gap)."""
+    h = handle or default_handle(blocks[0].device)
+    T = len(blocks)
+    if checkpoint is None:
+        checkpoint = max(1, int(round(T ** 0.5)))
+    arr = _blocks(blocks)
+    f = ctypes.c_double(0.0)
+    gap = ctypes.c_double(0.0)
+    grads = None
+    gptr = None
+    if want_grad:
+        grads = [torch.empty((b.shape[0], b.shape[1]), dtype=torch.float64, device=b.device) for b in blocks]
+        gptr = (ctypes.c_void_p * T)(*[g.data_ptr() for g in grads])
+    _check(_lib.cmsvd_tail_energy_grad(h.ptr, arr, T, r, checkpoint, ctypes.byref(f), gptr, ctypes.byref(gap)))
+    return f.value, grads, gap.value
+
+
+class TailEnergy(torch.autograd.Function):
+    """f = E~_r^2([A_1 ... A_T]) as a differentiable function of the blocks.
+
+    ``TailEnergy.apply(r, checkpoint, *blocks)`` returns a 0-d FP64 tensor.  The backward
+    calls the library again with gradients requested: it re-runs the forward keeping only
+    checkpointed states and recomputes every step's bases during the reverse sweep."""
+
+    @staticmethod
+    def forward(ctx, r, checkpoint, *blocks):
+        f, _, _ = cmsvd_tail_energy_grad(blocks, r, checkpoint, want_grad=False)
+        ctx.r = r
+        ctx.checkpoint = checkpoint
+        ctx.save_for_backward(*blocks)
+        return torch.tensor(f, dtype=torch.float64, device=blocks[0].device)
+
+    @staticmethod
+    def backward(ctx, gout):
+        blocks = ctx.saved_tensors
+        _, grads, _ = cmsvd_tail_energy_grad(blocks, ctx.r, ctx.checkpoint, want_grad=True)
+        out = [(g * gout).to(b.dtype) for g, b in zip(grads, blocks)]
+        return (None, None, *out)
+
+
+def tail_energy(blocks: Sequence[torch.Tensor], r: int, checkpoint: int | None = None) -> torch.Tensor:
+    """Differentiable tail energy of the chain (see ``TailEnergy``)."""
+    if checkpoint is None:
+        checkpoint = max(1, int(round(len(blocks) ** 0.5)))
+    return TailEnergy.apply(r, checkpoint, *blocks)
+
+
 def cmsvd_sym_eigvals(A: torch.Tensor, nkeep: int, handle: Handle | None = None) -> torch.Tensor:
     """Largest nkeep eigenvalues (descending) of a batch of symmetric FP64 matrices (..., n, n)."""
     if A.dtype != torch.float64 or not A.is_cuda:
@@ -259,4 +313,5 @@ def cmsvd_gemm_f64(opA: torch.Tensor, opB: torch.Tensor, C: torch.Tensor | None 
 
 
 __all__ = ["cmsvd_gemm_f64", "Handle", "State", "Block", "CmsvdError", "cmsvd_update", "cmsvd_merge_errors", "cmsvd_cluster",
-           "cmsvd_sym_eigvals", "default_handle", "LIB_PATH", "EXPORTS"]
+           "cmsvd_sym_eigvals", "cmsvd_tail_energy_grad", "TailEnergy", "tail_energy", "default_handle",
+           "LIB_PATH", "EXPORTS"]

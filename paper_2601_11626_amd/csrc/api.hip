@@ -217,6 +217,14 @@ struct CommitJob {
     double* S_out;
     double* acc;
     double* est;
+    // Decomposition only (the backward of the tail energy): when Z_out is set, all
+    // nc = r_in + k eigenpairs of the core are computed and returned -- Z_out (nc x nc
+    // column-major, eigenvectors by descending eigenvalue), lam_out (nc) and Qr_out (the
+    // residual basis transposed, k x m column-major) -- and U_out, S_out, acc and est
+    // are left untouched.
+    double* Z_out = nullptr;
+    double* lam_out = nullptr;
+    double* Qr_out = nullptr;
 };
 
 cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
@@ -225,17 +233,21 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
     Plan pl;
     struct Off {
         size_t nb, P, P2, Rt, G1, Li1, Q1, G2, Li2, Qr, F, KT, Sp, lam, d, e, V, tau, sum, Z, vs;
-        int k, nc, nkeep;
+        int k, nc, nkeep, nu;
+        bool full;
     };
     std::vector<Off> o(J);
     int nmax = 0;
     for (int j = 0; j < J; ++j) {
         const CommitJob& c = jobs[j];
-        const int k = (int)c.B.cols, nc = c.r_in + k, nk = std::min(c.r, nc);
+        const bool full = c.Z_out != nullptr;
+        const int k = (int)c.B.cols, nc = c.r_in + k, nk = full ? nc : std::min(c.r, nc);
         const size_t m = (size_t)c.m;
         o[j].k = k;
         o[j].nc = nc;
         o[j].nkeep = nk;
+        o[j].nu = std::min(c.r, nc);
+        o[j].full = full;
         nmax = std::max(nmax, nc);
         o[j].nb = pl.add(2 * 8);
         o[j].P = pl.add((size_t)c.r_in * k * 8);
@@ -265,6 +277,13 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
     if (st != CMSVD_OK) return st;
     char* W = h->ws;
     auto D = [&](size_t off) { return reinterpret_cast<double*>(W + off); };
+    // caller-owned storage for the decomposition outputs
+    std::vector<double*> pQr(J), pLam(J), pZ(J);
+    for (int j = 0; j < J; ++j) {
+        pQr[j] = jobs[j].Qr_out ? jobs[j].Qr_out : D(o[j].Qr);
+        pLam[j] = jobs[j].lam_out ? jobs[j].lam_out : D(o[j].lam);
+        pZ[j] = jobs[j].Z_out ? jobs[j].Z_out : D(o[j].Z);
+    }
 
     // descriptor tables
     std::vector<NormDesc> nd(J);
@@ -307,7 +326,7 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
         gQ1.push(GemmDesc{D(q.Li1), D(q.Rt), D(q.Q1), k, m, k, (long)k, (long)k, (long)k});
         gG2.push(GemmDesc{D(q.Q1), D(q.Q1), D(q.G2), k, k, m, (long)k, (long)k, (long)k});
         ch2[j] = CholDesc{k, D(q.G2), (long)k, D(q.Li2), (long)k, (double)k * k * EPS, nullptr, nullptr};
-        gQr.push(GemmDesc{D(q.Li2), D(q.Q1), D(q.Qr), k, m, k, (long)k, (long)k, (long)k});
+        gQr.push(GemmDesc{D(q.Li2), D(q.Q1), pQr[j], k, m, k, (long)k, (long)k, (long)k});
         gF.push(GemmDesc{D(q.G1), D(q.G2), D(q.F), k, k, k, (long)k, (long)k, (long)k});
         kd[j] = KtDesc{c.r_in, k, c.S, D(q.P), (long)std::max(c.r_in, 1), D(q.F), (long)k, D(q.KT), (long)nc};
         gS.push(GemmDesc{D(q.KT), D(q.KT), D(q.Sp), nc, nc, nc, (long)nc, (long)nc, (long)nc});
@@ -320,7 +339,7 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
         e.ldp = 1;
         e.Y = D(q.Sp);
         e.ldy = nc;
-        e.lam = D(q.lam);
+        e.lam = pLam[j];
         e.d = D(q.d);
         e.e = D(q.e);
         e.V = D(q.V);
@@ -328,14 +347,16 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
         e.tau = D(q.tau);
         e.sum_top = D(q.sum);
         ed[j] = e;
-        vd[j] = VecDesc{nc, q.nkeep, D(q.lam), D(q.d), D(q.e), D(q.V), (long)nc, D(q.tau), D(q.Z), (long)nc, D(q.vs)};
-        if (c.r_in > 0) {
-            gU1.push(GemmDesc{D(q.Z), c.U, c.U_out, q.nkeep, m, c.r_in, (long)nc, c.ldu, c.ldu_out});
-            gU2a.push(GemmDesc{D(q.Z) + c.r_in, D(q.Qr), c.U_out, q.nkeep, m, k, (long)nc, (long)k, c.ldu_out});
-        } else {
-            gU2b.push(GemmDesc{D(q.Z), D(q.Qr), c.U_out, q.nkeep, m, k, (long)nc, (long)k, c.ldu_out});
+        vd[j] = VecDesc{nc, q.nkeep, pLam[j], D(q.d), D(q.e), D(q.V), (long)nc, D(q.tau), pZ[j], (long)nc, D(q.vs)};
+        if (!q.full) {
+            if (c.r_in > 0) {
+                gU1.push(GemmDesc{pZ[j], c.U, c.U_out, q.nu, m, c.r_in, (long)nc, c.ldu, c.ldu_out});
+                gU2a.push(GemmDesc{pZ[j] + c.r_in, pQr[j], c.U_out, q.nu, m, k, (long)nc, (long)k, c.ldu_out});
+            } else {
+                gU2b.push(GemmDesc{pZ[j], pQr[j], c.U_out, q.nu, m, k, (long)nc, (long)k, c.ldu_out});
+            }
         }
-        fd[j] = FinDesc{c.r_in, c.r, q.nkeep, m, nc, c.S, D(q.lam), D(q.sum), D(q.nb), c.S_out, c.U_out,
+        fd[j] = FinDesc{c.r_in, c.r, q.nkeep, m, nc, c.S, pLam[j], D(q.sum), D(q.nb), c.S_out, c.U_out,
                         c.ldu_out, c.acc, c.est};
     }
     // P = Ut * Bt^T needs the block dtype: one group per dtype
@@ -350,7 +371,10 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
     }
     Stage stg;
     size_t o_nd = stg.add(nd), o_cd = stg.add(cd), o_ch1 = stg.add(ch1), o_ch2 = stg.add(ch2);
-    size_t o_kd = stg.add(kd), o_ed = stg.add(ed), o_vd = stg.add(vd), o_fd = stg.add(fd);
+    std::vector<FinDesc> fdk;
+    for (int j = 0; j < J; ++j)
+        if (!o[j].full) fdk.push_back(fd[j]);
+    size_t o_kd = stg.add(kd), o_ed = stg.add(ed), o_vd = stg.add(vd), o_fd = stg.add(fdk);
     for (GemmGroup* g : {&gP32, &gP64, &gR1, &gP2, &gR2, &gG1, &gQ1, &gG2, &gQr, &gF, &gS, &gU1, &gU2a, &gU2b})
         g->off = stg.add(g->d);
     char* db = nullptr;
@@ -383,7 +407,7 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
     run_gemm(gU1, db, s);
     run_gemm(gU2a, db, s);
     run_gemm(gU2b, db, s);
-    finalize_state_batched(reinterpret_cast<const FinDesc*>(db + o_fd), J, s);
+    if (!fdk.empty()) finalize_state_batched(reinterpret_cast<const FinDesc*>(db + o_fd), (int)fdk.size(), s);
     HIPCHK(hipGetLastError());
     return CMSVD_OK;
 }
@@ -509,6 +533,42 @@ cmsvd_status norms_and_grams(cmsvd_ctx* h, const std::vector<cmsvd_block>& bl, c
 
 // Persistent device buffers owned by one call (separate from the scratch arena,
 // which the pipelines above reuse).
+// One GEMM (column-major, FP64 accumulate) issued on the handle's stream.
+cmsvd_status gemm1(cmsvd_ctx* h, bool ta, bool tb, int M, int N, int K, double alpha, const void* A, long lda,
+                   bool af32, const void* B, long ldb, bool bf32, double beta, double* C, long ldc) {
+    if (M <= 0 || N <= 0) return CMSVD_OK;
+    GemmGroup g;
+    g.ta = ta;
+    g.tb = tb;
+    g.af32 = af32;
+    g.bf32 = bf32;
+    g.alpha = alpha;
+    g.beta = beta;
+    g.push(GemmDesc{A, B, C, M, N, K, lda, ldb, ldc});
+    Stage stg;
+    g.off = stg.add(g.d);
+    char* db = nullptr;
+    cmsvd_status st = upload(h, stg, &db);
+    if (st != CMSVD_OK) return st;
+    run_gemm(g, db, h->stream);
+    HIPCHK(hipGetLastError());
+    return CMSVD_OK;
+}
+
+// Cast-copy of a row-major block into a row-major FP64 matrix with row stride = cols.
+cmsvd_status copy_block(cmsvd_ctx* h, const cmsvd_block& b, double* dst) {
+    std::vector<CopyDesc> cd{CopyDesc{b.ptr, (int)b.rows, (int)b.cols, (long)b.ld, b.dtype == CMSVD_F32 ? 1 : 0, dst,
+                                      (long)b.cols}};
+    Stage stg;
+    const size_t o = stg.add(cd);
+    char* db = nullptr;
+    cmsvd_status st = upload(h, stg, &db);
+    if (st != CMSVD_OK) return st;
+    copy_f64_batched(reinterpret_cast<const CopyDesc*>(db + o), 1, (int)b.rows, h->stream);
+    HIPCHK(hipGetLastError());
+    return CMSVD_OK;
+}
+
 struct DevBuf {
     char* p = nullptr;
     ~DevBuf() {
@@ -934,6 +994,192 @@ cmsvd_status cmsvd_cluster(cmsvd_handle h, const cmsvd_block* blocks, int64_t nb
     *nclusters = ncl;
     if (cluster_rel)
         for (int c = 0; c < ncl; ++c) cluster_rel[c] = crel[c];
+    return CMSVD_OK;
+}
+
+
+/* Tail energy of a chain and its gradient; see include/cmsvd.h. */
+cmsvd_status cmsvd_tail_energy_grad(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r,
+                                    int64_t checkpoint, double* f, double* const* grads, double* min_gap) {
+    if (!h) return fail(CMSVD_EINVAL, "cmsvd_tail_energy_grad: null handle");
+    if (!blocks || nblocks < 1) return fail(CMSVD_EINVAL, "cmsvd_tail_energy_grad: no blocks");
+    if (!f) return fail(CMSVD_EINVAL, "cmsvd_tail_energy_grad: null f");
+    if (checkpoint < 1) return fail(CMSVD_EINVAL, "cmsvd_tail_energy_grad: checkpoint must be >= 1");
+    const int64_t m = blocks[0].rows;
+    if (r < 1 || r > m) return fail(CMSVD_ESHAPE, "cmsvd_tail_energy_grad: need 1 <= r <= m");
+    if (r > 4096) return fail(CMSVD_EUNSUPPORTED, "cmsvd_tail_energy_grad: r > 4096");
+    int kmax = 0;
+    for (int64_t i = 0; i < nblocks; ++i) {
+        cmsvd_status st = check_block(blocks[i], m, "block", i);
+        if (st != CMSVD_OK) return st;
+        if (grads && !grads[i]) return fail(CMSVD_EINVAL, "cmsvd_tail_energy_grad: null gradient %lld", (long long)i);
+        kmax = std::max(kmax, (int)blocks[i].cols);
+    }
+    const int T = (int)nblocks, R = (int)r, M = (int)m;
+    const int ck = (int)std::min<int64_t>(checkpoint, T);
+    const int ncmax = R + kmax;
+    // one state: U (m x r row-major) | S (r) | acc (4) | est (2) | pad (2)
+    const size_t SD = (size_t)M * R + R + 8;
+    const int nck = T / ck + 2;  // states at t = 0, ck, 2ck, ... and the final one
+    const size_t n_doubles = SD * (size_t)(nck + ck + 1)           // checkpoints + one segment
+                             + 2 * (size_t)R * R + 2 * (size_t)R * M  // C and Z of two consecutive steps
+                             + 2 * (size_t)R * R + (size_t)R * M      // M, N, X^T
+                             + (size_t)ncmax * R + (size_t)R * ncmax  // G, B_d
+                             + 2 * (size_t)R * kmax                   // Y, V
+                             + (size_t)ncmax * ncmax + ncmax          // core eigenvectors and eigenvalues
+                             + (size_t)kmax * M + T + 8               // residual basis, gaps, scratch acc
+                             + (size_t)R * M;                         // U_{t+1} across a segment boundary
+    DevBuf mem;
+    if (hipMalloc((void**)&mem.p, n_doubles * 8) != hipSuccess) {
+        (void)hipGetLastError();
+        mem.p = nullptr;
+        return fail(CMSVD_ENOMEM, "cmsvd_tail_energy_grad: hipMalloc(%zu bytes) failed", n_doubles * 8);
+    }
+    double* base = reinterpret_cast<double*>(mem.p);
+    double* ckp = base;
+    double* seg = ckp + SD * nck;
+    double* Cb[2] = {seg + SD * (ck + 1), nullptr};
+    Cb[1] = Cb[0] + (size_t)R * R;
+    double* Zb[2] = {Cb[1] + (size_t)R * R, nullptr};
+    Zb[1] = Zb[0] + (size_t)R * M;
+    double* Mm = Zb[1] + (size_t)R * M;
+    double* Nm = Mm + (size_t)R * R;
+    double* Xt = Nm + (size_t)R * R;
+    double* G = Xt + (size_t)R * M;
+    double* Bd = G + (size_t)ncmax * R;
+    double* Y = Bd + (size_t)R * ncmax;
+    double* V = Y + (size_t)R * kmax;
+    double* Zf = V + (size_t)R * kmax;
+    double* lam = Zf + (size_t)ncmax * ncmax;
+    double* Qr = lam + ncmax;
+    double* gaps = Qr + (size_t)kmax * M;
+    double* acc_scratch = gaps + T;
+    double* Ukeep = acc_scratch + 8;
+    hipStream_t s = h->stream;
+    auto U_of = [&](double* st) { return st; };
+    auto S_of = [&](double* st) { return st + (size_t)M * R; };
+    auto acc_of = [&](double* st) { return st + (size_t)M * R + R; };
+    auto est_of = [&](double* st) { return st + (size_t)M * R + R + 4; };
+    auto step = [&](double* from, int t_from, double* to, int b, double* acc, double* est) {
+        // state after block b from the state before it (t_from = number of blocks folded in)
+        HIPCHK(hipMemcpyAsync(acc, acc_of(from), 4 * sizeof(double), hipMemcpyDeviceToDevice, s));
+        CommitJob j{M, U_of(from), (long)R, S_of(from), t_from == 0 ? 0 : R, blocks[b], R,
+                    U_of(to), (long)R, S_of(to), acc, est};
+        return commit_batched(h, {j});
+    };
+    cmsvd_status st;
+    fill_diag(ckp, (int)SD, 1, (long)SD, 0.0, 0.0, s);  // empty state: zero accumulators
+    // ---- forward: fold the chain, keeping every ck-th state and the last one ----
+    {
+        double* prev = ckp;
+        for (int t = 1; t <= T; ++t) {
+            double* next = (t % ck == 0) ? ckp + SD * (t / ck) : seg + SD * (t & 1);
+            if (t == T) next = ckp + SD * (nck - 1);
+            st = step(prev, t - 1, next, t - 1, acc_of(next), est_of(next));
+            if (st != CMSVD_OK) return st;
+            prev = next;
+        }
+    }
+    double est_h[2];
+    HIPCHK(hipMemcpyAsync(est_h, est_of(ckp + SD * (nck - 1)), 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *f = est_h[0] * est_h[0];
+    if (!grads) {
+        if (min_gap) *min_gap = INFINITY;
+        return CMSVD_OK;
+    }
+    // ---- backward by segments of ck steps, newest first ----
+    int cur = 0;  // (Cb[cur], Zb[cur]) hold C, Z of the step after the one being processed
+    const double* Unext = nullptr;
+    const int nseg = (T + ck - 1) / ck;
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+        const int a = sg * ck, b = std::min(a + ck, T);
+        // states U_a .. U_b of this segment: slot i holds U_{a+i}
+        std::vector<double*> sl(b - a + 1);
+        sl[0] = ckp + SD * (a / ck);
+        sl[b - a] = (b == T) ? ckp + SD * (nck - 1) : ckp + SD * (b / ck);
+        for (int i = 1; i < b - a; ++i) {
+            sl[i] = seg + SD * i;
+            st = step(sl[i - 1], a + i - 1, sl[i], a + i - 1, acc_scratch, nullptr);
+            if (st != CMSVD_OK) return st;
+        }
+        for (int t = b; t > a; --t) {
+            const cmsvd_block& B = blocks[t - 1];
+            const int k = (int)B.cols, rp = (t - 1 == 0) ? 0 : R, nc = rp + k, nk = std::min(R, nc), d = nc - nk;
+            const bool bf = B.dtype == CMSVD_F32;
+            double* Up = U_of(sl[t - 1 - a]);
+            double* Ut = U_of(sl[t - a]);
+            // recompute the step's residual basis and every eigenpair of its core
+            CommitJob j{M, Up, (long)R, S_of(sl[t - 1 - a]), rp, B, R, Xt, (long)R, acc_scratch, acc_scratch, nullptr};
+            j.Z_out = Zf;
+            j.lam_out = lam;
+            j.Qr_out = Qr;
+            st = commit_batched(h, {j});
+            if (st != CMSVD_OK) return st;
+            cut_gap(lam, nk, nc, gaps + (t - 1), s);
+            double* Cn = Cb[cur ^ 1];
+            double* Zn = Zb[cur ^ 1];
+            if (t == T) {
+                // W_T = U_T U_T^T: C = I, Z = 0
+                fill_diag(Cn, R, R, R, 0.0, 1.0, s);
+                fill_diag(Zn, R, M, R, 0.0, 0.0, s);
+            } else {
+                const double* Cp = Cb[cur];
+                const double* Zp = Zb[cur];
+                // X = W_{t+1} U_t with W_{t+1} = U' C' U'^T + U' Z'^T + Z' U'^T:
+                // Mm = U_t^T U', Nm = Z'^T U_t, then Nm <- C' Mm^T + Nm (= E^T),
+                // X^T = E U'^T + Mm Z'^T
+                if ((st = gemm1(h, false, true, R, R, M, 1.0, Ut, R, false, Unext, R, false, 0.0, Mm, R))) return st;
+                if ((st = gemm1(h, false, true, R, R, M, 1.0, Zp, R, false, Ut, R, false, 0.0, Nm, R))) return st;
+                if ((st = gemm1(h, false, true, R, R, R, 1.0, Cp, R, false, Mm, R, false, 1.0, Nm, R))) return st;
+                if ((st = gemm1(h, true, false, R, M, R, 1.0, Nm, R, false, Unext, R, false, 0.0, Xt, R))) return st;
+                if ((st = gemm1(h, false, false, R, M, R, 1.0, Mm, R, false, Zp, R, false, 1.0, Xt, R))) return st;
+                // G = Qhat^T X, Qhat = [U_{t-1}, Q_res]
+                if ((st = gemm1(h, false, true, rp, R, M, 1.0, Up, R, false, Xt, R, false, 0.0, G, nc))) return st;
+                if ((st = gemm1(h, false, true, k, R, M, 1.0, Qr, k, false, Xt, R, false, 0.0, G + rp, nc))) return st;
+                // C_t = U_t^T X, in the stored basis of the state (the recomputed kept
+                // eigenvectors may differ from it by signs or within clusters)
+                if ((st = gemm1(h, false, true, R, R, M, 1.0, Ut, R, false, Xt, R, false, 0.0, Cn, R))) return st;
+                // Ghat = Z_d (Gamma o (G^T Z_d))^T - G
+                double ghat_sign = -1.0;
+                if (d > 0) {
+                    if ((st = gemm1(h, true, false, R, d, nc, 1.0, G, nc, false, Zf + (size_t)nk * nc, nc, false, 0.0, Bd, R)))
+                        return st;
+                    divdiff_scale(Bd, R, nk, d, lam, s);
+                    if ((st = gemm1(h, false, true, nc, R, d, 1.0, Zf + (size_t)nk * nc, nc, false, Bd, R, false, -1.0, G, nc)))
+                        return st;
+                    ghat_sign = 1.0;
+                }
+                // Z_t^T = Ghat^T Qhat^T + X^T  (built in X^T, then moved to Zn)
+                if ((st = gemm1(h, true, false, R, M, rp, ghat_sign, G, nc, false, Up, R, false, 1.0, Xt, R))) return st;
+                if ((st = gemm1(h, true, false, R, M, k, ghat_sign, G + rp, nc, false, Qr, k, false, 1.0, Xt, R))) return st;
+                HIPCHK(hipMemcpyAsync(Zn, Xt, (size_t)R * M * 8, hipMemcpyDeviceToDevice, s));
+            }
+            // grad_t = 2 A_t - 2 (U_t (C Y + V) + Z Y) with Y = U_t^T A_t, V = Z^T A_t
+            double* gt = grads[t - 1];
+            if ((st = gemm1(h, false, true, R, k, M, 1.0, Ut, R, false, B.ptr, B.ld, bf, 0.0, Y, R))) return st;
+            if ((st = gemm1(h, false, true, R, k, M, 1.0, Zn, R, false, B.ptr, B.ld, bf, 0.0, V, R))) return st;
+            if ((st = gemm1(h, false, false, R, k, R, 1.0, Cn, R, false, Y, R, false, 1.0, V, R))) return st;
+            if ((st = copy_block(h, B, gt))) return st;
+            if ((st = gemm1(h, true, false, k, M, R, -2.0, V, R, false, Ut, R, false, 2.0, gt, k))) return st;
+            if ((st = gemm1(h, true, false, k, M, R, -2.0, Y, R, false, Zn, R, false, 1.0, gt, k))) return st;
+            cur ^= 1;
+            Unext = Ut;
+        }
+        // the next segment recomputes into the slots that may hold U_{a+1}
+        if (Unext != Ukeep) {
+            HIPCHK(hipMemcpyAsync(Ukeep, Unext, (size_t)R * M * 8, hipMemcpyDeviceToDevice, s));
+            Unext = Ukeep;
+        }
+    }
+    std::vector<double> gh(T);
+    HIPCHK(hipMemcpyAsync(gh.data(), gaps, T * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (min_gap) {
+        double g = INFINITY;
+        for (double v : gh) g = std::min(g, v);
+        *min_gap = g;
+    }
     return CMSVD_OK;
 }
 

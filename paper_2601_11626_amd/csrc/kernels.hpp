@@ -150,4 +150,9 @@ struct ColNormDesc {
 };
 void colblock_sumsq_batched(const ColNormDesc* d_descs, int count, hipStream_t s);
 
+// Backward of the tail energy.
+void divdiff_scale(double* B, int r, int nk, int d, const double* ev, hipStream_t s);
+void fill_diag(double* A, int rows, int cols, long ld, double v, double dv, hipStream_t s);
+void cut_gap(const double* ev, int nk, int n, double* out, hipStream_t s);
+
 }  // namespace cmsvd

@@ -1,4 +1,6 @@
 // Small glue kernels of the update and the clustering decision.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -157,6 +159,58 @@ __global__ void __launch_bounds__(256) colblock_sumsq_kernel(const ColNormDesc* 
 void colblock_sumsq_batched(const ColNormDesc* d_descs, int count, hipStream_t s) {
     if (count <= 0) return;
     hipLaunchKernelGGL(colblock_sumsq_kernel, dim3(count), dim3(256), 0, s, d_descs);
+}
+
+// ---------------------------------------------------------------------------
+// Backward of the tail energy: small helpers.
+// ---------------------------------------------------------------------------
+// B (r x d, column-major, ld r) *= g[lam_i, mu_j] with lam = ev[0..nk), mu = ev[nk..nk+d):
+// the divided difference lam_i / (lam_i - mu_j) of the truncation between a kept and a
+// dropped eigenvalue (0 where the two coincide).
+__global__ void __launch_bounds__(256) divdiff_scale_kernel(double* __restrict__ B, int r, int nk, int d,
+                                                            const double* __restrict__ ev) {
+    for (long e = blockIdx.x * 256L + threadIdx.x; e < (long)r * d; e += 256L * gridDim.x) {
+        const int i = (int)(e % r), j = (int)(e / r);
+        double g = 0.0;
+        if (i < nk) {
+            const double li = ev[i], den = li - ev[nk + j];
+            g = den != 0.0 ? li / den : 0.0;
+        }
+        B[e] *= g;
+    }
+}
+
+void divdiff_scale(double* B, int r, int nk, int d, const double* ev, hipStream_t s) {
+    if (r <= 0 || d <= 0) return;
+    const long tot = (long)r * d;
+    const int grid = (int)std::min<long>((tot + 255) / 256, 1024);
+    hipLaunchKernelGGL(divdiff_scale_kernel, dim3(grid), dim3(256), 0, s, B, r, nk, d, ev);
+}
+
+// A (rows x cols, column-major, ld) = v off the diagonal and dv on it.
+__global__ void __launch_bounds__(256) fill_diag_kernel(double* __restrict__ A, int rows, int cols, long ld, double v,
+                                                        double dv) {
+    for (long e = blockIdx.x * 256L + threadIdx.x; e < (long)rows * cols; e += 256L * gridDim.x) {
+        const int i = (int)(e % rows), c = (int)(e / rows);
+        A[(long)i + (long)c * ld] = i == c ? dv : v;
+    }
+}
+
+void fill_diag(double* A, int rows, int cols, long ld, double v, double dv, hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return;
+    const long tot = (long)rows * cols;
+    const int grid = (int)std::min<long>((tot + 255) / 256, 2048);
+    hipLaunchKernelGGL(fill_diag_kernel, dim3(grid), dim3(256), 0, s, A, rows, cols, ld, v, dv);
+}
+
+// out = (ev[nk-1] - ev[nk]) / ev[0] (relative gap at the truncation), or +inf when
+// nothing is dropped.
+__global__ void cut_gap_kernel(const double* __restrict__ ev, int nk, int n, double* __restrict__ out) {
+    if (threadIdx.x == 0) *out = (nk < n && nk > 0 && ev[0] > 0.0) ? (ev[nk - 1] - ev[nk]) / ev[0] : INFINITY;
+}
+
+void cut_gap(const double* ev, int nk, int n, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(cut_gap_kernel, dim3(1), dim3(64), 0, s, ev, nk, n, out);
 }
 
 }  // namespace cmsvd
