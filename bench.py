@@ -92,6 +92,147 @@ def pmc_summary(fetch_csv, write_csv, copy_mib, kernel="sym_eig_reg_kernel<0>"):
     return out
 
 
+def chain_grad(args, cm, workloads, torch):
+    """Tail energy f = E~^2 of a 64-block chain (2048 x 512 FP32 blocks sharing a
+    2048 x 96 subspace, noise 0.05, r = 128) and its gradient with respect to every
+    block.  One step = one forward + backward (cmsvd_tail_energy_grad).  Checks that
+    hold at any size: the Euler identity sum <grad_t, A_t> = 2 f and central
+    differences of the GPU forward along random unit directions; reported (not a
+    criterion): cosine and relative difference against the exact-SVD gradient 2(M - M_r)."""
+    r = 128
+    t0 = time.time()
+    blocks_np = workloads.shared_chain(seed=0)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    blocks = [torch.from_numpy(b).to(dev) for b in blocks_np]
+    torch.cuda.synchronize()
+    log(f"generated {len(blocks)} blocks {tuple(blocks[0].shape)} in {time.time() - t0:.1f}s")
+    ck = 8
+    for w in range(args.warmup):
+        f, grads, gap = cm.cmsvd_tail_energy_grad(blocks, r, ck)
+        log(f"warmup {w + 1}/{args.warmup}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        f, grads, gap = cm.cmsvd_tail_energy_grad(blocks, r, ck)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    f_fwd, _, _ = cm.cmsvd_tail_energy_grad(blocks, r, ck, want_grad=False)
+    torch.cuda.synchronize()
+    fwd_s = time.perf_counter() - t2
+    if args.no_check:
+        print(json.dumps({"ms_per_step": round(1000.0 * el / max(args.steps, 1), 3),
+                          "forward_only_ms": round(1000.0 * fwd_s, 3), "f": f}), flush=True)
+        return
+    # checks that hold at any size
+    euler = sum(float(torch.sum(g * b.double())) for g, b in zip(grads, blocks))
+    gnorm = math.sqrt(sum(float(torch.sum(g * g)) for g in grads))
+    gen = torch.Generator(device="cpu").manual_seed(3)
+    fd_dev = []
+    h = 1e-3
+    for _ in range(2):
+        E = [torch.randn(b.shape, generator=gen, dtype=torch.float64) for b in blocks]
+        nrm = math.sqrt(sum(float(torch.sum(e * e)) for e in E))
+        E = [(e / nrm).to(dev) for e in E]
+        fp, _, _ = cm.cmsvd_tail_energy_grad([b.double() + h * e for b, e in zip(blocks, E)], r, ck, want_grad=False)
+        fm, _, _ = cm.cmsvd_tail_energy_grad([b.double() - h * e for b, e in zip(blocks, E)], r, ck, want_grad=False)
+        an = sum(float(torch.sum(g * e)) for g, e in zip(grads, E))
+        fd_dev.append(abs((fp - fm) / (2 * h) - an) / gnorm)
+    # exact-SVD gradient of the concatenation, for context
+    Mt = torch.cat([b.double() for b in blocks], dim=1)
+    lam, Uf = torch.linalg.eigh(Mt @ Mt.T)
+    Ur = Uf[:, -r:]
+    Gx = 2.0 * (Mt - Ur @ (Ur.T @ Mt))
+    Gi = torch.cat(grads, dim=1)
+    cos = float(torch.sum(Gx * Gi) / (torch.linalg.norm(Gx) * torch.linalg.norm(Gi)))
+    reld = float(torch.linalg.norm(Gx - Gi) / torch.linalg.norm(Gx))
+    exact_tail = float(torch.sum(lam[:-r]))
+    m, k = blocks_np[0].shape
+    out = {
+        "metric": "tail-energy gradient steps/sec (forward + backward over the whole chain)",
+        "value": round(args.steps / el, 4),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * el / args.steps, 3),
+        "forward_only_ms": round(1000.0 * fwd_s, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"shared_chain: {len(blocks)} FP32 blocks {m}x{k}, shared 96-dim subspace, "
+                               f"noise 0.05, r={r}, checkpoint every {ck} steps",
+                   "blocks": len(blocks), "m": int(m), "k": int(k), "r": r},
+        "f": f,
+        "exact_tail2": exact_tail,
+        "min_cut_gap": gap,
+        "euler_rel_dev": abs(euler - 2.0 * f) / (2.0 * f),
+        "fd_rel_dev": fd_dev,
+        "vs_exact_svd_gradient": {"cosine": cos, "rel_diff": reld},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cluster(args, cm, workloads, torch):
+    """Algorithm 3 on 512 FP32 blocks with 4096 rows and widths U{64..1024} from 32
+    latent 4096 x 48 subspaces (noise 1e-2), relative threshold 0.1, norm-ordered scan.
+    Reports the clustering time and, on a bounded sample of anchor-first pairs of the
+    same collection, the deviation of cmsvd_merge_errors from the FP64 oracle."""
+    r = args.rank
+    t0 = time.time()
+    blocks_np = workloads.latent_uneven(seed=0, nblocks=args.nblocks)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    blocks = [torch.from_numpy(b).to(dev) for b in blocks_np]
+    torch.cuda.synchronize()
+    widths = [b.shape[1] for b in blocks_np]
+    log(f"generated {len(blocks)} blocks, widths {min(widths)}..{max(widths)} in {time.time() - t0:.1f}s")
+    t1 = time.perf_counter()
+    lab, cl, crel = cm.cmsvd_cluster(blocks, r, 0.1, sort_mode="frobenius")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    log(f"clustered into {len(cl)} clusters in {el:.1f}s")
+    sizes = sorted((len(c) for c in cl), reverse=True)
+    parity = None
+    if not args.no_cpu:
+        import oracle
+
+        pairs = workloads.anchor_ordered_pairs(blocks_np)
+        rng = np.random.default_rng(2)
+        cs = rng.choice(len(pairs), size=min(args.cpu_pairs, len(pairs)), replace=False)
+        err, rel = cm.cmsvd_merge_errors(blocks, pairs[cs], r)
+        err = err.cpu().numpy()
+        tc = time.perf_counter()
+        e_o, _ = oracle.merge_errors(blocks_np, pairs[cs], r, nthreads=max(1, min(16, len(os.sched_getaffinity(0)))))
+        ct = time.perf_counter() - tc
+        nrm = np.array([math.sqrt(float(np.sum(blocks_np[i].astype(np.float64) ** 2)) +
+                                  float(np.sum(blocks_np[j].astype(np.float64) ** 2))) for i, j in pairs[cs]])
+        dev_rel = np.abs(err - e_o) / np.maximum(e_o, 1e-6 * nrm)
+        parity = {"pairs": int(len(cs)), "max_rel_dev": float(dev_rel.max()), "oracle_seconds": round(ct, 1),
+                  "widths": [[int(widths[i]), int(widths[j])] for i, j in pairs[cs]]}
+        log(f"parity {parity}")
+    out = {
+        "metric": "greedy error-constrained clustering (Algorithm 3) wall time",
+        "value": round(el, 3),
+        "unit": "s",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"latent_uneven: {len(blocks)} FP32 blocks 4096 x U{{64..1024}}, 32 latent 48-dim "
+                               f"subspaces, noise 1e-2, r={r}, eps=0.1, frobenius order",
+                   "r": r, "eps": 0.1},
+        "clusters": len(cl),
+        "largest_clusters": sizes[:8],
+        "max_cluster_rel": max(crel) if crel else None,
+        "parity": parity,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +250,13 @@ def main():
                     help="summarise two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, "
                          "WRITE_SIZE) of a run with --calibrate-copy, then exit")
     ap.add_argument("--pmc-mib", type=int, default=1024, help="copy size used with --pmc-summary")
+    ap.add_argument("--no-check", action="store_true", help="chain_grad: skip the finite-difference and "
+                    "exact-SVD checks (for profiling)")
+    ap.add_argument("--rank", type=int, default=32, help="cluster: target rank (32 or 128)")
+    ap.add_argument("--nblocks", type=int, default=512, help="cluster: collection size")
+    ap.add_argument("--workload", default="pairs", choices=("pairs", "chain_grad", "cluster"),
+                    help="pairs: batched merge errors (the default line); chain_grad: tail energy and "
+                         "its gradient along a 64-block chain")
     args = ap.parse_args()
     if args.pmc_summary:
         nb = args.groups * args.per_group
@@ -137,6 +285,11 @@ def main():
 
     import paper_2601_11626_amd as cm
     import workloads
+
+    if args.workload == "chain_grad":
+        return chain_grad(args, cm, workloads, torch)
+    if args.workload == "cluster":
+        return cluster(args, cm, workloads, torch)
 
     r = 64
     t0 = time.time()

@@ -201,6 +201,20 @@ def test_cluster_matches_oracle(cm):
         np.testing.assert_allclose(crel, crel_o, rtol=1e-8)
 
 
+@pytest.mark.parametrize("r", [12, 24])
+def test_cluster_uneven_latent_recipe_scaled(cm, r):
+    # the uneven-size clustering workload (latent subspaces + noise 1e-2, ragged
+    # widths), scaled down so that the oracle's Algorithm 3 finishes in seconds
+    blocks = workloads.latent_uneven(seed=0, m=384, nblocks=40, latents=5, d=10, nmin=12, nmax=80)
+    for mode in ("frobenius", "residual"):
+        say(f"cluster latent_uneven scaled r={r} mode={mode}")
+        lab_o, cl_o, crel_o = oracle.cluster(blocks, r, 0.1, sort_mode=mode)
+        lab, cl, crel = cm.cmsvd_cluster(dev_tensors(blocks), r, 0.1, sort_mode=mode)
+        assert lab == lab_o
+        np.testing.assert_allclose(crel, crel_o, rtol=1e-8)
+        assert all(c <= 0.1 for c in crel)
+
+
 def test_merge_errors_deterministic(cm):
     say("determinism")
     blocks = dev_tensors(workloads.tiny_groups())
