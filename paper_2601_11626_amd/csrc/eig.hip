@@ -770,6 +770,187 @@ __global__ void __launch_bounds__(RT) sym_eig_reg_kernel(const EigDesc* __restri
     }
 }
 
+// ---------------------------------------------------------------------------
+// Small cores (n <= 64): one wavefront per problem, several problems per workgroup.
+//
+// Lane i holds row i of the full symmetric matrix in VGPRs.  A v and the rank-2
+// update are then row-local (v and w are broadcast through the wave's LDS buffer), so a
+// column step has no cross-lane reduction besides two wave sums and no barrier.
+// Applying the update to the whole matrix with the whole p = tau A v is exactly the
+// two-sided reflection: v vanishes on indices <= j, rows above j are already reduced
+// (their p is zero), and row j's tail becomes (beta, 0, ...).  Bisection is a
+// multisection with floor(64 / nkeep) probes per eigenvalue and round.
+// ---------------------------------------------------------------------------
+constexpr int SN = 64;
+constexpr int SWV = 4;
+constexpr int S_LDS = 7 * SN + 8;
+
+template <int MODE>
+__global__ void __launch_bounds__(64 * SWV) sym_eig_small_kernel(const EigDesc* __restrict__ descs, int count) {
+    __shared__ double sh[SWV][S_LDS];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    double* vv = sh[wv];      // v of the step, later the lower bisection bounds
+    double* ww = vv + SN;     // w of the step, later the upper bisection bounds
+    double* dd = ww + SN;     // diagonal of T
+    double* e2 = dd + SN;     // squared off-diagonal of T
+    double* es = e2 + SN;     // signed off-diagonal of T
+    double* rb = es + SN;     // row broadcast (row j = column j)
+    int* fl = reinterpret_cast<int*>(rb + SN);  // bisection flags (SN ints)
+
+    for (int prob = blockIdx.x * SWV + wv; prob < count; prob += gridDim.x * SWV) {
+        const EigDesc D = descs[prob];
+        const int n = D.n;
+        double a[SN];
+#pragma unroll
+        for (int c = 0; c < SN; ++c) a[c] = (lane < n && c < n) ? hval(D, lane, c) : 0.0;
+        for (int j = 0; j + 1 < n; ++j) {
+            // column j of A = row j: lane j publishes its row
+            if (lane == j) {
+#pragma unroll
+                for (int c = 0; c < SN; ++c) rb[c] = a[c];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const double xi = rb[lane];
+            const double dj = rb[j];
+            const double alpha = rb[j + 1];
+            const double xn2 = wave_sum((lane >= j + 2 && lane < n) ? xi * xi : 0.0);
+            double tau = 0.0, beta = alpha, scale = 0.0;
+            if (xn2 > 0.0) {
+                beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+                tau = (beta - alpha) / beta;
+                scale = 1.0 / (alpha - beta);
+            }
+            const double vi = (tau == 0.0 || lane <= j || lane >= n) ? 0.0 : (lane == j + 1 ? 1.0 : xi * scale);
+            if (lane == 0) {
+                dd[j] = dj;
+                es[j] = beta;
+                e2[j] = beta * beta;
+                if (MODE == 1 && D.tau) D.tau[j] = tau;
+            }
+            if (MODE == 1 && D.V && lane >= j + 2 && lane < n) D.V[(long)lane + (long)j * D.ldv] = vi;
+            vv[lane] = vi;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < SN; ++c) acc = fma(a[c], vv[c], acc);  // a, v vanish beyond n
+            const double pi = tau * acc;
+            const double K = -0.5 * tau * wave_sum(pi * vi);
+            const double wi = pi + K * vi;
+            ww[lane] = wi;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int c = 0; c < SN; ++c) a[c] = fma(-vi, ww[c], fma(-wi, vv[c], a[c]));
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (lane == n - 1) {
+#pragma unroll
+            for (int c = 0; c < SN; ++c) rb[c] = a[c];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane == 0) dd[n - 1] = rb[n - 1];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+        // ---- multisection bisection for the nkeep largest eigenvalues ----
+        double glo = INFINITY, ghi = -INFINITY, em = 0.0;
+        if (lane < n) {
+            const double rad = (lane > 0 ? fabs(es[lane - 1]) : 0.0) + (lane < n - 1 ? fabs(es[lane]) : 0.0);
+            glo = dd[lane] - rad;
+            ghi = dd[lane] + rad;
+            if (lane < n - 1) em = e2[lane];
+        }
+        glo = -wave_max(-glo);
+        ghi = wave_max(ghi);
+        em = wave_max(em);
+        const double tnorm = fmax(fabs(glo), fabs(ghi));
+        const double pivmin = DBL_MIN * fmax(1.0, em);
+        const double tol = 4.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
+        glo -= tol;
+        ghi += tol;
+        const int nk = D.nkeep;
+        const int P = nk < 64 ? 64 / nk : 1;
+        double* blo = vv;
+        double* bhi = ww;
+        if (lane < nk) {
+            blo[lane] = glo;
+            bhi[lane] = ghi;
+        }
+        const double width = ghi - glo;
+        int iters = 1;
+        if (width > tol) iters = (int)ceil(log(width / tol) / log((double)(P + 1))) + 2;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int it = 0; it < iters; ++it) {
+            for (int base = 0; base < nk * P; base += 64) {
+                const int u = base + lane;
+                if (u < nk * P) {
+                    const int q = u / P, pi = u % P;
+                    const double lo = blo[q], hi = bhi[q];
+                    const double x = lo + (hi - lo) * (double)(pi + 1) / (double)(P + 1);
+                    fl[u - base] = sturm_count(dd, e2, n, x, pivmin) >= n - q;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const int q = base / P + lane;
+                if (lane < 64 / P && q < nk) {
+                    const double lo = blo[q], hi = bhi[q];
+                    const int* fq = fl + (q * P - base);
+                    int first = P;
+                    for (int pi = P - 1; pi >= 0; --pi)
+                        if (fq[pi]) first = pi;
+                    blo[q] = first > 0 ? lo + (hi - lo) * (double)first / (double)(P + 1) : lo;
+                    bhi[q] = first < P ? lo + (hi - lo) * (double)(first + 1) / (double)(P + 1) : hi;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        }
+        if (lane == 0) {
+            double hi = 0.0, lo = 0.0;
+            for (int q = 0; q < nk; ++q) dd_add(hi, lo, 0.5 * (blo[q] + bhi[q]));
+            if (MODE == 0) {
+                double eh = D.na[0], el = D.na[1];
+                if (D.nb) {
+                    dd_add(eh, el, D.nb[0]);
+                    el += D.nb[1];
+                }
+                double s2, e2s;
+                two_sum(eh, -hi, s2, e2s);
+                double tail = s2 + (e2s + el - lo);
+                if (tail < 0.0) tail = 0.0;  // clamp rounding below zero; NaN propagates
+                const double err = sqrt(tail);
+                const double etot = eh + el;
+                *D.out_err = err;
+                if (D.out_rel) *D.out_rel = etot != 0.0 ? err / sqrt(etot) : 0.0;
+            } else if (D.sum_top) {
+                D.sum_top[0] = hi;
+                D.sum_top[1] = lo;
+            }
+        }
+        if (MODE == 1) {
+            if (lane < nk) D.lam[lane] = 0.5 * (blo[lane] + bhi[lane]);
+            if (D.d && lane < n) {
+                D.d[lane] = dd[lane];
+                if (lane < n - 1) D.e[lane] = es[lane];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 size_t sym_eig_workspace_doubles(int nmax, int nslots) {
     const int T = (nmax + TILE - 1) / TILE;
     return (size_t)nslots * (size_t)T * (size_t)(T + 1) / 2 * TILE_EL;
@@ -779,6 +960,13 @@ void sym_eig_batched(const EigDesc* d_descs, int count, int nmax, int mode, doub
                      hipStream_t s) {
     if (count <= 0) return;
     const int T = (nmax + TILE - 1) / TILE, npad = T * TILE;
+    if (nmax <= SN) {
+        int grid = (count + SWV - 1) / SWV;
+        if (grid > 16384) grid = 16384;
+        if (mode == 0) hipLaunchKernelGGL(sym_eig_small_kernel<0>, dim3(grid), dim3(64 * SWV), 0, s, d_descs, count);
+        else hipLaunchKernelGGL(sym_eig_small_kernel<1>, dim3(grid), dim3(64 * SWV), 0, s, d_descs, count);
+        return;
+    }
     if (T <= REG_TMAX) {
         const size_t lds = (size_t)REG_LDS_DOUBLES * 8;
         const int grid = count < nslots ? count : nslots;
