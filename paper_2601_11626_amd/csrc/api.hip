@@ -498,6 +498,93 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
     return CMSVD_OK;
 }
 
+// Dense evaluation for thin blocks: when r or the candidate widths are below the
+// 64-wide MFMA tile, per-pair GEMMs waste most of every tile and re-read each basis and
+// block once per pair.  Then the projections of a chunk of anchors against all
+// candidates are one GEMM, [U_a0 .. U_a1]^T [B_1 .. B_N], and each pair's P is read in
+// place from the product.
+struct DenseEval {
+    const double* Uall;  // row-major m x (na * r): anchor a's basis in columns a*r .. a*r + r
+    int na, r, m;
+    const void* Ball;    // row-major m x ksum: the candidates side by side
+    bool ball_f32;
+    long ksum;
+};
+
+cmsvd_status eval_dense(cmsvd_ctx* h, const DenseEval& de, const std::vector<int>& pair_anchor,
+                        const std::vector<EvalJob>& jobs, const std::vector<long>& pair_coff) {
+    const size_t total = jobs.size();
+    if (total == 0) return CMSVD_OK;
+    const int r = de.r;
+    // pairs grouped by anchor
+    std::vector<size_t> order(total);
+    for (size_t i = 0; i < total; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return pair_anchor[x] < pair_anchor[y]; });
+    int kmax = 0;
+    for (const auto& j : jobs) kmax = std::max(kmax, (int)j.B.cols);
+    const int nmax = r + kmax;
+    const size_t row_bytes = (size_t)de.ksum * r * 8;  // C rows of one anchor
+    const int achunk = (int)std::max<size_t>(1, ((size_t)8 << 30) / std::max<size_t>(row_bytes, 1));
+    size_t pos = 0;
+    for (int a0 = 0; a0 < de.na && pos < total; a0 += achunk) {
+        const int a1 = std::min(de.na, a0 + achunk);
+        size_t end = pos;
+        while (end < total && pair_anchor[order[end]] < a1) ++end;
+        if (end == pos) continue;
+        const size_t nj = end - pos;
+        const int nslots = (int)std::min<size_t>(nj, (size_t)h->ncu);
+        const long ldc = (long)(a1 - a0) * r;
+        Plan pl;
+        const size_t c_off = pl.add((size_t)ldc * de.ksum * 8);
+        const size_t eig_off = pl.add(sym_eig_workspace_doubles(nmax, nslots) * 8);
+        cmsvd_status st = ensure(h, h->ws, h->ws_cap, pl.off);
+        if (st != CMSVD_OK) return st;
+        double* C = reinterpret_cast<double*>(h->ws + c_off);
+        GemmGroup g;
+        g.tb = true;
+        g.bf32 = de.ball_f32;
+        g.push(GemmDesc{de.Uall + (size_t)a0 * r, de.Ball, C, (int)ldc, (int)de.ksum, de.m, (long)de.na * r,
+                        de.ksum, ldc});
+        std::vector<EigDesc> ed(nj);
+        for (size_t i = 0; i < nj; ++i) {
+            const size_t p = order[pos + i];
+            const EvalJob& j = jobs[p];
+            EigDesc e{};
+            e.n = r + (int)j.B.cols;
+            e.n1 = r;
+            e.nkeep = r;
+            e.s = j.S;
+            e.P = C + (size_t)(pair_anchor[p] - a0) * r + (size_t)pair_coff[p] * ldc;
+            e.ldp = ldc;
+            e.Y = j.G;
+            e.ldy = (int)j.B.cols;
+            e.na = j.na;
+            e.nb = j.nb;
+            e.out_err = j.err;
+            e.out_rel = j.rel;
+            ed[i] = e;
+        }
+        Stage stg;
+        g.off = stg.add(g.d);
+        const size_t o_ed = stg.add(ed);
+        char* db = nullptr;
+        st = upload(h, stg, &db);
+        if (st != CMSVD_OK) return st;
+        {
+            StageMark mark(h, ST_PROJ);
+            run_gemm(g, db, h->stream);
+        }
+        {
+            StageMark mark(h, ST_CORE);
+            sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), (int)nj, nmax, 0,
+                            reinterpret_cast<double*>(h->ws + eig_off), nslots, h->stream);
+        }
+        HIPCHK(hipGetLastError());
+        pos = end;
+    }
+    return CMSVD_OK;
+}
+
 // Norms (double-double) and Grams B^T B of a list of blocks into caller-provided device memory.
 cmsvd_status norms_and_grams(cmsvd_ctx* h, const std::vector<cmsvd_block>& bl, const std::vector<double*>& nrm,
                              const std::vector<double*>& gram) {
@@ -715,6 +802,22 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
             cands.push_back(i);
         }
     }
+    // Thin blocks: one GEMM per chunk of anchors against all candidates (see eval_dense),
+    // when the requested pairs cover at least a quarter of the anchor x candidate grid.
+    long ksum = 0;
+    int kmax_c = 0;
+    bool all_f32 = true;
+    std::vector<long> coff(nblocks, -1);
+    for (int i = 0; i < nblocks; ++i)
+        if (is_cand[i]) {
+            coff[i] = ksum;
+            ksum += blocks[i].cols;
+            kmax_c = std::max(kmax_c, (int)blocks[i].cols);
+            all_f32 &= blocks[i].dtype == CMSVD_F32;
+        }
+    double pair_work = 0.0;
+    for (int64_t p = 0; p < npairs; ++p) pair_work += (double)blocks[pairs[2 * p + 1]].cols;
+    const bool dense = (r < 64 || kmax_c < 64) && (double)anchors.size() * (double)ksum <= 4.0 * pair_work;
     // persistent per-call buffers: norms + grams (all involved), anchor states
     Plan pl;
     std::vector<size_t> o_n(cands.size()), o_g(cands.size());
@@ -724,8 +827,11 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
         o_g[c] = is_cand[i] ? pl.add((size_t)blocks[i].cols * blocks[i].cols * 8) : (size_t)-1;
     }
     std::vector<size_t> o_U(anchors.size()), o_S(anchors.size()), o_acc(anchors.size());
+    const long ldu_a = dense ? (long)anchors.size() * r : (long)r;  // anchors side by side when dense
+    const size_t o_Uall = dense ? pl.add((size_t)m * ldu_a * 8) : 0;
+    const size_t o_Ball = dense ? pl.add((size_t)m * ksum * (all_f32 ? 4 : 8)) : 0;
     for (size_t a = 0; a < anchors.size(); ++a) {
-        o_U[a] = pl.add((size_t)m * r * 8);
+        o_U[a] = dense ? o_Uall + (size_t)a * r * 8 : pl.add((size_t)m * r * 8);
         o_S[a] = pl.add((size_t)r * 8);
         o_acc[a] = pl.add(4 * 8);
     }
@@ -758,7 +864,7 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
             std::vector<CommitJob> jobs;
             for (size_t a = a0; a < std::min(anchors.size(), a0 + chunk); ++a) {
                 const int i = anchors[a];
-                jobs.push_back(CommitJob{(int)m, nullptr, (long)r, nullptr, 0, blocks[i], (int)r, K(o_U[a]), (long)r,
+                jobs.push_back(CommitJob{(int)m, nullptr, (long)r, nullptr, 0, blocks[i], (int)r, K(o_U[a]), ldu_a,
                                          K(o_S[a]), K(o_acc[a]), nullptr});
             }
             st = commit_batched(h, jobs);
@@ -770,10 +876,38 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
     for (int64_t p = 0; p < npairs; ++p) {
         const int i = pairs[2 * p], jb = pairs[2 * p + 1];
         const int a = aslot[i];
-        ej.push_back(EvalJob{K(o_U[a]), (long)r, K(o_S[a]), (int)r, K(o_n[cslot[i]]), blocks[jb], K(o_n[cslot[jb]]),
+        ej.push_back(EvalJob{K(o_U[a]), ldu_a, K(o_S[a]), (int)r, K(o_n[cslot[i]]), blocks[jb], K(o_n[cslot[jb]]),
                              K(o_g[cslot[jb]]), err + p, rel ? rel + p : nullptr});
     }
-    st = eval_batched(h, ej, (int)m);
+    if (dense) {
+        // pack the candidates side by side
+        std::vector<PackDesc> pd;
+        for (int i = 0; i < nblocks; ++i)
+            if (is_cand[i])
+                pd.push_back(PackDesc{blocks[i].ptr, (int)m, (int)blocks[i].cols, (long)blocks[i].ld,
+                                      blocks[i].dtype == CMSVD_F32 ? 1 : 0,
+                                      keep.p + o_Ball + (size_t)coff[i] * (all_f32 ? 4 : 8), ksum, all_f32 ? 1 : 0});
+        Stage stg;
+        const size_t o_pd = stg.add(pd);
+        char* db = nullptr;
+        st = upload(h, stg, &db);
+        if (st != CMSVD_OK) return st;
+        {
+            StageMark mark(h, ST_PREP);
+            pack_batched(reinterpret_cast<const PackDesc*>(db + o_pd), (int)pd.size(), h->stream);
+        }
+        HIPCHK(hipGetLastError());
+        std::vector<int> pa((size_t)npairs);
+        std::vector<long> pc((size_t)npairs);
+        for (int64_t p = 0; p < npairs; ++p) {
+            pa[p] = aslot[pairs[2 * p]];
+            pc[p] = coff[pairs[2 * p + 1]];
+        }
+        DenseEval de{K(o_Uall), (int)anchors.size(), (int)r, (int)m, keep.p + o_Ball, all_f32, ksum};
+        st = eval_dense(h, de, pa, ej, pc);
+    } else {
+        st = eval_batched(h, ej, (int)m);
+    }
     if (st != CMSVD_OK) return st;
     // the per-call buffers are freed on return: wait for the work that reads them
     HIPCHK(hipStreamSynchronize(h->stream));

@@ -150,6 +150,19 @@ struct ColNormDesc {
 };
 void colblock_sumsq_batched(const ColNormDesc* d_descs, int count, hipStream_t s);
 
+// Row-major block (rows x cols, row stride lds, FP32 or FP64) copied into dst (row
+// stride ldd, FP32 or FP64); an FP32 -> FP32 or FP64 -> FP64 copy is exact.
+struct PackDesc {
+    const void* src;
+    int rows, cols;
+    long lds;
+    int f32_in;
+    void* dst;
+    long ldd;
+    int f32_out;
+};
+void pack_batched(const PackDesc* d_descs, int count, hipStream_t s);
+
 // Backward of the tail energy.
 void divdiff_scale(double* B, int r, int nk, int d, const double* ev, hipStream_t s);
 void fill_diag(double* A, int rows, int cols, long ld, double v, double dv, hipStream_t s);

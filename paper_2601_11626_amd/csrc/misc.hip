@@ -213,4 +213,35 @@ void cut_gap(const double* ev, int nk, int n, double* out, hipStream_t s) {
     hipLaunchKernelGGL(cut_gap_kernel, dim3(1), dim3(64), 0, s, ev, nk, n, out);
 }
 
+// ---------------------------------------------------------------------------
+// Packing of row-major blocks side by side into one row-major matrix (FP32 or FP64).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) pack_kernel(const PackDesc* __restrict__ descs) {
+    const PackDesc D = descs[blockIdx.y];
+    const long tot = (long)D.rows * D.cols;
+    const long stride = (long)gridDim.x * 256;
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < tot; e += stride) {
+        long r, c;
+        if (tot < 0x7fffffffL) {
+            const unsigned ue = (unsigned)e, uc = (unsigned)D.cols;
+            r = ue / uc;
+            c = ue - (unsigned)r * uc;
+        } else {
+            r = e / D.cols;
+            c = e - r * D.cols;
+        }
+        const double v = D.f32_in ? (double)static_cast<const float*>(D.src)[r * D.lds + c]
+                                  : static_cast<const double*>(D.src)[r * D.lds + c];
+        if (D.f32_out) static_cast<float*>(D.dst)[r * D.ldd + c] = (float)v;
+        else static_cast<double*>(D.dst)[r * D.ldd + c] = v;
+    }
+}
+
+void pack_batched(const PackDesc* d_descs, int count, hipStream_t s) {
+    for (int base = 0; base < count; base += 65535) {
+        const int n = count - base < 65535 ? count - base : 65535;
+        hipLaunchKernelGGL(pack_kernel, dim3(64, n), dim3(256), 0, s, d_descs + base);
+    }
+}
+
 }  // namespace cmsvd

@@ -19,6 +19,9 @@ Workloads (the paper's datasets are not available; these stand in for them):
                          columns from 32 latent 4096x48 subspaces, noise 1e-2.
 * ``shared_chain``    -- 64 FP32 blocks 2048x512 sharing a 2048x96 subspace,
                          noise sigma 0.05 (long chain).
+* ``table1_like``     -- the shapes of the paper's collections (Table 1: many thin
+                         blocks, e.g. 2468 blocks of 12800x20) with synthetic values:
+                         blocks drawn from a few latent subspaces plus noise.
 Each accepts size overrides so tests can run scaled-down versions of the same recipe.
 """
 from __future__ import annotations
@@ -97,6 +100,21 @@ def shared_chain(seed: int = 0, m: int = 2048, n: int = 512, d: int = 96, nblock
         C = rng.standard_normal((d, n))
         E = rng.standard_normal((m, n)) * noise
         blocks.append((S @ C + E).astype(dtype))
+    return blocks
+
+
+def table1_like(seed: int = 0, nblocks: int = 2468, m: int = 12800, k: int = 20, groups: int = 64,
+                d: int = 16, noise: float = 0.05, dtype=np.float32):
+    """Blocks of the paper's collection shapes (values synthetic).  Block i uses latent
+    basis g = i mod groups (m x d orthonormal); A_i = L_g C_i + noise, C_i (d x k) with
+    N(0,1) entries.  Draw order: all L_g, then per block C_i, noise."""
+    rng = np.random.default_rng(seed)
+    L = [orthonormal(rng, m, d) for _ in range(groups)]
+    blocks = []
+    for i in range(nblocks):
+        C = rng.standard_normal((d, k))
+        E = rng.standard_normal((m, k)) * noise
+        blocks.append((L[i % groups] @ C + E).astype(dtype))
     return blocks
 
 
