@@ -92,6 +92,18 @@ cmsvd_status cmsvd_update(cmsvd_handle handle, int64_t m, const double* U, int64
                           int64_t r_in, const cmsvd_block* B, int64_t r, double* U_out, int64_t ldu_out,
                           double* S_out, double* acc, double* est);
 
+/* Several independent incremental steps at once (for example chains advanced in
+   lockstep): step i takes state (U[i], S[i]) of width r_in, appends B[i] and writes
+   (U_out[i], S_out[i]), updating acc[i] and est[i] (est may be NULL, or hold NULL
+   entries).  Every argument means what it means for cmsvd_update; the pointer
+   arguments are HOST arrays of count DEVICE pointers (U and S are ignored when
+   r_in == 0), B is a host array of count block descriptors.  The steps share m, r,
+   r_in and the leading dimensions; different steps must not share output buffers. */
+cmsvd_status cmsvd_update_batch(cmsvd_handle handle, int64_t count, int64_t m, const double* const* U, int64_t ldu,
+                                const double* const* S, int64_t r_in, const cmsvd_block* B, int64_t r,
+                                double* const* U_out, int64_t ldu_out, double* const* S_out, double* const* acc,
+                                double* const* est);
+
 /* Merge errors for ordered candidate pairs (Corollary 2 applied to [A_i, A_j]: the
    anchor A_i is truncated to rank r first, then A_j is appended; order matters,
    Remark 3).

@@ -49,11 +49,12 @@ def _load():
     lib.cmsvd_gemm_f64.argtypes = [vp, i32, i32, i64, i64, i64, d, vp, i64, i32, vp, i64, i32, d, vp, i64]
     lib.cmsvd_profile.argtypes = [vp, i32]
     lib.cmsvd_profile_read.argtypes = [vp, vp, vp]
+    lib.cmsvd_update_batch.argtypes = [vp, i64, i64, vp, i64, vp, i64, ctypes.POINTER(Block), i64, vp, i64, vp, vp, vp]
     lib.cmsvd_tail_energy_grad.argtypes = [vp, ctypes.POINTER(Block), i64, i64, i64, ctypes.POINTER(d), vp,
                                            ctypes.POINTER(d)]
     for f in ("cmsvd_create", "cmsvd_destroy", "cmsvd_set_stream", "cmsvd_update", "cmsvd_merge_errors",
               "cmsvd_cluster", "cmsvd_sym_eigvals", "cmsvd_gemm_f64", "cmsvd_profile", "cmsvd_profile_read",
-              "cmsvd_tail_energy_grad"):
+              "cmsvd_tail_energy_grad", "cmsvd_update_batch"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -62,7 +63,7 @@ _lib = _load()
 
 EXPORTS = ("cmsvd_create", "cmsvd_destroy", "cmsvd_set_stream", "cmsvd_last_error", "cmsvd_update",
            "cmsvd_merge_errors", "cmsvd_cluster", "cmsvd_sym_eigvals", "cmsvd_gemm_f64", "cmsvd_profile",
-           "cmsvd_profile_read", "cmsvd_tail_energy_grad")
+           "cmsvd_profile_read", "cmsvd_tail_energy_grad", "cmsvd_update_batch")
 
 STAGES = ("norms_grams", "commit", "projection", "core_eig")
 
@@ -177,6 +178,38 @@ def cmsvd_update(state: State, B: torch.Tensor, r: int | None = None, handle: Ha
         ctypes.c_void_p(out.acc.data_ptr()), ctypes.c_void_p(out.est.data_ptr())))
     out.width = r
     return out
+
+
+def cmsvd_update_batch(states: Sequence[State], blocks: Sequence[torch.Tensor], r: int | None = None,
+                       handle: Handle | None = None) -> list:
+    """One incremental step for each (state, block) pair, in one batched call (states of
+    equal m, width and r, e.g. chains advanced in lockstep).  Returns new States."""
+    n = len(states)
+    if n != len(blocks):
+        raise ValueError("states and blocks differ in length")
+    if n == 0:
+        return []
+    h = handle or default_handle(blocks[0].device)
+    s0 = states[0]
+    r = s0.r if r is None else r
+    outs = []
+    for st in states:
+        if st.m != s0.m or st.width != s0.width or st.U.stride(0) != s0.U.stride(0):
+            raise ValueError("states must share m, width and layout")
+        o = State(st.m, r, blocks[0].device)
+        o.acc.copy_(st.acc)
+        outs.append(o)
+    P = ctypes.c_void_p * n
+    arr = _blocks(blocks)
+    U = P(*[st.U.data_ptr() for st in states]) if s0.width else None
+    S = P(*[st.S.data_ptr() for st in states]) if s0.width else None
+    _check(_lib.cmsvd_update_batch(
+        h.ptr, n, s0.m, U, s0.U.stride(0), S, s0.width, arr, r,
+        P(*[o.U.data_ptr() for o in outs]), outs[0].U.stride(0), P(*[o.S.data_ptr() for o in outs]),
+        P(*[o.acc.data_ptr() for o in outs]), P(*[o.est.data_ptr() for o in outs])))
+    for o in outs:
+        o.width = r
+    return outs
 
 
 def cmsvd_merge_errors(blocks: Sequence[torch.Tensor], pairs, r: int, handle: Handle | None = None):
@@ -312,6 +345,7 @@ def cmsvd_gemm_f64(opA: torch.Tensor, opB: torch.Tensor, C: torch.Tensor | None 
     return C
 
 
-__all__ = ["cmsvd_gemm_f64", "Handle", "State", "Block", "CmsvdError", "cmsvd_update", "cmsvd_merge_errors", "cmsvd_cluster",
+__all__ = ["cmsvd_gemm_f64", "Handle", "State", "Block", "CmsvdError", "cmsvd_update", "cmsvd_update_batch",
+           "cmsvd_merge_errors", "cmsvd_cluster",
            "cmsvd_sym_eigvals", "cmsvd_tail_energy_grad", "TailEnergy", "tail_energy", "default_handle",
            "LIB_PATH", "EXPORTS"]

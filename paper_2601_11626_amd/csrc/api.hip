@@ -766,6 +766,34 @@ cmsvd_status cmsvd_update(cmsvd_handle h, int64_t m, const double* U, int64_t ld
     return commit_batched(h, {j});
 }
 
+cmsvd_status cmsvd_update_batch(cmsvd_handle h, int64_t count, int64_t m, const double* const* U, int64_t ldu,
+                                const double* const* S, int64_t r_in, const cmsvd_block* B, int64_t r,
+                                double* const* U_out, int64_t ldu_out, double* const* S_out, double* const* acc,
+                                double* const* est) {
+    if (!h) return fail(CMSVD_EINVAL, "cmsvd_update_batch: null handle");
+    if (count < 0) return fail(CMSVD_EINVAL, "cmsvd_update_batch: count < 0");
+    if (count == 0) return CMSVD_OK;
+    if (!B || !U_out || !S_out || !acc) return fail(CMSVD_EINVAL, "cmsvd_update_batch: null array");
+    if (m < 1) return fail(CMSVD_ESHAPE, "cmsvd_update_batch: m < 1");
+    if (r < 1 || r > m) return fail(CMSVD_ESHAPE, "cmsvd_update_batch: need 1 <= r <= m");
+    if (r > 4096) return fail(CMSVD_EUNSUPPORTED, "cmsvd_update_batch: r > 4096");
+    if (r_in < 0 || r_in > m) return fail(CMSVD_ESHAPE, "cmsvd_update_batch: bad r_in");
+    if (r_in > 0 && (!U || !S || ldu < r_in)) return fail(CMSVD_EINVAL, "cmsvd_update_batch: bad state arrays");
+    if (ldu_out < r) return fail(CMSVD_ESHAPE, "cmsvd_update_batch: ldu_out < r");
+    std::vector<CommitJob> jobs;
+    for (int64_t i = 0; i < count; ++i) {
+        cmsvd_status st = check_block(B[i], m, "block", i);
+        if (st != CMSVD_OK) return st;
+        if (!U_out[i] || !S_out[i] || !acc[i]) return fail(CMSVD_EINVAL, "cmsvd_update_batch: null output %lld", (long long)i);
+        if (r_in > 0 && (!U[i] || !S[i])) return fail(CMSVD_EINVAL, "cmsvd_update_batch: null state %lld", (long long)i);
+        if (r_in > 0 && (U_out[i] == U[i] || S_out[i] == S[i]))
+            return fail(CMSVD_EINVAL, "cmsvd_update_batch: outputs alias inputs (%lld)", (long long)i);
+        jobs.push_back(CommitJob{(int)m, r_in > 0 ? U[i] : nullptr, (long)ldu, r_in > 0 ? S[i] : nullptr, (int)r_in, B[i],
+                                 (int)r, U_out[i], (long)ldu_out, S_out[i], acc[i], est ? est[i] : nullptr});
+    }
+    return commit_batched(h, jobs);
+}
+
 cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, const int32_t* pairs,
                                 int64_t npairs, int64_t r, double* err, double* rel) {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_merge_errors: null handle");

@@ -115,6 +115,31 @@ def test_chain_tiny_groups(cm):
                                    atol=1e-12 * states[t].sigma[0])
 
 
+def test_weight_chains_in_panels_scaled(cm):
+    # the weight-shaped recipe scaled down (2 chains of 28 blocks 128 x 128, r = 16);
+    # each block is appended as 8 panels of 16 columns, the two chains advance together
+    r, npan = 16, 8
+    blocks = workloads.weight_like(layers=8, m=128, n=128, basis=16, dtype=np.float64)
+    chains = [blocks[28 * g:28 * (g + 1)] for g in range(2)]
+    w = 128 // npan
+    panels = [[b[:, w * p:w * (p + 1)] for b in ch for p in range(npan)] for ch in chains]
+    say("weight chains 2 x 224 panel steps r=16")
+    refs = [oracle.chain_c([np.ascontiguousarray(x) for x in pc], r) for pc in panels]
+    dev = [torch.from_numpy(np.ascontiguousarray(np.stack(ch))).cuda() for ch in chains]  # (28, 128, 128)
+    states = [cm.State(128, r, "cuda") for _ in range(2)]
+    for step in range(28 * npan):
+        b, p = divmod(step, npan)
+        states = cm.cmsvd_update_batch(states, [dev[g][b][:, w * p:w * (p + 1)] for g in range(2)], r)
+        if step % 16 == 15 or step == 28 * npan - 1:
+            torch.cuda.synchronize()
+            for g in range(2):
+                est, _, etot, _, _ = refs[g]
+                e = states[g].est.cpu().numpy()
+                assert_est(e[0], est[step], math.sqrt(etot[step]), f"chain {g} step {step}")
+                # the plug-in equals the discarded-energy tally to rounding
+                assert abs(e[0] ** 2 - e[1] ** 2) <= 1e-10 * etot[step]
+
+
 def test_merge_errors_tiny_groups_all_pairs(cm):
     say("merge_errors tiny_groups 120 pairs r=8")
     blocks = workloads.tiny_groups()

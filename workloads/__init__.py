@@ -19,6 +19,10 @@ Workloads (the paper's datasets are not available; these stand in for them):
                          columns from 32 latent 4096x48 subspaces, noise 1e-2.
 * ``shared_chain``    -- 64 FP32 blocks 2048x512 sharing a 2048x96 subspace,
                          noise sigma 0.05 (long chain).
+* ``weight_like``     -- weight-matrix-shaped blocks U diag(sigma) V^T, sigma_i = i^-0.8,
+                         U from 8 shared bases (70 % of its leading columns) plus 30 %
+                         fresh directions, completed to an orthogonal matrix; one shared
+                         orthogonal V; blocks grouped into chains of 28 (4 layers x 7).
 * ``table1_like``     -- the shapes of the paper's collections (Table 1: many thin
                          blocks, e.g. 2468 blocks of 12800x20) with synthetic values:
                          blocks drawn from a few latent subspaces plus noise.
@@ -115,6 +119,32 @@ def table1_like(seed: int = 0, nblocks: int = 2468, m: int = 12800, k: int = 20,
         C = rng.standard_normal((d, k))
         E = rng.standard_normal((m, k)) * noise
         blocks.append((L[i % groups] @ C + E).astype(dtype))
+    return blocks
+
+
+def weight_like(seed: int = 0, layers: int = 32, proj: int = 7, m: int = 4096, n: int = 4096,
+                basis: int = 512, lead_frac: float = 0.7, decay: float = 0.8, dtype=np.float32):
+    """Blocks in order layer * proj + p; chain g holds layers 4g .. 4g + 3 (28 blocks).
+    Draw order: the shared group bases B_g (m x basis); the shared V (n x n); then per
+    block a Haar rotation H (basis x basis), the fresh directions (m x (basis - lead)),
+    and the completion (m x (m - basis)) of U."""
+    rng = np.random.default_rng(seed)
+    groups = (layers + 3) // 4
+    Bg = [orthonormal(rng, m, basis) for _ in range(groups)]
+    V = orthonormal(rng, n, n)
+    nl = int(round(lead_frac * basis))
+    q = min(m, n)
+    sig = np.arange(1, q + 1, dtype=np.float64) ** (-decay)
+    blocks = []
+    for layer in range(layers):
+        for _ in range(proj):
+            H = orthonormal(rng, basis, basis)
+            lead = Bg[layer // 4] @ H[:, :nl]
+            fresh = rng.standard_normal((m, basis - nl))
+            rest = rng.standard_normal((m, m - basis))
+            Q, R = np.linalg.qr(np.concatenate([lead, fresh, rest], axis=1))
+            U = Q * np.sign(np.diag(R))[None, :]
+            blocks.append(((U[:, :q] * sig[None, :]) @ V[:, :q].T).astype(dtype))
     return blocks
 
 
