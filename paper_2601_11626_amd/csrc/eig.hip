@@ -1078,19 +1078,30 @@ __global__ void __launch_bounds__(ET) sym_vectors_kernel(const VecDesc* __restri
     }
     __syncthreads();
 
-    // (2) Gram-Schmidt in descending-eigenvalue order, two passes (CGS2)
+    // (2) Gram-Schmidt in descending-eigenvalue order, two passes (CGS2).  The dot
+    // products and updates keep 8 independent loads and partial sums in flight.
     for (int q = 0; q < nk; ++q) {
         for (int pass = 0; pass < 2; ++pass) {
             for (int qq = t; qq < q; qq += ET) {
-                double s = 0.0;
-                for (int i = 0; i < n; ++i) s += at(4, i, qq) * at(4, i, q);
-                coef[qq] = s;
+                double sp[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                int i = 0;
+                for (; i + 8 <= n; i += 8) {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) sp[u] = fma(at(4, i + u, qq), at(4, i + u, q), sp[u]);
+                }
+                for (; i < n; ++i) sp[0] = fma(at(4, i, qq), at(4, i, q), sp[0]);
+                coef[qq] = ((sp[0] + sp[1]) + (sp[2] + sp[3])) + ((sp[4] + sp[5]) + (sp[6] + sp[7]));
             }
             __syncthreads();
             for (int i = t; i < n; i += ET) {
-                double v = at(4, i, q);
-                for (int qq = 0; qq < q; ++qq) v -= coef[qq] * at(4, i, qq);
-                at(4, i, q) = v;
+                double vp8[8] = {at(4, i, q), 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                int qq = 0;
+                for (; qq + 8 <= q; qq += 8) {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) vp8[u] = fma(-coef[qq + u], at(4, i, qq + u), vp8[u]);
+                }
+                for (; qq < q; ++qq) vp8[0] = fma(-coef[qq], at(4, i, qq), vp8[0]);
+                at(4, i, q) = ((vp8[0] + vp8[1]) + (vp8[2] + vp8[3])) + ((vp8[4] + vp8[5]) + (vp8[6] + vp8[7]));
             }
             __syncthreads();
         }
@@ -1119,11 +1130,16 @@ __global__ void __launch_bounds__(ET) sym_vectors_kernel(const VecDesc* __restri
             if (tj == 0.0) continue;
             for (int i = t; i < n; i += ET) vj[i] = (i == j + 1) ? 1.0 : (i > j + 1 ? D.V[(long)i + (long)j * D.ldv] : 0.0);
             __syncthreads();
-            for (int qq = t; qq < pq; qq += ET) {
+            // 8 lanes per vector, DPP-reduced
+            for (int base = 0; base < pq; base += ET / 8) {
+                const int qq = base + (t >> 3), part = t & 7;
                 double s = 0.0;
-                const double* x = X + (size_t)qq * n;
-                for (int i = j + 1; i < n; ++i) s += vj[i] * x[i];
-                coef[qq] = tj * s;
+                if (qq < pq) {
+                    const double* x = X + (size_t)qq * n;
+                    for (int i = j + 1 + part; i < n; i += 8) s = fma(vj[i], x[i], s);
+                }
+                s = sum_lanes8(s);
+                if (qq < pq && part == 0) coef[qq] = tj * s;
             }
             __syncthreads();
             for (int el = t; el < pq * (n - j - 1); el += ET) {
