@@ -301,6 +301,59 @@ def smallk(args, cm, workloads, torch):
     print(json.dumps(out), flush=True)
 
 
+def weights(args, cm, workloads, torch):
+    """224 FP32 weight-shaped blocks of 4096 x 4096 (32 layers x 7 projections) in 8
+    chains of 28; each block is appended as 8 panels of 512 columns and the 8 chains
+    advance together (one cmsvd_update_batch per panel step, 224 steps), r = 512.
+    Checks that hold at any size: the plug-in error equals the discarded-energy tally,
+    and the estimate is non-decreasing along every chain and below ||M||_F."""
+    r, npan = 512, 8
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    blocks = workloads.weight_like_torch(seed=0, device=dev)
+    torch.cuda.synchronize()
+    log(f"generated {len(blocks)} blocks {tuple(blocks[0].shape)} on the device in {time.time() - t0:.1f}s")
+    chains = [blocks[28 * g:28 * (g + 1)] for g in range(8)]
+    w = blocks[0].shape[1] // npan
+    m = blocks[0].shape[0]
+    h = cm.Handle(dev)
+    states = [cm.State(m, r, dev) for _ in range(8)]
+    hist = []
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for step in range(28 * npan):
+        b, p = divmod(step, npan)
+        states = cm.cmsvd_update_batch(states, [ch[b][:, w * p:w * (p + 1)] for ch in chains], r, handle=h)
+        if p == npan - 1:
+            torch.cuda.synchronize()
+            hist.append(torch.stack([s.est for s in states]).cpu().numpy())
+            log(f"block {b + 1}/28 of every chain done, {time.perf_counter() - t1:.1f}s")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    hist = np.array(hist)  # (28, 8, 2)
+    etot = np.array([[float(s.acc[0] + s.acc[1]) for s in states]])
+    out = {
+        "metric": "incremental rank-512 estimate over 8 chains of 28 weight-shaped blocks (8 panels each)",
+        "value": round(el, 3),
+        "unit": "s",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "weight_like: 224 FP32 blocks 4096x4096 (sigma_i = i^-0.8, 8 shared 512-dim bases, "
+                               "30% fresh directions), 8 chains x 28 blocks x 8 panels of 512, r=512",
+                   "chains": 8, "blocks_per_chain": 28, "panels": npan, "r": r},
+        "ms_per_panel_step": round(1000.0 * el / (28 * npan), 3),
+        "final_rel": (hist[-1, :, 0] / np.sqrt(etot[0])).tolist(),
+        "plugin_vs_discarded_max_rel": float(np.max(np.abs(hist[..., 0] ** 2 - hist[..., 1] ** 2)
+                                               / np.maximum(hist[..., 0] ** 2, 1e-300))),
+        "monotone": bool(np.all(np.diff(hist[..., 0], axis=0) >= -1e-12 * hist[1:, :, 0])),
+        "below_norm": bool(np.all(hist[-1, :, 0] <= np.sqrt(etot[0]))),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -324,7 +377,7 @@ def main():
     ap.add_argument("--nblocks", type=int, default=512, help="cluster: collection size")
     ap.add_argument("--preset", default="qualcomm", choices=("qualcomm", "bigearthnet", "pdebench"),
                     help="smallk: collection shape (Table 1 of the paper; values synthetic)")
-    ap.add_argument("--workload", default="pairs", choices=("pairs", "chain_grad", "cluster", "smallk"),
+    ap.add_argument("--workload", default="pairs", choices=("pairs", "chain_grad", "cluster", "smallk", "weights"),
                     help="pairs: batched merge errors (the default line); chain_grad: tail energy and "
                          "its gradient along a 64-block chain")
     args = ap.parse_args()
@@ -362,6 +415,8 @@ def main():
         return cluster(args, cm, workloads, torch)
     if args.workload == "smallk":
         return smallk(args, cm, workloads, torch)
+    if args.workload == "weights":
+        return weights(args, cm, workloads, torch)
 
     r = 64
     t0 = time.time()

@@ -148,6 +148,39 @@ def weight_like(seed: int = 0, layers: int = 32, proj: int = 7, m: int = 4096, n
     return blocks
 
 
+def weight_like_torch(seed: int = 0, layers: int = 32, proj: int = 7, m: int = 4096, n: int = 4096,
+                      basis: int = 512, lead_frac: float = 0.7, decay: float = 0.8, device="cuda"):
+    """The weight_like recipe drawn with torch on the device (for sizes where host QR
+    factorisations would take too long).  Same construction and draw order as
+    weight_like, with torch's generator seeded by `seed`; the values differ from
+    weight_like's.  Returns FP32 device tensors."""
+    import torch
+
+    g = torch.Generator(device=device).manual_seed(seed)
+
+    def orth(rows, cols):
+        q, r = torch.linalg.qr(torch.randn(rows, cols, generator=g, device=device, dtype=torch.float32))
+        return q * torch.sign(torch.diagonal(r))[None, :]
+
+    groups = (layers + 3) // 4
+    Bg = [orth(m, basis) for _ in range(groups)]
+    V = orth(n, n)
+    nl = int(round(lead_frac * basis))
+    q = min(m, n)
+    sig = torch.arange(1, q + 1, device=device, dtype=torch.float32) ** (-decay)
+    blocks = []
+    for layer in range(layers):
+        for _ in range(proj):
+            H = orth(basis, basis)
+            lead = Bg[layer // 4] @ H[:, :nl]
+            fresh = torch.randn(m, basis - nl, generator=g, device=device, dtype=torch.float32)
+            rest = torch.randn(m, m - basis, generator=g, device=device, dtype=torch.float32)
+            Q, R = torch.linalg.qr(torch.cat([lead, fresh, rest], dim=1))
+            U = Q * torch.sign(torch.diagonal(R))[None, :]
+            blocks.append(((U[:, :q] * sig[None, :]) @ V[:, :q].T).contiguous())
+    return blocks
+
+
 def anchor_ordered_pairs(blocks) -> np.ndarray:
     """All unordered pairs {i, j}, i < j, oriented anchor-first: the block with the
     larger Frobenius norm heads the pair (ties: the lower index)."""
