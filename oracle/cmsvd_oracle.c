@@ -491,9 +491,10 @@ double oracle_weyl_bound2(int m, int nblocks, const double* data, const long* of
 /* Theorem 2 / Corollary 1 (residual bound).  Residuals are taken      */
 /* against a full-span orthonormal basis of the blocks seen so far:    */
 /*   R_i = (I - Q_{i-1} Q_{i-1}^T) A_i.                                */
-/* The basis is extended by the Householder Q of R_i restricted to the */
-/* columns whose R-factor diagonal exceeds rank_tol * ||A_i||_F (so    */
-/* that numerically absent directions are not added).  mu (length      */
+/* The basis is extended by the left singular vectors of R_i whose    */
+/* singular value exceeds rank_tol * ||A_i||_F (so that numerically    */
+/* absent directions are not added; rank_tol < 0: sqrt(n_i u), u=2^-52)*/
+/* re-orthogonalised against the basis.  mu (length                   */
 /* sum n_i, descending) receives the singular values of [R_1 ... R_K]; */
 /* because the residual ranges are mutually orthogonal these are the   */
 /* union of the per-block residual spectra.  Returns                   */
@@ -527,7 +528,8 @@ double oracle_residual_bound2(int m, int nblocks, const double* data, const long
         double* Ul = (double*)malloc(sizeof(double) * (size_t)m * (size_t)k);
         memcpy(W, R, sizeof(double) * (size_t)m * (size_t)k);
         oracle_jacobi_svd(m, k, W, m, s, Ul, m, 60);
-        double thr = rank_tol * sqrt(a2);
+        /* rank_tol < 0 selects the per-block cutoff sqrt(k_i u) ||A_i||_F, u = 2^-52 */
+        double thr = (rank_tol >= 0.0 ? rank_tol : sqrt((double)k * 2.220446049250313e-16)) * sqrt(a2);
         for (int j = 0; j < k; ++j) {
             allmu[nmu++] = s[j];
             if (s[j] > thr && q < m) {
