@@ -7,7 +7,9 @@
  * Compression Bounds, Incremental Approximation, and Error-Constrained Clustering",
  * TMLR 2026: Methodology, incremental truncated SVD, and Appendix B) and the plug-in
  * error of Corollary 2, for single updates, for all requested candidate pairs, and
- * inside the greedy error-constrained clustering of Algorithm 3 (Appendix E).
+ * inside the greedy error-constrained clustering of Algorithm 3 (Appendix E); and
+ * the residual certificate of Theorem 2 / Corollary 1 with the clustering of
+ * Algorithm 2.
  *
  * Conventions shared by every call
  *   - Blocks A_i are real m x n_i matrices with a common row count m (Problem
@@ -25,8 +27,8 @@
  *   - All calls are ordered on the handle's HIP stream.  cmsvd_update and
  *     cmsvd_merge_errors return once their work is enqueued (the host may block
  *     briefly while descriptor tables are uploaded); results are valid after a
- *     stream synchronisation.  cmsvd_cluster is synchronous (its outputs are host
- *     memory).
+ *     stream synchronisation.  The clustering calls are synchronous (their outputs
+ *     are host memory).
  *   - Argument validation happens before any launch.  A non-OK status means no
  *     kernel was launched by that call, except CMSVD_EHIP, which reports a HIP
  *     runtime failure.  cmsvd_last_error() gives a thread-local message.
@@ -130,6 +132,40 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle handle, const cmsvd_block* blocks, 
 cmsvd_status cmsvd_cluster(cmsvd_handle handle, const cmsvd_block* blocks, int64_t nblocks, int64_t r,
                            double eps, int32_t sort_mode, int32_t* labels, int64_t* nclusters,
                            double* cluster_rel);
+
+/* Algorithm 2 (residual-based clustering, Appendix E) with the certificate of
+   Corollary 1: a cluster C keeps an orthonormal basis Q_C of the span of its blocks,
+   its energy S_C and the r largest singular values mu of its concatenated residuals
+   R_j = (I - Q Q^T) A_j, Q spanning the blocks accepted before j (Theorem 2).  The
+   residual ranges are mutually orthogonal, so a candidate's certificate is
+     b^2 = S_C + ||A_j||_F^2 - (sum of the r largest squares in mu u sigma(R_j)),
+   which bounds the optimal rank-r error of M_{C+j} from above; the candidate joins
+   iff b / ||M_{C+j}||_F <= eps (non-strict).  The loop is the pass-based one of
+   cmsvd_cluster (same anchor choice, sort modes, tie rules and scan semantics), with
+   the residual ordering ||(I - Q_C Q_C^T) A_j||_F taken against the full-span basis.
+   Numerical span: the residual is projected twice and orthonormalised by
+   CholeskyQR2; a direction whose squared singular value is below about
+   k_j u ||A_j||_F^2 (u = 2^-52, the pivot threshold) is not added to Q_C.  Blocks
+   may have at most 8192 columns; Q_C takes m * min(m, sum_j n_j) doubles of device
+   memory for the whole call.
+     labels, nclusters   as cmsvd_cluster
+     cluster_rel  HOST nblocks FP64 (may be NULL): the certified ratio
+                  b / ||M_C||_F of each final cluster (first *nclusters entries)
+   Synchronous. */
+cmsvd_status cmsvd_cluster_residual(cmsvd_handle handle, const cmsvd_block* blocks, int64_t nblocks, int64_t r,
+                                    double eps, int32_t sort_mode, int32_t* labels, int64_t* nclusters,
+                                    double* cluster_rel);
+
+/* Corollary 1 for a fixed order: the residual certificate of [A_1 ... A_K] with the
+   blocks processed in the given order (the same state updates as
+   cmsvd_cluster_residual, every block accepted).
+     bound2   HOST out: S - sum_{l<=r} mu_l^2, clamped at 0 (an upper bound on the
+              optimal rank-r error squared of the concatenation)
+     mu       HOST r FP64 (may be NULL): the r largest residual singular values,
+              descending, zero-padded
+   Synchronous. */
+cmsvd_status cmsvd_residual_bound(cmsvd_handle handle, const cmsvd_block* blocks, int64_t nblocks, int64_t r,
+                                  double* bound2, double* mu);
 
 /* Tail energy of a chain and its gradient with respect to every block.
    The chain folds the blocks in order (the incremental state of Lemma 1 and

@@ -50,11 +50,13 @@ def _load():
     lib.cmsvd_profile.argtypes = [vp, i32]
     lib.cmsvd_profile_read.argtypes = [vp, vp, vp]
     lib.cmsvd_update_batch.argtypes = [vp, i64, i64, vp, i64, vp, i64, ctypes.POINTER(Block), i64, vp, i64, vp, vp, vp]
+    lib.cmsvd_cluster_residual.argtypes = [vp, ctypes.POINTER(Block), i64, i64, d, i32, vp, ctypes.POINTER(i64), vp]
+    lib.cmsvd_residual_bound.argtypes = [vp, ctypes.POINTER(Block), i64, i64, ctypes.POINTER(d), vp]
     lib.cmsvd_tail_energy_grad.argtypes = [vp, ctypes.POINTER(Block), i64, i64, i64, ctypes.POINTER(d), vp,
                                            ctypes.POINTER(d)]
     for f in ("cmsvd_create", "cmsvd_destroy", "cmsvd_set_stream", "cmsvd_update", "cmsvd_merge_errors",
               "cmsvd_cluster", "cmsvd_sym_eigvals", "cmsvd_gemm_f64", "cmsvd_profile", "cmsvd_profile_read",
-              "cmsvd_tail_energy_grad", "cmsvd_update_batch"):
+              "cmsvd_tail_energy_grad", "cmsvd_update_batch", "cmsvd_cluster_residual", "cmsvd_residual_bound"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -63,7 +65,8 @@ _lib = _load()
 
 EXPORTS = ("cmsvd_create", "cmsvd_destroy", "cmsvd_set_stream", "cmsvd_last_error", "cmsvd_update",
            "cmsvd_merge_errors", "cmsvd_cluster", "cmsvd_sym_eigvals", "cmsvd_gemm_f64", "cmsvd_profile",
-           "cmsvd_profile_read", "cmsvd_tail_energy_grad", "cmsvd_update_batch")
+           "cmsvd_profile_read", "cmsvd_tail_energy_grad", "cmsvd_update_batch", "cmsvd_cluster_residual",
+           "cmsvd_residual_bound")
 
 STAGES = ("norms_grams", "commit", "projection", "core_eig")
 
@@ -250,6 +253,36 @@ def cmsvd_cluster(blocks: Sequence[torch.Tensor], r: int, eps: float, sort_mode:
     return lab, clusters, list(crel)[: ncl.value]
 
 
+def cmsvd_cluster_residual(blocks: Sequence[torch.Tensor], r: int, eps: float, sort_mode: str = "frobenius",
+                           handle: Handle | None = None):
+    """Algorithm 2 on the device.  Returns (labels list, clusters list, certified ratio list)."""
+    dev = blocks[0].device
+    h = handle or default_handle(dev)
+    mode = {"frobenius": 0, "residual": 1}[sort_mode]
+    n = len(blocks)
+    labels = (ctypes.c_int32 * n)()
+    ncl = ctypes.c_int64(0)
+    crel = (ctypes.c_double * n)()
+    arr = _blocks(blocks)
+    _check(_lib.cmsvd_cluster_residual(h.ptr, arr, n, r, float(eps), mode, labels, ctypes.byref(ncl), crel))
+    lab = list(labels)
+    clusters = [[] for _ in range(ncl.value)]
+    for i, c in enumerate(lab):
+        clusters[c].append(i)
+    return lab, clusters, list(crel)[: ncl.value]
+
+
+def cmsvd_residual_bound(blocks: Sequence[torch.Tensor], r: int, handle: Handle | None = None):
+    """Corollary 1 for the blocks in order.  Returns (bound^2, mu: the r largest
+    residual singular values, descending, as a list)."""
+    h = handle or default_handle(blocks[0].device)
+    arr = _blocks(blocks)
+    b2 = ctypes.c_double(0.0)
+    mu = (ctypes.c_double * r)()
+    _check(_lib.cmsvd_residual_bound(h.ptr, arr, len(blocks), r, ctypes.byref(b2), mu))
+    return b2.value, list(mu)
+
+
 def cmsvd_tail_energy_grad(blocks: Sequence[torch.Tensor], r: int, checkpoint: int | None = None,
                            want_grad: bool = True, handle: Handle | None = None):
     """Tail energy f = E~_r^2 of the chain ``blocks`` (in order) and, if ``want_grad``,
@@ -346,6 +379,6 @@ def cmsvd_gemm_f64(opA: torch.Tensor, opB: torch.Tensor, C: torch.Tensor | None 
 
 
 __all__ = ["cmsvd_gemm_f64", "Handle", "State", "Block", "CmsvdError", "cmsvd_update", "cmsvd_update_batch",
-           "cmsvd_merge_errors", "cmsvd_cluster",
+           "cmsvd_merge_errors", "cmsvd_cluster", "cmsvd_cluster_residual", "cmsvd_residual_bound",
            "cmsvd_sym_eigvals", "cmsvd_tail_energy_grad", "TailEnergy", "tail_energy", "default_handle",
            "LIB_PATH", "EXPORTS"]

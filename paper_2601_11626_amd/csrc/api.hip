@@ -656,12 +656,373 @@ cmsvd_status copy_block(cmsvd_ctx* h, const cmsvd_block& b, double* dst) {
     return CMSVD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Residual-certified clustering (Theorem 2, Corollary 1, Algorithm 2).
+//
+// Cluster state: Q, an orthonormal basis of the numerical span of the accepted blocks
+// (row-major m x qcap, the first q columns valid); L, the r largest squared residual
+// singular values (non-increasing, zero-padded); S, the energy (double-double).  L and
+// S are ping-pong pairs so that an acceptance never reads what it writes.
+// ---------------------------------------------------------------------------
+struct ResidState {
+    int m = 0, r = 0, qcap = 0, q = 0, cur = 0;
+    double* Q = nullptr;
+    double* L[2] = {nullptr, nullptr};
+    double* S[2] = {nullptr, nullptr};
+    int* map = nullptr;    // kmax ints
+    int* count = nullptr;  // 1 int
+};
+
+struct ResidCand {
+    cmsvd_block B;
+    const double* nb;  // double-double ||B||^2
+    const double* G;   // B^T B (k x k)
+    double* lam;       // min(r, k) slots: the largest residual-Gram eigenvalues
+    double* rel;
+    double* err;       // may be null
+};
+
+// The residual Gram of a candidate is G - P^T P with P = Q^T B (Q orthonormal), so its
+// spectrum needs one projection GEMM and a k x k eigenproblem; the certificate then
+// merges the top of that spectrum with L.
+cmsvd_status resid_eval(cmsvd_ctx* h, const ResidState& st, const std::vector<ResidCand>& cands) {
+    const size_t total = cands.size();
+    if (total == 0) return CMSVD_OK;
+    const int q = st.q, r = st.r;
+    size_t b0 = 0;
+    while (b0 < total) {
+        // chunk so that the per-candidate P and residual Gram stay within ~8 GiB
+        size_t b1 = b0, bytes = 0;
+        int kmax = 1;
+        while (b1 < total) {
+            const size_t k = (size_t)cands[b1].B.cols;
+            const size_t need = q > 0 ? align256((size_t)q * k * 8) + align256(k * k * 8) : 0;
+            if (b1 > b0 && bytes + need > ((size_t)8 << 30)) break;
+            bytes += need;
+            kmax = std::max(kmax, (int)k);
+            ++b1;
+        }
+        const int nj = (int)(b1 - b0);
+        const int nslots = std::min(nj, h->ncu);
+        Plan pl;
+        std::vector<size_t> oP(nj), oG(nj);
+        if (q > 0)
+            for (int i = 0; i < nj; ++i) {
+                const size_t k = (size_t)cands[b0 + i].B.cols;
+                oP[i] = pl.add((size_t)q * k * 8);
+                oG[i] = pl.add(k * k * 8);
+            }
+        const size_t eig_off = pl.add(sym_eig_workspace_doubles(kmax, nslots) * 8);
+        cmsvd_status s = ensure(h, h->ws, h->ws_cap, pl.off);
+        if (s != CMSVD_OK) return s;
+        auto D = [&](size_t off) { return reinterpret_cast<double*>(h->ws + off); };
+        GemmGroup gP32, gP64, gS;
+        gP32.tb = gP64.tb = true;  // P = Q^T B
+        gP32.bf32 = true;
+        gS.ta = true;              // GR -= P^T P
+        gS.alpha = -1.0;
+        gS.beta = 1.0;
+        std::vector<CopyDesc> cd;
+        std::vector<EigDesc> ed(nj);
+        std::vector<CertDesc> ct(nj);
+        int nkmax = 1;
+        for (int i = 0; i < nj; ++i) {
+            const ResidCand& c = cands[b0 + i];
+            const int k = (int)c.B.cols, nk = std::min(r, k);
+            nkmax = std::max(nkmax, nk);
+            const double* Y = c.G;
+            if (q > 0) {
+                GemmDesc g{st.Q, c.B.ptr, D(oP[i]), q, k, st.m, (long)st.qcap, (long)c.B.ld, (long)q};
+                (c.B.dtype == CMSVD_F32 ? gP32 : gP64).push(g);
+                cd.push_back(CopyDesc{c.G, k, k, (long)k, 0, D(oG[i]), (long)k});
+                gS.push(GemmDesc{D(oP[i]), D(oP[i]), D(oG[i]), k, k, q, (long)q, (long)q, (long)k});
+                Y = D(oG[i]);
+            }
+            EigDesc e{};
+            e.n = k;
+            e.n1 = 0;
+            e.nkeep = nk;
+            e.Y = Y;
+            e.ldy = k;
+            e.lam = c.lam;
+            ed[i] = e;
+            ct[i] = CertDesc{st.L[st.cur], st.S[st.cur], c.nb, c.lam, nk, c.rel, c.err};
+        }
+        Stage stg;
+        gP32.off = stg.add(gP32.d);
+        gP64.off = stg.add(gP64.d);
+        gS.off = stg.add(gS.d);
+        const size_t o_cd = stg.add(cd), o_ed = stg.add(ed), o_ct = stg.add(ct);
+        char* db = nullptr;
+        s = upload(h, stg, &db);
+        if (s != CMSVD_OK) return s;
+        if (q > 0) {
+            StageMark mark(h, ST_PROJ);
+            run_gemm(gP32, db, h->stream);
+            run_gemm(gP64, db, h->stream);
+            copy_f64_batched(reinterpret_cast<const CopyDesc*>(db + o_cd), (int)cd.size(), kmax, h->stream);
+            run_gemm(gS, db, h->stream);
+        }
+        {
+            StageMark mark(h, ST_CORE);
+            sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), nj, kmax, 1, D(eig_off), nslots, h->stream);
+        }
+        resid_cert_batched(reinterpret_cast<const CertDesc*>(db + o_ct), nj, r, nkmax, h->stream);
+        HIPCHK(hipGetLastError());
+        b0 = b1;
+    }
+    return CMSVD_OK;
+}
+
+// ||Q^T B_j||_F^2 for every candidate (the residual ordering of a pass: the residual
+// energy is ||B_j||^2 minus this).
+cmsvd_status resid_proj_norms(cmsvd_ctx* h, const ResidState& st, const std::vector<cmsvd_block>& bl,
+                              const std::vector<double*>& out) {
+    const size_t total = bl.size();
+    if (total == 0) return CMSVD_OK;
+    if (st.q == 0) {
+        for (double* o : out) fill_f64(o, 1, 0.0, h->stream);
+        HIPCHK(hipGetLastError());
+        return CMSVD_OK;
+    }
+    size_t b0 = 0;
+    while (b0 < total) {
+        size_t b1 = b0, bytes = 0;
+        while (b1 < total) {
+            const size_t need = align256((size_t)st.q * bl[b1].cols * 8);
+            if (b1 > b0 && bytes + need > ((size_t)8 << 30)) break;
+            bytes += need;
+            ++b1;
+        }
+        Plan pl;
+        std::vector<size_t> oP(b1 - b0);
+        for (size_t i = b0; i < b1; ++i) oP[i - b0] = pl.add((size_t)st.q * bl[i].cols * 8);
+        cmsvd_status s = ensure(h, h->ws, h->ws_cap, pl.off);
+        if (s != CMSVD_OK) return s;
+        GemmGroup g32, g64;
+        g32.tb = g64.tb = true;
+        g32.bf32 = true;
+        std::vector<ColNormDesc> cn;
+        for (size_t i = b0; i < b1; ++i) {
+            double* P = reinterpret_cast<double*>(h->ws + oP[i - b0]);
+            GemmDesc g{st.Q, bl[i].ptr, P, st.q, (int)bl[i].cols, st.m, (long)st.qcap, (long)bl[i].ld, (long)st.q};
+            (bl[i].dtype == CMSVD_F32 ? g32 : g64).push(g);
+            cn.push_back(ColNormDesc{P, st.q, (int)bl[i].cols, (long)st.q, out[i]});
+        }
+        Stage stg;
+        g32.off = stg.add(g32.d);
+        g64.off = stg.add(g64.d);
+        const size_t oc = stg.add(cn);
+        char* db = nullptr;
+        s = upload(h, stg, &db);
+        if (s != CMSVD_OK) return s;
+        {
+            StageMark mark(h, ST_PROJ);
+            run_gemm(g32, db, h->stream);
+            run_gemm(g64, db, h->stream);
+        }
+        colblock_sumsq_batched(reinterpret_cast<const ColNormDesc*>(db + oc), (int)cn.size(), h->stream);
+        HIPCHK(hipGetLastError());
+        b0 = b1;
+    }
+    return CMSVD_OK;
+}
+
+// Accepts a block whose residual spectrum `lam` (nk values) was computed against the
+// current state: merges the spectrum into L, adds the energy, and appends the
+// numerically present directions of its residual to Q.  The residual is projected
+// twice (classical Gram-Schmidt, twice) and orthonormalised by CholeskyQR2 with the
+// semidefinite pivot threshold k u ||B||^2, so that a direction with squared singular
+// value below it is not added.  Synchronises to learn the new basis width.
+cmsvd_status resid_accept_block(cmsvd_ctx* h, ResidState& st, const cmsvd_block& B, const double* nb,
+                                const double* lam, int nk) {
+    hipStream_t s = h->stream;
+    const int nxt = 1 - st.cur;
+    resid_accept(st.L[st.cur], st.r, lam, nk, st.S[st.cur], nb, st.L[nxt], st.S[nxt], s);
+    st.cur = nxt;
+    const int k = (int)B.cols, m = st.m, q = st.q;
+    if (q >= st.qcap) {
+        HIPCHK(hipGetLastError());
+        return CMSVD_OK;
+    }
+    Plan pl;
+    const size_t oRt = pl.add((size_t)k * m * 8), oP = pl.add((size_t)std::max(q, 1) * k * 8),
+                 oP2 = pl.add((size_t)std::max(q, 1) * k * 8), oG1 = pl.add((size_t)k * k * 8),
+                 oL1 = pl.add((size_t)k * k * 8), oQ1 = pl.add((size_t)k * m * 8), oG2 = pl.add((size_t)k * k * 8),
+                 oL2 = pl.add((size_t)k * k * 8), oQr = pl.add((size_t)k * m * 8);
+    cmsvd_status st_ = ensure(h, h->ws, h->ws_cap, pl.off);
+    if (st_ != CMSVD_OK) return st_;
+    auto D = [&](size_t off) { return reinterpret_cast<double*>(h->ws + off); };
+    const bool f32 = B.dtype == CMSVD_F32;
+    std::vector<CopyDesc> cd{CopyDesc{B.ptr, m, k, (long)B.ld, f32 ? 1 : 0, D(oRt), (long)k}};
+    GemmGroup gP, gR1, gP2, gR2, gG1, gQ1, gG2, gQr;
+    gP.tb = true;
+    gP.bf32 = f32;
+    gR1.ta = true;
+    gR1.alpha = -1.0;
+    gR1.beta = 1.0;
+    gP2.tb = true;
+    gR2.ta = true;
+    gR2.alpha = -1.0;
+    gR2.beta = 1.0;
+    gG1.tb = true;
+    gG2.tb = true;
+    if (q > 0) {
+        gP.push(GemmDesc{st.Q, B.ptr, D(oP), q, k, m, (long)st.qcap, (long)B.ld, (long)q});
+        gR1.push(GemmDesc{D(oP), st.Q, D(oRt), k, m, q, (long)q, (long)st.qcap, (long)k});
+        gP2.push(GemmDesc{st.Q, D(oRt), D(oP2), q, k, m, (long)st.qcap, (long)k, (long)q});
+        gR2.push(GemmDesc{D(oP2), st.Q, D(oRt), k, m, q, (long)q, (long)st.qcap, (long)k});
+    }
+    gG1.push(GemmDesc{D(oRt), D(oRt), D(oG1), k, k, m, (long)k, (long)k, (long)k});
+    gQ1.push(GemmDesc{D(oL1), D(oRt), D(oQ1), k, m, k, (long)k, (long)k, (long)k});
+    gG2.push(GemmDesc{D(oQ1), D(oQ1), D(oG2), k, k, m, (long)k, (long)k, (long)k});
+    gQr.push(GemmDesc{D(oL2), D(oQ1), D(oQr), k, m, k, (long)k, (long)k, (long)k});
+    std::vector<CholDesc> ch1{CholDesc{k, D(oG1), (long)k, D(oL1), (long)k, (double)k * EPS, nb, nullptr}};
+    std::vector<CholDesc> ch2{CholDesc{k, D(oG2), (long)k, D(oL2), (long)k, (double)k * k * EPS, nullptr, nullptr}};
+    Stage stg;
+    const size_t o_cd = stg.add(cd), o_c1 = stg.add(ch1), o_c2 = stg.add(ch2);
+    for (GemmGroup* g : {&gP, &gR1, &gP2, &gR2, &gG1, &gQ1, &gG2, &gQr}) g->off = stg.add(g->d);
+    char* db = nullptr;
+    st_ = upload(h, stg, &db);
+    if (st_ != CMSVD_OK) return st_;
+    {
+        StageMark mark(h, ST_COMMIT);
+        copy_f64_batched(reinterpret_cast<const CopyDesc*>(db + o_cd), 1, m, s);
+        run_gemm(gP, db, s);
+        run_gemm(gR1, db, s);
+        run_gemm(gP2, db, s);
+        run_gemm(gR2, db, s);
+        run_gemm(gG1, db, s);
+        chol_semidef_batched(reinterpret_cast<const CholDesc*>(db + o_c1), 1, s);
+        run_gemm(gQ1, db, s);
+        run_gemm(gG2, db, s);
+        chol_semidef_batched(reinterpret_cast<const CholDesc*>(db + o_c2), 1, s);
+        run_gemm(gQr, db, s);
+        append_kept_columns(D(oQr), m, k, D(oL2), (long)k, st.Q, (long)st.qcap, q, st.qcap - q, st.map, st.count, s);
+    }
+    HIPCHK(hipGetLastError());
+    int added = 0;
+    HIPCHK(hipMemcpyAsync(&added, st.count, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    st.q += added;
+    return CMSVD_OK;
+}
+
+// Empties the state (basis width 0, L = 0, S = 0).
+cmsvd_status resid_reset(cmsvd_ctx* h, ResidState& st) {
+    st.q = 0;
+    st.cur = 0;
+    fill_f64(st.L[0], st.r, 0.0, h->stream);
+    fill_f64(st.S[0], 2, 0.0, h->stream);
+    HIPCHK(hipGetLastError());
+    return CMSVD_OK;
+}
+
 struct DevBuf {
     char* p = nullptr;
     ~DevBuf() {
         if (p) (void)hipFree(p);
     }
 };
+
+
+struct ResidBuffers {
+    DevBuf keep;
+    std::vector<double*> nrm, gram;
+    double *lam = nullptr, *rel = nullptr, *err = nullptr, *pn = nullptr;
+    int* first = nullptr;
+    int nkcap = 1;
+    ResidState st;
+};
+
+cmsvd_status resid_setup(cmsvd_ctx* h, const cmsvd_block* blocks, int N, int64_t r, const char* who, ResidBuffers& rb) {
+    if (N < 1 || !blocks) return fail(CMSVD_EINVAL, "%s: no blocks", who);
+    const int64_t m = blocks[0].rows;
+    if (m < 1) return fail(CMSVD_ESHAPE, "%s: m < 1", who);
+    if (r < 1 || r > m) return fail(CMSVD_ESHAPE, "%s: need 1 <= r <= m", who);
+    if (r > 4096) return fail(CMSVD_EUNSUPPORTED, "%s: r > 4096", who);
+    int64_t kmax = 0, ksum = 0;
+    for (int i = 0; i < N; ++i) {
+        cmsvd_status s = check_block(blocks[i], m, "block", i);
+        if (s != CMSVD_OK) return s;
+        if (blocks[i].cols > 8192) return fail(CMSVD_EUNSUPPORTED, "%s: block %d has more than 8192 columns", who, i);
+        kmax = std::max(kmax, blocks[i].cols);
+        ksum += blocks[i].cols;
+    }
+    const int64_t qcap = std::min(m, ksum);
+    rb.nkcap = (int)std::min<int64_t>(r, kmax);
+    Plan pl;
+    std::vector<size_t> o_n(N), o_g(N);
+    for (int i = 0; i < N; ++i) {
+        o_n[i] = pl.add(16);
+        o_g[i] = pl.add((size_t)blocks[i].cols * blocks[i].cols * 8);
+    }
+    const size_t o_Q = pl.add((size_t)m * qcap * 8);
+    size_t o_L[2], o_S[2];
+    for (int s = 0; s < 2; ++s) {
+        o_L[s] = pl.add((size_t)r * 8);
+        o_S[s] = pl.add(16);
+    }
+    const size_t o_lam = pl.add((size_t)N * rb.nkcap * 8), o_rel = pl.add((size_t)N * 8), o_err = pl.add((size_t)N * 8),
+                 o_pn = pl.add((size_t)N * 8), o_first = pl.add(8), o_cnt = pl.add(8), o_map = pl.add((size_t)kmax * 4);
+    if (hipMalloc((void**)&rb.keep.p, pl.off) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CMSVD_ENOMEM, "%s: hipMalloc(%zu) failed", who, pl.off);
+    }
+    char* base = rb.keep.p;
+    auto K = [&](size_t off) { return reinterpret_cast<double*>(base + off); };
+    for (int i = 0; i < N; ++i) {
+        rb.nrm.push_back(K(o_n[i]));
+        rb.gram.push_back(K(o_g[i]));
+    }
+    rb.lam = K(o_lam);
+    rb.rel = K(o_rel);
+    rb.err = K(o_err);
+    rb.pn = K(o_pn);
+    rb.first = reinterpret_cast<int*>(base + o_first);
+    rb.st.m = (int)m;
+    rb.st.r = (int)r;
+    rb.st.qcap = (int)qcap;
+    rb.st.Q = K(o_Q);
+    for (int s = 0; s < 2; ++s) {
+        rb.st.L[s] = K(o_L[s]);
+        rb.st.S[s] = K(o_S[s]);
+    }
+    rb.st.count = reinterpret_cast<int*>(base + o_cnt);
+    rb.st.map = reinterpret_cast<int*>(base + o_map);
+    std::vector<cmsvd_block> bl(blocks, blocks + N);
+    return norms_and_grams(h, bl, rb.nrm, rb.gram);
+}
+
+// Tests the candidates `cand` (in order) against the current state; rel[i], lam slot i.
+cmsvd_status resid_test(cmsvd_ctx* h, ResidBuffers& rb, const cmsvd_block* blocks, const std::vector<int>& cand) {
+    std::vector<ResidCand> rc;
+    rc.reserve(cand.size());
+    for (size_t i = 0; i < cand.size(); ++i) {
+        const int j = cand[i];
+        rc.push_back(ResidCand{blocks[j], rb.nrm[j], rb.gram[j], rb.lam + i * (size_t)rb.nkcap, rb.rel + i, rb.err + i});
+    }
+    return resid_eval(h, rb.st, rc);
+}
+
+// Certified ratio sqrt(max(0, S - sum L) / S) of the current state (device rel[0]).
+cmsvd_status resid_state_rel(cmsvd_ctx* h, ResidBuffers& rb, double* rel_host, double* b2_host) {
+    std::vector<CertDesc> ct{CertDesc{rb.st.L[rb.st.cur], rb.st.S[rb.st.cur], nullptr, rb.lam, 0, rb.rel, rb.err}};
+    Stage stg;
+    const size_t o = stg.add(ct);
+    char* db = nullptr;
+    cmsvd_status s = upload(h, stg, &db);
+    if (s != CMSVD_OK) return s;
+    resid_cert_batched(reinterpret_cast<const CertDesc*>(db + o), 1, rb.st.r, 1, h->stream);
+    HIPCHK(hipGetLastError());
+    double v[2] = {0.0, 0.0};
+    HIPCHK(hipMemcpyAsync(&v[0], rb.rel, 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(&v[1], rb.err, 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (rel_host) *rel_host = v[0];
+    if (b2_host) *b2_host = v[1] * v[1];
+    return CMSVD_OK;
+}
 
 }  // namespace
 
@@ -1156,6 +1517,128 @@ cmsvd_status cmsvd_cluster(cmsvd_handle h, const cmsvd_block* blocks, int64_t nb
     *nclusters = ncl;
     if (cluster_rel)
         for (int c = 0; c < ncl; ++c) cluster_rel[c] = crel[c];
+    return CMSVD_OK;
+}
+
+
+/* Residual-certified clustering (Algorithm 2); see include/cmsvd.h. */
+
+cmsvd_status cmsvd_cluster_residual(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double eps,
+                                    int32_t sort_mode, int32_t* labels, int64_t* nclusters, double* cluster_rel) {
+    if (!h) return fail(CMSVD_EINVAL, "cmsvd_cluster_residual: null handle");
+    if (!labels || !nclusters) return fail(CMSVD_EINVAL, "cmsvd_cluster_residual: null output");
+    if (!(eps >= 0.0)) return fail(CMSVD_EINVAL, "cmsvd_cluster_residual: eps must be >= 0");
+    if (sort_mode != 0 && sort_mode != 1) return fail(CMSVD_EINVAL, "cmsvd_cluster_residual: sort_mode must be 0 or 1");
+    if (nblocks > INT32_MAX) return fail(CMSVD_EUNSUPPORTED, "cmsvd_cluster_residual: too many blocks");
+    const int N = (int)nblocks;
+    ResidBuffers rb;
+    cmsvd_status st = resid_setup(h, blocks, N, r, "cmsvd_cluster_residual", rb);
+    if (st != CMSVD_OK) return st;
+    std::vector<double> n2h(2 * (size_t)N);
+    for (int i = 0; i < N; ++i) HIPCHK(hipMemcpyAsync(&n2h[2 * i], rb.nrm[i], 16, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    std::vector<double> n2(N);
+    for (int i = 0; i < N; ++i) n2[i] = n2h[2 * i] + n2h[2 * i + 1];
+    std::vector<int> remaining(N);
+    for (int i = 0; i < N; ++i) remaining[i] = i;
+    std::stable_sort(remaining.begin(), remaining.end(), [&](int a, int b) { return n2[a] > n2[b]; });
+    for (int i = 0; i < N; ++i) labels[i] = -1;
+    int ncl = 0;
+    std::vector<double> crel;
+    while (!remaining.empty()) {
+        const int anchor = remaining.front();
+        remaining.erase(remaining.begin());
+        st = resid_reset(h, rb.st);
+        if (st != CMSVD_OK) return st;
+        st = resid_test(h, rb, blocks, {anchor});
+        if (st != CMSVD_OK) return st;
+        st = resid_accept_block(h, rb.st, blocks[anchor], rb.nrm[anchor], rb.lam,
+                                (int)std::min<int64_t>(r, blocks[anchor].cols));
+        if (st != CMSVD_OK) return st;
+        labels[anchor] = ncl;
+        for (;;) {  // passes
+            std::vector<int> order = remaining;
+            if (sort_mode == 0) {
+                std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+                    return n2[a] < n2[b] || (n2[a] == n2[b] && a < b);
+                });
+            } else if (!order.empty()) {
+                std::vector<cmsvd_block> bl;
+                std::vector<double*> out;
+                for (size_t c = 0; c < order.size(); ++c) {
+                    bl.push_back(blocks[order[c]]);
+                    out.push_back(rb.pn + c);
+                }
+                st = resid_proj_norms(h, rb.st, bl, out);
+                if (st != CMSVD_OK) return st;
+                std::vector<double> pn(order.size());
+                HIPCHK(hipMemcpyAsync(pn.data(), rb.pn, order.size() * 8, hipMemcpyDeviceToHost, h->stream));
+                HIPCHK(hipStreamSynchronize(h->stream));
+                std::vector<double> res(N, 0.0);
+                for (size_t c = 0; c < order.size(); ++c) res[order[c]] = n2[order[c]] - pn[c];
+                std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+                    return res[a] < res[b] || (res[a] == res[b] && a < b);
+                });
+            }
+            bool accepted_any = false;
+            size_t pos = 0;
+            while (pos < order.size()) {
+                const std::vector<int> cand(order.begin() + pos, order.end());
+                st = resid_test(h, rb, blocks, cand);
+                if (st != CMSVD_OK) return st;
+                first_feasible(rb.rel, (int)cand.size(), eps, rb.first, h->stream);
+                int idx = 0;
+                HIPCHK(hipMemcpyAsync(&idx, rb.first, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+                HIPCHK(hipStreamSynchronize(h->stream));
+                if (idx >= (int)cand.size()) break;
+                const int jacc = cand[idx];
+                st = resid_accept_block(h, rb.st, blocks[jacc], rb.nrm[jacc], rb.lam + (size_t)idx * rb.nkcap,
+                                        (int)std::min<int64_t>(r, blocks[jacc].cols));
+                if (st != CMSVD_OK) return st;
+                labels[jacc] = ncl;
+                remaining.erase(std::find(remaining.begin(), remaining.end(), jacc));
+                accepted_any = true;
+                pos = pos + idx + 1;
+            }
+            if (!accepted_any) break;
+        }
+        double rel = 0.0;
+        st = resid_state_rel(h, rb, &rel, nullptr);
+        if (st != CMSVD_OK) return st;
+        crel.push_back(rel);
+        ++ncl;
+    }
+    *nclusters = ncl;
+    if (cluster_rel)
+        for (int c = 0; c < ncl; ++c) cluster_rel[c] = crel[c];
+    return CMSVD_OK;
+}
+
+cmsvd_status cmsvd_residual_bound(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r,
+                                  double* bound2, double* mu) {
+    if (!h) return fail(CMSVD_EINVAL, "cmsvd_residual_bound: null handle");
+    if (!bound2) return fail(CMSVD_EINVAL, "cmsvd_residual_bound: null output");
+    if (nblocks > INT32_MAX) return fail(CMSVD_EUNSUPPORTED, "cmsvd_residual_bound: too many blocks");
+    const int N = (int)nblocks;
+    ResidBuffers rb;
+    cmsvd_status st = resid_setup(h, blocks, N, r, "cmsvd_residual_bound", rb);
+    if (st != CMSVD_OK) return st;
+    st = resid_reset(h, rb.st);
+    if (st != CMSVD_OK) return st;
+    for (int j = 0; j < N; ++j) {
+        st = resid_test(h, rb, blocks, {j});
+        if (st != CMSVD_OK) return st;
+        st = resid_accept_block(h, rb.st, blocks[j], rb.nrm[j], rb.lam, (int)std::min<int64_t>(r, blocks[j].cols));
+        if (st != CMSVD_OK) return st;
+    }
+    st = resid_state_rel(h, rb, nullptr, bound2);
+    if (st != CMSVD_OK) return st;
+    if (mu) {
+        std::vector<double> L((size_t)r);
+        HIPCHK(hipMemcpyAsync(L.data(), rb.st.L[rb.st.cur], (size_t)r * 8, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        for (int64_t i = 0; i < r; ++i) mu[i] = std::sqrt(std::max(L[(size_t)i], 0.0));
+    }
     return CMSVD_OK;
 }
 

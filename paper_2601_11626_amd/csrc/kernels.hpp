@@ -163,6 +163,31 @@ struct PackDesc {
 };
 void pack_batched(const PackDesc* d_descs, int count, hipStream_t s);
 
+// Residual-certified clustering (Algorithm 2).  A cluster keeps the r largest squared
+// residual singular values L (non-increasing, zero-padded) and its energy S (hi, lo).
+// Certificate of a candidate with residual-Gram eigenvalues lam (nk, descending):
+//   b^2 = S + nb - (sum of the r largest of L u lam);  err = sqrt(max(0, b^2)),
+//   rel = err / sqrt(S + nb).  nb may be null (the cluster alone).
+struct CertDesc {
+    const double* L;
+    const double* S;
+    const double* nb;
+    const double* lam;
+    int nk;
+    double* rel;
+    double* err;
+};
+void resid_cert_batched(const CertDesc* d_descs, int count, int r, int nkmax, hipStream_t s);
+// Lout = r largest of L u lam (non-increasing), Sout = S + nb; one block, no aliasing.
+void resid_accept(const double* L, int r, const double* lam, int nk, const double* S, const double* nb, double* Lout,
+                  double* Sout, hipStream_t s);
+// Appends the columns of Qr (row-major m x k, ld k) whose pivot survived (Li[c,c] != 0)
+// to Q (row-major, ld ldq) at columns q0, q0 + 1, ... (at most `room`); *count (device)
+// receives the number appended; map holds k ints of scratch.
+void append_kept_columns(const double* Qr, int m, int k, const double* Li, long ldl, double* Q, long ldq, int q0,
+                         int room, int* map, int* count, hipStream_t s);
+void fill_f64(double* x, long n, double v, hipStream_t s);
+
 // Backward of the tail energy.
 void divdiff_scale(double* B, int r, int nk, int d, const double* ev, hipStream_t s);
 void fill_diag(double* A, int rows, int cols, long ld, double v, double dv, hipStream_t s);
