@@ -202,6 +202,150 @@ void run_gemm(const GemmGroup& g, char* dbase, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// Semidefinite Cholesky + restricted inverse for a list of Grams.
+//
+// Many problems: one workgroup each (chol_semidef_batched).  A few large ones (where
+// one workgroup per matrix would leave the chip idle and run the factorisation and
+// the inverse row by row): right-looking by 64-column panels -- the panel's diagonal
+// block is factored by the same kernel (pivot threshold, zeroed columns, inverse on
+// the kept pivots), the panel below becomes A21 Dinv^T and the trailing matrix is
+// updated by A22 -= L21 L21^T, both on the matrix cores; the inverse is then merged
+// bottom-up from the diagonal blocks, inv([[A, 0], [B, C]]) = [[A', 0], [-C' B A', C']]
+// (A', C' the inverses on the kept pivots).  Both orders compute the same factor and
+// the same dropped pivots up to rounding.
+// ---------------------------------------------------------------------------
+struct CholPlan {
+    static constexpr int NB = 64;
+    std::vector<CholDesc> jobs;
+    bool blocked = false;
+    size_t o_desc = 0;
+    struct Panel {
+        std::vector<CholDesc> diag;
+        std::vector<CopyDesc> cp;
+        GemmGroup pan, trail;
+        size_t o_diag = 0, o_cp = 0;
+        int cprows = 0;
+    };
+    std::vector<Panel> panels;
+    struct Level {
+        GemmGroup t, x;
+    };
+    std::vector<Level> levels;
+    std::vector<double*> up;  // matrices whose strict upper triangle is zeroed at the end
+    std::vector<int> upk;
+    std::vector<long> upld;
+
+    static bool use_blocked(const std::vector<int>& ks) {
+        int kmax = 0;
+        for (int k : ks) kmax = std::max(kmax, k);
+        return kmax >= 192 && ks.size() <= 32;
+    }
+    // scratch doubles per problem of order k (blocked path): the panel copy (k x NB)
+    // and the products of the inverse merge (k x k)
+    static size_t scratch_doubles(int k) { return (size_t)k * NB + (size_t)k * k; }
+
+    // `scratch[j]` points at scratch_doubles(k_j) doubles (blocked path only).
+    void build(const std::vector<CholDesc>& js, const std::vector<double*>& scratch) {
+        jobs = js;
+        std::vector<int> ks;
+        for (const auto& c : js) ks.push_back(c.k);
+        blocked = use_blocked(ks);
+        if (!blocked) return;
+        int kmax = 0;
+        for (int k : ks) kmax = std::max(kmax, k);
+        for (int p = 0; p < kmax; p += NB) {
+            Panel P;
+            P.pan.tb = true;
+            P.trail.tb = true;
+            P.trail.alpha = -1.0;
+            P.trail.beta = 1.0;
+            for (size_t j = 0; j < js.size(); ++j) {
+                const CholDesc& c = js[j];
+                if (p >= c.k) continue;
+                const int w = std::min(NB, c.k - p), hgt = c.k - p - w;
+                double* Gpp = c.G + p + (long)p * c.ldg;
+                double* Ipp = c.Linv + p + (long)p * c.ldi;
+                P.diag.push_back(CholDesc{w, Gpp, c.ldg, Ipp, c.ldi, c.thresh_scale, c.thresh_ref, nullptr});
+                if (hgt > 0) {
+                    double* A21 = c.G + (p + w) + (long)p * c.ldg;
+                    double* T = scratch[j];
+                    // column-major hgt x w panel == row-major w x hgt rows of stride ldg
+                    P.cp.push_back(CopyDesc{A21, w, hgt, c.ldg, 0, T, (long)hgt});
+                    P.cprows = std::max(P.cprows, w);
+                    P.pan.push(GemmDesc{T, Ipp, A21, hgt, w, w, (long)hgt, c.ldi, c.ldg});
+                    P.trail.push(GemmDesc{A21, A21, c.G + (p + w) + (long)(p + w) * c.ldg, hgt, hgt, w, c.ldg, c.ldg,
+                                          c.ldg});
+                }
+            }
+            panels.push_back(std::move(P));
+        }
+        for (int s = NB; s < kmax; s *= 2) {
+            Level L;
+            L.x.alpha = -1.0;
+            for (size_t j = 0; j < js.size(); ++j) {
+                const CholDesc& c = js[j];
+                double* T = scratch[j] + (size_t)c.k * NB;
+                size_t toff = 0;
+                for (int i = 0; i + s < c.k; i += 2 * s) {
+                    const int nc = std::min(s, c.k - i - s);
+                    const double* B = c.G + (i + s) + (long)i * c.ldg;         // L[C, A]
+                    const double* XA = c.Linv + i + (long)i * c.ldi;            // A'
+                    const double* XC = c.Linv + (i + s) + (long)(i + s) * c.ldi;  // C'
+                    double* Ti = T + toff;
+                    toff += (size_t)nc * s;
+                    L.t.push(GemmDesc{B, XA, Ti, nc, s, s, c.ldg, c.ldi, (long)nc});
+                    L.x.push(GemmDesc{XC, Ti, c.Linv + (i + s) + (long)i * c.ldi, nc, s, nc, c.ldi, (long)nc, c.ldi});
+                }
+            }
+            levels.push_back(std::move(L));
+        }
+        for (const auto& c : js) {  // the inverse is lower triangular by construction
+            up.push_back(c.G);
+            upk.push_back(c.k);
+            upld.push_back(c.ldg);
+        }
+    }
+
+    void stage(Stage& stg) {
+        if (!blocked) {
+            o_desc = stg.add(jobs);
+            return;
+        }
+        for (auto& P : panels) {
+            P.o_diag = stg.add(P.diag);
+            P.o_cp = stg.add(P.cp);
+            P.pan.off = stg.add(P.pan.d);
+            P.trail.off = stg.add(P.trail.d);
+        }
+        for (auto& L : levels) {
+            L.t.off = stg.add(L.t.d);
+            L.x.off = stg.add(L.x.d);
+        }
+    }
+
+    void run(char* db, hipStream_t s) {
+        if (!blocked) {
+            chol_semidef_batched(reinterpret_cast<const CholDesc*>(db + o_desc), (int)jobs.size(), s);
+            return;
+        }
+        for (const auto& c : jobs) fill_f64(c.Linv, (long)c.ldi * c.k, 0.0, s);
+        for (auto& P : panels) {
+            chol_semidef_batched(reinterpret_cast<const CholDesc*>(db + P.o_diag), (int)P.diag.size(), s);
+            if (!P.cp.empty()) {
+                copy_f64_batched(reinterpret_cast<const CopyDesc*>(db + P.o_cp), (int)P.cp.size(), P.cprows, s);
+                run_gemm(P.pan, db, s);
+                run_gemm(P.trail, db, s);
+            }
+        }
+        for (auto& L : levels) {
+            run_gemm(L.t, db, s);
+            run_gemm(L.x, db, s);
+        }
+        for (size_t i = 0; i < up.size(); ++i) zero_upper(up[i], upk[i], upld[i], s);
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Commit pipeline.
 // ---------------------------------------------------------------------------
 struct CommitJob {
@@ -232,12 +376,15 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
     if (J == 0) return CMSVD_OK;
     Plan pl;
     struct Off {
-        size_t nb, P, P2, Rt, G1, Li1, Q1, G2, Li2, Qr, F, KT, Sp, lam, d, e, V, tau, sum, Z, vs;
+        size_t nb, P, P2, Rt, G1, Li1, Q1, G2, Li2, Qr, F, KT, Sp, lam, d, e, V, tau, sum, Z, vs, cs;
         int k, nc, nkeep, nu;
         bool full;
     };
     std::vector<Off> o(J);
     int nmax = 0;
+    std::vector<int> ks;
+    for (const auto& c : jobs) ks.push_back((int)c.B.cols);
+    const bool chol_blocked = CholPlan::use_blocked(ks);
     for (int j = 0; j < J; ++j) {
         const CommitJob& c = jobs[j];
         const bool full = c.Z_out != nullptr;
@@ -270,6 +417,7 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
         o[j].sum = pl.add(2 * 8);
         o[j].Z = pl.add((size_t)nc * nk * 8);
         o[j].vs = pl.add((size_t)6 * nc * nk * 8);
+        o[j].cs = chol_blocked ? pl.add(CholPlan::scratch_doubles(k) * 8) : 0;
     }
     const int nslots = std::min(J, h->ncu);
     const size_t eig_off = pl.add(sym_eig_workspace_doubles(nmax, nslots) * 8);
@@ -369,8 +517,17 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
         GemmDesc g{c.U, c.B.ptr, D(q.P), c.r_in, q.k, c.m, c.ldu, (long)c.B.ld, (long)c.r_in};
         (c.B.dtype == CMSVD_F32 ? gP32 : gP64).push(g);
     }
+    CholPlan cp1, cp2;
+    {
+        std::vector<double*> scr(J);
+        for (int j = 0; j < J; ++j) scr[j] = D(o[j].cs);
+        cp1.build(ch1, scr);
+        cp2.build(ch2, scr);  // runs after cp1 is done with the scratch
+    }
     Stage stg;
-    size_t o_nd = stg.add(nd), o_cd = stg.add(cd), o_ch1 = stg.add(ch1), o_ch2 = stg.add(ch2);
+    size_t o_nd = stg.add(nd), o_cd = stg.add(cd);
+    cp1.stage(stg);
+    cp2.stage(stg);
     std::vector<FinDesc> fdk;
     for (int j = 0; j < J; ++j)
         if (!o[j].full) fdk.push_back(fd[j]);
@@ -394,10 +551,10 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
     for (int j = 0; j < J; ++j)
         if (jobs[j].r_in > 0) add_f64(D(o[j].P2), D(o[j].P), (long)jobs[j].r_in * o[j].k, s);
     run_gemm(gG1, db, s);
-    chol_semidef_batched(reinterpret_cast<const CholDesc*>(db + o_ch1), J, s);
+    cp1.run(db, s);
     run_gemm(gQ1, db, s);
     run_gemm(gG2, db, s);
-    chol_semidef_batched(reinterpret_cast<const CholDesc*>(db + o_ch2), J, s);
+    cp2.run(db, s);
     run_gemm(gQr, db, s);
     run_gemm(gF, db, s);
     assemble_kt_batched(reinterpret_cast<const KtDesc*>(db + o_kd), J, nmax, s);
@@ -849,7 +1006,8 @@ cmsvd_status resid_accept_block(cmsvd_ctx* h, ResidState& st, const cmsvd_block&
     const size_t oRt = pl.add((size_t)k * m * 8), oP = pl.add((size_t)std::max(q, 1) * k * 8),
                  oP2 = pl.add((size_t)std::max(q, 1) * k * 8), oG1 = pl.add((size_t)k * k * 8),
                  oL1 = pl.add((size_t)k * k * 8), oQ1 = pl.add((size_t)k * m * 8), oG2 = pl.add((size_t)k * k * 8),
-                 oL2 = pl.add((size_t)k * k * 8), oQr = pl.add((size_t)k * m * 8);
+                 oL2 = pl.add((size_t)k * k * 8), oQr = pl.add((size_t)k * m * 8),
+                 oCs = pl.add(CholPlan::scratch_doubles(k) * 8);
     cmsvd_status st_ = ensure(h, h->ws, h->ws_cap, pl.off);
     if (st_ != CMSVD_OK) return st_;
     auto D = [&](size_t off) { return reinterpret_cast<double*>(h->ws + off); };
@@ -877,10 +1035,13 @@ cmsvd_status resid_accept_block(cmsvd_ctx* h, ResidState& st, const cmsvd_block&
     gQ1.push(GemmDesc{D(oL1), D(oRt), D(oQ1), k, m, k, (long)k, (long)k, (long)k});
     gG2.push(GemmDesc{D(oQ1), D(oQ1), D(oG2), k, k, m, (long)k, (long)k, (long)k});
     gQr.push(GemmDesc{D(oL2), D(oQ1), D(oQr), k, m, k, (long)k, (long)k, (long)k});
-    std::vector<CholDesc> ch1{CholDesc{k, D(oG1), (long)k, D(oL1), (long)k, (double)k * EPS, nb, nullptr}};
-    std::vector<CholDesc> ch2{CholDesc{k, D(oG2), (long)k, D(oL2), (long)k, (double)k * k * EPS, nullptr, nullptr}};
+    CholPlan cp1, cp2;
+    cp1.build({CholDesc{k, D(oG1), (long)k, D(oL1), (long)k, (double)k * EPS, nb, nullptr}}, {D(oCs)});
+    cp2.build({CholDesc{k, D(oG2), (long)k, D(oL2), (long)k, (double)k * k * EPS, nullptr, nullptr}}, {D(oCs)});
     Stage stg;
-    const size_t o_cd = stg.add(cd), o_c1 = stg.add(ch1), o_c2 = stg.add(ch2);
+    const size_t o_cd = stg.add(cd);
+    cp1.stage(stg);
+    cp2.stage(stg);
     for (GemmGroup* g : {&gP, &gR1, &gP2, &gR2, &gG1, &gQ1, &gG2, &gQr}) g->off = stg.add(g->d);
     char* db = nullptr;
     st_ = upload(h, stg, &db);
@@ -893,10 +1054,10 @@ cmsvd_status resid_accept_block(cmsvd_ctx* h, ResidState& st, const cmsvd_block&
         run_gemm(gP2, db, s);
         run_gemm(gR2, db, s);
         run_gemm(gG1, db, s);
-        chol_semidef_batched(reinterpret_cast<const CholDesc*>(db + o_c1), 1, s);
+        cp1.run(db, s);
         run_gemm(gQ1, db, s);
         run_gemm(gG2, db, s);
-        chol_semidef_batched(reinterpret_cast<const CholDesc*>(db + o_c2), 1, s);
+        cp2.run(db, s);
         run_gemm(gQr, db, s);
         append_kept_columns(D(oQr), m, k, D(oL2), (long)k, st.Q, (long)st.qcap, q, st.qcap - q, st.map, st.count, s);
     }
@@ -931,6 +1092,7 @@ struct ResidBuffers {
     std::vector<double*> nrm, gram;
     double *lam = nullptr, *rel = nullptr, *err = nullptr, *pn = nullptr;
     int* first = nullptr;
+    int* flags = nullptr;  // nblocks ints
     int nkcap = 1;
     ResidState st;
 };
@@ -964,7 +1126,8 @@ cmsvd_status resid_setup(cmsvd_ctx* h, const cmsvd_block* blocks, int N, int64_t
         o_S[s] = pl.add(16);
     }
     const size_t o_lam = pl.add((size_t)N * rb.nkcap * 8), o_rel = pl.add((size_t)N * 8), o_err = pl.add((size_t)N * 8),
-                 o_pn = pl.add((size_t)N * 8), o_first = pl.add(8), o_cnt = pl.add(8), o_map = pl.add((size_t)kmax * 4);
+                 o_pn = pl.add((size_t)N * 8), o_first = pl.add(8), o_cnt = pl.add(8), o_map = pl.add((size_t)kmax * 4),
+                 o_flags = pl.add((size_t)N * 4);
     if (hipMalloc((void**)&rb.keep.p, pl.off) != hipSuccess) {
         (void)hipGetLastError();
         return fail(CMSVD_ENOMEM, "%s: hipMalloc(%zu) failed", who, pl.off);
@@ -980,6 +1143,7 @@ cmsvd_status resid_setup(cmsvd_ctx* h, const cmsvd_block* blocks, int N, int64_t
     rb.err = K(o_err);
     rb.pn = K(o_pn);
     rb.first = reinterpret_cast<int*>(base + o_first);
+    rb.flags = reinterpret_cast<int*>(base + o_flags);
     rb.st.m = (int)m;
     rb.st.r = (int)r;
     rb.st.qcap = (int)qcap;
@@ -1003,6 +1167,169 @@ cmsvd_status resid_test(cmsvd_ctx* h, ResidBuffers& rb, const cmsvd_block* block
         rc.push_back(ResidCand{blocks[j], rb.nrm[j], rb.gram[j], rb.lam + i * (size_t)rb.nkcap, rb.rel + i, rb.err + i});
     }
     return resid_eval(h, rb.st, rc);
+}
+
+// Scans the candidates `cand` (in order) for the first whose certificate is within
+// eps.  Chunk by chunk: the projections P_c = Q^T B_c and ||P_c||_F^2 settle most
+// candidates without eigenvalues (resid_screen); the certificate proper (residual
+// Gram G - P^T P, its top eigenvalues, the merge with L) is computed only for the
+// unsettled candidates ahead of the first sure acceptance, and for an accepted
+// candidate whose spectrum is still missing.  *first = index of the first feasible
+// candidate (cand.size() if none); its residual spectrum is then in lam slot *first.
+// Synchronises once or twice per chunk.
+cmsvd_status resid_scan(cmsvd_ctx* h, ResidBuffers& rb, const cmsvd_block* blocks, const std::vector<int>& cand,
+                        double eps, int* first) {
+    const ResidState& st = rb.st;
+    const size_t total = cand.size();
+    const int q = st.q, r = st.r;
+    hipStream_t s = h->stream;
+    *first = (int)total;
+    size_t b0 = 0;
+    while (b0 < total) {
+        size_t b1 = b0, bytes = 0;
+        int kmax = 1;
+        while (b1 < total) {
+            const size_t k = (size_t)blocks[cand[b1]].cols;
+            const size_t need = align256((size_t)std::max(q, 1) * k * 8) + align256(k * k * 8);
+            if (b1 > b0 && bytes + need > ((size_t)8 << 30)) break;
+            bytes += need;
+            kmax = std::max(kmax, (int)k);
+            ++b1;
+        }
+        const int nj = (int)(b1 - b0);
+        Plan pl;
+        std::vector<size_t> oP(nj), oG(nj);
+        for (int i = 0; i < nj; ++i) {
+            const size_t k = (size_t)blocks[cand[b0 + i]].cols;
+            oP[i] = pl.add((size_t)std::max(q, 1) * k * 8);
+            oG[i] = pl.add(k * k * 8);
+        }
+        const int nslots = std::min(nj, h->ncu);
+        const size_t eig_off = pl.add(sym_eig_workspace_doubles(kmax, nslots) * 8);
+        cmsvd_status stt = ensure(h, h->ws, h->ws_cap, pl.off);
+        if (stt != CMSVD_OK) return stt;
+        auto D = [&](size_t off) { return reinterpret_cast<double*>(h->ws + off); };
+        // phase 1: projections, their norms, the screen
+        {
+            GemmGroup g32, g64;
+            g32.tb = g64.tb = true;
+            g32.bf32 = true;
+            std::vector<ColNormDesc> cn;
+            std::vector<ScreenDesc> sd(nj);
+            for (int i = 0; i < nj; ++i) {
+                const int j = cand[b0 + i];
+                const cmsvd_block& B = blocks[j];
+                if (q > 0) {
+                    GemmDesc g{st.Q, B.ptr, D(oP[i]), q, (int)B.cols, st.m, (long)st.qcap, (long)B.ld, (long)q};
+                    (B.dtype == CMSVD_F32 ? g32 : g64).push(g);
+                    cn.push_back(ColNormDesc{D(oP[i]), q, (int)B.cols, (long)q, rb.pn + b0 + i});
+                }
+                sd[i] = ScreenDesc{rb.nrm[j], rb.pn + b0 + i, rb.flags + i};
+            }
+            Stage stg;
+            g32.off = stg.add(g32.d);
+            g64.off = stg.add(g64.d);
+            const size_t o_cn = stg.add(cn), o_sd = stg.add(sd);
+            char* db = nullptr;
+            stt = upload(h, stg, &db);
+            if (stt != CMSVD_OK) return stt;
+            if (q > 0) {
+                StageMark mark(h, ST_PROJ);
+                run_gemm(g32, db, s);
+                run_gemm(g64, db, s);
+                colblock_sumsq_batched(reinterpret_cast<const ColNormDesc*>(db + o_cn), (int)cn.size(), s);
+            } else {
+                fill_f64(rb.pn + b0, nj, 0.0, s);
+            }
+            resid_screen(reinterpret_cast<const ScreenDesc*>(db + o_sd), nj, st.L[st.cur], r, st.S[st.cur], eps, s);
+            HIPCHK(hipGetLastError());
+        }
+        std::vector<int> flags(nj);
+        HIPCHK(hipMemcpyAsync(flags.data(), rb.flags, (size_t)nj * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        int sure = nj;
+        for (int i = 0; i < nj; ++i)
+            if (flags[i] == 2) {
+                sure = i;
+                break;
+            }
+        std::vector<int> need;
+        for (int i = 0; i < sure; ++i)
+            if (flags[i] == 1) need.push_back(i);
+        if (need.empty() && sure == nj) {
+            b0 = b1;
+            continue;
+        }
+        if (sure < nj) need.push_back(sure);  // its spectrum is needed for the acceptance
+        // phase 2: the certificate of the unsettled candidates (and of the sure one)
+        {
+            GemmGroup gS;
+            gS.ta = true;
+            gS.alpha = -1.0;
+            gS.beta = 1.0;
+            std::vector<CopyDesc> cd;
+            std::vector<EigDesc> ed;
+            std::vector<CertDesc> ct;
+            int kneed = 1, nkmax = 1;
+            for (size_t u = 0; u < need.size(); ++u) {
+                const int i = need[u], j = cand[b0 + i];
+                const int k = (int)blocks[j].cols, nk = std::min(r, k);
+                kneed = std::max(kneed, k);
+                nkmax = std::max(nkmax, nk);
+                double* lam = rb.lam + (b0 + i) * (size_t)rb.nkcap;
+                const double* Y = rb.gram[j];
+                if (q > 0) {
+                    cd.push_back(CopyDesc{rb.gram[j], k, k, (long)k, 0, D(oG[i]), (long)k});
+                    gS.push(GemmDesc{D(oP[i]), D(oP[i]), D(oG[i]), k, k, q, (long)q, (long)q, (long)k});
+                    Y = D(oG[i]);
+                }
+                EigDesc e{};
+                e.n = k;
+                e.n1 = 0;
+                e.nkeep = nk;
+                e.Y = Y;
+                e.ldy = k;
+                e.lam = lam;
+                ed.push_back(e);
+                ct.push_back(CertDesc{st.L[st.cur], st.S[st.cur], rb.nrm[j], lam, nk, rb.rel + u, rb.err + u});
+            }
+            Stage stg;
+            gS.off = stg.add(gS.d);
+            const size_t o_cd = stg.add(cd), o_ed = stg.add(ed), o_ct = stg.add(ct);
+            char* db = nullptr;
+            stt = upload(h, stg, &db);
+            if (stt != CMSVD_OK) return stt;
+            if (q > 0) {
+                StageMark mark(h, ST_PROJ);
+                copy_f64_batched(reinterpret_cast<const CopyDesc*>(db + o_cd), (int)cd.size(), kneed, s);
+                run_gemm(gS, db, s);
+            }
+            {
+                StageMark mark(h, ST_CORE);
+                sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), (int)ed.size(), kneed, 1, D(eig_off),
+                                std::min((int)ed.size(), nslots), s);
+            }
+            resid_cert_batched(reinterpret_cast<const CertDesc*>(db + o_ct), (int)ct.size(), r, nkmax, s);
+            HIPCHK(hipGetLastError());
+        }
+        const int nun = (int)need.size() - (sure < nj ? 1 : 0);  // unsettled ones, in scan order
+        int idx = nun;
+        if (nun > 0) {
+            first_feasible(rb.rel, nun, eps, rb.first, s);
+            HIPCHK(hipMemcpyAsync(&idx, rb.first, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        if (idx < nun) {
+            *first = (int)b0 + need[idx];
+            return CMSVD_OK;
+        }
+        if (sure < nj) {
+            *first = (int)(b0 + sure);
+            return CMSVD_OK;
+        }
+        b0 = b1;
+    }
+    return CMSVD_OK;
 }
 
 // Certified ratio sqrt(max(0, S - sum L) / S) of the current state (device rel[0]).
@@ -1584,12 +1911,9 @@ cmsvd_status cmsvd_cluster_residual(cmsvd_handle h, const cmsvd_block* blocks, i
             size_t pos = 0;
             while (pos < order.size()) {
                 const std::vector<int> cand(order.begin() + pos, order.end());
-                st = resid_test(h, rb, blocks, cand);
-                if (st != CMSVD_OK) return st;
-                first_feasible(rb.rel, (int)cand.size(), eps, rb.first, h->stream);
                 int idx = 0;
-                HIPCHK(hipMemcpyAsync(&idx, rb.first, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-                HIPCHK(hipStreamSynchronize(h->stream));
+                st = resid_scan(h, rb, blocks, cand, eps, &idx);
+                if (st != CMSVD_OK) return st;
                 if (idx >= (int)cand.size()) break;
                 const int jacc = cand[idx];
                 st = resid_accept_block(h, rb.st, blocks[jacc], rb.nrm[jacc], rb.lam + (size_t)idx * rb.nkcap,

@@ -187,6 +187,16 @@ void resid_accept(const double* L, int r, const double* lam, int nk, const doubl
 void append_kept_columns(const double* Qr, int m, int k, const double* Li, long ldl, double* Q, long ldq, int q0,
                          int room, int* map, int* count, hipStream_t s);
 void fill_f64(double* x, long n, double v, hipStream_t s);
+// Eigenvalue-free settling of candidates: with b_C^2 = S - sum L,
+//   b_C^2 + ||P||^2 <= b^2 <= b_C^2 + ||B||^2;
+// flag = 0 (rejected), 2 (accepted) or 1 (needs the certificate).  pn = ||Q^T B||_F^2.
+struct ScreenDesc {
+    const double* nb;
+    const double* pn;
+    int* flag;
+};
+void resid_screen(const ScreenDesc* d_descs, int count, const double* L, int r, const double* S, double eps,
+                  hipStream_t s);
 
 // Backward of the tail energy.
 void divdiff_scale(double* B, int r, int nk, int d, const double* ev, hipStream_t s);

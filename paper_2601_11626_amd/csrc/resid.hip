@@ -216,6 +216,54 @@ void append_kept_columns(const double* Qr, int m, int k, const double* Li, long 
     hipLaunchKernelGGL(scatter_cols_kernel, dim3(grid), dim3(CT), 0, s, Qr, m, k, map, Q, ldq, q0);
 }
 
+// Settles candidates without their residual spectrum.  With b_C^2 = S - sum L and
+// tr(G_R) = ||B||^2 - ||P||^2, the r largest of L u lam sum to at least sum L and at
+// most sum L + tr(G_R), so b_C^2 + ||P||^2 <= b^2 <= b_C^2 + ||B||^2.  flag = 0 when the
+// lower end exceeds eps^2 (S + ||B||^2) (rejected), 2 when the upper end is below it
+// (accepted), 1 otherwise; a band of 1e-8 (S + ||B||^2) around the threshold, far wider
+// than the rounding of either end, is left to the certificate proper.  One block.
+__global__ void __launch_bounds__(CT) resid_screen_kernel(const ScreenDesc* __restrict__ descs, int count,
+                                                          const double* __restrict__ L, int r,
+                                                          const double* __restrict__ S, double eps2) {
+    __shared__ double red[CT], red2[CT];
+    __shared__ double bc[2];
+    const int t = threadIdx.x;
+    double hi = 0.0, lo = 0.0;
+    for (int i = t; i < r; i += CT) dd_add(hi, lo, L[i]);
+    red[t] = hi;
+    red2[t] = lo;
+    __syncthreads();
+    if (t == 0) {
+        double h = S[0], l = S[1];
+        for (int i = 0; i < CT; ++i) {
+            dd_add(h, l, -red[i]);
+            l -= red2[i];
+        }
+        bc[0] = h;
+        bc[1] = l;
+    }
+    __syncthreads();
+    const double b2c = bc[0] + bc[1];
+    const double s_c = S[0] + S[1];
+    for (int i = t; i < count; i += CT) {
+        const ScreenDesc D = descs[i];
+        const double a = D.nb[0] + D.nb[1];
+        const double tot = s_c + a;
+        const double thr = eps2 * tot, band = 1e-8 * tot;
+        const double lower = b2c + *D.pn, upper = b2c + a;
+        int f = 1;
+        if (lower > thr + band) f = 0;
+        else if (upper < thr - band) f = 2;
+        *D.flag = f;
+    }
+}
+
+void resid_screen(const ScreenDesc* d_descs, int count, const double* L, int r, const double* S, double eps,
+                  hipStream_t s) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(resid_screen_kernel, dim3(1), dim3(CT), 0, s, d_descs, count, L, r, S, eps * eps);
+}
+
 __global__ void fill_f64_kernel(double* __restrict__ x, long n, double v) {
     for (long i = (long)blockIdx.x * CT + threadIdx.x; i < n; i += (long)gridDim.x * CT) x[i] = v;
 }

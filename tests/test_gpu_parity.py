@@ -66,7 +66,8 @@ def test_sym_eigvals_against_oracle_svd(cm, n):
     assert np.max(np.abs(lam - ref)) <= 1e-12 * ref[0] * max(n, 1)
 
 
-@pytest.mark.parametrize("m,k,r", [(64, 32, 8), (100, 37, 10), (50, 5, 8), (40, 60, 12), (96, 64, 64), (257, 70, 33)])
+@pytest.mark.parametrize("m,k,r", [(64, 32, 8), (100, 37, 10), (50, 5, 8), (40, 60, 12), (96, 64, 64), (257, 70, 33),
+                                   (400, 256, 32), (300, 500, 40)])
 def test_update_from_empty_is_truncated_svd(cm, m, k, r):
     say(f"update_from_empty m={m} k={k} r={r}")
     rng = np.random.default_rng(m * 1000 + k)
@@ -96,6 +97,26 @@ def test_update_from_empty_is_truncated_svd(cm, m, k, r):
     d = np.diag(G)
     assert np.all((np.abs(d - 1) < 1e-10) | (d < 1e-20))
     assert np.max(np.abs(G - np.diag(d))) < 1e-10
+
+
+def test_chain_wide_rank_deficient_blocks(cm):
+    # blocks wide enough for the panelled Cholesky (k >= 192), one with repeated columns
+    # and one wider than the free dimension: dropped pivots inside and across panels
+    rng = np.random.default_rng(77)
+    m, r = 420, 64
+    X = rng.standard_normal((m, 150))
+    blocks = [rng.standard_normal((m, 200)), np.concatenate([X, X], axis=1),
+              0.1 * rng.standard_normal((m, 390)) + X[:, :1] @ rng.standard_normal((1, 390))]
+    say("chain wide rank-deficient blocks m=420 k=200,300,390 r=64")
+    est_o, _, states = oracle.chain(blocks, r)
+    st = cm.State(m, r, "cuda")
+    for t, B in enumerate(dev_tensors(blocks)):
+        st = cm.cmsvd_update(st, B, r)
+        torch.cuda.synchronize()
+        nm = math.sqrt(states[t].etot)
+        assert_est(st.est.cpu().numpy()[0], est_o[t], nm, f"step {t}")
+        np.testing.assert_allclose(st.S.cpu().numpy()[: states[t].rho], states[t].sigma, rtol=1e-9,
+                                   atol=1e-12 * states[t].sigma[0])
 
 
 def test_chain_tiny_groups(cm):
