@@ -1093,6 +1093,7 @@ struct ResidBuffers {
     double *lam = nullptr, *rel = nullptr, *err = nullptr, *pn = nullptr;
     int* first = nullptr;
     int* flags = nullptr;  // nblocks ints
+    double* own = nullptr;  // nblocks x nkcap: the largest eigenvalues of each block's own Gram
     int nkcap = 1;
     ResidState st;
 };
@@ -1127,7 +1128,7 @@ cmsvd_status resid_setup(cmsvd_ctx* h, const cmsvd_block* blocks, int N, int64_t
     }
     const size_t o_lam = pl.add((size_t)N * rb.nkcap * 8), o_rel = pl.add((size_t)N * 8), o_err = pl.add((size_t)N * 8),
                  o_pn = pl.add((size_t)N * 8), o_first = pl.add(8), o_cnt = pl.add(8), o_map = pl.add((size_t)kmax * 4),
-                 o_flags = pl.add((size_t)N * 4);
+                 o_flags = pl.add((size_t)N * 4), o_own = pl.add((size_t)N * rb.nkcap * 8);
     if (hipMalloc((void**)&rb.keep.p, pl.off) != hipSuccess) {
         (void)hipGetLastError();
         return fail(CMSVD_ENOMEM, "%s: hipMalloc(%zu) failed", who, pl.off);
@@ -1144,6 +1145,7 @@ cmsvd_status resid_setup(cmsvd_ctx* h, const cmsvd_block* blocks, int N, int64_t
     rb.pn = K(o_pn);
     rb.first = reinterpret_cast<int*>(base + o_first);
     rb.flags = reinterpret_cast<int*>(base + o_flags);
+    rb.own = K(o_own);
     rb.st.m = (int)m;
     rb.st.r = (int)r;
     rb.st.qcap = (int)qcap;
@@ -1155,7 +1157,38 @@ cmsvd_status resid_setup(cmsvd_ctx* h, const cmsvd_block* blocks, int N, int64_t
     rb.st.count = reinterpret_cast<int*>(base + o_cnt);
     rb.st.map = reinterpret_cast<int*>(base + o_map);
     std::vector<cmsvd_block> bl(blocks, blocks + N);
-    return norms_and_grams(h, bl, rb.nrm, rb.gram);
+    cmsvd_status s = norms_and_grams(h, bl, rb.nrm, rb.gram);
+    if (s != CMSVD_OK) return s;
+    // every block's own residual spectrum against an empty basis (the anchor's), in one
+    // batched launch: the top min(r, k) eigenvalues of its Gram
+    const int nslots = std::min(N, h->ncu);
+    Plan pw;
+    const size_t eig_off = pw.add(sym_eig_workspace_doubles((int)kmax, nslots) * 8);
+    s = ensure(h, h->ws, h->ws_cap, pw.off);
+    if (s != CMSVD_OK) return s;
+    std::vector<EigDesc> ed(N);
+    for (int i = 0; i < N; ++i) {
+        EigDesc e{};
+        e.n = (int)blocks[i].cols;
+        e.n1 = 0;
+        e.nkeep = (int)std::min<int64_t>(r, blocks[i].cols);
+        e.Y = rb.gram[i];
+        e.ldy = (long)blocks[i].cols;
+        e.lam = rb.own + (size_t)i * rb.nkcap;
+        ed[i] = e;
+    }
+    Stage stg;
+    const size_t o = stg.add(ed);
+    char* db = nullptr;
+    s = upload(h, stg, &db);
+    if (s != CMSVD_OK) return s;
+    {
+        StageMark mark(h, ST_PREP);
+        sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o), N, (int)kmax, 1,
+                        reinterpret_cast<double*>(h->ws + eig_off), nslots, h->stream);
+    }
+    HIPCHK(hipGetLastError());
+    return CMSVD_OK;
 }
 
 // Tests the candidates `cand` (in order) against the current state; rel[i], lam slot i.
@@ -1877,9 +1910,7 @@ cmsvd_status cmsvd_cluster_residual(cmsvd_handle h, const cmsvd_block* blocks, i
         remaining.erase(remaining.begin());
         st = resid_reset(h, rb.st);
         if (st != CMSVD_OK) return st;
-        st = resid_test(h, rb, blocks, {anchor});
-        if (st != CMSVD_OK) return st;
-        st = resid_accept_block(h, rb.st, blocks[anchor], rb.nrm[anchor], rb.lam,
+        st = resid_accept_block(h, rb.st, blocks[anchor], rb.nrm[anchor], rb.own + (size_t)anchor * rb.nkcap,
                                 (int)std::min<int64_t>(r, blocks[anchor].cols));
         if (st != CMSVD_OK) return st;
         labels[anchor] = ncl;
