@@ -190,11 +190,16 @@ def cluster(args, cm, workloads, torch):
     torch.cuda.synchronize()
     widths = [b.shape[1] for b in blocks_np]
     log(f"generated {len(blocks)} blocks, widths {min(widths)}..{max(widths)} in {time.time() - t0:.1f}s")
+    h = cm.default_handle(dev)
+    h.profile(True)
+    h.profile_read()
     t1 = time.perf_counter()
-    lab, cl, crel = cm.cmsvd_cluster(blocks, r, 0.1, sort_mode="frobenius")
+    lab, cl, crel = cm.cmsvd_cluster(blocks, r, 0.1, sort_mode="frobenius", handle=h)
     torch.cuda.synchronize()
     el = time.perf_counter() - t1
-    log(f"clustered into {len(cl)} clusters in {el:.1f}s")
+    stages = h.profile_read()
+    h.profile(False)
+    log(f"clustered into {len(cl)} clusters in {el:.1f}s; stages {stages}")
     sizes = sorted((len(c) for c in cl), reverse=True)
     parity = None
     if not args.no_cpu:
@@ -228,6 +233,7 @@ def cluster(args, cm, workloads, torch):
         "clusters": len(cl),
         "largest_clusters": sizes[:8],
         "max_cluster_rel": max(crel) if crel else None,
+        "stages_ms_launches": {k: [round(v[0], 1), v[1]] for k, v in stages.items()},
         "parity": parity,
     }
     print(json.dumps(out), flush=True)

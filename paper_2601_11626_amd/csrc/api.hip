@@ -369,6 +369,9 @@ struct CommitJob {
     double* Z_out = nullptr;
     double* lam_out = nullptr;
     double* Qr_out = nullptr;
+    // Optional: the block energy ||B||_F^2 (double-double, device) when the caller has
+    // it already; otherwise the pipeline computes it.
+    const double* nb_in = nullptr;
 };
 
 cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
@@ -434,7 +437,8 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
     }
 
     // descriptor tables
-    std::vector<NormDesc> nd(J);
+    std::vector<NormDesc> nd;
+    std::vector<const double*> pnb(J);
     std::vector<CopyDesc> cd(J);
     GemmGroup gP, gR1, gP2, gR2, gG1, gQ1, gG2, gQr, gF, gS, gU1, gU2a, gU2b;
     gP.tb = true;                        // P = Ut * Bt^T
@@ -462,7 +466,12 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
         (f32 ? f32jobs : f64jobs).push_back(j);
         anyf32 |= f32;
         anyf64 |= !f32;
-        nd[j] = NormDesc{c.B.ptr, m, k, (long)c.B.ld, f32 ? 1 : 0, D(q.nb)};
+        if (c.nb_in) {
+            pnb[j] = c.nb_in;
+        } else {
+            pnb[j] = D(q.nb);
+            nd.push_back(NormDesc{c.B.ptr, m, k, (long)c.B.ld, f32 ? 1 : 0, D(q.nb)});
+        }
         cd[j] = CopyDesc{c.B.ptr, m, k, (long)c.B.ld, f32 ? 1 : 0, D(q.Rt), (long)k};
         if (c.r_in > 0) {
             gR1.push(GemmDesc{D(q.P), c.U, D(q.Rt), k, m, c.r_in, (long)c.r_in, c.ldu, (long)k});
@@ -470,7 +479,7 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
             gR2.push(GemmDesc{D(q.P2), c.U, D(q.Rt), k, m, c.r_in, (long)c.r_in, c.ldu, (long)k});
         }
         gG1.push(GemmDesc{D(q.Rt), D(q.Rt), D(q.G1), k, k, m, (long)k, (long)k, (long)k});
-        ch1[j] = CholDesc{k, D(q.G1), (long)k, D(q.Li1), (long)k, (double)k * EPS, D(q.nb), nullptr};
+        ch1[j] = CholDesc{k, D(q.G1), (long)k, D(q.Li1), (long)k, (double)k * EPS, pnb[j], nullptr};
         gQ1.push(GemmDesc{D(q.Li1), D(q.Rt), D(q.Q1), k, m, k, (long)k, (long)k, (long)k});
         gG2.push(GemmDesc{D(q.Q1), D(q.Q1), D(q.G2), k, k, m, (long)k, (long)k, (long)k});
         ch2[j] = CholDesc{k, D(q.G2), (long)k, D(q.Li2), (long)k, (double)k * k * EPS, nullptr, nullptr};
@@ -504,7 +513,7 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
                 gU2b.push(GemmDesc{pZ[j], pQr[j], c.U_out, q.nu, m, k, (long)nc, (long)k, c.ldu_out});
             }
         }
-        fd[j] = FinDesc{c.r_in, c.r, q.nkeep, m, nc, c.S, pLam[j], D(q.sum), D(q.nb), c.S_out, c.U_out,
+        fd[j] = FinDesc{c.r_in, c.r, q.nkeep, m, nc, c.S, pLam[j], D(q.sum), pnb[j], c.S_out, c.U_out,
                         c.ldu_out, c.acc, c.est};
     }
     // P = Ut * Bt^T needs the block dtype: one group per dtype
@@ -541,7 +550,7 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
     hipStream_t s = h->stream;
     int maxrows = 0;
     for (const auto& c : jobs) maxrows = std::max(maxrows, c.m);
-    sumsq_batched(reinterpret_cast<const NormDesc*>(db + o_nd), J, s);
+    sumsq_batched(reinterpret_cast<const NormDesc*>(db + o_nd), (int)nd.size(), s);
     run_gemm(gP32, db, s);
     run_gemm(gP64, db, s);
     copy_f64_batched(reinterpret_cast<const CopyDesc*>(db + o_cd), J, maxrows, s);
@@ -1796,9 +1805,10 @@ cmsvd_status cmsvd_cluster(cmsvd_handle h, const cmsvd_block* blocks, int64_t nb
         remaining.erase(remaining.begin());
         int cur = 0;
         HIPCHK(hipMemsetAsync(K(o_acc[cur]), 0, 32, h->stream));
-        cmsvd_status st = commit_batched(
-            h, {CommitJob{(int)m, nullptr, (long)r, nullptr, 0, blocks[anchor], (int)r, K(o_U[cur]), (long)r, K(o_S[cur]),
-                          K(o_acc[cur]), K(o_est)}});
+        CommitJob aj{(int)m, nullptr, (long)r, nullptr, 0, blocks[anchor], (int)r, K(o_U[cur]), (long)r, K(o_S[cur]),
+                     K(o_acc[cur]), K(o_est)};
+        aj.nb_in = K(o_n[anchor]);
+        cmsvd_status st = commit_batched(h, {aj});
         if (st != CMSVD_OK) return st;
         labels[anchor] = ncl;
         for (;;) {  // passes
@@ -1837,9 +1847,15 @@ cmsvd_status cmsvd_cluster(cmsvd_handle h, const cmsvd_block* blocks, int64_t nb
             }
             bool accepted_any = false;
             size_t pos = 0;
+            // The scan only needs the first feasible candidate: evaluate the suffix in
+            // chunks (a quarter of the compute units first, doubling while nothing in
+            // the chunk is feasible) instead of all of it after every acceptance.
+            const size_t chunk0 = (size_t)std::max(16, h->ncu / 4);
+            size_t chunk = chunk0;
             while (pos < order.size()) {
+                const size_t end = std::min(order.size(), pos + chunk);
                 std::vector<EvalJob> ej;
-                for (size_t c = pos; c < order.size(); ++c) {
+                for (size_t c = pos; c < end; ++c) {
                     const int j = order[c];
                     ej.push_back(EvalJob{K(o_U[cur]), (long)r, K(o_S[cur]), (int)r, K(o_acc[cur]), blocks[j], K(o_n[j]),
                                          K(o_g[j]), K(o_err) + (c - pos), K(o_rel) + (c - pos)});
@@ -1850,12 +1866,19 @@ cmsvd_status cmsvd_cluster(cmsvd_handle h, const cmsvd_block* blocks, int64_t nb
                 int idx = 0;
                 HIPCHK(hipMemcpyAsync(&idx, K(o_first), sizeof(int), hipMemcpyDeviceToHost, h->stream));
                 HIPCHK(hipStreamSynchronize(h->stream));
-                if (idx >= (int)ej.size()) break;
+                if (idx >= (int)ej.size()) {
+                    pos = end;
+                    chunk *= 2;
+                    continue;
+                }
+                chunk = chunk0;
                 const int jacc = order[pos + idx];
                 const int nxt = 1 - cur;
                 HIPCHK(hipMemcpyAsync(K(o_acc[nxt]), K(o_acc[cur]), 32, hipMemcpyDeviceToDevice, h->stream));
-                st = commit_batched(h, {CommitJob{(int)m, K(o_U[cur]), (long)r, K(o_S[cur]), (int)r, blocks[jacc], (int)r,
-                                                  K(o_U[nxt]), (long)r, K(o_S[nxt]), K(o_acc[nxt]), K(o_est)}});
+                CommitJob cj{(int)m, K(o_U[cur]), (long)r, K(o_S[cur]), (int)r, blocks[jacc], (int)r,
+                             K(o_U[nxt]), (long)r, K(o_S[nxt]), K(o_acc[nxt]), K(o_est)};
+                cj.nb_in = K(o_n[jacc]);
+                st = commit_batched(h, {cj});
                 if (st != CMSVD_OK) return st;
                 cur = nxt;
                 labels[jacc] = ncl;
