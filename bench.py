@@ -308,6 +308,93 @@ def cluster_residual(args, cm, workloads, torch):
     print(json.dumps(out), flush=True)
 
 
+def slack(args, cm, workloads, torch):
+    """Estimator conservativeness (the paper's slack diagnostic): for cluster sizes
+    2 .. 64 and 10 uniform block samples each, the explicit rank-r error E_r of the
+    concatenation and the three estimates -- max-norm (Theorem 1), residual
+    (Corollary 1) and approximate incremental (Corollary 2) -- with the blocks in the
+    clustering order (largest norm first, then increasing norm).  Slack = estimate - E_r,
+    both divided by ||M||_F.  Data: a 256-block pool drawn with the Table-1-like recipe
+    of the chosen preset.  A few samples are re-computed by the FP64 oracle."""
+    nb, m, k, r = SMALLK[args.preset]
+    pool = min(nb, 256)
+    t0 = time.time()
+    blocks_np = workloads.table1_like(seed=0, nblocks=pool, m=m, k=k)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    blocks = [torch.from_numpy(b).to(dev) for b in blocks_np]
+    n2 = [float(np.sum(b.astype(np.float64) ** 2)) for b in blocks_np]
+    torch.cuda.synchronize()
+    log(f"generated a pool of {pool} blocks {m}x{k} in {time.time() - t0:.1f}s")
+    rng = np.random.default_rng(5)
+    sizes = [2, 4, 8, 16, 32, 64]
+    rows = []
+    t1 = time.perf_counter()
+    for size in sizes:
+        for trial in range(10):
+            pick = [int(i) for i in rng.choice(pool, size=size, replace=False)]
+            first = max(pick, key=lambda i: (n2[i], -i))
+            order = [first] + sorted((i for i in pick if i != first), key=lambda i: (n2[i], i))
+            sub = [blocks[i] for i in order]
+            tot = math.sqrt(sum(n2[i] for i in order))
+            exact = math.sqrt(cm.cmsvd_exact_tail(sub, r))
+            weyl = math.sqrt(cm.cmsvd_weyl_bound(sub, r))
+            resid = math.sqrt(cm.cmsvd_residual_bound(sub, r)[0])
+            st = cm.State(m, r, dev)
+            for b in sub:
+                st = cm.cmsvd_update(st, b, r)
+            approx = float(st.est[0].item())
+            rows.append({"size": size, "trial": trial, "order": order, "E": exact / tot, "max_norm": weyl / tot,
+                         "residual": resid / tot, "approx": approx / tot})
+        log(f"size {size} done")
+    el = time.perf_counter() - t1
+    summary = {}
+    for size in sizes:
+        sel = [x for x in rows if x["size"] == size]
+        summary[str(size)] = {est: {"min": min(x[est] - x["E"] for x in sel), "median": float(np.median([x[est] - x["E"] for x in sel])),
+                                    "max": max(x[est] - x["E"] for x in sel)} for est in ("max_norm", "residual", "approx")}
+    parity = None
+    if not args.no_cpu:
+        import oracle
+        from oracle import alg1, alg2
+
+        worst = 0.0
+        tc = time.perf_counter()
+        checked = 0
+        for x in rows:
+            if x["size"] > 16 or x["trial"] != 0:
+                continue
+            sub = [blocks_np[i].astype(np.float64) for i in x["order"]]
+            tot = math.sqrt(sum(n2[i] for i in x["order"]))
+            M = np.concatenate(sub, axis=1)
+            sv = np.linalg.svd(M, compute_uv=False)
+            ref = {"E": math.sqrt(math.fsum((sv[r:] ** 2).tolist())) / tot,
+                   "max_norm": math.sqrt(alg1.bound2(sub, r)) / tot,
+                   "residual": math.sqrt(alg2.chain_bound2(sub, r)[0]) / tot,
+                   "approx": float(oracle.chain_c(sub, r)[0][-1]) / tot}
+            for key, v in ref.items():
+                worst = max(worst, abs(x[key] - v) / max(v, 1e-6))
+            checked += 1
+        parity = {"samples": checked, "max_rel_dev": worst, "seconds": round(time.perf_counter() - tc, 1)}
+        log(f"parity {parity}")
+    neg = {est: sum(1 for x in rows if x[est] - x["E"] < -1e-9) for est in ("max_norm", "residual", "approx")}
+    out = {
+        "metric": "estimator slack (estimate - E_r) / ||M||_F, 10 trials per cluster size",
+        "value": round(el, 3),
+        "unit": "s",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"table1_like/{args.preset} pool of {pool} FP32 blocks {m}x{k}, r={r}, "
+                               f"cluster sizes {sizes}, clustering order", "r": r},
+        "slack": summary,
+        "negative_slack_count": neg,
+        "parity": parity,
+    }
+    print(json.dumps(out), flush=True)
+
+
 SMALLK = {  # name: (blocks, m, k, r) -- the shapes of the paper's collections
     "qualcomm": (2468, 12800, 20, 20),
     "bigearthnet": (10000, 1440, 20, 20),
@@ -456,7 +543,7 @@ def main():
                     help="cluster_residual: candidate order of a pass")
     ap.add_argument("--cpu-chains", type=int, default=6, help="cluster_residual: oracle sample (narrow pairs)")
     ap.add_argument("--workload", default="pairs",
-                    choices=("pairs", "chain_grad", "cluster", "cluster_residual", "smallk", "weights"),
+                    choices=("pairs", "chain_grad", "cluster", "cluster_residual", "smallk", "weights", "slack"),
                     help="pairs: batched merge errors (the default line); chain_grad: tail energy and "
                          "its gradient along a 64-block chain")
     args = ap.parse_args()
@@ -496,6 +583,8 @@ def main():
         return cluster_residual(args, cm, workloads, torch)
     if args.workload == "smallk":
         return smallk(args, cm, workloads, torch)
+    if args.workload == "slack":
+        return slack(args, cm, workloads, torch)
     if args.workload == "weights":
         return weights(args, cm, workloads, torch)
 

@@ -9,7 +9,8 @@
  * error of Corollary 2, for single updates, for all requested candidate pairs, and
  * inside the greedy error-constrained clustering of Algorithm 3 (Appendix E); and
  * the residual certificate of Theorem 2 / Corollary 1 with the clustering of
- * Algorithm 2.
+ * Algorithm 2, and the Weyl-type certificate of Theorem 1 with the clustering of
+ * Algorithm 1.
  *
  * Conventions shared by every call
  *   - Blocks A_i are real m x n_i matrices with a common row count m (Problem
@@ -166,6 +167,39 @@ cmsvd_status cmsvd_cluster_residual(cmsvd_handle handle, const cmsvd_block* bloc
    Synchronous. */
 cmsvd_status cmsvd_residual_bound(cmsvd_handle handle, const cmsvd_block* blocks, int64_t nblocks, int64_t r,
                                   double* bound2, double* mu);
+
+/* Theorem 1 (Weyl-type bound) for a set of blocks: bound2 = S - max_j h_j, clamped at
+   0, where S = sum_j ||A_j||_F^2 and h_j = sum_{l<=r} sigma_l(A_j)^2 is block j's
+   r-head energy (its whole energy when it has at most r columns, else the sum of the r
+   largest eigenvalues of its Gram A_j^T A_j).  An upper bound on the optimal rank-r
+   error squared of the concatenation, for every r >= 1.
+     bound2   HOST out
+   Blocks wider than r may have at most 8192 columns.  Synchronous. */
+cmsvd_status cmsvd_weyl_bound(cmsvd_handle handle, const cmsvd_block* blocks, int64_t nblocks, int64_t r,
+                              double* bound2);
+
+/* Algorithm 1 (Weyl-based max-norm clustering, Appendix E) with the certificate of
+   Theorem 1: a cluster C keeps S_C and m_C = max_{j in C} h_j (h_j as in
+   cmsvd_weyl_bound; when r covers every block's rank this is the largest block
+   energy of the algorithm's step list); a candidate joins iff
+   sqrt(max(0, S_C + ||A_j||^2 - max(m_C, h_j))) / sqrt(S_C + ||A_j||^2) <= eps.
+   Anchor = largest remaining block by Frobenius norm; a pass scans the remaining
+   blocks by increasing Frobenius norm (ties: lower index) and updates the state at
+   each acceptance; passes repeat until one accepts nothing.
+     labels, nclusters   as cmsvd_cluster
+     cluster_rel  HOST nblocks FP64 (may be NULL): the certified ratio of each cluster
+   Synchronous. */
+cmsvd_status cmsvd_cluster_weyl(cmsvd_handle handle, const cmsvd_block* blocks, int64_t nblocks, int64_t r,
+                                double eps, int32_t* labels, int64_t* nclusters, double* cluster_rel);
+
+/* The optimal rank-r error squared of the concatenation, sum_{l>r} sigma_l^2 (Problem
+   Formulation; Eckart-Young), from the eigenvalues of its explicit Gram (M^T M or
+   M M^T, whichever is smaller): the reference value of the slack diagnostics.
+   min(m, sum_j n_j) may be at most 8192.  The workspace holds M in FP64.
+     tail2    HOST out, clamped at 0
+   Synchronous. */
+cmsvd_status cmsvd_exact_tail(cmsvd_handle handle, const cmsvd_block* blocks, int64_t nblocks, int64_t r,
+                              double* tail2);
 
 /* Tail energy of a chain and its gradient with respect to every block.
    The chain folds the blocks in order (the incremental state of Lemma 1 and

@@ -52,11 +52,15 @@ def _load():
     lib.cmsvd_update_batch.argtypes = [vp, i64, i64, vp, i64, vp, i64, ctypes.POINTER(Block), i64, vp, i64, vp, vp, vp]
     lib.cmsvd_cluster_residual.argtypes = [vp, ctypes.POINTER(Block), i64, i64, d, i32, vp, ctypes.POINTER(i64), vp]
     lib.cmsvd_residual_bound.argtypes = [vp, ctypes.POINTER(Block), i64, i64, ctypes.POINTER(d), vp]
+    lib.cmsvd_weyl_bound.argtypes = [vp, ctypes.POINTER(Block), i64, i64, ctypes.POINTER(d)]
+    lib.cmsvd_cluster_weyl.argtypes = [vp, ctypes.POINTER(Block), i64, i64, d, vp, ctypes.POINTER(i64), vp]
+    lib.cmsvd_exact_tail.argtypes = [vp, ctypes.POINTER(Block), i64, i64, ctypes.POINTER(d)]
     lib.cmsvd_tail_energy_grad.argtypes = [vp, ctypes.POINTER(Block), i64, i64, i64, ctypes.POINTER(d), vp,
                                            ctypes.POINTER(d)]
     for f in ("cmsvd_create", "cmsvd_destroy", "cmsvd_set_stream", "cmsvd_update", "cmsvd_merge_errors",
               "cmsvd_cluster", "cmsvd_sym_eigvals", "cmsvd_gemm_f64", "cmsvd_profile", "cmsvd_profile_read",
-              "cmsvd_tail_energy_grad", "cmsvd_update_batch", "cmsvd_cluster_residual", "cmsvd_residual_bound"):
+              "cmsvd_tail_energy_grad", "cmsvd_update_batch", "cmsvd_cluster_residual", "cmsvd_residual_bound",
+              "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -66,7 +70,7 @@ _lib = _load()
 EXPORTS = ("cmsvd_create", "cmsvd_destroy", "cmsvd_set_stream", "cmsvd_last_error", "cmsvd_update",
            "cmsvd_merge_errors", "cmsvd_cluster", "cmsvd_sym_eigvals", "cmsvd_gemm_f64", "cmsvd_profile",
            "cmsvd_profile_read", "cmsvd_tail_energy_grad", "cmsvd_update_batch", "cmsvd_cluster_residual",
-           "cmsvd_residual_bound")
+           "cmsvd_residual_bound", "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail")
 
 STAGES = ("norms_grams", "commit", "projection", "core_eig")
 
@@ -283,6 +287,37 @@ def cmsvd_residual_bound(blocks: Sequence[torch.Tensor], r: int, handle: Handle 
     return b2.value, list(mu)
 
 
+def cmsvd_weyl_bound(blocks: Sequence[torch.Tensor], r: int, handle: Handle | None = None) -> float:
+    """Theorem 1: S - max_j (r-head energy of A_j), clamped at 0."""
+    h = handle or default_handle(blocks[0].device)
+    out = ctypes.c_double(0.0)
+    _check(_lib.cmsvd_weyl_bound(h.ptr, _blocks(blocks), len(blocks), r, ctypes.byref(out)))
+    return out.value
+
+
+def cmsvd_cluster_weyl(blocks: Sequence[torch.Tensor], r: int, eps: float, handle: Handle | None = None):
+    """Algorithm 1 on the device.  Returns (labels list, clusters list, certified ratio list)."""
+    h = handle or default_handle(blocks[0].device)
+    n = len(blocks)
+    labels = (ctypes.c_int32 * n)()
+    ncl = ctypes.c_int64(0)
+    crel = (ctypes.c_double * n)()
+    _check(_lib.cmsvd_cluster_weyl(h.ptr, _blocks(blocks), n, r, float(eps), labels, ctypes.byref(ncl), crel))
+    lab = list(labels)
+    clusters = [[] for _ in range(ncl.value)]
+    for i, c in enumerate(lab):
+        clusters[c].append(i)
+    return lab, clusters, list(crel)[: ncl.value]
+
+
+def cmsvd_exact_tail(blocks: Sequence[torch.Tensor], r: int, handle: Handle | None = None) -> float:
+    """sum_{l>r} sigma_l^2 of the concatenation, from its explicit Gram."""
+    h = handle or default_handle(blocks[0].device)
+    out = ctypes.c_double(0.0)
+    _check(_lib.cmsvd_exact_tail(h.ptr, _blocks(blocks), len(blocks), r, ctypes.byref(out)))
+    return out.value
+
+
 def cmsvd_tail_energy_grad(blocks: Sequence[torch.Tensor], r: int, checkpoint: int | None = None,
                            want_grad: bool = True, handle: Handle | None = None):
     """Tail energy f = E~_r^2 of the chain ``blocks`` (in order) and, if ``want_grad``,
@@ -380,5 +415,5 @@ def cmsvd_gemm_f64(opA: torch.Tensor, opB: torch.Tensor, C: torch.Tensor | None 
 
 __all__ = ["cmsvd_gemm_f64", "Handle", "State", "Block", "CmsvdError", "cmsvd_update", "cmsvd_update_batch",
            "cmsvd_merge_errors", "cmsvd_cluster", "cmsvd_cluster_residual", "cmsvd_residual_bound",
-           "cmsvd_sym_eigvals", "cmsvd_tail_energy_grad", "TailEnergy", "tail_energy", "default_handle",
+           "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail", "cmsvd_sym_eigvals", "cmsvd_tail_energy_grad", "TailEnergy", "tail_energy", "default_handle",
            "LIB_PATH", "EXPORTS"]

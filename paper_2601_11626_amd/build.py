@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcmsvd.so")
-SOURCES = ["api.hip", "gemm.hip", "eig.hip", "chol.hip", "misc.hip", "resid.hip"]
+SOURCES = ["api.hip", "gemm.hip", "eig.hip", "chol.hip", "misc.hip", "resid.hip", "weyl.hip"]
 
 
 def build(verbose: bool = False) -> str:

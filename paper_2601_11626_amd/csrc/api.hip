@@ -1393,6 +1393,93 @@ cmsvd_status resid_state_rel(cmsvd_ctx* h, ResidBuffers& rb, double* rel_host, d
     return CMSVD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Theorem 1 (Weyl-based certificate), Algorithm 1, and the explicit tail.
+// ---------------------------------------------------------------------------
+struct WeylBuffers {
+    DevBuf keep;
+    double* a2 = nullptr;     // nblocks x 2: block energies (double-double)
+    double* h = nullptr;      // nblocks: r-head energies
+    double* state = nullptr;  // S hi, S lo, m
+    double* rel = nullptr;
+    int* first = nullptr;
+};
+
+cmsvd_status weyl_setup(cmsvd_ctx* h, const cmsvd_block* blocks, int N, int64_t r, const char* who, WeylBuffers& wb) {
+    if (N < 1 || !blocks) return fail(CMSVD_EINVAL, "%s: no blocks", who);
+    const int64_t m = blocks[0].rows;
+    if (m < 1) return fail(CMSVD_ESHAPE, "%s: m < 1", who);
+    if (r < 1) return fail(CMSVD_ESHAPE, "%s: need r >= 1", who);
+    int kmax = 0;
+    for (int i = 0; i < N; ++i) {
+        cmsvd_status s = check_block(blocks[i], m, "block", i);
+        if (s != CMSVD_OK) return s;
+        if (blocks[i].cols > r && blocks[i].cols > 8192)
+            return fail(CMSVD_EUNSUPPORTED, "%s: block %d has more than 8192 columns", who, i);
+        if (blocks[i].cols > r) kmax = std::max(kmax, (int)blocks[i].cols);
+    }
+    Plan pl;
+    const size_t o_a2 = pl.add((size_t)N * 16), o_top = pl.add((size_t)N * 16), o_h = pl.add((size_t)N * 8),
+                 o_st = pl.add(24), o_rel = pl.add(8), o_first = pl.add(8);
+    if (hipMalloc((void**)&wb.keep.p, pl.off) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CMSVD_ENOMEM, "%s: hipMalloc(%zu) failed", who, pl.off);
+    }
+    char* base = wb.keep.p;
+    wb.a2 = reinterpret_cast<double*>(base + o_a2);
+    double* top = reinterpret_cast<double*>(base + o_top);
+    wb.h = reinterpret_cast<double*>(base + o_h);
+    wb.state = reinterpret_cast<double*>(base + o_st);
+    wb.rel = reinterpret_cast<double*>(base + o_rel);
+    wb.first = reinterpret_cast<int*>(base + o_first);
+    // energies; Grams and head energies of the blocks wider than r
+    std::vector<int> wide;
+    for (int i = 0; i < N; ++i)
+        if (blocks[i].cols > r) wide.push_back(i);
+    Plan pw;
+    std::vector<size_t> og(wide.size());
+    for (size_t w = 0; w < wide.size(); ++w) og[w] = pw.add((size_t)blocks[wide[w]].cols * blocks[wide[w]].cols * 8);
+    const size_t o_lam = pw.add(wide.size() * (size_t)r * 8);  // the eigenvalues themselves (unused)
+    const int nslots = std::max(1, std::min((int)wide.size(), h->ncu));
+    const size_t eig_off = pw.add(sym_eig_workspace_doubles(std::max(kmax, 1), nslots) * 8);
+    cmsvd_status s = ensure(h, h->ws, h->ws_cap, pw.off);
+    if (s != CMSVD_OK) return s;
+    std::vector<cmsvd_block> bl(blocks, blocks + N);
+    std::vector<double*> nrm(N), gram(N, nullptr);
+    for (int i = 0; i < N; ++i) nrm[i] = wb.a2 + 2 * i;
+    for (size_t w = 0; w < wide.size(); ++w) gram[wide[w]] = reinterpret_cast<double*>(h->ws + og[w]);
+    s = norms_and_grams(h, bl, nrm, gram);
+    if (s != CMSVD_OK) return s;
+    std::vector<EigDesc> ed;
+    for (size_t w = 0; w < wide.size(); ++w) {
+        const int i = wide[w], k = (int)blocks[i].cols;
+        EigDesc e{};
+        e.n = k;
+        e.n1 = 0;
+        e.nkeep = (int)r;
+        e.Y = gram[i];
+        e.ldy = k;
+        e.lam = reinterpret_cast<double*>(h->ws + o_lam) + w * (size_t)r;
+        e.sum_top = top + 2 * i;
+        ed.push_back(e);
+    }
+    std::vector<int> cols(N);
+    for (int i = 0; i < N; ++i) cols[i] = (int)blocks[i].cols;
+    Stage stg;
+    const size_t o_ed = stg.add(ed), o_cols = stg.add(cols);
+    char* db = nullptr;
+    s = upload(h, stg, &db);
+    if (s != CMSVD_OK) return s;
+    if (!ed.empty()) {
+        StageMark mark(h, ST_PREP);
+        sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), (int)ed.size(), kmax, 1,
+                        reinterpret_cast<double*>(h->ws + eig_off), nslots, h->stream);
+    }
+    weyl_heads(wb.a2, top, reinterpret_cast<const int*>(db + o_cols), (int)r, N, wb.h, h->stream);
+    HIPCHK(hipGetLastError());
+    return CMSVD_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -2017,6 +2104,164 @@ cmsvd_status cmsvd_residual_bound(cmsvd_handle h, const cmsvd_block* blocks, int
         HIPCHK(hipStreamSynchronize(h->stream));
         for (int64_t i = 0; i < r; ++i) mu[i] = std::sqrt(std::max(L[(size_t)i], 0.0));
     }
+    return CMSVD_OK;
+}
+
+
+/* Theorem 1, Algorithm 1 and the explicit tail; see include/cmsvd.h. */
+cmsvd_status cmsvd_weyl_bound(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double* bound2) {
+    if (!h) return fail(CMSVD_EINVAL, "cmsvd_weyl_bound: null handle");
+    if (!bound2) return fail(CMSVD_EINVAL, "cmsvd_weyl_bound: null output");
+    if (nblocks > INT32_MAX) return fail(CMSVD_EUNSUPPORTED, "cmsvd_weyl_bound: too many blocks");
+    WeylBuffers wb;
+    cmsvd_status st = weyl_setup(h, blocks, (int)nblocks, r, "cmsvd_weyl_bound", wb);
+    if (st != CMSVD_OK) return st;
+    weyl_bound(wb.a2, wb.h, (int)nblocks, wb.rel, h->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(bound2, wb.rel, 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return CMSVD_OK;
+}
+
+cmsvd_status cmsvd_cluster_weyl(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double eps,
+                                int32_t* labels, int64_t* nclusters, double* cluster_rel) {
+    if (!h) return fail(CMSVD_EINVAL, "cmsvd_cluster_weyl: null handle");
+    if (!labels || !nclusters) return fail(CMSVD_EINVAL, "cmsvd_cluster_weyl: null output");
+    if (!(eps >= 0.0)) return fail(CMSVD_EINVAL, "cmsvd_cluster_weyl: eps must be >= 0");
+    if (nblocks > INT32_MAX) return fail(CMSVD_EUNSUPPORTED, "cmsvd_cluster_weyl: too many blocks");
+    const int N = (int)nblocks;
+    WeylBuffers wb;
+    cmsvd_status st = weyl_setup(h, blocks, N, r, "cmsvd_cluster_weyl", wb);
+    if (st != CMSVD_OK) return st;
+    std::vector<double> a2h(2 * (size_t)N);
+    HIPCHK(hipMemcpyAsync(a2h.data(), wb.a2, (size_t)N * 16, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    std::vector<double> n2(N);
+    for (int i = 0; i < N; ++i) n2[i] = a2h[2 * i] + a2h[2 * i + 1];
+    std::vector<int> remaining(N);
+    for (int i = 0; i < N; ++i) remaining[i] = i;
+    std::stable_sort(remaining.begin(), remaining.end(), [&](int a, int b) { return n2[a] > n2[b]; });
+    for (int i = 0; i < N; ++i) labels[i] = -1;
+    int ncl = 0;
+    std::vector<double> crel;
+    while (!remaining.empty()) {
+        const int anchor = remaining.front();
+        remaining.erase(remaining.begin());
+        labels[anchor] = ncl;
+        int init = anchor, acc = -1;
+        for (;;) {  // passes
+            std::vector<int> order = remaining;
+            std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+                return n2[a] < n2[b] || (n2[a] == n2[b] && a < b);
+            });
+            if (order.empty()) break;
+            Stage stg;
+            const size_t o_c = stg.add(order);
+            char* db = nullptr;
+            st = upload(h, stg, &db);
+            if (st != CMSVD_OK) return st;
+            const int* cand = reinterpret_cast<const int*>(db + o_c);
+            bool accepted_any = false;
+            size_t pos = 0;
+            while (pos < order.size()) {
+                const int cnt = (int)(order.size() - pos);
+                weyl_step(cand + pos, cnt, init, acc, wb.a2, wb.h, wb.state, eps, wb.first, wb.rel, h->stream);
+                HIPCHK(hipGetLastError());
+                init = acc = -1;
+                int idx = 0;
+                HIPCHK(hipMemcpyAsync(&idx, wb.first, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+                HIPCHK(hipStreamSynchronize(h->stream));
+                if (idx >= cnt) break;
+                const int j = order[pos + idx];
+                labels[j] = ncl;
+                remaining.erase(std::find(remaining.begin(), remaining.end(), j));
+                acc = j;
+                accepted_any = true;
+                pos += idx + 1;
+            }
+            if (!accepted_any) break;
+        }
+        // apply a pending state change and read the cluster's ratio
+        weyl_step(wb.first /* unused with count 0 */, 0, init, acc, wb.a2, wb.h, wb.state, eps, wb.first, wb.rel,
+                  h->stream);
+        HIPCHK(hipGetLastError());
+        double rel = 0.0;
+        HIPCHK(hipMemcpyAsync(&rel, wb.rel, 8, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        crel.push_back(rel);
+        ++ncl;
+    }
+    *nclusters = ncl;
+    if (cluster_rel)
+        for (int c = 0; c < ncl; ++c) cluster_rel[c] = crel[c];
+    return CMSVD_OK;
+}
+
+cmsvd_status cmsvd_exact_tail(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double* tail2) {
+    if (!h) return fail(CMSVD_EINVAL, "cmsvd_exact_tail: null handle");
+    if (!tail2) return fail(CMSVD_EINVAL, "cmsvd_exact_tail: null output");
+    if (nblocks < 1 || !blocks) return fail(CMSVD_EINVAL, "cmsvd_exact_tail: no blocks");
+    if (nblocks > INT32_MAX) return fail(CMSVD_EUNSUPPORTED, "cmsvd_exact_tail: too many blocks");
+    const int N = (int)nblocks;
+    const int64_t m = blocks[0].rows;
+    if (m < 1 || r < 1) return fail(CMSVD_ESHAPE, "cmsvd_exact_tail: need m >= 1 and r >= 1");
+    int64_t ksum = 0;
+    for (int i = 0; i < N; ++i) {
+        cmsvd_status s = check_block(blocks[i], m, "block", i);
+        if (s != CMSVD_OK) return s;
+        ksum += blocks[i].cols;
+    }
+    const int64_t n = std::min(m, ksum);
+    if (n > 8192) return fail(CMSVD_EUNSUPPORTED, "cmsvd_exact_tail: min(m, total columns) > 8192");
+    const int nk = (int)std::min<int64_t>(r, n);
+    Plan pl;
+    const size_t o_M = pl.add((size_t)m * ksum * 8), o_G = pl.add((size_t)n * n * 8), o_a2 = pl.add((size_t)N * 16),
+                 o_top = pl.add(16), o_lam = pl.add((size_t)nk * 8), o_out = pl.add(8),
+                 o_eig = pl.add(sym_eig_workspace_doubles((int)n, 1) * 8);
+    cmsvd_status st = ensure(h, h->ws, h->ws_cap, pl.off);
+    if (st != CMSVD_OK) return st;
+    auto D = [&](size_t off) { return reinterpret_cast<double*>(h->ws + off); };
+    std::vector<PackDesc> pk;
+    std::vector<NormDesc> nd;
+    long coff = 0;
+    for (int i = 0; i < N; ++i) {
+        const cmsvd_block& b = blocks[i];
+        const bool f32 = b.dtype == CMSVD_F32;
+        pk.push_back(PackDesc{b.ptr, (int)m, (int)b.cols, (long)b.ld, f32 ? 1 : 0, D(o_M) + coff, (long)ksum, 0});
+        nd.push_back(NormDesc{b.ptr, (int)m, (int)b.cols, (long)b.ld, f32 ? 1 : 0, D(o_a2) + 2 * i});
+        coff += b.cols;
+    }
+    GemmGroup g;
+    if (ksum <= m) {  // M^T M
+        g.tb = true;
+        g.push(GemmDesc{D(o_M), D(o_M), D(o_G), (int)ksum, (int)ksum, (int)m, (long)ksum, (long)ksum, (long)ksum});
+    } else {  // M M^T
+        g.ta = true;
+        g.push(GemmDesc{D(o_M), D(o_M), D(o_G), (int)m, (int)m, (int)ksum, (long)ksum, (long)ksum, (long)m});
+    }
+    EigDesc e{};
+    e.n = (int)n;
+    e.n1 = 0;
+    e.nkeep = nk;
+    e.Y = D(o_G);
+    e.ldy = (long)n;
+    e.lam = D(o_lam);
+    e.sum_top = D(o_top);
+    std::vector<EigDesc> ed{e};
+    Stage stg;
+    const size_t o_pk = stg.add(pk), o_nd = stg.add(nd), o_ed = stg.add(ed);
+    g.off = stg.add(g.d);
+    char* db = nullptr;
+    st = upload(h, stg, &db);
+    if (st != CMSVD_OK) return st;
+    pack_batched(reinterpret_cast<const PackDesc*>(db + o_pk), N, h->stream);
+    sumsq_batched(reinterpret_cast<const NormDesc*>(db + o_nd), N, h->stream);
+    run_gemm(g, db, h->stream);
+    sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), 1, (int)n, 1, D(o_eig), 1, h->stream);
+    energy_minus(D(o_a2), N, D(o_top), D(o_out), h->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(tail2, D(o_out), 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
     return CMSVD_OK;
 }
 

@@ -198,6 +198,13 @@ struct ScreenDesc {
 void resid_screen(const ScreenDesc* d_descs, int count, const double* L, int r, const double* S, double eps,
                   hipStream_t s);
 
+// Theorem 1 / Algorithm 1 (weyl.hip).  Energies are double-double pairs a2[2i], a2[2i+1].
+void weyl_heads(const double* a2, const double* top, const int* cols, int r, int n, double* h, hipStream_t s);
+void weyl_step(const int* cand, int count, int init, int acc, const double* a2, const double* h, double* state,
+               double eps, int* first, double* rel, hipStream_t s);
+void weyl_bound(const double* a2, const double* h, int n, double* out, hipStream_t s);
+void energy_minus(const double* a2, int n, const double* top, double* out, hipStream_t s);
+
 // Backward of the tail energy.
 void divdiff_scale(double* B, int r, int nk, int d, const double* ev, hipStream_t s);
 void fill_diag(double* A, int rows, int cols, long ld, double v, double dv, hipStream_t s);
