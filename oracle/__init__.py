@@ -8,7 +8,8 @@ The arithmetic lives in ``cmsvd_oracle.c`` (one-sided Jacobi SVD, Householder QR
 the incremental step of Lemma 1 + Corollary 3, the plug-in estimate of Corollary 2,
 and the bounds of Theorem 1 / Corollary 1).  This module only marshals arrays and
 hosts the greedy clustering loops of Algorithm 3 (``alg3.py``), Algorithm 2
-(``alg2.py``) and Algorithm 1 (``alg1.py``).
+(``alg2.py``) and Algorithm 1 (``alg1.py``), and the compression back-end
+(``compress.py``).
 
 Conventions: blocks are 2-D arrays ``A_i`` of shape ``(m, n_i)``; they are promoted to
 FP64 (exactly, from FP32 inputs) before any arithmetic.
@@ -261,9 +262,9 @@ def exact_tail2(blocks, r: int) -> float:
 
 
 from .alg3 import cluster  # noqa: E402  (re-export)
-from . import alg1, alg2  # noqa: E402
+from . import alg1, alg2, compress  # noqa: E402
 
 __all__ = [
     "build", "frob2", "svd", "householder_qr", "State", "update", "chain", "chain_c", "pair",
-    "merge_errors", "weyl_bound2", "residual_bound2", "exact_tail2", "cluster", "alg1", "alg2",
+    "merge_errors", "weyl_bound2", "residual_bound2", "exact_tail2", "cluster", "alg1", "alg2", "compress",
 ]
