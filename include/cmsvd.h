@@ -33,6 +33,11 @@
  *   - Argument validation happens before any launch.  A non-OK status means no
  *     kernel was launched by that call, except CMSVD_EHIP, which reports a HIP
  *     runtime failure.  cmsvd_last_error() gives a thread-local message.
+ *   - Every symmetric eigenproblem the library solves has order at most 2016: the
+ *     core of an update (r_in + n_i), of a candidate merge (r + n_j), a block's or
+ *     residual's Gram (n_j) and an explicit Gram (min(m, sum n_j)).  Larger orders
+ *     return CMSVD_EUNSUPPORTED; append wider blocks as column panels (concatenation
+ *     is associative, so the same matrix results).
  *   - NaN/Inf in the data propagate into the affected results; they are not errors.
  *     A rank-deficient residual is not an error either: its numerically absent
  *     directions are dropped (their energy stays in the error estimate).
@@ -146,9 +151,8 @@ cmsvd_status cmsvd_cluster(cmsvd_handle handle, const cmsvd_block* blocks, int64
    the residual ordering ||(I - Q_C Q_C^T) A_j||_F taken against the full-span basis.
    Numerical span: the residual is projected twice and orthonormalised by
    CholeskyQR2; a direction whose squared singular value is below about
-   k_j u ||A_j||_F^2 (u = 2^-52, the pivot threshold) is not added to Q_C.  Blocks
-   may have at most 8192 columns; Q_C takes m * min(m, sum_j n_j) doubles of device
-   memory for the whole call.
+   k_j u ||A_j||_F^2 (u = 2^-52, the pivot threshold) is not added to Q_C.  Q_C takes
+   m * min(m, sum_j n_j) doubles of device memory for the whole call.
      labels, nclusters   as cmsvd_cluster
      cluster_rel  HOST nblocks FP64 (may be NULL): the certified ratio
                   b / ||M_C||_F of each final cluster (first *nclusters entries)
@@ -174,7 +178,7 @@ cmsvd_status cmsvd_residual_bound(cmsvd_handle handle, const cmsvd_block* blocks
    largest eigenvalues of its Gram A_j^T A_j).  An upper bound on the optimal rank-r
    error squared of the concatenation, for every r >= 1.
      bound2   HOST out
-   Blocks wider than r may have at most 8192 columns.  Synchronous. */
+   Synchronous. */
 cmsvd_status cmsvd_weyl_bound(cmsvd_handle handle, const cmsvd_block* blocks, int64_t nblocks, int64_t r,
                               double* bound2);
 
@@ -195,11 +199,30 @@ cmsvd_status cmsvd_cluster_weyl(cmsvd_handle handle, const cmsvd_block* blocks, 
 /* The optimal rank-r error squared of the concatenation, sum_{l>r} sigma_l^2 (Problem
    Formulation; Eckart-Young), from the eigenvalues of its explicit Gram (M^T M or
    M M^T, whichever is smaller): the reference value of the slack diagnostics.
-   min(m, sum_j n_j) may be at most 8192.  The workspace holds M in FP64.
+   The workspace holds M in FP64.
      tail2    HOST out, clamped at 0
    Synchronous. */
 cmsvd_status cmsvd_exact_tail(cmsvd_handle handle, const cmsvd_block* blocks, int64_t nblocks, int64_t r,
                               double* tail2);
+
+/* Compression back-end (Problem Formulation, cluster-concatenate-SVD representation):
+   the factors stored for one cluster M_C = [A_1 ... A_K] (the blocks given, in order),
+   the rank-r_C truncated SVD with the singular values absorbed into the left factor,
+   U~ = U S (m x r_C) and V (N_C x r_C), N_C = sum_j n_j, r_C = min(r, m, N_C).  Block j
+   is recovered as U~ V_j^T with V_j its n_j rows of V; the error of the cluster is
+   sum_{l > r_C} sigma_l^2 (Eckart-Young) and its memory r_C (m + N_C).  Computed from
+   the eigenpairs of the explicit Gram (M^T M or M M^T, whichever is smaller);
+   directions whose Gram eigenvalue is at most 8 n u lambda_1 (the Gram's resolution)
+   are stored as zero columns.
+     Ut      DEVICE out, row-major m x r_C FP64, row stride ldu >= r_C: U S
+     Vt      DEVICE out, row-major r_C x N_C FP64, row stride ldv >= N_C: V^T (block j
+             occupies its n_j columns, in the order given)
+     rank    HOST out: r_C
+     tail2   HOST out: sum_{l > r_C} sigma_l^2 of M_C, clamped at 0
+     energy  HOST out (may be NULL): ||M_C||_F^2
+   The workspace holds M_C and its Gram in FP64.  Synchronous. */
+cmsvd_status cmsvd_compress(cmsvd_handle handle, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double* Ut,
+                            int64_t ldu, double* Vt, int64_t ldv, int64_t* rank, double* tail2, double* energy);
 
 /* Tail energy of a chain and its gradient with respect to every block.
    The chain folds the blocks in order (the incremental state of Lemma 1 and

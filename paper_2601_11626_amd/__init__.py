@@ -55,12 +55,14 @@ def _load():
     lib.cmsvd_weyl_bound.argtypes = [vp, ctypes.POINTER(Block), i64, i64, ctypes.POINTER(d)]
     lib.cmsvd_cluster_weyl.argtypes = [vp, ctypes.POINTER(Block), i64, i64, d, vp, ctypes.POINTER(i64), vp]
     lib.cmsvd_exact_tail.argtypes = [vp, ctypes.POINTER(Block), i64, i64, ctypes.POINTER(d)]
+    lib.cmsvd_compress.argtypes = [vp, ctypes.POINTER(Block), i64, i64, vp, i64, vp, i64, ctypes.POINTER(i64),
+                                   ctypes.POINTER(d), ctypes.POINTER(d)]
     lib.cmsvd_tail_energy_grad.argtypes = [vp, ctypes.POINTER(Block), i64, i64, i64, ctypes.POINTER(d), vp,
                                            ctypes.POINTER(d)]
     for f in ("cmsvd_create", "cmsvd_destroy", "cmsvd_set_stream", "cmsvd_update", "cmsvd_merge_errors",
               "cmsvd_cluster", "cmsvd_sym_eigvals", "cmsvd_gemm_f64", "cmsvd_profile", "cmsvd_profile_read",
               "cmsvd_tail_energy_grad", "cmsvd_update_batch", "cmsvd_cluster_residual", "cmsvd_residual_bound",
-              "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail"):
+              "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail", "cmsvd_compress"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -70,7 +72,7 @@ _lib = _load()
 EXPORTS = ("cmsvd_create", "cmsvd_destroy", "cmsvd_set_stream", "cmsvd_last_error", "cmsvd_update",
            "cmsvd_merge_errors", "cmsvd_cluster", "cmsvd_sym_eigvals", "cmsvd_gemm_f64", "cmsvd_profile",
            "cmsvd_profile_read", "cmsvd_tail_energy_grad", "cmsvd_update_batch", "cmsvd_cluster_residual",
-           "cmsvd_residual_bound", "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail")
+           "cmsvd_residual_bound", "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail", "cmsvd_compress")
 
 STAGES = ("norms_grams", "commit", "projection", "core_eig")
 
@@ -318,6 +320,47 @@ def cmsvd_exact_tail(blocks: Sequence[torch.Tensor], r: int, handle: Handle | No
     return out.value
 
 
+def cmsvd_compress(blocks: Sequence[torch.Tensor], r: int, handle: Handle | None = None, with_energy: bool = False):
+    """Stored factors of one cluster: (Ut = U S (m x r_C), Vt = V^T (r_C x N_C), tail2),
+    plus ||M_C||_F^2 as a fourth item when ``with_energy``."""
+    h = handle or default_handle(blocks[0].device)
+    m = blocks[0].shape[0]
+    N = sum(int(b.shape[1]) for b in blocks)
+    rc = min(r, m, N)
+    Ut = torch.empty((m, rc), dtype=torch.float64, device=blocks[0].device)
+    Vt = torch.empty((rc, N), dtype=torch.float64, device=blocks[0].device)
+    rank = ctypes.c_int64(0)
+    tail2 = ctypes.c_double(0.0)
+    energy = ctypes.c_double(0.0)
+    _check(_lib.cmsvd_compress(h.ptr, _blocks(blocks), len(blocks), r, ctypes.c_void_p(Ut.data_ptr()), rc,
+                               ctypes.c_void_p(Vt.data_ptr()), N, ctypes.byref(rank), ctypes.byref(tail2),
+                               ctypes.byref(energy)))
+    if with_energy:
+        return Ut, Vt, tail2.value, energy.value
+    return Ut, Vt, tail2.value
+
+
+def compress_partition(blocks: Sequence[torch.Tensor], labels, r: int, handle: Handle | None = None):
+    """Factors of every cluster of a partition (labels as returned by the clustering
+    calls) and the summary: compression ratio (stored entries of the blocks over those of
+    the factors) and the relative error sqrt(sum of the cluster tails) / ||all blocks||_F.
+    Returns (factors: list of (members, Ut, Vt, tail2), summary dict)."""
+    m = blocks[0].shape[0]
+    ncl = max(labels) + 1
+    members = [[i for i, c in enumerate(labels) if c == k] for k in range(ncl)]
+    factors, before, after, tails, total = [], 0, 0, 0.0, 0.0
+    for mem in members:
+        Ut, Vt, t2, e2 = cmsvd_compress([blocks[i] for i in mem], r, handle, with_energy=True)
+        N = sum(int(blocks[i].shape[1]) for i in mem)
+        before += m * N
+        after += Ut.shape[1] * (m + N)
+        tails += t2
+        total += e2
+        factors.append((mem, Ut, Vt, t2))
+    return factors, {"compression_ratio": before / after, "rel_error": (tails / total) ** 0.5 if total > 0 else 0.0,
+                     "clusters": ncl}
+
+
 def cmsvd_tail_energy_grad(blocks: Sequence[torch.Tensor], r: int, checkpoint: int | None = None,
                            want_grad: bool = True, handle: Handle | None = None):
     """Tail energy f = E~_r^2 of the chain ``blocks`` (in order) and, if ``want_grad``,
@@ -415,5 +458,6 @@ def cmsvd_gemm_f64(opA: torch.Tensor, opB: torch.Tensor, C: torch.Tensor | None 
 
 __all__ = ["cmsvd_gemm_f64", "Handle", "State", "Block", "CmsvdError", "cmsvd_update", "cmsvd_update_batch",
            "cmsvd_merge_errors", "cmsvd_cluster", "cmsvd_cluster_residual", "cmsvd_residual_bound",
-           "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail", "cmsvd_sym_eigvals", "cmsvd_tail_energy_grad", "TailEnergy", "tail_energy", "default_handle",
+           "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail", "cmsvd_compress", "compress_partition",
+           "cmsvd_sym_eigvals", "cmsvd_tail_energy_grad", "TailEnergy", "tail_energy", "default_handle",
            "LIB_PATH", "EXPORTS"]

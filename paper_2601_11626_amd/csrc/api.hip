@@ -168,6 +168,15 @@ struct StageMark {
     }
 };
 
+// Every symmetric eigenproblem of the library (the update's core of order r_in + k,
+// a candidate's Gram, an explicit Gram) is at most sym_eig_nmax() (2016).
+cmsvd_status check_order(int64_t n, const char* who) {
+    if (n > sym_eig_nmax())
+        return fail(CMSVD_EUNSUPPORTED, "%s: eigenproblem of order %lld exceeds %d (append wide blocks as column panels)",
+                    who, (long long)n, sym_eig_nmax());
+    return CMSVD_OK;
+}
+
 cmsvd_status check_block(const cmsvd_block& b, int64_t m, const char* what, int64_t idx) {
     if (!b.ptr) return fail(CMSVD_EINVAL, "%s %lld: null data pointer", what, (long long)idx);
     if (b.dtype != CMSVD_F32 && b.dtype != CMSVD_F64)
@@ -1117,7 +1126,8 @@ cmsvd_status resid_setup(cmsvd_ctx* h, const cmsvd_block* blocks, int N, int64_t
     for (int i = 0; i < N; ++i) {
         cmsvd_status s = check_block(blocks[i], m, "block", i);
         if (s != CMSVD_OK) return s;
-        if (blocks[i].cols > 8192) return fail(CMSVD_EUNSUPPORTED, "%s: block %d has more than 8192 columns", who, i);
+        s = check_order(blocks[i].cols, who);
+        if (s != CMSVD_OK) return s;
         kmax = std::max(kmax, blocks[i].cols);
         ksum += blocks[i].cols;
     }
@@ -1414,8 +1424,10 @@ cmsvd_status weyl_setup(cmsvd_ctx* h, const cmsvd_block* blocks, int N, int64_t 
     for (int i = 0; i < N; ++i) {
         cmsvd_status s = check_block(blocks[i], m, "block", i);
         if (s != CMSVD_OK) return s;
-        if (blocks[i].cols > r && blocks[i].cols > 8192)
-            return fail(CMSVD_EUNSUPPORTED, "%s: block %d has more than 8192 columns", who, i);
+        if (blocks[i].cols > r) {
+            s = check_order(blocks[i].cols, who);
+            if (s != CMSVD_OK) return s;
+        }
         if (blocks[i].cols > r) kmax = std::max(kmax, (int)blocks[i].cols);
     }
     Plan pl;
@@ -1579,6 +1591,8 @@ cmsvd_status cmsvd_update(cmsvd_handle h, int64_t m, const double* U, int64_t ld
     if (U_out == U || S_out == S) return fail(CMSVD_EINVAL, "cmsvd_update: outputs alias inputs");
     cmsvd_status st = check_block(*B, m, "block", 0);
     if (st != CMSVD_OK) return st;
+    st = check_order(r_in + B->cols, "cmsvd_update");
+    if (st != CMSVD_OK) return st;
     CommitJob j{(int)m, U, (long)ldu, S, (int)r_in, *B, (int)r, U_out, (long)ldu_out, S_out, acc, est};
     return commit_batched(h, {j});
 }
@@ -1600,6 +1614,8 @@ cmsvd_status cmsvd_update_batch(cmsvd_handle h, int64_t count, int64_t m, const 
     std::vector<CommitJob> jobs;
     for (int64_t i = 0; i < count; ++i) {
         cmsvd_status st = check_block(B[i], m, "block", i);
+        if (st != CMSVD_OK) return st;
+        st = check_order(r_in + B[i].cols, "cmsvd_update_batch");
         if (st != CMSVD_OK) return st;
         if (!U_out[i] || !S_out[i] || !acc[i]) return fail(CMSVD_EINVAL, "cmsvd_update_batch: null output %lld", (long long)i);
         if (r_in > 0 && (!U[i] || !S[i])) return fail(CMSVD_EINVAL, "cmsvd_update_batch: null state %lld", (long long)i);
@@ -1628,6 +1644,9 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
         const int32_t a = pairs[2 * p], b = pairs[2 * p + 1];
         if (a < 0 || a >= nblocks || b < 0 || b >= nblocks)
             return fail(CMSVD_EINVAL, "cmsvd_merge_errors: pair %lld = (%d, %d) out of range", (long long)p, a, b);
+        cmsvd_status st = check_order(std::max(blocks[a].cols, std::min<int64_t>(r, blocks[a].cols) + blocks[b].cols),
+                                      "cmsvd_merge_errors");
+        if (st != CMSVD_OK) return st;
     }
     if (npairs == 0) return CMSVD_OK;
     // anchors and candidates
@@ -1764,7 +1783,7 @@ cmsvd_status cmsvd_sym_eigvals(cmsvd_handle h, const double* A, int64_t n, int64
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_sym_eigvals: null handle");
     if (!A || !lam) return fail(CMSVD_EINVAL, "cmsvd_sym_eigvals: null pointer");
     if (n < 1 || lda < n || count < 0 || nkeep < 1 || nkeep > n) return fail(CMSVD_ESHAPE, "cmsvd_sym_eigvals: bad sizes");
-    if (n > 8192) return fail(CMSVD_EUNSUPPORTED, "cmsvd_sym_eigvals: n > 8192");
+    if (n > sym_eig_nmax()) return fail(CMSVD_EUNSUPPORTED, "cmsvd_sym_eigvals: n > %d", sym_eig_nmax());
     if (count == 0) return CMSVD_OK;
     const int nslots = (int)std::min<int64_t>(count, h->ncu);
     Plan pl;
@@ -1837,6 +1856,8 @@ cmsvd_status cmsvd_cluster(cmsvd_handle h, const cmsvd_block* blocks, int64_t nb
     if (r > 4096) return fail(CMSVD_EUNSUPPORTED, "cmsvd_cluster: r > 4096");
     for (int64_t i = 0; i < nblocks; ++i) {
         cmsvd_status st = check_block(blocks[i], m, "block", i);
+        if (st != CMSVD_OK) return st;
+        st = check_order(r + blocks[i].cols, "cmsvd_cluster");
         if (st != CMSVD_OK) return st;
     }
     const int N = (int)nblocks;
@@ -2212,7 +2233,8 @@ cmsvd_status cmsvd_exact_tail(cmsvd_handle h, const cmsvd_block* blocks, int64_t
         ksum += blocks[i].cols;
     }
     const int64_t n = std::min(m, ksum);
-    if (n > 8192) return fail(CMSVD_EUNSUPPORTED, "cmsvd_exact_tail: min(m, total columns) > 8192");
+    cmsvd_status so = check_order(n, "cmsvd_exact_tail");
+    if (so != CMSVD_OK) return so;
     const int nk = (int)std::min<int64_t>(r, n);
     Plan pl;
     const size_t o_M = pl.add((size_t)m * ksum * 8), o_G = pl.add((size_t)n * n * 8), o_a2 = pl.add((size_t)N * 16),
@@ -2266,6 +2288,113 @@ cmsvd_status cmsvd_exact_tail(cmsvd_handle h, const cmsvd_block* blocks, int64_t
 }
 
 
+/* Compression back-end: the truncated SVD factors of one cluster; see include/cmsvd.h. */
+cmsvd_status cmsvd_compress(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double* Ut,
+                            int64_t ldu, double* Vt, int64_t ldv, int64_t* rank, double* tail2, double* energy) {
+    if (!h) return fail(CMSVD_EINVAL, "cmsvd_compress: null handle");
+    if (!Ut || !Vt || !rank || !tail2) return fail(CMSVD_EINVAL, "cmsvd_compress: null output");
+    if (nblocks < 1 || !blocks) return fail(CMSVD_EINVAL, "cmsvd_compress: no blocks");
+    if (nblocks > INT32_MAX) return fail(CMSVD_EUNSUPPORTED, "cmsvd_compress: too many blocks");
+    const int N = (int)nblocks;
+    const int64_t m = blocks[0].rows;
+    if (m < 1 || r < 1) return fail(CMSVD_ESHAPE, "cmsvd_compress: need m >= 1 and r >= 1");
+    int64_t ncol = 0;
+    for (int i = 0; i < N; ++i) {
+        cmsvd_status s = check_block(blocks[i], m, "block", i);
+        if (s != CMSVD_OK) return s;
+        ncol += blocks[i].cols;
+    }
+    const int64_t n = std::min(m, ncol);
+    cmsvd_status so = check_order(n, "cmsvd_compress");
+    if (so != CMSVD_OK) return so;
+    if (ncol > INT32_MAX / 2 || m > INT32_MAX / 2) return fail(CMSVD_EUNSUPPORTED, "cmsvd_compress: too large");
+    const int rc = (int)std::min<int64_t>(r, n);
+    if (ldu < rc || ldv < ncol) return fail(CMSVD_ESHAPE, "cmsvd_compress: ldu < rank or ldv < total columns");
+    const bool cols_side = ncol <= m;  // Gram M^T M (else M M^T)
+    Plan pl;
+    const size_t o_M = pl.add((size_t)m * ncol * 8), o_G = pl.add((size_t)n * n * 8), o_a2 = pl.add((size_t)N * 16),
+                 o_top = pl.add(16), o_lam = pl.add((size_t)rc * 8), o_d = pl.add((size_t)n * 8),
+                 o_e = pl.add((size_t)n * 8), o_V = pl.add((size_t)n * n * 8), o_tau = pl.add((size_t)n * 8),
+                 o_vs = pl.add((size_t)6 * n * rc * 8), o_Z = pl.add(cols_side ? 8 : (size_t)n * rc * 8),
+                 o_out = pl.add(16), o_zero = pl.add(16), o_eig = pl.add(sym_eig_workspace_doubles((int)n, 1) * 8);
+    cmsvd_status st = ensure(h, h->ws, h->ws_cap, pl.off);
+    if (st != CMSVD_OK) return st;
+    auto D = [&](size_t off) { return reinterpret_cast<double*>(h->ws + off); };
+    std::vector<PackDesc> pk;
+    std::vector<NormDesc> nd;
+    long coff = 0;
+    for (int i = 0; i < N; ++i) {
+        const cmsvd_block& b = blocks[i];
+        const bool f32 = b.dtype == CMSVD_F32;
+        pk.push_back(PackDesc{b.ptr, (int)m, (int)b.cols, (long)b.ld, f32 ? 1 : 0, D(o_M) + coff, (long)ncol, 0});
+        nd.push_back(NormDesc{b.ptr, (int)m, (int)b.cols, (long)b.ld, f32 ? 1 : 0, D(o_a2) + 2 * i});
+        coff += b.cols;
+    }
+    GemmGroup gG, gV, gU;
+    if (cols_side) {
+        gG.tb = true;
+        gG.push(GemmDesc{D(o_M), D(o_M), D(o_G), (int)ncol, (int)ncol, (int)m, (long)ncol, (long)ncol, (long)ncol});
+    } else {
+        gG.ta = true;
+        gG.push(GemmDesc{D(o_M), D(o_M), D(o_G), (int)m, (int)m, (int)ncol, (long)ncol, (long)ncol, (long)m});
+        // V (ncol x rc, column-major, ld ldv) = M^T Z
+        gV.push(GemmDesc{D(o_M), D(o_Z), Vt, (int)ncol, rc, (int)m, (long)ncol, (long)m, (long)ldv});
+    }
+    // U S (rc x m column-major = m x rc row-major) = V^T M^T
+    gU.ta = true;
+    gU.push(GemmDesc{Vt, D(o_M), Ut, rc, (int)m, (int)ncol, (long)ldv, (long)ncol, (long)ldu});
+    double* Z = cols_side ? Vt : D(o_Z);
+    const long ldz = cols_side ? (long)ldv : (long)n;
+    EigDesc e{};
+    e.n = (int)n;
+    e.n1 = 0;
+    e.nkeep = rc;
+    e.Y = D(o_G);
+    e.ldy = (long)n;
+    e.lam = D(o_lam);
+    e.d = D(o_d);
+    e.e = D(o_e);
+    e.V = D(o_V);
+    e.ldv = (long)n;
+    e.tau = D(o_tau);
+    e.sum_top = D(o_top);
+    std::vector<EigDesc> ed{e};
+    std::vector<VecDesc> vd{VecDesc{(int)n, rc, D(o_lam), D(o_d), D(o_e), D(o_V), (long)n, D(o_tau), Z, ldz, D(o_vs)}};
+    Stage stg;
+    const size_t o_pk = stg.add(pk), o_nd = stg.add(nd), o_ed = stg.add(ed), o_vd = stg.add(vd);
+    for (GemmGroup* g : {&gG, &gV, &gU}) g->off = stg.add(g->d);
+    char* db = nullptr;
+    st = upload(h, stg, &db);
+    if (st != CMSVD_OK) return st;
+    hipStream_t s = h->stream;
+    pack_batched(reinterpret_cast<const PackDesc*>(db + o_pk), N, s);
+    sumsq_batched(reinterpret_cast<const NormDesc*>(db + o_nd), N, s);
+    run_gemm(gG, db, s);
+    sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), 1, (int)n, 1, D(o_eig), 1, s);
+    sym_vectors_batched(reinterpret_cast<const VecDesc*>(db + o_vd), 1, s);
+    // directions below the Gram's resolution (8 n u lam_1) are stored as zero columns
+    const double cut_rel = 8.0 * (double)n * EPS;
+    if (cols_side) {
+        scale_cols(Vt, (int)ncol, rc, (long)ldv, D(o_lam), 0, cut_rel, s);
+    } else {
+        run_gemm(gV, db, s);
+        scale_cols(Vt, (int)ncol, rc, (long)ldv, D(o_lam), 1, cut_rel, s);
+    }
+    run_gemm(gU, db, s);
+    energy_minus(D(o_a2), N, D(o_top), D(o_out), s);
+    fill_f64(D(o_zero), 2, 0.0, s);
+    energy_minus(D(o_a2), N, D(o_zero), D(o_out) + 1, s);  // ||M_C||_F^2
+    HIPCHK(hipGetLastError());
+    double v[2] = {0.0, 0.0};
+    HIPCHK(hipMemcpyAsync(v, D(o_out), 16, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *tail2 = v[0];
+    if (energy) *energy = v[1];
+    *rank = rc;
+    return CMSVD_OK;
+}
+
+
 /* Tail energy of a chain and its gradient; see include/cmsvd.h. */
 cmsvd_status cmsvd_tail_energy_grad(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r,
                                     int64_t checkpoint, double* f, double* const* grads, double* min_gap) {
@@ -2279,6 +2408,8 @@ cmsvd_status cmsvd_tail_energy_grad(cmsvd_handle h, const cmsvd_block* blocks, i
     int kmax = 0;
     for (int64_t i = 0; i < nblocks; ++i) {
         cmsvd_status st = check_block(blocks[i], m, "block", i);
+        if (st != CMSVD_OK) return st;
+        st = check_order(r + blocks[i].cols, "cmsvd_tail_energy_grad");
         if (st != CMSVD_OK) return st;
         if (grads && !grads[i]) return fail(CMSVD_EINVAL, "cmsvd_tail_energy_grad: null gradient %lld", (long long)i);
         kmax = std::max(kmax, (int)blocks[i].cols);

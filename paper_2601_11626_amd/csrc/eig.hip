@@ -951,6 +951,11 @@ __global__ void __launch_bounds__(64 * SWV) sym_eig_small_kernel(const EigDesc* 
     }
 }
 
+int sym_eig_nmax() {
+    // the general kernel keeps 10 order-n vectors of LDS besides its tiles
+    return (int)(((LDS_BYTES / 8 - 32) / 10) / TILE * TILE);
+}
+
 size_t sym_eig_workspace_doubles(int nmax, int nslots) {
     const int T = (nmax + TILE - 1) / TILE;
     return (size_t)nslots * (size_t)T * (size_t)(T + 1) / 2 * TILE_EL;

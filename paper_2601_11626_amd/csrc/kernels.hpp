@@ -50,6 +50,8 @@ struct EigDesc {
 void sym_eig_batched(const EigDesc* d_descs, int count, int nmax, int mode, double* gws, int nslots,
                      hipStream_t s);
 size_t sym_eig_workspace_doubles(int nmax, int nslots);
+// Largest order the eigenvalue (and eigenvector) kernels accept (2016 on gfx950).
+int sym_eig_nmax();
 
 // Inverse iteration on the tridiagonal (lam, d, e) for the nkeep top eigenvectors,
 // orthonormalised, then back-transformed by the stored Householder vectors.  Z is
@@ -204,6 +206,8 @@ void weyl_step(const int* cand, int count, int init, int acc, const double* a2, 
                double eps, int* first, double* rel, hipStream_t s);
 void weyl_bound(const double* a2, const double* h, int n, double* out, hipStream_t s);
 void energy_minus(const double* a2, int n, const double* top, double* out, hipStream_t s);
+// A[:, c] *= (lam[c] > cut_rel * lam[0]) ? (inv ? 1 / sqrt(lam[c]) : 1) : 0  (column-major)
+void scale_cols(double* A, int rows, int cols, long ld, const double* lam, int inv, double cut_rel, hipStream_t s);
 
 // Backward of the tail energy.
 void divdiff_scale(double* B, int r, int nk, int d, const double* ev, hipStream_t s);

@@ -155,4 +155,26 @@ void energy_minus(const double* a2, int n, const double* top, double* out, hipSt
     hipLaunchKernelGGL(energy_minus_kernel, dim3(1), dim3(WT), 0, s, a2, n, top, out);
 }
 
+// Column c of A (rows x cols, column-major, ld) times f_c, where f_c = 0 when
+// lam[c] <= cut_rel * lam[0] (numerically absent direction), else 1 / sqrt(lam[c])
+// (inv) or 1: the right factor of a truncated SVD from Gram eigenpairs.
+__global__ void scale_cols_kernel(double* __restrict__ A, int rows, int cols, long ld, const double* __restrict__ lam,
+                                  int inv, double cut_rel) {
+    const double cut = cut_rel * lam[0];
+    const long tot = (long)rows * cols;
+    for (long e = (long)blockIdx.x * WT + threadIdx.x; e < tot; e += (long)gridDim.x * WT) {
+        const int c = (int)(e / rows), i = (int)(e - (long)c * rows);
+        const double l = lam[c];
+        const double f = l > cut && l > 0.0 ? (inv ? 1.0 / sqrt(l) : 1.0) : 0.0;
+        A[(long)i + (long)c * ld] *= f;
+    }
+}
+
+void scale_cols(double* A, int rows, int cols, long ld, const double* lam, int inv, double cut_rel, hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return;
+    const long tot = (long)rows * cols;
+    const int g = (int)((tot + WT - 1) / WT < 2048 ? (tot + WT - 1) / WT : 2048);
+    hipLaunchKernelGGL(scale_cols_kernel, dim3(g), dim3(WT), 0, s, A, rows, cols, ld, lam, inv, cut_rel);
+}
+
 }  // namespace cmsvd
