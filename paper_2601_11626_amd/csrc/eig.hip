@@ -23,6 +23,7 @@
 namespace cmsvd {
 
 constexpr int ET = 256;          // threads per workgroup
+constexpr int GT = 1024;         // threads per workgroup of the general (n > 320) kernel
 constexpr int TILE = 32;         // tile edge
 constexpr int TILE_EL = TILE * TILE;
 constexpr int LDS_BYTES = 163840;  // gfx950: 160 KiB per workgroup
@@ -133,8 +134,8 @@ __device__ __forceinline__ void tile_step(double (&a)[16], int R, int C, const d
                                           const double* __restrict__ vp, const double* __restrict__ wp,
                                           double* pww, int ly, int lx);
 
-template <int MODE>
-__global__ void __launch_bounds__(ET) sym_eig_kernel(const EigDesc* __restrict__ descs, int count, int NP,
+template <int MODE, int NT>
+__global__ void __launch_bounds__(NT) sym_eig_kernel(const EigDesc* __restrict__ descs, int count, int NP,
                                                      int TLmax, double* __restrict__ gws, long slot_doubles) {
     extern __shared__ double lds[];
     double* vc = lds;             // current Householder vector
@@ -162,9 +163,9 @@ __global__ void __launch_bounds__(ET) sym_eig_kernel(const EigDesc* __restrict__
         for (int C = 0; C < T; ++C)
             for (int R = C; R < T; ++R) {
                 double* tp = tile_ptr(R, C, T, c0, TL, gt, lt);
-                for (int el = t; el < TILE_EL; el += ET) tp[el] = hval(D, R * TILE + plane_row(el), C * TILE + plane_col(el));
+                for (int el = t; el < TILE_EL; el += NT) tp[el] = hval(D, R * TILE + plane_row(el), C * TILE + plane_col(el));
             }
-        for (int i = t; i < npad; i += ET) {
+        for (int i = t; i < npad; i += NT) {
             vc[i] = vp[i] = wp[i] = xv[i] = 0.0;
             pw[i] = pw[NP + i] = pw[2 * NP + i] = pw[3 * NP + i] = 0.0;
             dd[i] = ee[i] = 0.0;
@@ -177,7 +178,7 @@ __global__ void __launch_bounds__(ET) sym_eig_kernel(const EigDesc* __restrict__
             // (A) column j with the pending update of step j-1
             const double vpj = vp[j], wpj = wp[j];
             double part = 0.0;
-            for (int i = j + t; i < n; i += ET) {
+            for (int i = j + t; i < n; i += NT) {
                 const double* tp = tile_ptr(i >> 5, Cj, T, c0, TL, gt, lt);
                 const double val = tp[tile_off(i & 31, cj)] - (vp[i] * wpj + wp[i] * vpj);
                 if (i == j) dd[j] = val;
@@ -203,7 +204,7 @@ __global__ void __launch_bounds__(ET) sym_eig_kernel(const EigDesc* __restrict__
             }
             __syncthreads();
             const double tau = scal[0], scale = scal[1];
-            for (int i = t; i < npad; i += ET) {
+            for (int i = t; i < npad; i += NT) {
                 double v = 0.0;
                 if (tau != 0.0) {
                     if (i == j + 1) v = 1.0;
@@ -219,12 +220,12 @@ __global__ void __launch_bounds__(ET) sym_eig_kernel(const EigDesc* __restrict__
             int f = 0;
             for (int C = Cj; C < T; ++C) {
                 for (int R = C; R < T; ++R, ++f) {
-                    if ((f & 3) != w) continue;
+                    if ((f % (NT / 64)) != w) continue;
                     double* tp = tile_ptr(R, C, T, c0, TL, gt, lt);
                     double a[16];
 #pragma unroll
                     for (int e = 0; e < 16; ++e) a[e] = tp[(e << 6) + lane];
-                    tile_step(a, R, C, vc, vp, wp, pw + w * NP, ly, lx);
+                    tile_step(a, R, C, vc, vp, wp, pw + (w & 3) * NP, ly, lx);
 #pragma unroll
                     for (int e = 0; e < 16; ++e) tp[(e << 6) + lane] = a[e];
                 }
@@ -233,7 +234,7 @@ __global__ void __launch_bounds__(ET) sym_eig_kernel(const EigDesc* __restrict__
 
             // (C) p = tau * A v, w = p - (tau/2)(p.v) v
             double dpart = 0.0;
-            for (int i = t; i < npad; i += ET) {
+            for (int i = t; i < npad; i += NT) {
                 const double sacc = pw[i] + pw[NP + i] + pw[2 * NP + i] + pw[3 * NP + i];
                 pw[i] = pw[NP + i] = pw[2 * NP + i] = pw[3 * NP + i] = 0.0;
                 const double pi = (i >= j + 1 && i < n) ? tau * sacc : 0.0;
@@ -242,7 +243,7 @@ __global__ void __launch_bounds__(ET) sym_eig_kernel(const EigDesc* __restrict__
             }
             const double dot = block_sum(dpart, red);
             const double K = -0.5 * tau * dot;
-            for (int i = t; i < npad; i += ET) {
+            for (int i = t; i < npad; i += NT) {
                 wp[i] = (i >= j + 1 && i < n) ? xv[i] + K * vc[i] : 0.0;
                 vp[i] = vc[i];
             }
@@ -251,9 +252,9 @@ __global__ void __launch_bounds__(ET) sym_eig_kernel(const EigDesc* __restrict__
         __syncthreads();
 
         // ---- bisection for the nkeep largest eigenvalues ----
-        for (int i = t; i < npad; i += ET) xv[i] = (i < n - 1) ? ee[i] * ee[i] : 0.0;
+        for (int i = t; i < npad; i += NT) xv[i] = (i < n - 1) ? ee[i] * ee[i] : 0.0;
         double glo = INFINITY, ghi = -INFINITY, em = 0.0;
-        for (int i = t; i < n; i += ET) {
+        for (int i = t; i < n; i += NT) {
             const double rad = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i < n - 1 ? fabs(ee[i]) : 0.0);
             glo = fmin(glo, dd[i] - rad);
             ghi = fmax(ghi, dd[i] + rad);
@@ -268,7 +269,7 @@ __global__ void __launch_bounds__(ET) sym_eig_kernel(const EigDesc* __restrict__
         glo -= tol;
         ghi += tol;
         double* lamv = pw;  // free now
-        for (int q = t; q < D.nkeep; q += ET) {
+        for (int q = t; q < D.nkeep; q += NT) {
             double lo = glo, hi = ghi;
             const int target = n - q;
             while (hi - lo > tol) {
@@ -303,9 +304,9 @@ __global__ void __launch_bounds__(ET) sym_eig_kernel(const EigDesc* __restrict__
             }
         }
         if (MODE == 1) {
-            for (int q = t; q < D.nkeep; q += ET) D.lam[q] = lamv[q];
+            for (int q = t; q < D.nkeep; q += NT) D.lam[q] = lamv[q];
             if (D.d)
-                for (int i = t; i < n; i += ET) {
+                for (int i = t; i < n; i += NT) {
                     D.d[i] = dd[i];
                     if (i < n - 1) D.e[i] = ee[i];
                 }
@@ -989,11 +990,11 @@ void sym_eig_batched(const EigDesc* d_descs, int count, int nmax, int mode, doub
     const long slot = (long)T * (T + 1) / 2 * TILE_EL;
     const int grid = count < nslots ? count : nslots;
     if (mode == 0) {
-        (void)hipFuncSetAttribute((const void*)sym_eig_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(sym_eig_kernel<0>, dim3(grid), dim3(ET), lds, s, d_descs, count, npad, TL, gws, slot);
+        (void)hipFuncSetAttribute((const void*)sym_eig_kernel<0, GT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((sym_eig_kernel<0, GT>), dim3(grid), dim3(GT), lds, s, d_descs, count, npad, TL, gws, slot);
     } else {
-        (void)hipFuncSetAttribute((const void*)sym_eig_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(sym_eig_kernel<1>, dim3(grid), dim3(ET), lds, s, d_descs, count, npad, TL, gws, slot);
+        (void)hipFuncSetAttribute((const void*)sym_eig_kernel<1, GT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((sym_eig_kernel<1, GT>), dim3(grid), dim3(GT), lds, s, d_descs, count, npad, TL, gws, slot);
     }
 }
 
