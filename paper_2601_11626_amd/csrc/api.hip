@@ -355,6 +355,107 @@ struct CholPlan {
 };
 
 // ---------------------------------------------------------------------------
+// Eigenvectors of a few large cores: the per-workgroup kernel leaves the eigenvectors
+// of the tridiagonal in Z, and the reflectors are applied in blocks of 32 in compact
+// WY form, Z <- (I - V T V^T) Z from the last block to the first, as MFMA GEMMs
+// batched across problems (one per block and stage).  Many small problems keep the
+// one-workgroup back-transformation.
+// ---------------------------------------------------------------------------
+struct BackPlan {
+    static constexpr int BB = 32;
+    std::vector<VecDesc> jobs;
+    bool blocked = false;
+    size_t o_vd = 0, o_lf = 0;
+    std::vector<LarftDesc> lf;
+    GemmGroup gS;
+    struct Step {
+        GemmGroup g1, g2, g3;
+    };
+    std::vector<Step> steps;
+
+    static bool use_blocked(const std::vector<int>& ns) {
+        int nmax = 0;
+        for (int n : ns) nmax = std::max(nmax, n);
+        return nmax >= 256 && ns.size() <= 32;
+    }
+    static int nblocks(int n) { return n > 2 ? (n - 2 + BB - 1) / BB : 0; }
+    // scratch doubles per problem: the Grams and T of its blocks, W1 and W2
+    static size_t scratch_doubles(int n, int nk) { return (size_t)nblocks(n) * BB * BB * 2 + (size_t)BB * nk * 2; }
+
+    void build(const std::vector<VecDesc>& js, const std::vector<double*>& scratch) {
+        jobs = js;
+        std::vector<int> ns;
+        for (const auto& v : js) ns.push_back(v.n);
+        blocked = use_blocked(ns);
+        if (!blocked) return;
+        int bmax = 0;
+        for (auto& v : jobs) {
+            v.skip_bt = 1;
+            bmax = std::max(bmax, nblocks(v.n));
+        }
+        gS.ta = true;
+        for (size_t p = 0; p < jobs.size(); ++p) {
+            const VecDesc& v = jobs[p];
+            const int nb = nblocks(v.n);
+            double* S = scratch[p];
+            double* T = S + (size_t)nb * BB * BB;
+            for (int b = 0; b < nb; ++b) {
+                const int j0 = b * BB, be = std::min(BB, v.n - 2 - j0), r0 = j0 + 1, h = v.n - r0;
+                const double* Vb = v.V + r0 + (long)j0 * v.ldv;
+                gS.push(GemmDesc{Vb, Vb, S + (size_t)b * BB * BB, be, be, h, v.ldv, v.ldv, (long)BB});
+                lf.push_back(LarftDesc{S + (size_t)b * BB * BB, v.tau + j0, T + (size_t)b * BB * BB, be, (long)BB});
+            }
+        }
+        for (int b = bmax - 1; b >= 0; --b) {
+            Step st;
+            st.g1.ta = true;
+            st.g3.alpha = -1.0;
+            st.g3.beta = 1.0;
+            for (size_t p = 0; p < jobs.size(); ++p) {
+                const VecDesc& v = jobs[p];
+                const int nb = nblocks(v.n);
+                if (b >= nb) continue;
+                double* S = scratch[p];
+                double* T = S + (size_t)nb * BB * BB;
+                double* W1 = T + (size_t)nb * BB * BB;
+                double* W2 = W1 + (size_t)BB * v.nkeep;
+                const int j0 = b * BB, be = std::min(BB, v.n - 2 - j0), r0 = j0 + 1, h = v.n - r0;
+                const double* Vb = v.V + r0 + (long)j0 * v.ldv;
+                st.g1.push(GemmDesc{Vb, v.Z + r0, W1, be, v.nkeep, h, v.ldv, v.ldz, (long)BB});
+                st.g2.push(GemmDesc{T + (size_t)b * BB * BB, W1, W2, be, v.nkeep, be, (long)BB, (long)BB, (long)BB});
+                st.g3.push(GemmDesc{Vb, W2, v.Z + r0, h, v.nkeep, be, v.ldv, (long)BB, v.ldz});
+            }
+            steps.push_back(std::move(st));
+        }
+    }
+
+    void stage(Stage& stg) {
+        o_vd = stg.add(jobs);
+        if (!blocked) return;
+        o_lf = stg.add(lf);
+        gS.off = stg.add(gS.d);
+        for (auto& st : steps) {
+            st.g1.off = stg.add(st.g1.d);
+            st.g2.off = stg.add(st.g2.d);
+            st.g3.off = stg.add(st.g3.d);
+        }
+    }
+
+    void run(char* db, hipStream_t s) {
+        sym_vectors_batched(reinterpret_cast<const VecDesc*>(db + o_vd), (int)jobs.size(), s);
+        if (!blocked) return;
+        for (const auto& v : jobs) materialize_reflectors(const_cast<double*>(v.V), v.n, v.ldv, s);
+        run_gemm(gS, db, s);
+        larft_batched(reinterpret_cast<const LarftDesc*>(db + o_lf), (int)lf.size(), s);
+        for (auto& st : steps) {
+            run_gemm(st.g1, db, s);
+            run_gemm(st.g2, db, s);
+            run_gemm(st.g3, db, s);
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Commit pipeline.
 // ---------------------------------------------------------------------------
 struct CommitJob {
@@ -388,7 +489,7 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
     if (J == 0) return CMSVD_OK;
     Plan pl;
     struct Off {
-        size_t nb, P, P2, Rt, G1, Li1, Q1, G2, Li2, Qr, F, KT, Sp, lam, d, e, V, tau, sum, Z, vs, cs;
+        size_t nb, P, P2, Rt, G1, Li1, Q1, G2, Li2, Qr, F, KT, Sp, lam, d, e, V, tau, sum, Z, vs, cs, bs;
         int k, nc, nkeep, nu;
         bool full;
     };
@@ -397,6 +498,9 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
     std::vector<int> ks;
     for (const auto& c : jobs) ks.push_back((int)c.B.cols);
     const bool chol_blocked = CholPlan::use_blocked(ks);
+    std::vector<int> ncs;
+    for (const auto& c : jobs) ncs.push_back(c.r_in + (int)c.B.cols);
+    const bool back_blocked = BackPlan::use_blocked(ncs);
     for (int j = 0; j < J; ++j) {
         const CommitJob& c = jobs[j];
         const bool full = c.Z_out != nullptr;
@@ -430,6 +534,7 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
         o[j].Z = pl.add((size_t)nc * nk * 8);
         o[j].vs = pl.add((size_t)6 * nc * nk * 8);
         o[j].cs = chol_blocked ? pl.add(CholPlan::scratch_doubles(k) * 8) : 0;
+        o[j].bs = back_blocked ? pl.add(BackPlan::scratch_doubles(nc, nk) * 8) : 0;
     }
     const int nslots = std::min(J, h->ncu);
     const size_t eig_off = pl.add(sym_eig_workspace_doubles(nmax, nslots) * 8);
@@ -549,7 +654,14 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
     std::vector<FinDesc> fdk;
     for (int j = 0; j < J; ++j)
         if (!o[j].full) fdk.push_back(fd[j]);
-    size_t o_kd = stg.add(kd), o_ed = stg.add(ed), o_vd = stg.add(vd), o_fd = stg.add(fdk);
+    BackPlan bp;
+    {
+        std::vector<double*> scr(J);
+        for (int j = 0; j < J; ++j) scr[j] = D(o[j].bs);
+        bp.build(vd, scr);
+    }
+    size_t o_kd = stg.add(kd), o_ed = stg.add(ed), o_fd = stg.add(fdk);
+    bp.stage(stg);
     for (GemmGroup* g : {&gP32, &gP64, &gR1, &gP2, &gR2, &gG1, &gQ1, &gG2, &gQr, &gF, &gS, &gU1, &gU2a, &gU2b})
         g->off = stg.add(g->d);
     char* db = nullptr;
@@ -578,7 +690,7 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
     assemble_kt_batched(reinterpret_cast<const KtDesc*>(db + o_kd), J, nmax, s);
     run_gemm(gS, db, s);
     sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), J, nmax, 1, D(eig_off), nslots, s);
-    sym_vectors_batched(reinterpret_cast<const VecDesc*>(db + o_vd), J, s);
+    bp.run(db, s);
     run_gemm(gU1, db, s);
     run_gemm(gU2a, db, s);
     run_gemm(gU2b, db, s);
@@ -2316,7 +2428,8 @@ cmsvd_status cmsvd_compress(cmsvd_handle h, const cmsvd_block* blocks, int64_t n
                  o_top = pl.add(16), o_lam = pl.add((size_t)rc * 8), o_d = pl.add((size_t)n * 8),
                  o_e = pl.add((size_t)n * 8), o_V = pl.add((size_t)n * n * 8), o_tau = pl.add((size_t)n * 8),
                  o_vs = pl.add((size_t)6 * n * rc * 8), o_Z = pl.add(cols_side ? 8 : (size_t)n * rc * 8),
-                 o_out = pl.add(16), o_zero = pl.add(16), o_eig = pl.add(sym_eig_workspace_doubles((int)n, 1) * 8);
+                 o_out = pl.add(16), o_zero = pl.add(16), o_eig = pl.add(sym_eig_workspace_doubles((int)n, 1) * 8),
+                 o_bs = pl.add(BackPlan::scratch_doubles((int)n, rc) * 8);
     cmsvd_status st = ensure(h, h->ws, h->ws_cap, pl.off);
     if (st != CMSVD_OK) return st;
     auto D = [&](size_t off) { return reinterpret_cast<double*>(h->ws + off); };
@@ -2360,8 +2473,11 @@ cmsvd_status cmsvd_compress(cmsvd_handle h, const cmsvd_block* blocks, int64_t n
     e.sum_top = D(o_top);
     std::vector<EigDesc> ed{e};
     std::vector<VecDesc> vd{VecDesc{(int)n, rc, D(o_lam), D(o_d), D(o_e), D(o_V), (long)n, D(o_tau), Z, ldz, D(o_vs)}};
+    BackPlan bp;
+    bp.build(vd, {D(o_bs)});
     Stage stg;
-    const size_t o_pk = stg.add(pk), o_nd = stg.add(nd), o_ed = stg.add(ed), o_vd = stg.add(vd);
+    const size_t o_pk = stg.add(pk), o_nd = stg.add(nd), o_ed = stg.add(ed);
+    bp.stage(stg);
     for (GemmGroup* g : {&gG, &gV, &gU}) g->off = stg.add(g->d);
     char* db = nullptr;
     st = upload(h, stg, &db);
@@ -2371,7 +2487,7 @@ cmsvd_status cmsvd_compress(cmsvd_handle h, const cmsvd_block* blocks, int64_t n
     sumsq_batched(reinterpret_cast<const NormDesc*>(db + o_nd), N, s);
     run_gemm(gG, db, s);
     sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), 1, (int)n, 1, D(o_eig), 1, s);
-    sym_vectors_batched(reinterpret_cast<const VecDesc*>(db + o_vd), 1, s);
+    bp.run(db, s);
     // directions below the Gram's resolution (8 n u lam_1) are stored as zero columns
     const double cut_rel = 8.0 * (double)n * EPS;
     if (cols_side) {

@@ -1119,6 +1119,14 @@ __global__ void __launch_bounds__(ET) sym_vectors_kernel(const VecDesc* __restri
         __syncthreads();
     }
 
+    if (D.skip_bt) {
+        for (int el = t; el < nk * n; el += ET) {
+            const int i = el % n, q = el / n;
+            D.Z[(long)i + (long)q * D.ldz] = at(4, i, q);
+        }
+        return;
+    }
+
     // (3) back-transformation z = H_0 H_1 ... H_{n-3} x, vectors in LDS panels
     const long hdr = (16L + ((nk + 15) / 16) * 16) * 8 + (long)n * 8;  // red + coef + v_j
     const int nv = (int)((LDS_BYTES - hdr) / ((long)n * 8));

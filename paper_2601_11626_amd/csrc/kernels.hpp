@@ -67,8 +67,26 @@ struct VecDesc {
     double* Z;
     long ldz;
     double* scratch;
+    // nonzero: stop after the orthonormalisation and leave the eigenvectors of the
+    // tridiagonal in Z (the caller applies the reflectors, e.g. blocked)
+    int skip_bt;
 };
 void sym_vectors_batched(const VecDesc* d_descs, int count, hipStream_t s);
+
+// Blocked back-transformation helpers.  V (n x n column-major, ldv) holds reflector j
+// in column j on rows >= j + 2; materialize_reflectors writes the implicit unit at row
+// j + 1 and zeros above it (j < n - 2).  larft: for a block of b reflectors with Gram
+// S = V_b^T V_b (b x b, ld ldst) and tau, the upper-triangular T (ld ldst) of
+// H_j0 ... H_j0+b-1 = I - V_b T V_b^T.
+void materialize_reflectors(double* V, int n, long ldv, hipStream_t s);
+struct LarftDesc {
+    const double* S;
+    const double* tau;
+    double* T;
+    int b;
+    long ld;
+};
+void larft_batched(const LarftDesc* d_descs, int count, hipStream_t s);
 
 // Semidefinite Cholesky with a pivot threshold, in place on the lower triangle
 // of G (column-major, ldg).  A pivot <= thresh zeroes its column of L.  Then

@@ -244,4 +244,62 @@ void pack_batched(const PackDesc* d_descs, int count, hipStream_t s) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Blocked back-transformation of eigenvectors (compact WY form of the stored
+// Householder reflectors).
+// ---------------------------------------------------------------------------
+__global__ void materialize_reflectors_kernel(double* __restrict__ V, int n, long ldv) {
+    // column j (< n - 2): zeros on rows <= j, the implicit 1 on row j + 1
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < (long)(n - 2) * n; e += (long)gridDim.x * 256) {
+        const int j = (int)(e / n), i = (int)(e - (long)j * n);
+        if (i <= j) V[(long)i + (long)j * ldv] = 0.0;
+        else if (i == j + 1) V[(long)i + (long)j * ldv] = 1.0;
+    }
+}
+
+void materialize_reflectors(double* V, int n, long ldv, hipStream_t s) {
+    if (n < 3) return;
+    const long tot = (long)(n - 2) * n;
+    const int g = (int)std::min<long>((tot + 255) / 256, 2048);
+    hipLaunchKernelGGL(materialize_reflectors_kernel, dim3(g), dim3(256), 0, s, V, n, ldv);
+}
+
+// One wavefront per block (b <= 32): column i of T from the columns before it
+// (forward, columnwise): T(i,i) = tau_i, T(0:i, i) = -tau_i T(0:i, 0:i) S(0:i, i).
+// T is built in LDS and written out at the end.
+__global__ void __launch_bounds__(64) larft_kernel(const LarftDesc* __restrict__ descs) {
+    const LarftDesc D = descs[blockIdx.x];
+    __shared__ double Ts[32 * 32];
+    const int k = threadIdx.x, b = D.b;
+    for (int e = k; e < 32 * 32; e += 64) Ts[e] = 0.0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int i = 0; i < b; ++i) {
+        const double ti = D.tau[i];
+        double v = 0.0;
+        if (k < i) {
+            for (int l = k; l < i; ++l) v = fma(Ts[k + 32 * l], D.S[(long)l + (long)i * D.ld], v);
+            v *= -ti;
+        }
+        if (k < i) Ts[k + 32 * i] = v;
+        if (k == i) Ts[i + 32 * i] = ti;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    for (int e = k; e < b * b; e += 64) {
+        const int r = e % b, c = e / b;
+        D.T[(long)r + (long)c * D.ld] = Ts[r + 32 * c];
+    }
+}
+
+void larft_batched(const LarftDesc* d_descs, int count, hipStream_t s) {
+    if (count <= 0) return;
+    for (int base = 0; base < count; base += 65535) {
+        const int n = count - base < 65535 ? count - base : 65535;
+        hipLaunchKernelGGL(larft_kernel, dim3(n), dim3(64), 0, s, d_descs + base);
+    }
+}
+
 }  // namespace cmsvd
