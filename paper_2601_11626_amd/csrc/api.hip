@@ -821,8 +821,15 @@ cmsvd_status eval_dense(cmsvd_ctx* h, const DenseEval& de, const std::vector<int
         const size_t nj = end - pos;
         const int nslots = (int)std::min<size_t>(nj, (size_t)h->ncu);
         const long ldc = (long)(a1 - a0) * r;
+        // the packed candidate columns this chunk's pairs use
+        long cmin = de.ksum, cmax = 0;
+        for (size_t i = pos; i < end; ++i) {
+            const size_t p = order[i];
+            cmin = std::min(cmin, pair_coff[p]);
+            cmax = std::max(cmax, pair_coff[p] + (long)jobs[p].B.cols);
+        }
         Plan pl;
-        const size_t c_off = pl.add((size_t)ldc * de.ksum * 8);
+        const size_t c_off = pl.add((size_t)ldc * (cmax - cmin) * 8);
         const size_t eig_off = pl.add(sym_eig_workspace_doubles(nmax, nslots) * 8);
         cmsvd_status st = ensure(h, h->ws, h->ws_cap, pl.off);
         if (st != CMSVD_OK) return st;
@@ -830,7 +837,8 @@ cmsvd_status eval_dense(cmsvd_ctx* h, const DenseEval& de, const std::vector<int
         GemmGroup g;
         g.tb = true;
         g.bf32 = de.ball_f32;
-        g.push(GemmDesc{de.Uall + (size_t)a0 * r, de.Ball, C, (int)ldc, (int)de.ksum, de.m, (long)de.na * r,
+        const char* Bc = static_cast<const char*>(de.Ball) + (size_t)cmin * (de.ball_f32 ? 4 : 8);
+        g.push(GemmDesc{de.Uall + (size_t)a0 * r, Bc, C, (int)ldc, (int)(cmax - cmin), de.m, (long)de.na * r,
                         de.ksum, ldc});
         std::vector<EigDesc> ed(nj);
         for (size_t i = 0; i < nj; ++i) {
@@ -841,7 +849,7 @@ cmsvd_status eval_dense(cmsvd_ctx* h, const DenseEval& de, const std::vector<int
             e.n1 = r;
             e.nkeep = r;
             e.s = j.S;
-            e.P = C + (size_t)(pair_anchor[p] - a0) * r + (size_t)pair_coff[p] * ldc;
+            e.P = C + (size_t)(pair_anchor[p] - a0) * r + (size_t)(pair_coff[p] - cmin) * ldc;
             e.ldp = ldc;
             e.Y = j.G;
             e.ldy = (int)j.B.cols;
@@ -1791,9 +1799,15 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
             kmax_c = std::max(kmax_c, (int)blocks[i].cols);
             all_f32 &= blocks[i].dtype == CMSVD_F32;
         }
-    double pair_work = 0.0;
-    for (int64_t p = 0; p < npairs; ++p) pair_work += (double)blocks[pairs[2 * p + 1]].cols;
-    const bool dense = (r < 64 || kmax_c < 64) && (double)anchors.size() * (double)ksum <= 4.0 * pair_work;
+    // per-pair GEMMs fill 64 x 64 tiles: with r x k outputs well below whole tiles the
+    // dense form (every anchor against a range of packed candidates) does less work
+    double pair_work = 0.0, tile_work = 0.0;
+    for (int64_t p = 0; p < npairs; ++p) {
+        const double k = (double)blocks[pairs[2 * p + 1]].cols;
+        pair_work += k;
+        tile_work += std::ceil(k / 64.0) * 64.0 * std::ceil((double)r / 64.0) * 64.0 / (double)r;
+    }
+    const bool dense = pair_work < 0.5 * tile_work && (double)anchors.size() * (double)ksum <= 4.0 * pair_work;
     // persistent per-call buffers: norms + grams (all involved), anchor states
     Plan pl;
     std::vector<size_t> o_n(cands.size()), o_g(cands.size());
@@ -1826,6 +1840,29 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
     }
     cmsvd_status st = norms_and_grams(h, bl, nrm, gram);
     if (st != CMSVD_OK) return st;
+    if (dense) {
+        // Anchors side by side and candidates packed both by decreasing norm: for the
+        // usual anchor-first pair lists a chunk of anchors then pairs with a suffix of
+        // the packed candidates, and its GEMM covers only that column range.
+        std::vector<double> nh(2 * cands.size());
+        for (size_t c = 0; c < cands.size(); ++c)
+            HIPCHK(hipMemcpyAsync(&nh[2 * c], K(o_n[c]), 16, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        std::vector<double> n2(nblocks, 0.0);
+        for (size_t c = 0; c < cands.size(); ++c) n2[cands[c]] = nh[2 * c] + nh[2 * c + 1];
+        auto by_norm = [&](int a, int b) { return n2[a] > n2[b] || (n2[a] == n2[b] && a < b); };
+        std::stable_sort(anchors.begin(), anchors.end(), by_norm);
+        for (size_t a = 0; a < anchors.size(); ++a) aslot[anchors[a]] = (int)a;
+        std::vector<int> corder;
+        for (int i = 0; i < nblocks; ++i)
+            if (is_cand[i]) corder.push_back(i);
+        std::stable_sort(corder.begin(), corder.end(), by_norm);
+        long off = 0;
+        for (int i : corder) {
+            coff[i] = off;
+            off += blocks[i].cols;
+        }
+    }
     // anchor states: the update from the empty state (Algorithm 3, step 1)
     for (size_t a = 0; a < anchors.size(); ++a) HIPCHK(hipMemsetAsync(K(o_acc[a]), 0, 32, h->stream));
     {

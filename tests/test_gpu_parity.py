@@ -192,6 +192,26 @@ def test_merge_errors_ragged_and_uneven(cm):
         assert_est(err[p], err_o[p], nm, f"pair {(i, j)}")
 
 
+@pytest.mark.parametrize("r,k", [(67, 67), (20, 20), (40, 100)])
+def test_merge_errors_dense_projection_shapes(cm, r, k):
+    """Shapes whose per-pair products fill 64 x 64 tiles poorly take the dense form
+    (anchors and candidates ordered by norm, one GEMM per anchor chunk over the candidate
+    columns its pairs use): all anchor-first pairs, plus a shuffled list of both orders."""
+    say(f"merge_errors dense shapes r={r} k={k}")
+    blocks = workloads.table1_like(seed=3, nblocks=10, m=160, k=k, groups=3, d=8, noise=0.05, dtype=np.float64)
+    rng = np.random.default_rng(r + k)
+    pairs = workloads.anchor_ordered_pairs(blocks)
+    both = [(i, j) for i in range(10) for j in range(10) if i != j]
+    shuffled = [both[t] for t in rng.permutation(len(both))]
+    for plist in (pairs, shuffled):
+        err_o, _ = oracle.merge_errors(blocks, plist, r, nthreads=8)
+        err, _ = cm.cmsvd_merge_errors(dev_tensors(blocks), plist, r)
+        err = err.cpu().numpy()
+        for p, (i, j) in enumerate(plist):
+            nm = math.sqrt(oracle.frob2(blocks[i]) + oracle.frob2(blocks[j]))
+            assert_est(err[p], err_o[p], nm, f"pair {(i, j)}")
+
+
 def test_merge_errors_rotated_groups_full_shape(cm):
     """Full per-block shape of the batched-pair workload (1024x256, r=64): 4 blocks
     from 2 groups, all 6 anchor-first pairs."""
