@@ -442,10 +442,16 @@ constexpr int REG_PWL = RW * REG_NP;                                     // per-
 constexpr int REG_GEO_INTS = RW * NSLOT + RW * REG_TMAX;
 constexpr int REG_LDS_DOUBLES = 7 * REG_NP + REG_PWL + 16 + RTL * (RTL + 1) / 2 * TILE_EL + REG_GEO_INTS / 2;
 static_assert(REG_LDS_DOUBLES * 8 <= LDS_BYTES, "register-resident eigen kernel exceeds the LDS");
+// Thin cores (65..160): 256 threads, 4 slots per wave (16 >= 15 tiles), no LDS tiles.
+constexpr int THIN_TMAX = 5;
+constexpr int THIN_NSLOT = 4;
+constexpr int THIN_LDS_DOUBLES = 7 * THIN_TMAX * TILE + 4 * THIN_TMAX * TILE + 16 + (4 * THIN_NSLOT + 4 * THIN_TMAX + 1) / 2;
 
-template <int MODE>
-__global__ void __launch_bounds__(RT) sym_eig_reg_kernel(const EigDesc* __restrict__ descs, int count) {
-    constexpr int NP = REG_NP, PWL = REG_PWL;
+template <int MODE, int RT_, int NSLOT_, int RTL_, int TMAX_>
+__global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_reg_kernel(const EigDesc* __restrict__ descs,
+                                                                                 int count) {
+    constexpr int RT = RT_, RW = RT_ / 64, NSLOT = NSLOT_, RTL = RTL_;
+    constexpr int NP = TMAX_ * TILE, PWL = RW * NP;
     extern __shared__ double lds[];
     double* xv = lds;           // current column below the diagonal (later e^2)
     double* vc = xv + NP;       // Householder vector v_j of the current step
@@ -973,15 +979,31 @@ void sym_eig_batched(const EigDesc* d_descs, int count, int nmax, int mode, doub
         else hipLaunchKernelGGL(sym_eig_small_kernel<1>, dim3(grid), dim3(64 * SWV), 0, s, d_descs, count);
         return;
     }
+    if (T <= THIN_TMAX) {
+        // cores up to 160: every tile in the VGPRs of four waves, so two problems share a CU
+        const size_t lds = (size_t)THIN_LDS_DOUBLES * 8;
+        const int grid = count < 2048 ? count : 2048;
+        if (mode == 0)
+            hipLaunchKernelGGL((sym_eig_reg_kernel<0, 256, THIN_NSLOT, 0, THIN_TMAX>), dim3(grid), dim3(256), lds, s,
+                               d_descs, count);
+        else
+            hipLaunchKernelGGL((sym_eig_reg_kernel<1, 256, THIN_NSLOT, 0, THIN_TMAX>), dim3(grid), dim3(256), lds, s,
+                               d_descs, count);
+        return;
+    }
     if (T <= REG_TMAX) {
         const size_t lds = (size_t)REG_LDS_DOUBLES * 8;
         const int grid = count < nslots ? count : nslots;
         if (mode == 0) {
-            (void)hipFuncSetAttribute((const void*)sym_eig_reg_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(sym_eig_reg_kernel<0>, dim3(grid), dim3(RT), lds, s, d_descs, count);
+            (void)hipFuncSetAttribute((const void*)sym_eig_reg_kernel<0, RT, NSLOT, RTL, REG_TMAX>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL((sym_eig_reg_kernel<0, RT, NSLOT, RTL, REG_TMAX>), dim3(grid), dim3(RT), lds, s, d_descs,
+                               count);
         } else {
-            (void)hipFuncSetAttribute((const void*)sym_eig_reg_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(sym_eig_reg_kernel<1>, dim3(grid), dim3(RT), lds, s, d_descs, count);
+            (void)hipFuncSetAttribute((const void*)sym_eig_reg_kernel<1, RT, NSLOT, RTL, REG_TMAX>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL((sym_eig_reg_kernel<1, RT, NSLOT, RTL, REG_TMAX>), dim3(grid), dim3(RT), lds, s, d_descs,
+                               count);
         }
         return;
     }
