@@ -137,6 +137,14 @@ cmsvd_status upload(cmsvd_ctx* h, const Stage& st, char** dbase) {
     return CMSVD_OK;
 }
 
+// A device allocation owned by one call (separate from the workspace arena).
+struct DevBuf {
+    char* p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
 enum { ST_PREP = 0, ST_COMMIT = 1, ST_PROJ = 2, ST_CORE = 3, NSTAGE = 4 };
 
 hipEvent_t take_event(cmsvd_ctx* h) {
@@ -798,25 +806,42 @@ struct DenseEval {
     long ksum;
 };
 
-cmsvd_status eval_dense(cmsvd_ctx* h, const DenseEval& de, const std::vector<int>& pair_anchor,
-                        const std::vector<EvalJob>& jobs, const std::vector<long>& pair_coff) {
-    const size_t total = jobs.size();
+cmsvd_status eval_dense(cmsvd_ctx* h, const DenseEval& de, const std::vector<PairRec>& pairs,
+                        const std::vector<AnchorRec>& arec, const std::vector<CandRec>& crec, double* err,
+                        double* rel) {
+    const size_t total = pairs.size();
     if (total == 0) return CMSVD_OK;
     const int r = de.r;
-    // pairs grouped by anchor
-    std::vector<size_t> order(total);
-    for (size_t i = 0; i < total; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return pair_anchor[x] < pair_anchor[y]; });
+    // pairs grouped by anchor slot (counting sort, stable)
+    std::vector<size_t> start((size_t)de.na + 1, 0);
+    for (const auto& p : pairs) ++start[(size_t)p.slot + 1];
+    for (int a = 0; a < de.na; ++a) start[(size_t)a + 1] += start[(size_t)a];
+    std::vector<PairRec> sorted(total);
+    {
+        std::vector<size_t> fill(start.begin(), start.end() - 1);
+        for (const auto& p : pairs) sorted[fill[(size_t)p.slot]++] = p;
+    }
     int kmax = 0;
-    for (const auto& j : jobs) kmax = std::max(kmax, (int)j.B.cols);
+    for (const auto& c : crec) kmax = std::max(kmax, c.k);
     const int nmax = r + kmax;
+    // the records live on the device for the whole call
+    DevBuf recs;
+    const size_t b_a = align256(arec.size() * sizeof(AnchorRec)), b_c = align256(crec.size() * sizeof(CandRec));
+    if (hipMalloc((void**)&recs.p, b_a + b_c + total * sizeof(PairRec)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CMSVD_ENOMEM, "cmsvd_merge_errors: hipMalloc of %zu pair records failed", total);
+    }
+    const AnchorRec* dA = reinterpret_cast<const AnchorRec*>(recs.p);
+    const CandRec* dC = reinterpret_cast<const CandRec*>(recs.p + b_a);
+    const PairRec* dP = reinterpret_cast<const PairRec*>(recs.p + b_a + b_c);
+    HIPCHK(hipMemcpy(recs.p, arec.data(), arec.size() * sizeof(AnchorRec), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(recs.p + b_a, crec.data(), crec.size() * sizeof(CandRec), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(recs.p + b_a + b_c, sorted.data(), total * sizeof(PairRec), hipMemcpyHostToDevice));
     const size_t row_bytes = (size_t)de.ksum * r * 8;  // C rows of one anchor
     const int achunk = (int)std::max<size_t>(1, ((size_t)8 << 30) / std::max<size_t>(row_bytes, 1));
-    size_t pos = 0;
-    for (int a0 = 0; a0 < de.na && pos < total; a0 += achunk) {
+    for (int a0 = 0; a0 < de.na; a0 += achunk) {
         const int a1 = std::min(de.na, a0 + achunk);
-        size_t end = pos;
-        while (end < total && pair_anchor[order[end]] < a1) ++end;
+        const size_t pos = start[(size_t)a0], end = start[(size_t)a1];
         if (end == pos) continue;
         const size_t nj = end - pos;
         const int nslots = (int)std::min<size_t>(nj, (size_t)h->ncu);
@@ -824,44 +849,26 @@ cmsvd_status eval_dense(cmsvd_ctx* h, const DenseEval& de, const std::vector<int
         // the packed candidate columns this chunk's pairs use
         long cmin = de.ksum, cmax = 0;
         for (size_t i = pos; i < end; ++i) {
-            const size_t p = order[i];
-            cmin = std::min(cmin, pair_coff[p]);
-            cmax = std::max(cmax, pair_coff[p] + (long)jobs[p].B.cols);
+            const CandRec& c = crec[(size_t)sorted[i].cand];
+            cmin = std::min(cmin, c.coff);
+            cmax = std::max(cmax, c.coff + (long)c.k);
         }
         Plan pl;
         const size_t c_off = pl.add((size_t)ldc * (cmax - cmin) * 8);
+        const size_t d_off = pl.add(nj * sizeof(EigDesc));
         const size_t eig_off = pl.add(sym_eig_workspace_doubles(nmax, nslots) * 8);
         cmsvd_status st = ensure(h, h->ws, h->ws_cap, pl.off);
         if (st != CMSVD_OK) return st;
         double* C = reinterpret_cast<double*>(h->ws + c_off);
+        EigDesc* ed = reinterpret_cast<EigDesc*>(h->ws + d_off);
         GemmGroup g;
         g.tb = true;
         g.bf32 = de.ball_f32;
         const char* Bc = static_cast<const char*>(de.Ball) + (size_t)cmin * (de.ball_f32 ? 4 : 8);
         g.push(GemmDesc{de.Uall + (size_t)a0 * r, Bc, C, (int)ldc, (int)(cmax - cmin), de.m, (long)de.na * r,
                         de.ksum, ldc});
-        std::vector<EigDesc> ed(nj);
-        for (size_t i = 0; i < nj; ++i) {
-            const size_t p = order[pos + i];
-            const EvalJob& j = jobs[p];
-            EigDesc e{};
-            e.n = r + (int)j.B.cols;
-            e.n1 = r;
-            e.nkeep = r;
-            e.s = j.S;
-            e.P = C + (size_t)(pair_anchor[p] - a0) * r + (size_t)(pair_coff[p] - cmin) * ldc;
-            e.ldp = ldc;
-            e.Y = j.G;
-            e.ldy = (int)j.B.cols;
-            e.na = j.na;
-            e.nb = j.nb;
-            e.out_err = j.err;
-            e.out_rel = j.rel;
-            ed[i] = e;
-        }
         Stage stg;
         g.off = stg.add(g.d);
-        const size_t o_ed = stg.add(ed);
         char* db = nullptr;
         st = upload(h, stg, &db);
         if (st != CMSVD_OK) return st;
@@ -869,14 +876,15 @@ cmsvd_status eval_dense(cmsvd_ctx* h, const DenseEval& de, const std::vector<int
             StageMark mark(h, ST_PROJ);
             run_gemm(g, db, h->stream);
         }
+        expand_dense_descs(dP + pos, (int)nj, dA, dC, r, a0, C, ldc, cmin, err, rel, ed, h->stream);
         {
             StageMark mark(h, ST_CORE);
-            sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), (int)nj, nmax, 0,
-                            reinterpret_cast<double*>(h->ws + eig_off), nslots, h->stream);
+            sym_eig_batched(ed, (int)nj, nmax, 0, reinterpret_cast<double*>(h->ws + eig_off), nslots, h->stream);
         }
         HIPCHK(hipGetLastError());
-        pos = end;
     }
+    // the records are freed on return
+    HIPCHK(hipStreamSynchronize(h->stream));
     return CMSVD_OK;
 }
 
@@ -913,8 +921,6 @@ cmsvd_status norms_and_grams(cmsvd_ctx* h, const std::vector<cmsvd_block>& bl, c
     return CMSVD_OK;
 }
 
-// Persistent device buffers owned by one call (separate from the scratch arena,
-// which the pipelines above reuse).
 // One GEMM (column-major, FP64 accumulate) issued on the handle's stream.
 cmsvd_status gemm1(cmsvd_ctx* h, bool ta, bool tb, int M, int N, int K, double alpha, const void* A, long lda,
                    bool af32, const void* B, long ldb, bool bf32, double beta, double* C, long ldc) {
@@ -1217,12 +1223,6 @@ cmsvd_status resid_reset(cmsvd_ctx* h, ResidState& st) {
     return CMSVD_OK;
 }
 
-struct DevBuf {
-    char* p = nullptr;
-    ~DevBuf() {
-        if (p) (void)hipFree(p);
-    }
-};
 
 
 struct ResidBuffers {
@@ -1884,14 +1884,6 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
             if (st != CMSVD_OK) return st;
         }
     }
-    std::vector<EvalJob> ej;
-    ej.reserve((size_t)npairs);
-    for (int64_t p = 0; p < npairs; ++p) {
-        const int i = pairs[2 * p], jb = pairs[2 * p + 1];
-        const int a = aslot[i];
-        ej.push_back(EvalJob{K(o_U[a]), ldu_a, K(o_S[a]), (int)r, K(o_n[cslot[i]]), blocks[jb], K(o_n[cslot[jb]]),
-                             K(o_g[cslot[jb]]), err + p, rel ? rel + p : nullptr});
-    }
     if (dense) {
         // pack the candidates side by side
         std::vector<PackDesc> pd;
@@ -1910,15 +1902,24 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
             pack_batched(reinterpret_cast<const PackDesc*>(db + o_pd), (int)pd.size(), h->stream);
         }
         HIPCHK(hipGetLastError());
-        std::vector<int> pa((size_t)npairs);
-        std::vector<long> pc((size_t)npairs);
-        for (int64_t p = 0; p < npairs; ++p) {
-            pa[p] = aslot[pairs[2 * p]];
-            pc[p] = coff[pairs[2 * p + 1]];
-        }
+        std::vector<AnchorRec> arec(anchors.size());
+        for (size_t a = 0; a < anchors.size(); ++a) arec[a] = AnchorRec{K(o_S[a]), K(o_n[cslot[anchors[a]]])};
+        std::vector<CandRec> crec(nblocks, CandRec{nullptr, nullptr, 0, 0});
+        for (int i = 0; i < nblocks; ++i)
+            if (is_cand[i]) crec[i] = CandRec{K(o_n[cslot[i]]), K(o_g[cslot[i]]), coff[i], (int)blocks[i].cols};
+        std::vector<PairRec> pr((size_t)npairs);
+        for (int64_t p = 0; p < npairs; ++p) pr[(size_t)p] = PairRec{aslot[pairs[2 * p]], pairs[2 * p + 1], (int)p};
         DenseEval de{K(o_Uall), (int)anchors.size(), (int)r, (int)m, keep.p + o_Ball, all_f32, ksum};
-        st = eval_dense(h, de, pa, ej, pc);
+        st = eval_dense(h, de, pr, arec, crec, err, rel);
     } else {
+        std::vector<EvalJob> ej;
+        ej.reserve((size_t)npairs);
+        for (int64_t p = 0; p < npairs; ++p) {
+            const int i = pairs[2 * p], jb = pairs[2 * p + 1];
+            const int a = aslot[i];
+            ej.push_back(EvalJob{K(o_U[a]), ldu_a, K(o_S[a]), (int)r, K(o_n[cslot[i]]), blocks[jb], K(o_n[cslot[jb]]),
+                                 K(o_g[cslot[jb]]), err + p, rel ? rel + p : nullptr});
+        }
         st = eval_batched(h, ej, (int)m);
     }
     if (st != CMSVD_OK) return st;

@@ -73,6 +73,26 @@ struct VecDesc {
 };
 void sym_vectors_batched(const VecDesc* d_descs, int count, hipStream_t s);
 
+// Dense evaluation of many pairs: compact records expanded into eigenproblem
+// descriptors on the device.  Pair i of a chunk: anchor slot, candidate block, output
+// index; the candidate's P is read in place from the chunk's product C
+// (P = C + (slot - a0) r + (coff - cmin) ldc).
+struct AnchorRec {
+    const double* S;   // singular values of the anchor state (r)
+    const double* na;  // its energy (double-double)
+};
+struct CandRec {
+    const double* nb;  // energy (double-double)
+    const double* G;   // Gram B^T B (k x k)
+    long coff;         // first column in the packed candidates
+    int k;
+};
+struct PairRec {
+    int slot, cand, out;
+};
+void expand_dense_descs(const PairRec* pr, int count, const AnchorRec* A, const CandRec* Cr, int r, int a0,
+                        const double* C, long ldc, long cmin, double* err, double* rel, EigDesc* out, hipStream_t s);
+
 // Blocked back-transformation helpers.  V (n x n column-major, ldv) holds reflector j
 // in column j on rows >= j + 2; materialize_reflectors writes the implicit unit at row
 // j + 1 and zeros above it (j < n - 2).  larft: for a block of b reflectors with Gram

@@ -245,6 +245,41 @@ void pack_batched(const PackDesc* d_descs, int count, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// Dense evaluation: one eigenproblem descriptor per compact pair record.
+// ---------------------------------------------------------------------------
+__global__ void expand_dense_descs_kernel(const PairRec* __restrict__ pr, int count, const AnchorRec* __restrict__ A,
+                                          const CandRec* __restrict__ Cr, int r, int a0, const double* C, long ldc,
+                                          long cmin, double* err, double* rel, EigDesc* __restrict__ out) {
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < count; i += gridDim.x * 256) {
+        const PairRec p = pr[i];
+        const AnchorRec a = A[p.slot];
+        const CandRec c = Cr[p.cand];
+        EigDesc e{};
+        e.n = r + c.k;
+        e.n1 = r;
+        e.nkeep = r;
+        e.s = a.S;
+        e.P = C + (size_t)(p.slot - a0) * r + (size_t)(c.coff - cmin) * ldc;
+        e.ldp = ldc;
+        e.Y = c.G;
+        e.ldy = c.k;
+        e.na = a.na;
+        e.nb = c.nb;
+        e.out_err = err + p.out;
+        e.out_rel = rel ? rel + p.out : nullptr;
+        out[i] = e;
+    }
+}
+
+void expand_dense_descs(const PairRec* pr, int count, const AnchorRec* A, const CandRec* Cr, int r, int a0,
+                        const double* C, long ldc, long cmin, double* err, double* rel, EigDesc* out, hipStream_t s) {
+    if (count <= 0) return;
+    const int g = (count + 255) / 256 < 4096 ? (count + 255) / 256 : 4096;
+    hipLaunchKernelGGL(expand_dense_descs_kernel, dim3(g), dim3(256), 0, s, pr, count, A, Cr, r, a0, C, ldc, cmin, err,
+                       rel, out);
+}
+
+// ---------------------------------------------------------------------------
 // Blocked back-transformation of eigenvectors (compact WY form of the stored
 // Householder reflectors).
 // ---------------------------------------------------------------------------
