@@ -23,7 +23,8 @@ import math
 import numpy as np
 
 
-def cluster(blocks, r: int, eps: float, sort_mode: str = "frobenius", record: list | None = None):
+def cluster(blocks, r: int, eps: float, sort_mode: str = "frobenius", record: list | None = None,
+            projection: str = "f64"):
     """Returns (labels, clusters, cluster_rel).
 
     labels[i]   -- cluster id of block i, ids in creation order;
@@ -31,8 +32,11 @@ def cluster(blocks, r: int, eps: float, sort_mode: str = "frobenius", record: li
     cluster_rel -- final Etilde / ||M_C||_F per cluster.
     If ``record`` is a list, every tentative evaluation is appended to it as a dict
     {cluster, candidate, rel, accepted}.
+    ``projection`` "bf16" evaluates candidates in the Gram form with BF16-rounded
+    projection operands (``lowprec.candidate_estimate2``); an accepted candidate is
+    still committed by the FP64 update.
     """
-    from . import State, frob2, update, _f64
+    from . import State, frob2, update, _f64, lowprec
 
     if sort_mode not in ("frobenius", "residual"):
         raise ValueError("sort_mode must be 'frobenius' or 'residual'")
@@ -65,13 +69,18 @@ def cluster(blocks, r: int, eps: float, sort_mode: str = "frobenius", record: li
                 order = sorted(remaining, key=lambda j: (keys[j], j))
             accepted = False
             for j in order:
-                cand = update(state, blocks[j], r)
-                rel = cand.estimate() / math.sqrt(cand.etot) if cand.etot > 0 else 0.0
+                if projection == "f64":
+                    cand = update(state, blocks[j], r)
+                    rel = cand.estimate() / math.sqrt(cand.etot) if cand.etot > 0 else 0.0
+                else:
+                    e2, et = lowprec.candidate_estimate2(state, blocks[j], r, projection)
+                    rel = math.sqrt(e2) / math.sqrt(et) if et > 0 else 0.0
+                    cand = None
                 ok = rel <= eps
                 if record is not None:
                     record.append({"cluster": cid, "candidate": j, "rel": rel, "accepted": ok})
                 if ok:
-                    state = cand
+                    state = cand if cand is not None else update(state, blocks[j], r)
                     members.append(j)
                     labels[j] = cid
                     remaining.remove(j)
