@@ -55,6 +55,9 @@ typedef struct cmsvd_ctx* cmsvd_handle;
 
 typedef enum { CMSVD_F32 = 0, CMSVD_F64 = 2 } cmsvd_dtype;
 
+/* Precision of the candidate projections Y = U_r^T A_j (see cmsvd_set_projection). */
+typedef enum { CMSVD_PROJ_F64 = 0, CMSVD_PROJ_BF16 = 1, CMSVD_PROJ_BF16X3 = 2 } cmsvd_projection;
+
 typedef enum {
     CMSVD_OK = 0,
     CMSVD_EINVAL = 1,      /* bad argument value (null pointer, r < 1, index out of range, ...) */
@@ -77,6 +80,27 @@ typedef struct {
 cmsvd_status cmsvd_create(cmsvd_handle* handle, void* hip_stream);
 cmsvd_status cmsvd_destroy(cmsvd_handle handle);
 cmsvd_status cmsvd_set_stream(cmsvd_handle handle, void* hip_stream);
+
+/* Selects the precision of the projections Y = U_r^T A_j that candidate evaluations
+   compute (Lemma 1; the off-diagonal block of the enlarged Gram of Corollary 3) in
+   cmsvd_merge_errors and in the scan of cmsvd_cluster.
+     CMSVD_PROJ_F64    (default) operands promoted to FP64 exactly, FP64 accumulation.
+     CMSVD_PROJ_BF16   every element x of U_r and of A_j is rounded to FP32 (x32) and
+                       then to BF16 (hi), both round-to-nearest-even; the products
+                       hi_U hi_A are summed in FP32 on the matrix cores and widened to
+                       FP64.
+     CMSVD_PROJ_BF16X3 the same with lo = BF16(x32 - hi) staged too, summing
+                       lo_U hi_A + hi_U lo_A + hi_U hi_A in FP32: three BF16 matrix-core
+                       passes that carry about 16 significant bits per operand.
+   Everything else stays FP64: block norms and Grams A_j^T A_j, the anchors'
+   truncations and every state update of the clustering (an accepted candidate is
+   committed in FP64), the residual ordering of sort_mode 1, the core eigenvalues and
+   the compensated plug-in subtraction.  The core is evaluated in Gram form
+   [[S^2, S Y], [Y^T S, A_j^T A_j]], where an error in Y moves the top-r eigenvalue sum
+   to first order, so the relative deviation of err from the FP64 path grows as
+   err / ||[A_i, A_j]||_F shrinks.  Returns CMSVD_EINVAL for any other value; the
+   setting applies to calls issued afterwards on this handle. */
+cmsvd_status cmsvd_set_projection(cmsvd_handle handle, int32_t precision);
 const char* cmsvd_last_error(void);
 
 /* One incremental step: Lemma 1 (projection Y = U^T B, residual R = B - U Y, thin
@@ -282,6 +306,16 @@ cmsvd_status cmsvd_profile_read(cmsvd_handle handle, double* ms, int64_t* count)
 cmsvd_status cmsvd_gemm_f64(cmsvd_handle handle, int32_t trans_a, int32_t trans_b, int64_t M, int64_t N, int64_t K,
                             double alpha, const void* A, int64_t lda, int32_t a_dtype, const void* B, int64_t ldb,
                             int32_t b_dtype, double beta, double* C, int64_t ldc);
+
+/* The same GEMM with BF16 operands, the kernel of CMSVD_PROJ_BF16 (passes = 1) and
+   CMSVD_PROJ_BF16X3 (passes = 3): every element of op(A) and op(B) is rounded to FP32
+   and then to BF16 (round-to-nearest-even) as it is staged, with the BF16 remainder as
+   a second part when passes = 3; products are summed in FP32 on the matrix cores
+   (v_mfma_f32_16x16x32_bf16), and alpha, beta and C are FP64.  Otherwise the same
+   arguments and errors as cmsvd_gemm_f64; passes other than 1 or 3 give CMSVD_EINVAL. */
+cmsvd_status cmsvd_gemm_bf16(cmsvd_handle handle, int32_t passes, int32_t trans_a, int32_t trans_b, int64_t M,
+                             int64_t N, int64_t K, double alpha, const void* A, int64_t lda, int32_t a_dtype,
+                             const void* B, int64_t ldb, int32_t b_dtype, double beta, double* C, int64_t ldc);
 
 #ifdef __cplusplus
 }

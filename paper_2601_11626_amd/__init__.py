@@ -47,6 +47,8 @@ def _load():
     lib.cmsvd_cluster.argtypes = [vp, ctypes.POINTER(Block), i64, i64, d, i32, vp, ctypes.POINTER(i64), vp]
     lib.cmsvd_sym_eigvals.argtypes = [vp, vp, i64, i64, i64, i64, i64, vp]
     lib.cmsvd_gemm_f64.argtypes = [vp, i32, i32, i64, i64, i64, d, vp, i64, i32, vp, i64, i32, d, vp, i64]
+    lib.cmsvd_gemm_bf16.argtypes = [vp, i32, i32, i32, i64, i64, i64, d, vp, i64, i32, vp, i64, i32, d, vp, i64]
+    lib.cmsvd_set_projection.argtypes = [vp, i32]
     lib.cmsvd_profile.argtypes = [vp, i32]
     lib.cmsvd_profile_read.argtypes = [vp, vp, vp]
     lib.cmsvd_update_batch.argtypes = [vp, i64, i64, vp, i64, vp, i64, ctypes.POINTER(Block), i64, vp, i64, vp, vp, vp]
@@ -62,7 +64,8 @@ def _load():
     for f in ("cmsvd_create", "cmsvd_destroy", "cmsvd_set_stream", "cmsvd_update", "cmsvd_merge_errors",
               "cmsvd_cluster", "cmsvd_sym_eigvals", "cmsvd_gemm_f64", "cmsvd_profile", "cmsvd_profile_read",
               "cmsvd_tail_energy_grad", "cmsvd_update_batch", "cmsvd_cluster_residual", "cmsvd_residual_bound",
-              "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail", "cmsvd_compress"):
+              "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail", "cmsvd_compress", "cmsvd_gemm_bf16",
+              "cmsvd_set_projection"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -72,7 +75,10 @@ _lib = _load()
 EXPORTS = ("cmsvd_create", "cmsvd_destroy", "cmsvd_set_stream", "cmsvd_last_error", "cmsvd_update",
            "cmsvd_merge_errors", "cmsvd_cluster", "cmsvd_sym_eigvals", "cmsvd_gemm_f64", "cmsvd_profile",
            "cmsvd_profile_read", "cmsvd_tail_energy_grad", "cmsvd_update_batch", "cmsvd_cluster_residual",
-           "cmsvd_residual_bound", "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail", "cmsvd_compress")
+           "cmsvd_residual_bound", "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail", "cmsvd_compress",
+           "cmsvd_gemm_bf16", "cmsvd_set_projection")
+
+PROJECTIONS = {"f64": 0, "bf16": 1, "bf16x3": 2}  # cmsvd_projection
 
 STAGES = ("norms_grams", "commit", "projection", "core_eig")
 
@@ -91,6 +97,7 @@ class Handle:
 
     def __init__(self, device=None):
         self._h = ctypes.c_void_p()
+        self.projection = "f64"
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else torch.device(device).index)
         with torch.cuda.device(self.device):
             _check(_lib.cmsvd_create(ctypes.byref(self._h), _stream_ptr(self.device)))
@@ -112,6 +119,23 @@ class Handle:
     @property
     def ptr(self):
         return self._h
+
+    def set_projection(self, precision: str):
+        """'f64' (default), 'bf16' or 'bf16x3': precision of the candidate projections
+        Y = U_r^T A_j."""
+        _check(_lib.cmsvd_set_projection(self._h, PROJECTIONS[precision]))
+        self.projection = precision
+
+    def call_with_projection(self, precision, fn):
+        """Runs fn() with the projection precision set to ``precision`` (None: as set)."""
+        if precision is None or precision == self.projection:
+            return fn()
+        prev = self.projection
+        self.set_projection(precision)
+        try:
+            return fn()
+        finally:
+            self.set_projection(prev)
 
     def profile(self, enable: bool = True):
         _check(_lib.cmsvd_profile(self._h, 1 if enable else 0))
@@ -221,8 +245,10 @@ def cmsvd_update_batch(states: Sequence[State], blocks: Sequence[torch.Tensor], 
     return outs
 
 
-def cmsvd_merge_errors(blocks: Sequence[torch.Tensor], pairs, r: int, handle: Handle | None = None):
-    """Returns (err, rel) device FP64 tensors for the ordered pairs (i, j)."""
+def cmsvd_merge_errors(blocks: Sequence[torch.Tensor], pairs, r: int, handle: Handle | None = None,
+                       projection: str | None = None):
+    """Returns (err, rel) device FP64 tensors for the ordered pairs (i, j).  projection:
+    'f64', 'bf16' or 'bf16x3' for this call (None: the handle's setting)."""
     dev = blocks[0].device
     h = handle or default_handle(dev)
     if isinstance(pairs, torch.Tensor):
@@ -235,14 +261,17 @@ def cmsvd_merge_errors(blocks: Sequence[torch.Tensor], pairs, r: int, handle: Ha
     err = torch.empty(npairs, dtype=torch.float64, device=dev)
     rel = torch.empty(npairs, dtype=torch.float64, device=dev)
     arr = _blocks(blocks)
-    _check(_lib.cmsvd_merge_errors(h.ptr, arr, len(blocks), ctypes.c_void_p(pr.data_ptr()), npairs, r,
-                                   ctypes.c_void_p(err.data_ptr()), ctypes.c_void_p(rel.data_ptr())))
+    h.call_with_projection(projection, lambda: _check(_lib.cmsvd_merge_errors(
+        h.ptr, arr, len(blocks), ctypes.c_void_p(pr.data_ptr()), npairs, r, ctypes.c_void_p(err.data_ptr()),
+        ctypes.c_void_p(rel.data_ptr()))))
     return err, rel
 
 
 def cmsvd_cluster(blocks: Sequence[torch.Tensor], r: int, eps: float, sort_mode: str = "frobenius",
-                  handle: Handle | None = None):
-    """Algorithm 3 on the device.  Returns (labels list, clusters list, cluster_rel list)."""
+                  handle: Handle | None = None, projection: str | None = None):
+    """Algorithm 3 on the device.  Returns (labels list, clusters list, cluster_rel list).
+    projection: 'f64', 'bf16' or 'bf16x3' for the candidate evaluations of this call
+    (None: the handle's setting)."""
     dev = blocks[0].device
     h = handle or default_handle(dev)
     mode = {"frobenius": 0, "residual": 1}[sort_mode]
@@ -251,7 +280,8 @@ def cmsvd_cluster(blocks: Sequence[torch.Tensor], r: int, eps: float, sort_mode:
     ncl = ctypes.c_int64(0)
     crel = (ctypes.c_double * n)()
     arr = _blocks(blocks)
-    _check(_lib.cmsvd_cluster(h.ptr, arr, n, r, float(eps), mode, labels, ctypes.byref(ncl), crel))
+    h.call_with_projection(projection, lambda: _check(_lib.cmsvd_cluster(
+        h.ptr, arr, n, r, float(eps), mode, labels, ctypes.byref(ncl), crel)))
     lab = list(labels)
     clusters = [[] for _ in range(ncl.value)]
     for i, c in enumerate(lab):
@@ -430,6 +460,17 @@ def cmsvd_gemm_f64(opA: torch.Tensor, opB: torch.Tensor, C: torch.Tensor | None 
                    beta: float = 0.0, handle: Handle | None = None) -> torch.Tensor:
     """C = alpha opA @ opB + beta C on the matrix cores.  opA (M x K) and opB (K x N) may be
     transposed views of contiguous FP32/FP64 tensors; C is FP64."""
+    return _gemm(_lib.cmsvd_gemm_f64, opA, opB, C, alpha, beta, handle)
+
+
+def cmsvd_gemm_bf16(opA: torch.Tensor, opB: torch.Tensor, C: torch.Tensor | None = None, alpha: float = 1.0,
+                    beta: float = 0.0, handle: Handle | None = None, passes: int = 1) -> torch.Tensor:
+    """As cmsvd_gemm_f64 with the operands rounded to BF16 (passes = 3: split into two
+    BF16 parts) and FP32 accumulation."""
+    return _gemm(lambda *a: _lib.cmsvd_gemm_bf16(a[0], passes, *a[1:]), opA, opB, C, alpha, beta, handle)
+
+
+def _gemm(fn, opA, opB, C, alpha, beta, handle):
     h = handle or default_handle(opA.device)
 
     def desc(t):
@@ -450,13 +491,13 @@ def cmsvd_gemm_f64(opA: torch.Tensor, opB: torch.Tensor, C: torch.Tensor | None 
         C = torch.zeros((N, M), dtype=torch.float64, device=opA.device).t()
     assert C.stride(0) == 1
     dt = {torch.float32: CMSVD_F32, torch.float64: CMSVD_F64}
-    _check(_lib.cmsvd_gemm_f64(h.ptr, ta, tb, M, N, K, float(alpha), ctypes.c_void_p(a.data_ptr()), lda,
-                               dt[a.dtype], ctypes.c_void_p(b.data_ptr()), ldb, dt[b.dtype], float(beta),
-                               ctypes.c_void_p(C.data_ptr()), C.stride(1)))
+    _check(fn(h.ptr, ta, tb, M, N, K, float(alpha), ctypes.c_void_p(a.data_ptr()), lda, dt[a.dtype],
+              ctypes.c_void_p(b.data_ptr()), ldb, dt[b.dtype], float(beta), ctypes.c_void_p(C.data_ptr()),
+              C.stride(1)))
     return C
 
 
-__all__ = ["cmsvd_gemm_f64", "Handle", "State", "Block", "CmsvdError", "cmsvd_update", "cmsvd_update_batch",
+__all__ = ["cmsvd_gemm_f64", "cmsvd_gemm_bf16", "PROJECTIONS", "Handle", "State", "Block", "CmsvdError", "cmsvd_update", "cmsvd_update_batch",
            "cmsvd_merge_errors", "cmsvd_cluster", "cmsvd_cluster_residual", "cmsvd_residual_bound",
            "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail", "cmsvd_compress", "compress_partition",
            "cmsvd_sym_eigvals", "cmsvd_tail_energy_grad", "TailEnergy", "tail_energy", "default_handle",

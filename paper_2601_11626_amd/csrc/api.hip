@@ -90,6 +90,7 @@ struct cmsvd_ctx {
     size_t pin_cap = 0;
     hipEvent_t pin_ev = nullptr;
     bool pin_ev_armed = false;
+    int proj = CMSVD_PROJ_F64;  // precision of the candidate projections
     // stage timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> marks[4];
@@ -199,9 +200,15 @@ cmsvd_status check_block(const cmsvd_block& b, int64_t m, const char* what, int6
 // ---------------------------------------------------------------------------
 // Batched GEMM helper: groups problems that share (transA, transB, types).
 // ---------------------------------------------------------------------------
+// BF16 passes of the candidate projections (0 = the FP64 kernel).
+int proj_passes(const cmsvd_ctx* h) {
+    return h->proj == CMSVD_PROJ_BF16 ? 1 : h->proj == CMSVD_PROJ_BF16X3 ? 3 : 0;
+}
+
 struct GemmGroup {
     std::vector<GemmDesc> d;
     bool ta = false, tb = false, af32 = false, bf32 = false;
+    int bf16 = 0;  // 0: FP64 kernel; 1 or 3: BF16 operand passes, FP32 accumulation
     double alpha = 1.0, beta = 0.0;
     size_t off = 0;
     int maxM = 0, maxN = 0;
@@ -214,8 +221,12 @@ struct GemmGroup {
 
 void run_gemm(const GemmGroup& g, char* dbase, hipStream_t s) {
     if (g.d.empty()) return;
-    gemm_f64_batched(reinterpret_cast<const GemmDesc*>(dbase + g.off), (int)g.d.size(), g.maxM, g.maxN, g.ta, g.tb,
-                     g.af32, g.bf32, g.alpha, g.beta, s);
+    if (g.bf16)
+        gemm_bf16_batched(reinterpret_cast<const GemmDesc*>(dbase + g.off), (int)g.d.size(), g.maxM, g.maxN, g.ta,
+                          g.tb, g.af32, g.bf32, g.bf16, g.alpha, g.beta, s);
+    else
+        gemm_f64_batched(reinterpret_cast<const GemmDesc*>(dbase + g.off), (int)g.d.size(), g.maxM, g.maxN, g.ta,
+                         g.tb, g.af32, g.bf32, g.alpha, g.beta, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -749,6 +760,7 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
         GemmGroup g32, g64;
         g32.tb = g64.tb = true;
         g32.bf32 = true;
+        g32.bf16 = g64.bf16 = proj_passes(h);
         std::vector<EigDesc> ed(nj);
         for (size_t i = 0; i < nj; ++i) {
             const EvalJob& j = jobs[b0 + i];
@@ -864,6 +876,7 @@ cmsvd_status eval_dense(cmsvd_ctx* h, const DenseEval& de, const std::vector<Pai
         GemmGroup g;
         g.tb = true;
         g.bf32 = de.ball_f32;
+        g.bf16 = proj_passes(h);
         const char* Bc = static_cast<const char*>(de.Ball) + (size_t)cmin * (de.ball_f32 ? 4 : 8);
         g.push(GemmDesc{de.Uall + (size_t)a0 * r, Bc, C, (int)ldc, (int)(cmax - cmin), de.m, (long)de.na * r,
                         de.ksum, ldc});
@@ -1612,6 +1625,38 @@ cmsvd_status weyl_setup(cmsvd_ctx* h, const cmsvd_block* blocks, int N, int64_t 
     return CMSVD_OK;
 }
 
+cmsvd_status gemm_entry(cmsvd_handle h, const char* who, int bf16, int32_t trans_a, int32_t trans_b, int64_t M,
+                        int64_t N, int64_t K, double alpha, const void* A, int64_t lda, int32_t a_dtype, const void* B,
+                        int64_t ldb, int32_t b_dtype, double beta, double* C, int64_t ldc) {
+    if (!h) return fail(CMSVD_EINVAL, "%s: null handle", who);
+    if (!A || !B || !C) return fail(CMSVD_EINVAL, "%s: null pointer", who);
+    if (M < 0 || N < 0 || K < 0 || M > INT32_MAX || N > INT32_MAX || K > INT32_MAX)
+        return fail(CMSVD_ESHAPE, "%s: bad sizes", who);
+    if ((a_dtype != CMSVD_F32 && a_dtype != CMSVD_F64) || (b_dtype != CMSVD_F32 && b_dtype != CMSVD_F64))
+        return fail(CMSVD_EUNSUPPORTED, "%s: dtype must be F32 or F64", who);
+    const int64_t ar = trans_a ? K : M, br = trans_b ? N : K;
+    if (lda < std::max<int64_t>(ar, 1) || ldb < std::max<int64_t>(br, 1) || ldc < std::max<int64_t>(M, 1))
+        return fail(CMSVD_ESHAPE, "%s: leading dimension too small", who);
+    if (M == 0 || N == 0) return CMSVD_OK;
+    GemmGroup g;
+    g.bf16 = bf16;
+    g.ta = trans_a != 0;
+    g.tb = trans_b != 0;
+    g.af32 = a_dtype == CMSVD_F32;
+    g.bf32 = b_dtype == CMSVD_F32;
+    g.alpha = alpha;
+    g.beta = beta;
+    g.push(GemmDesc{A, B, C, (int)M, (int)N, (int)K, (long)lda, (long)ldb, (long)ldc});
+    Stage stg;
+    g.off = stg.add(g.d);
+    char* db = nullptr;
+    cmsvd_status st = upload(h, stg, &db);
+    if (st != CMSVD_OK) return st;
+    run_gemm(g, db, h->stream);
+    HIPCHK(hipGetLastError());
+    return CMSVD_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1686,6 +1731,14 @@ cmsvd_status cmsvd_profile_read(cmsvd_handle h, double* ms, int64_t* count) {
         count[st] = (int64_t)h->marks[st].size();
         h->marks[st].clear();
     }
+    return CMSVD_OK;
+}
+
+cmsvd_status cmsvd_set_projection(cmsvd_handle h, int32_t precision) {
+    if (!h) return fail(CMSVD_EINVAL, "cmsvd_set_projection: null handle");
+    if (precision != CMSVD_PROJ_F64 && precision != CMSVD_PROJ_BF16 && precision != CMSVD_PROJ_BF16X3)
+        return fail(CMSVD_EINVAL, "cmsvd_set_projection: precision must be CMSVD_PROJ_F64, _BF16 or _BF16X3");
+    h->proj = precision;
     return CMSVD_OK;
 }
 
@@ -1965,32 +2018,16 @@ cmsvd_status cmsvd_sym_eigvals(cmsvd_handle h, const double* A, int64_t n, int64
 cmsvd_status cmsvd_gemm_f64(cmsvd_handle h, int32_t trans_a, int32_t trans_b, int64_t M, int64_t N, int64_t K,
                             double alpha, const void* A, int64_t lda, int32_t a_dtype, const void* B, int64_t ldb,
                             int32_t b_dtype, double beta, double* C, int64_t ldc) {
-    if (!h) return fail(CMSVD_EINVAL, "cmsvd_gemm_f64: null handle");
-    if (!A || !B || !C) return fail(CMSVD_EINVAL, "cmsvd_gemm_f64: null pointer");
-    if (M < 0 || N < 0 || K < 0 || M > INT32_MAX || N > INT32_MAX || K > INT32_MAX)
-        return fail(CMSVD_ESHAPE, "cmsvd_gemm_f64: bad sizes");
-    if ((a_dtype != CMSVD_F32 && a_dtype != CMSVD_F64) || (b_dtype != CMSVD_F32 && b_dtype != CMSVD_F64))
-        return fail(CMSVD_EUNSUPPORTED, "cmsvd_gemm_f64: dtype must be F32 or F64");
-    const int64_t ar = trans_a ? K : M, br = trans_b ? N : K;
-    if (lda < std::max<int64_t>(ar, 1) || ldb < std::max<int64_t>(br, 1) || ldc < std::max<int64_t>(M, 1))
-        return fail(CMSVD_ESHAPE, "cmsvd_gemm_f64: leading dimension too small");
-    if (M == 0 || N == 0) return CMSVD_OK;
-    GemmGroup g;
-    g.ta = trans_a != 0;
-    g.tb = trans_b != 0;
-    g.af32 = a_dtype == CMSVD_F32;
-    g.bf32 = b_dtype == CMSVD_F32;
-    g.alpha = alpha;
-    g.beta = beta;
-    g.push(GemmDesc{A, B, C, (int)M, (int)N, (int)K, (long)lda, (long)ldb, (long)ldc});
-    Stage stg;
-    g.off = stg.add(g.d);
-    char* db = nullptr;
-    cmsvd_status st = upload(h, stg, &db);
-    if (st != CMSVD_OK) return st;
-    run_gemm(g, db, h->stream);
-    HIPCHK(hipGetLastError());
-    return CMSVD_OK;
+    return gemm_entry(h, "cmsvd_gemm_f64", 0, trans_a, trans_b, M, N, K, alpha, A, lda, a_dtype, B, ldb, b_dtype,
+                      beta, C, ldc);
+}
+
+cmsvd_status cmsvd_gemm_bf16(cmsvd_handle h, int32_t passes, int32_t trans_a, int32_t trans_b, int64_t M, int64_t N,
+                             int64_t K, double alpha, const void* A, int64_t lda, int32_t a_dtype, const void* B,
+                             int64_t ldb, int32_t b_dtype, double beta, double* C, int64_t ldc) {
+    if (passes != 1 && passes != 3) return fail(CMSVD_EINVAL, "cmsvd_gemm_bf16: passes must be 1 or 3");
+    return gemm_entry(h, "cmsvd_gemm_bf16", passes, trans_a, trans_b, M, N, K, alpha, A, lda, a_dtype, B, ldb, b_dtype,
+                      beta, C, ldc);
 }
 
 cmsvd_status cmsvd_cluster(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double eps,

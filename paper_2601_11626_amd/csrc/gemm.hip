@@ -156,4 +156,180 @@ void gemm_f64_batched(const GemmDesc* d_descs, int count, int maxM, int maxN, bo
     else launch_typed<double, double>(d_descs, count, maxM, maxN, transA, transB, alpha, beta, s);
 }
 
+// ---------------------------------------------------------------------------
+// Grouped batched GEMM with BF16 operands and FP32 accumulation on the CDNA4 matrix
+// cores (v_mfma_f32_16x16x32_bf16), for the low-precision projection options.
+//
+//   C_b = alpha * op(A_b) * op(B_b) + beta * C_b      (C FP64, column-major)
+//
+// Every operand element x is rounded to FP32 (x32) and then to BF16 (hi), both
+// round-to-nearest-even, while it is staged into LDS.  SPLIT = 1: op(A) op(B) is summed
+// from the hi parts.  SPLIT = 3 also stages lo = BF16(x32 - hi) (the FP32 difference is
+// exact) and sums lo_A hi_B + hi_A lo_B + hi_A hi_B, which carries about 16 significant
+// bits per operand instead of 8.  Products of BF16 values are exact in FP32; the matrix
+// cores sum them in FP32 and C receives the FP32 sums widened to FP64.
+//
+// Tiling: as the FP64 kernel, a 256-thread workgroup owns a 64x64 tile of C and each
+// wave a 32x32 quadrant of 2x2 MFMA blocks; K advances by 32 (one MFMA depth) through
+// a double-buffered LDS stage holding the operand parts as [free index][32 K values]
+// rows of BF16, so that each lane's 8 consecutive K values are one 16-byte LDS read.
+// ---------------------------------------------------------------------------
+constexpr int BBK = 32;
+constexpr int BROW = BBK + 8;  // LDS row length in BF16 (16-byte padding)
+
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float to_f32(double x) { return (float)x; }
+__device__ __forceinline__ float to_f32(float x) { return x; }
+
+// Loads 8 elements of the 64 x 32 slab op(X)[f0:f0+64, k0:k0+32] (free index f,
+// contraction index k) and splits them into BF16 parts hi (and lo when SPLIT).
+// KCONTIG: element (f, k) at X[k + f*ld] (the contraction index is contiguous; thread
+// t takes row t/4, K values 8*(t%4)..+7); otherwise at X[f + k*ld] (thread t takes row
+// t%64, K values 8*(t/64)..+7, so that a wave reads 64 consecutive free indices per
+// load).
+template <typename T, bool KCONTIG, bool SPLIT>
+__device__ __forceinline__ void load_slab_bf16(const T* __restrict__ X, long ld, int nf, int nk, int f0, int k0,
+                                               int t, bf8_t& hi, bf8_t& lo, int& row, int& kg) {
+    if (KCONTIG) {
+        row = t >> 2;
+        kg = t & 3;
+    } else {
+        row = t & 63;
+        kg = t >> 6;
+    }
+    const int f = f0 + row;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int k = k0 + kg * 8 + q;
+        const bool in = f < nf && k < nk;
+        const long idx = KCONTIG ? (long)k + (long)f * ld : (long)f + (long)k * ld;
+        const float x = in ? to_f32(X[idx]) : 0.0f;
+        const __bf16 h = (__bf16)x;
+        hi[q] = h;
+        if (SPLIT) lo[q] = (__bf16)(x - (float)h);
+    }
+}
+
+template <typename TA, typename TB, bool TA_T, bool TB_T, bool SPLIT>
+__global__ void __launch_bounds__(256) gemm_bf16_kernel(const GemmDesc* __restrict__ descs, int base,
+                                                        double alpha, double beta) {
+    const GemmDesc d = descs[base + blockIdx.y];
+    const int tilesM = (d.M + GBM - 1) / GBM;
+    const int tilesN = (d.N + GBN - 1) / GBN;
+    if ((int)blockIdx.x >= tilesM * tilesN) return;
+    const int tm = blockIdx.x % tilesM, tn = blockIdx.x / tilesM;
+    const int m0 = tm * GBM, n0 = tn * GBN;
+    const TA* __restrict__ A = static_cast<const TA*>(d.A);
+    const TB* __restrict__ B = static_cast<const TB*>(d.B);
+    // op(A) = A (M x K, free index contiguous) or A^T (K contiguous);
+    // op(B) = B (K x N, K contiguous) or B^T (free index contiguous).
+    constexpr bool AK = TA_T, BK = !TB_T;
+    constexpr int NP = SPLIT ? 2 : 1;  // staged parts per operand
+
+    __shared__ __attribute__((aligned(16))) __bf16 As[2][NP][GBM * BROW];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[2][NP][GBN * BROW];
+
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    f4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
+
+    bf8_t ah, al, bh, bl;
+    int ra, ka, rb, kb;
+    const int nk = (d.K + BBK - 1) / BBK;
+    auto stage = [&](int buf) {
+        *reinterpret_cast<bf8_t*>(&As[buf][0][ra * BROW + ka * 8]) = ah;
+        *reinterpret_cast<bf8_t*>(&Bs[buf][0][rb * BROW + kb * 8]) = bh;
+        if (SPLIT) {
+            *reinterpret_cast<bf8_t*>(&As[buf][NP - 1][ra * BROW + ka * 8]) = al;
+            *reinterpret_cast<bf8_t*>(&Bs[buf][NP - 1][rb * BROW + kb * 8]) = bl;
+        }
+    };
+    load_slab_bf16<TA, AK, SPLIT>(A, d.lda, d.M, d.K, m0, 0, t, ah, al, ra, ka);
+    load_slab_bf16<TB, BK, SPLIT>(B, d.ldb, d.N, d.K, n0, 0, t, bh, bl, rb, kb);
+    stage(0);
+    __syncthreads();
+    const int lr = lane & 15, lk = (lane >> 4) * 8;
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) {
+            load_slab_bf16<TA, AK, SPLIT>(A, d.lda, d.M, d.K, m0, (kt + 1) * BBK, t, ah, al, ra, ka);
+            load_slab_bf16<TB, BK, SPLIT>(B, d.ldb, d.N, d.K, n0, (kt + 1) * BBK, t, bh, bl, rb, kb);
+        }
+        // A operand: lane holds row (lane % 16), K values 8*(lane/16)..+7; B operand:
+        // column (lane % 16), the same K values.
+        bf8_t a[NP][2], b[NP][2];
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                a[p][i] = *reinterpret_cast<const bf8_t*>(&As[cur][p][(wm * 32 + i * 16 + lr) * BROW + lk]);
+                b[p][i] = *reinterpret_cast<const bf8_t*>(&Bs[cur][p][(wn * 32 + i * 16 + lr) * BROW + lk]);
+            }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                if (SPLIT) {  // the small cross terms first
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[NP - 1][i], b[0][j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[NP - 1][j], acc[i][j], 0, 0, 0);
+                }
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+            }
+        if (kt + 1 < nk) stage(cur ^ 1);
+        __syncthreads();
+    }
+    // D[i][j] of a 16x16 FP32 block sits in lane j + 16*(i/4), element i%4.
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + wm * 32 + bi * 16 + (lane >> 4) * 4 + v;
+                const int col = n0 + wn * 32 + bj * 16 + (lane & 15);
+                if (row < d.M && col < d.N) {
+                    double* c = d.C + (long)row + (long)col * d.ldc;
+                    double val = alpha * (double)acc[bi][bj][v];
+                    if (beta != 0.0) val += beta * (*c);
+                    *c = val;
+                }
+            }
+}
+
+template <typename TA, typename TB, bool SPLIT>
+static void launch_bf16(const GemmDesc* descs, int count, int maxM, int maxN, bool ta, bool tb, double alpha,
+                        double beta, hipStream_t s) {
+    const int tiles = ((maxM + GBM - 1) / GBM) * ((maxN + GBN - 1) / GBN);
+    for (int base = 0; base < count; base += 65535) {
+        const int n = count - base < 65535 ? count - base : 65535;
+        dim3 grid(tiles, n), block(256);
+        if (!ta && !tb) hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, false, false, SPLIT>), grid, block, 0, s, descs, base, alpha, beta);
+        if (!ta && tb) hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, false, true, SPLIT>), grid, block, 0, s, descs, base, alpha, beta);
+        if (ta && !tb) hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, true, false, SPLIT>), grid, block, 0, s, descs, base, alpha, beta);
+        if (ta && tb) hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, true, true, SPLIT>), grid, block, 0, s, descs, base, alpha, beta);
+    }
+}
+
+template <bool SPLIT>
+static void launch_bf16_types(const GemmDesc* d, int count, int maxM, int maxN, bool ta, bool tb, bool a_f32,
+                              bool b_f32, double alpha, double beta, hipStream_t s) {
+    if (a_f32 && b_f32) launch_bf16<float, float, SPLIT>(d, count, maxM, maxN, ta, tb, alpha, beta, s);
+    else if (a_f32) launch_bf16<float, double, SPLIT>(d, count, maxM, maxN, ta, tb, alpha, beta, s);
+    else if (b_f32) launch_bf16<double, float, SPLIT>(d, count, maxM, maxN, ta, tb, alpha, beta, s);
+    else launch_bf16<double, double, SPLIT>(d, count, maxM, maxN, ta, tb, alpha, beta, s);
+}
+
+void gemm_bf16_batched(const GemmDesc* d_descs, int count, int maxM, int maxN, bool transA, bool transB,
+                       bool a_f32, bool b_f32, int passes, double alpha, double beta, hipStream_t s) {
+    if (count <= 0 || maxM <= 0 || maxN <= 0) return;
+    if (passes == 3) launch_bf16_types<true>(d_descs, count, maxM, maxN, transA, transB, a_f32, b_f32, alpha, beta, s);
+    else launch_bf16_types<false>(d_descs, count, maxM, maxN, transA, transB, a_f32, b_f32, alpha, beta, s);
+}
+
 }  // namespace cmsvd
