@@ -181,9 +181,12 @@ def chain_grad(args, cm, workloads, torch):
 
 def cluster(args, cm, workloads, torch):
     """Algorithm 3 on 512 FP32 blocks with 4096 rows and widths U{64..1024} from 32
-    latent 4096 x 48 subspaces (noise 1e-2), relative threshold 0.1, norm-ordered scan.
-    Reports the clustering time and, on a bounded sample of anchor-first pairs of the
-    same collection, the deviation of cmsvd_merge_errors from the FP64 oracle."""
+    latent 4096 x 48 subspaces (noise 1e-2), relative threshold 0.1, norm-ordered scan,
+    with the candidate projections in the precision --projection selects.  Reports the
+    clustering time and, on a bounded sample of narrow anchor-first pairs of the same
+    collection (both widths <= 256, so that the oracle stays fast; half of them sharing a
+    latent subspace), the deviation of cmsvd_merge_errors in that precision from the
+    FP64 oracle; with --compare-f64 also the partition of the FP64 run."""
     r = args.rank
     t0 = time.time()
     blocks_np = workloads.latent_uneven(seed=0, nblocks=args.nblocks)
@@ -194,6 +197,7 @@ def cluster(args, cm, workloads, torch):
     widths = [b.shape[1] for b in blocks_np]
     log(f"generated {len(blocks)} blocks, widths {min(widths)}..{max(widths)} in {time.time() - t0:.1f}s")
     h = cm.default_handle(dev)
+    h.set_projection(args.projection)
     h.profile(True)
     h.profile_read()
     t1 = time.perf_counter()
@@ -202,25 +206,44 @@ def cluster(args, cm, workloads, torch):
     el = time.perf_counter() - t1
     stages = h.profile_read()
     h.profile(False)
-    log(f"clustered into {len(cl)} clusters in {el:.1f}s; stages {stages}")
+    log(f"clustered into {len(cl)} clusters in {el:.1f}s ({args.projection} projections); stages {stages}")
     sizes = sorted((len(c) for c in cl), reverse=True)
+    versus = None
+    if args.compare_f64 and args.projection != "f64":
+        h.set_projection("f64")
+        t2 = time.perf_counter()
+        lab_f, cl_f, crel_f = cm.cmsvd_cluster(blocks, r, 0.1, sort_mode="frobenius", handle=h)
+        torch.cuda.synchronize()
+        versus = {"f64_seconds": round(time.perf_counter() - t2, 3), "identical_partition": lab == lab_f,
+                  "f64_clusters": len(cl_f)}
+        if lab == lab_f:
+            versus["max_cluster_rel_diff"] = max(abs(a - b) for a, b in zip(crel, crel_f))
+        log(f"FP64 run: {versus}")
+        h.set_projection(args.projection)
     parity = None
     if not args.no_cpu:
         import oracle
 
         pairs = workloads.anchor_ordered_pairs(blocks_np)
+        pairs = pairs[[widths[i] <= 256 and widths[j] <= 256 for i, j in pairs]]
+        # half of the sample from pairs sharing a latent subspace (block i uses latent
+        # i mod 32): those have the small relative errors where precision matters most
+        same = np.array([i % 32 == j % 32 for i, j in pairs])
         rng = np.random.default_rng(2)
-        cs = rng.choice(len(pairs), size=min(args.cpu_pairs, len(pairs)), replace=False)
-        err, rel = cm.cmsvd_merge_errors(blocks, pairs[cs], r)
+        n_same = min(args.parity_pairs // 2, int(same.sum()))
+        cs = np.concatenate([rng.choice(np.flatnonzero(same), size=n_same, replace=False),
+                             rng.choice(np.flatnonzero(~same), size=min(args.parity_pairs - n_same, int((~same).sum())),
+                                        replace=False)])
+        err, rel = cm.cmsvd_merge_errors(blocks, pairs[cs], r, handle=h)
         err = err.cpu().numpy()
         tc = time.perf_counter()
-        e_o, _ = oracle.merge_errors(blocks_np, pairs[cs], r, nthreads=max(1, min(16, len(os.sched_getaffinity(0)))))
+        e_o, rel_o = oracle.merge_errors(blocks_np, pairs[cs], r, nthreads=max(1, min(16, len(os.sched_getaffinity(0)))))
         ct = time.perf_counter() - tc
-        nrm = np.array([math.sqrt(float(np.sum(blocks_np[i].astype(np.float64) ** 2)) +
-                                  float(np.sum(blocks_np[j].astype(np.float64) ** 2))) for i, j in pairs[cs]])
-        dev_rel = np.abs(err - e_o) / np.maximum(e_o, 1e-6 * nrm)
-        parity = {"pairs": int(len(cs)), "max_rel_dev": float(dev_rel.max()), "oracle_seconds": round(ct, 1),
-                  "widths": [[int(widths[i]), int(widths[j])] for i, j in pairs[cs]]}
+        dev_rel = np.abs(err - e_o) / e_o
+        k = int(np.argmax(dev_rel))
+        parity = {"pairs": int(len(cs)), "projection": args.projection, "max_rel_dev": float(dev_rel.max()),
+                  "median_rel_dev": float(np.median(dev_rel)), "rel_at_max": float(rel_o[k]),
+                  "oracle_seconds": round(ct, 1), "same_latent_pairs": int(sum(i % 32 == j % 32 for i, j in pairs[cs]))}
         log(f"parity {parity}")
     out = {
         "metric": "greedy error-constrained clustering (Algorithm 3) wall time",
@@ -228,15 +251,17 @@ def cluster(args, cm, workloads, torch):
         "unit": "s",
         "n_gpus": 1,
         "higher_is_better": False,
-        "dtype": "f64",
+        "dtype": {"f64": "f64", "bf16": "bf16 projections (fp32 accumulate), f64 core",
+                  "bf16x3": "split bf16 projections (fp32 accumulate), f64 core"}[args.projection],
         "data": "synthetic",
         "config": {"workload": f"latent_uneven: {len(blocks)} FP32 blocks 4096 x U{{64..1024}}, 32 latent 48-dim "
                                f"subspaces, noise 1e-2, r={r}, eps=0.1, frobenius order",
-                   "r": r, "eps": 0.1},
+                   "r": r, "eps": 0.1, "projection": args.projection},
         "clusters": len(cl),
         "largest_clusters": sizes[:8],
         "max_cluster_rel": max(crel) if crel else None,
         "stages_ms_launches": {k: [round(v[0], 1), v[1]] for k, v in stages.items()},
+        "versus_f64": versus,
         "parity": parity,
     }
     print(json.dumps(out), flush=True)
@@ -545,6 +570,10 @@ def main():
     ap.add_argument("--sort-mode", default="frobenius", choices=("frobenius", "residual"),
                     help="cluster_residual: candidate order of a pass")
     ap.add_argument("--cpu-chains", type=int, default=6, help="cluster_residual: oracle sample (narrow pairs)")
+    ap.add_argument("--projection", default="f64", choices=("f64", "bf16", "bf16x3"),
+                    help="pairs, cluster: precision of the candidate projections")
+    ap.add_argument("--compare-f64", action="store_true", help="cluster: also run the FP64 clustering")
+    ap.add_argument("--parity-pairs", type=int, default=48, help="cluster: oracle sample (narrow pairs)")
     ap.add_argument("--workload", default="pairs",
                     choices=("pairs", "chain_grad", "cluster", "cluster_residual", "smallk", "weights", "slack"),
                     help="pairs: batched merge errors (the default line); chain_grad: tail energy and "
@@ -601,6 +630,7 @@ def main():
     blocks = [torch.from_numpy(np.ascontiguousarray(b)).to(dev) for b in blocks_np]
     torch.cuda.synchronize()
     h = cm.Handle(dev)
+    h.set_projection(args.projection)
     m, k = blocks_np[0].shape
     npairs = len(pairs)
 
@@ -713,9 +743,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.projection == "f64" else f"f64 core, {args.projection} projections",
         "data": "synthetic",
         "config": {
+            "projection": args.projection,
             "workload": f"rotated_groups: {len(blocks_np)} FP32 blocks {m}x{k}, r={r}, all {npairs} anchor-first "
                         f"pairs per step (anchor init included)",
             "blocks": len(blocks_np), "m": int(m), "k": int(k), "r": r, "pairs": npairs,
