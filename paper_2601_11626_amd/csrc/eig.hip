@@ -57,70 +57,91 @@ __device__ __forceinline__ double hval(const EigDesc& D, int i, int c) {
     return D.Y[(long)(i - n1) + (long)(c - n1) * D.ldy];
 }
 
-// Number of eigenvalues of the tridiagonal (dd, e2 = off-diagonal squared) below x,
-// from the signs of the LDL^T pivots of T - x I (Sturm sequence).  The reciprocal
-// is v_rcp_f64 refined by one Newton step; pivots below pivmin in magnitude are
-// replaced by -pivmin.  Loads are issued 8 at a time ahead of the dependent chain.
-__device__ __forceinline__ double rcp_refined(double q) {
-    double r = __builtin_amdgcn_rcp(q);
-    const double e = fma(-q, r, 1.0);
-    return fma(r, e, r);
-}
-
-__device__ __forceinline__ int sturm_count(const double* dd, const double* e2, int n, double x, double pivmin) {
-    double q = dd[0] - x;
-    if (fabs(q) < pivmin) q = -pivmin;
-    int cnt = q < 0.0;
-    for (int i0 = 1; i0 < n; i0 += 8) {
-        double dl[8], el[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            dl[k] = dd[i0 + k];
-            el[k] = e2[i0 + k - 1];
-        }
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (i0 + k < n) {
-                q = (dl[k] - x) - el[k] * rcp_refined(q);
-                if (fabs(q) < pivmin) q = -pivmin;
-                cnt += q < 0.0;
-            }
-        }
-    }
-    return cnt;
-}
-
-// KP Sturm counts at once (independent shifts x[k]); the recurrences are
-// interleaved so that their dependent chains overlap.
+// Number of eigenvalues of the tridiagonal T (diagonal dd, e2 = off-diagonal squared)
+// below x: the number of negative pivots q_i of T - x I = L D L^T.  The pivots are kept
+// as ratios q_i = p_i / p_{i-1} of the leading minors, which obey the three-term
+// recurrence p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2} (p_{-1} = 1): one FMA per step
+// on the dependent chain (e^2 p_{i-2} is formed a step ahead), where the pivot form needs
+// a reciprocal and its refinement.  Each computed ratio satisfies the pivot recurrence
+// with d_i - x and e_{i-1}^2 perturbed by a few ulps, so the count is exact for a
+// tridiagonal that close to T, as for the pivot form.  sc = 2^-k >= ... scales T to norm
+// below 1 exactly (a power of two), and the pair (p_{i-1}, p_i) is renormalised by a
+// power of two every four steps, so nothing overflows or underflows; signs are exact.
+// An exactly zero minor stands for a negative pivot of size 2^-60 ||T||.
 template <int KP>
-__device__ __forceinline__ void sturm_count_k(const double* dd, const double* e2, int n, const double (&x)[KP],
-                                              double pivmin, int (&cnt)[KP]) {
-    double q[KP];
+__device__ __forceinline__ void sturm_step(double dl, double el, const double (&xs)[KP], double sc, double (&p1)[KP],
+                                           double (&p2)[KP], int (&cnt)[KP]) {
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-        q[k] = dd[0] - x[k];
-        if (fabs(q[k]) < pivmin) q[k] = -pivmin;
-        cnt[k] = q[k] < 0.0;
+        const double tk = -el * p2[k];
+        double p = fma(dl * sc - xs[k], p1[k], tk);
+        if (p == 0.0) p = -0x1p-60 * p1[k];
+        cnt[k] += (p < 0.0) != (p1[k] < 0.0);
+        p2[k] = p1[k];
+        p1[k] = p;
     }
-    for (int i0 = 1; i0 < n; i0 += 8) {
-        double dl[8], el[8];
+}
+
+template <int KP>
+__device__ __forceinline__ void sturm_renorm(double (&p1)[KP], double (&p2)[KP]) {
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            dl[m] = dd[i0 + m];
-            el[m] = e2[i0 + m - 1];
+    for (int k = 0; k < KP; ++k) {
+        const int e = __builtin_amdgcn_frexp_exp(fmax(fabs(p1[k]), fabs(p2[k])));
+        p1[k] = ldexp(p1[k], -e);
+        p2[k] = ldexp(p2[k], -e);
+        if (p1[k] == 0.0) p1[k] = -0x1p-60 * p2[k];  // underflow of a tiny minor
+    }
+}
+
+// Full blocks of four steps run without bounds checks, with the next block's operands
+// loaded ahead (at most three entries past n - 1 are read and not used; the callers'
+// arrays are padded past n); the last n - 1 mod 4 steps follow one by one.
+template <int KP>
+__device__ __forceinline__ void sturm_count_k(const double* dd, const double* e2, int n, const double (&x)[KP],
+                                              double sc, int (&cnt)[KP]) {
+    const double sc2 = sc * sc;
+    double xs[KP], p1[KP], p2[KP];  // x sc, p_{i-1}, p_{i-2}
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        xs[k] = x[k] * sc;
+        p2[k] = 1.0;
+        p1[k] = dd[0] * sc - xs[k];
+        if (p1[k] == 0.0) p1[k] = -0x1p-60;
+        cnt[k] = p1[k] < 0.0;
+    }
+    int i = 1;
+    double dn[4], en[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        dn[m] = dd[i + m];
+        en[m] = e2[i + m - 1];
+    }
+    for (; i + 3 < n; i += 4) {
+        double dl[4], el[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            dl[m] = dn[m];
+            el[m] = en[m] * sc2;
+            dn[m] = dd[i + 4 + m];
+            en[m] = e2[i + 3 + m];
         }
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            if (i0 + m < n) {
-#pragma unroll
-                for (int k = 0; k < KP; ++k) {
-                    q[k] = (dl[m] - x[k]) - el[m] * rcp_refined(q[k]);
-                    if (fabs(q[k]) < pivmin) q[k] = -pivmin;
-                    cnt[k] += q[k] < 0.0;
-                }
-            }
-        }
+        for (int m = 0; m < 4; ++m) sturm_step<KP>(dl[m], el[m], xs, sc, p1, p2, cnt);
+        sturm_renorm<KP>(p1, p2);
     }
+    for (int m = 0; i < n; ++i, ++m) sturm_step<KP>(dn[m], en[m] * sc2, xs, sc, p1, p2, cnt);
+}
+
+__device__ __forceinline__ int sturm_count(const double* dd, const double* e2, int n, double x, double sc) {
+    const double xs[1] = {x};
+    int c[1];
+    sturm_count_k<1>(dd, e2, n, xs, sc, c);
+    return c[0];
+}
+
+// 2^-k with 2^(k-1) <= tnorm < 2^k (1 for tnorm = 0): scales T to norm below 1 exactly.
+__device__ __forceinline__ double sturm_scale(double tnorm) {
+    return tnorm > 0.0 && tnorm < INFINITY ? ldexp(1.0, -__builtin_amdgcn_frexp_exp(tnorm)) : 1.0;
 }
 
 static int tl_for(int npad, int T) {
@@ -266,6 +287,7 @@ __global__ void __launch_bounds__(NT) sym_eig_kernel(const EigDesc* __restrict__
         const double tnorm = fmax(fabs(glo), fabs(ghi));
         const double pivmin = DBL_MIN * fmax(1.0, em);
         const double tol = 4.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
+        const double sc = sturm_scale(tnorm);
         glo -= tol;
         ghi += tol;
         double* lamv = pw;  // free now
@@ -275,7 +297,7 @@ __global__ void __launch_bounds__(NT) sym_eig_kernel(const EigDesc* __restrict__
             while (hi - lo > tol) {
                 const double mid = 0.5 * (lo + hi);
                 if (mid <= lo || mid >= hi) break;
-                if (sturm_count(dd, xv, n, mid, pivmin) >= target) hi = mid;
+                if (sturm_count(dd, xv, n, mid, sc) >= target) hi = mid;
                 else lo = mid;
             }
             lamv[q] = 0.5 * (lo + hi);
@@ -688,14 +710,14 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
         const double tnorm = fmax(fabs(glo), fabs(ghi));
         const double pivmin = DBL_MIN * fmax(1.0, em);
         const double tol = 4.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
+        const double sc = sturm_scale(tnorm);
         glo -= tol;
         ghi += tol;
-        // One probe per thread (the Sturm recurrence already keeps the VALU busy);
-        // P probes per eigenvalue and round split its interval into P + 1 parts.
+        // One probe per thread; P probes per eigenvalue and round split its interval
+        // into P + 1 parts, with P as large as the threads allow.
         constexpr int KP = 1, NPROBE = KP * RT;
         const int nk = D.nkeep;
-        int P = 1;
-        while (2 * P * nk <= NPROBE) P *= 2;
+        const int P = nk > 0 && nk <= NPROBE ? NPROBE / nk : 1;
         double* blo = pw;
         double* bhi = pw + NP;
         int* flag = reinterpret_cast<int*>(pw + 2 * NP);  // NPROBE ints
@@ -703,9 +725,11 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
             blo[q] = glo;
             bhi[q] = ghi;
         }
+        // Each round divides every interval by exactly P + 1, so this many rounds
+        // bring the Gershgorin width below tol (the resolution of the Sturm count).
         const double width = ghi - glo;
         int iters = 1;
-        if (width > tol) iters = (int)ceil(log(width / tol) / log((double)(P + 1))) + 2;
+        if (width > tol) iters = (int)ceil(log(width / tol) / log((double)(P + 1)));
         __syncthreads();
         for (int it = 0; it < iters; ++it) {
             for (int base = 0; base < nk * P; base += NPROBE) {
@@ -721,7 +745,7 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                         x[k] = lo + (hi - lo) * (double)(pi + 1) / (double)(P + 1);
                     }
                 }
-                sturm_count_k<KP>(dd, xv, n, x, pivmin, cnt);
+                sturm_count_k<KP>(dd, xv, n, x, sc, cnt);
 #pragma unroll
                 for (int k = 0; k < KP; ++k) {
                     const int u = base + t * KP + k;
@@ -882,6 +906,7 @@ __global__ void __launch_bounds__(64 * SWV) sym_eig_small_kernel(const EigDesc* 
         const double tnorm = fmax(fabs(glo), fabs(ghi));
         const double pivmin = DBL_MIN * fmax(1.0, em);
         const double tol = 4.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
+        const double sc = sturm_scale(tnorm);
         glo -= tol;
         ghi += tol;
         const int nk = D.nkeep;
@@ -892,9 +917,10 @@ __global__ void __launch_bounds__(64 * SWV) sym_eig_small_kernel(const EigDesc* 
             blo[lane] = glo;
             bhi[lane] = ghi;
         }
+        // Each round divides every interval by exactly P + 1 (see the register kernel).
         const double width = ghi - glo;
         int iters = 1;
-        if (width > tol) iters = (int)ceil(log(width / tol) / log((double)(P + 1))) + 2;
+        if (width > tol) iters = (int)ceil(log(width / tol) / log((double)(P + 1)));
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -905,7 +931,7 @@ __global__ void __launch_bounds__(64 * SWV) sym_eig_small_kernel(const EigDesc* 
                     const int q = u / P, pi = u % P;
                     const double lo = blo[q], hi = bhi[q];
                     const double x = lo + (hi - lo) * (double)(pi + 1) / (double)(P + 1);
-                    fl[u - base] = sturm_count(dd, e2, n, x, pivmin) >= n - q;
+                    fl[u - base] = sturm_count(dd, e2, n, x, sc) >= n - q;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
