@@ -344,6 +344,8 @@ def slack(args, cm, workloads, torch):
     clustering order (largest norm first, then increasing norm).  Slack = estimate - E_r,
     both divided by ||M||_F.  Data: a 256-block pool drawn with the Table-1-like recipe
     of the chosen preset.  A few samples are re-computed by the FP64 oracle."""
+    if args.preset not in SMALLK:
+        raise SystemExit(f"--preset {args.preset} is a --workload table2 shape")
     nb, m, k, r = SMALLK[args.preset]
     pool = min(nb, 256)
     t0 = time.time()
@@ -430,10 +432,86 @@ SMALLK = {  # name: (blocks, m, k, r) -- the shapes of the paper's collections
 }
 
 
+# Table 2 protocol: (blocks, m, k, r, eps, noise) per collection shape of Table 1.  The
+# values are synthetic (64 latent 16-dim subspaces plus Gaussian noise); the noise puts
+# the per-block noise-to-signal energy at 1e-3 (1e-2 for the 20 % SmolVLM threshold), so
+# that clusters of one latent subspace fit the error threshold.
+TABLE2 = {
+    "qualcomm": (2468, 12800, 20, 20, 0.05, 1.12e-3),
+    "bigearthnet": (10000, 1440, 20, 20, 0.05, 3.33e-3),
+    "pdebench": (5000, 3072, 67, 67, 0.05, 2.28e-3),
+    "smolvlm": (333760, 768, 1, 32, 0.20, 1.44e-2),
+}
+
+
+def table2(args, cm, workloads, torch):
+    """The paper's Table 2 protocol on a synthetic collection of one Table 1 shape: the
+    five clustering variants (max norm = Algorithm 1; residual = Algorithm 2 with norm or
+    residual sorting; approximate = Algorithm 3 with norm or residual sorting) at the
+    shape's rank and threshold, each followed by the compression back-end.  Reports per
+    variant the clustering wall time (decomposition excluded, as in the paper), the time
+    relative to max norm, the compression ratio, the realised relative error and the
+    number of clusters.  --pool takes the first N blocks of the collection (the SmolVLM
+    shape defaults to 20,000 of its 333,760 one-column blocks)."""
+    nb, m, k, r, eps, noise = TABLE2[args.preset]
+    pool = args.pool if args.pool > 0 else (20000 if args.preset == "smolvlm" else nb)
+    pool = min(pool, nb)
+    t0 = time.time()
+    blocks_np = workloads.table1_like(seed=0, nblocks=pool, m=m, k=k, noise=noise)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    blocks = [torch.from_numpy(b).to(dev) for b in blocks_np]
+    torch.cuda.synchronize()
+    log(f"generated {pool} blocks {m}x{k} in {time.time() - t0:.1f}s")
+    h = cm.default_handle(dev)
+    variants = [
+        ("max norm", lambda: cm.cmsvd_cluster_weyl(blocks, r, eps, handle=h)),
+        ("res. (norm sorting)", lambda: cm.cmsvd_cluster_residual(blocks, r, eps, "frobenius", handle=h)),
+        ("res. (res. sorting)", lambda: cm.cmsvd_cluster_residual(blocks, r, eps, "residual", handle=h)),
+        ("approx. (norm sorting)", lambda: cm.cmsvd_cluster(blocks, r, eps, "frobenius", handle=h)),
+        ("approx. (res. sorting)", lambda: cm.cmsvd_cluster(blocks, r, eps, "residual", handle=h)),
+    ]
+    rows = []
+    for name, run in variants:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lab, cl, crel = run()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        t2 = time.perf_counter()
+        _, summ = cm.compress_partition(blocks, lab, r, handle=h)
+        torch.cuda.synchronize()
+        ct = time.perf_counter() - t2
+        sizes = sorted((len(c) for c in cl), reverse=True)
+        row = {"method": name, "seconds": round(el, 3), "compression_ratio": round(summ["compression_ratio"], 4),
+               "rel_error": round(summ["rel_error"], 5), "clusters": len(cl), "largest": sizes[:4],
+               "max_cluster_rel": round(max(crel), 5) if crel else None, "compress_seconds": round(ct, 2)}
+        rows.append(row)
+        log(f"{name}: {row}")
+    base = rows[0]["seconds"]
+    for row in rows:
+        row["relative_time"] = round(row["seconds"] / base, 2) if base > 0 else None
+    out = {
+        "metric": "Table 2 protocol: compression ratio and clustering wall time per variant",
+        "unit": "s",
+        "n_gpus": 1,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"table1_like/{args.preset}: {pool} of {nb} FP32 blocks {m}x{k}, 64 latent 16-dim "
+                               f"subspaces, noise {noise}, r={r}, eps={eps}",
+                   "blocks": pool, "m": m, "k": k, "r": r, "eps": eps},
+        "variants": rows,
+        "all_within_eps": all(row["rel_error"] <= eps + 1e-9 for row in rows),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def smallk(args, cm, workloads, torch):
     """All anchor-first pairs of a collection with the paper's shapes (Table 1: many thin
     blocks) and synthetic values (64 latent 16-dim subspaces + noise 0.05), evaluated in
     one cmsvd_merge_errors call per step; sampled parity against the FP64 oracle."""
+    if args.preset not in SMALLK:
+        raise SystemExit(f"--preset {args.preset} is a --workload table2 shape")
     nb, m, k, r = SMALLK[args.preset]
     t0 = time.time()
     blocks_np = workloads.table1_like(seed=0, nblocks=nb, m=m, k=k)
@@ -565,8 +643,9 @@ def main():
                     "exact-SVD checks (for profiling)")
     ap.add_argument("--rank", type=int, default=32, help="cluster: target rank (32 or 128)")
     ap.add_argument("--nblocks", type=int, default=512, help="cluster: collection size")
-    ap.add_argument("--preset", default="qualcomm", choices=("qualcomm", "bigearthnet", "pdebench"),
-                    help="smallk: collection shape (Table 1 of the paper; values synthetic)")
+    ap.add_argument("--pool", type=int, default=0, help="table2: blocks used (0: the preset's default)")
+    ap.add_argument("--preset", default="qualcomm", choices=("qualcomm", "bigearthnet", "pdebench", "smolvlm"),
+                    help="smallk, slack, table2: collection shape (Table 1 of the paper; values synthetic)")
     ap.add_argument("--sort-mode", default="frobenius", choices=("frobenius", "residual"),
                     help="cluster_residual: candidate order of a pass")
     ap.add_argument("--cpu-chains", type=int, default=6, help="cluster_residual: oracle sample (narrow pairs)")
@@ -575,7 +654,8 @@ def main():
     ap.add_argument("--compare-f64", action="store_true", help="cluster: also run the FP64 clustering")
     ap.add_argument("--parity-pairs", type=int, default=48, help="cluster: oracle sample (narrow pairs)")
     ap.add_argument("--workload", default="pairs",
-                    choices=("pairs", "chain_grad", "cluster", "cluster_residual", "smallk", "weights", "slack"),
+                    choices=("pairs", "chain_grad", "cluster", "cluster_residual", "smallk", "weights", "slack",
+                             "table2"),
                     help="pairs: batched merge errors (the default line); chain_grad: tail energy and "
                          "its gradient along a 64-block chain")
     args = ap.parse_args()
@@ -615,6 +695,8 @@ def main():
         return cluster_residual(args, cm, workloads, torch)
     if args.workload == "smallk":
         return smallk(args, cm, workloads, torch)
+    if args.workload == "table2":
+        return table2(args, cm, workloads, torch)
     if args.workload == "slack":
         return slack(args, cm, workloads, torch)
     if args.workload == "weights":

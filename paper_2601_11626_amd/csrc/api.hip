@@ -91,6 +91,8 @@ struct cmsvd_ctx {
     hipEvent_t pin_ev = nullptr;
     bool pin_ev_armed = false;
     int proj = CMSVD_PROJ_F64;  // precision of the candidate projections
+    char* gsk = nullptr;        // split-K partial products of the GEMMs
+    size_t gsk_cap = 0;
     // stage timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> marks[4];
@@ -219,14 +221,31 @@ struct GemmGroup {
     }
 };
 
-void run_gemm(const GemmGroup& g, char* dbase, hipStream_t s) {
+// A launch with few output tiles and a long contraction (the single-problem Grams and
+// projections of a commit at large m) would stream its whole K range through a few
+// compute units; there the K range is split over up to ncu / tiles workgroups per tile
+// (at least 256 K values each) and the partials are summed in a fixed order.
+void run_gemm(cmsvd_ctx* h, const GemmGroup& g, char* dbase) {
     if (g.d.empty()) return;
-    if (g.bf16)
-        gemm_bf16_batched(reinterpret_cast<const GemmDesc*>(dbase + g.off), (int)g.d.size(), g.maxM, g.maxN, g.ta,
-                          g.tb, g.af32, g.bf32, g.bf16, g.alpha, g.beta, s);
-    else
-        gemm_f64_batched(reinterpret_cast<const GemmDesc*>(dbase + g.off), (int)g.d.size(), g.maxM, g.maxN, g.ta,
-                         g.tb, g.af32, g.bf32, g.alpha, g.beta, s);
+    const GemmDesc* dd = reinterpret_cast<const GemmDesc*>(dbase + g.off);
+    if (g.bf16) {
+        gemm_bf16_batched(dd, (int)g.d.size(), g.maxM, g.maxN, g.ta, g.tb, g.af32, g.bf32, g.bf16, g.alpha, g.beta,
+                          h->stream);
+        return;
+    }
+    int maxK = 0;
+    for (const auto& x : g.d) maxK = std::max(maxK, x.K);
+    const long tiles = (long)((g.maxM + 63) / 64) * ((g.maxN + 63) / 64) * (long)g.d.size();
+    int ks = 1;
+    if (2 * tiles <= h->ncu && maxK >= 1024) ks = (int)std::min<long>(std::min<long>(h->ncu / tiles, maxK / 256), 64);
+    double* part = nullptr;
+    if (ks > 1) {
+        const size_t need = g.d.size() * (size_t)ks * g.maxM * g.maxN * sizeof(double);
+        if (ensure(h, h->gsk, h->gsk_cap, need) == CMSVD_OK) part = reinterpret_cast<double*>(h->gsk);
+        else ks = 1;  // no memory for the partials: the unsplit launch is still correct
+    }
+    gemm_f64_batched(dd, (int)g.d.size(), g.maxM, g.maxN, g.ta, g.tb, g.af32, g.bf32, g.alpha, g.beta, h->stream, ks,
+                     part);
 }
 
 // ---------------------------------------------------------------------------
@@ -351,7 +370,8 @@ struct CholPlan {
         }
     }
 
-    void run(char* db, hipStream_t s) {
+    void run(cmsvd_ctx* h, char* db) {
+        hipStream_t s = h->stream;
         if (!blocked) {
             chol_semidef_batched(reinterpret_cast<const CholDesc*>(db + o_desc), (int)jobs.size(), s);
             return;
@@ -361,13 +381,13 @@ struct CholPlan {
             chol_semidef_batched(reinterpret_cast<const CholDesc*>(db + P.o_diag), (int)P.diag.size(), s);
             if (!P.cp.empty()) {
                 copy_f64_batched(reinterpret_cast<const CopyDesc*>(db + P.o_cp), (int)P.cp.size(), P.cprows, s);
-                run_gemm(P.pan, db, s);
-                run_gemm(P.trail, db, s);
+                run_gemm(h, P.pan, db);
+                run_gemm(h, P.trail, db);
             }
         }
         for (auto& L : levels) {
-            run_gemm(L.t, db, s);
-            run_gemm(L.x, db, s);
+            run_gemm(h, L.t, db);
+            run_gemm(h, L.x, db);
         }
         for (size_t i = 0; i < up.size(); ++i) zero_upper(up[i], upk[i], upld[i], s);
     }
@@ -460,16 +480,17 @@ struct BackPlan {
         }
     }
 
-    void run(char* db, hipStream_t s) {
+    void run(cmsvd_ctx* h, char* db) {
+        hipStream_t s = h->stream;
         sym_vectors_batched(reinterpret_cast<const VecDesc*>(db + o_vd), (int)jobs.size(), s);
         if (!blocked) return;
         for (const auto& v : jobs) materialize_reflectors(const_cast<double*>(v.V), v.n, v.ldv, s);
-        run_gemm(gS, db, s);
+        run_gemm(h, gS, db);
         larft_batched(reinterpret_cast<const LarftDesc*>(db + o_lf), (int)lf.size(), s);
         for (auto& st : steps) {
-            run_gemm(st.g1, db, s);
-            run_gemm(st.g2, db, s);
-            run_gemm(st.g3, db, s);
+            run_gemm(h, st.g1, db);
+            run_gemm(h, st.g2, db);
+            run_gemm(h, st.g3, db);
         }
     }
 };
@@ -691,28 +712,28 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
     int maxrows = 0;
     for (const auto& c : jobs) maxrows = std::max(maxrows, c.m);
     sumsq_batched(reinterpret_cast<const NormDesc*>(db + o_nd), (int)nd.size(), s);
-    run_gemm(gP32, db, s);
-    run_gemm(gP64, db, s);
+    run_gemm(h, gP32, db);
+    run_gemm(h, gP64, db);
     copy_f64_batched(reinterpret_cast<const CopyDesc*>(db + o_cd), J, maxrows, s);
-    run_gemm(gR1, db, s);
-    run_gemm(gP2, db, s);
-    run_gemm(gR2, db, s);
+    run_gemm(h, gR1, db);
+    run_gemm(h, gP2, db);
+    run_gemm(h, gR2, db);
     for (int j = 0; j < J; ++j)
         if (jobs[j].r_in > 0) add_f64(D(o[j].P2), D(o[j].P), (long)jobs[j].r_in * o[j].k, s);
-    run_gemm(gG1, db, s);
-    cp1.run(db, s);
-    run_gemm(gQ1, db, s);
-    run_gemm(gG2, db, s);
-    cp2.run(db, s);
-    run_gemm(gQr, db, s);
-    run_gemm(gF, db, s);
+    run_gemm(h, gG1, db);
+    cp1.run(h, db);
+    run_gemm(h, gQ1, db);
+    run_gemm(h, gG2, db);
+    cp2.run(h, db);
+    run_gemm(h, gQr, db);
+    run_gemm(h, gF, db);
     assemble_kt_batched(reinterpret_cast<const KtDesc*>(db + o_kd), J, nmax, s);
-    run_gemm(gS, db, s);
+    run_gemm(h, gS, db);
     sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), J, nmax, 1, D(eig_off), nslots, s);
-    bp.run(db, s);
-    run_gemm(gU1, db, s);
-    run_gemm(gU2a, db, s);
-    run_gemm(gU2b, db, s);
+    bp.run(h, db);
+    run_gemm(h, gU1, db);
+    run_gemm(h, gU2a, db);
+    run_gemm(h, gU2b, db);
     if (!fdk.empty()) finalize_state_batched(reinterpret_cast<const FinDesc*>(db + o_fd), (int)fdk.size(), s);
     HIPCHK(hipGetLastError());
     return CMSVD_OK;
@@ -792,8 +813,8 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
         if (st != CMSVD_OK) return st;
         {
             StageMark mark(h, ST_PROJ);
-            run_gemm(g32, db, h->stream);
-            run_gemm(g64, db, h->stream);
+            run_gemm(h, g32, db);
+            run_gemm(h, g64, db);
         }
         {
             StageMark mark(h, ST_CORE);
@@ -887,7 +908,7 @@ cmsvd_status eval_dense(cmsvd_ctx* h, const DenseEval& de, const std::vector<Pai
         if (st != CMSVD_OK) return st;
         {
             StageMark mark(h, ST_PROJ);
-            run_gemm(g, db, h->stream);
+            run_gemm(h, g, db);
         }
         expand_dense_descs(dP + pos, (int)nj, dA, dC, r, a0, C, ldc, cmin, err, rel, ed, h->stream);
         {
@@ -927,8 +948,8 @@ cmsvd_status norms_and_grams(cmsvd_ctx* h, const std::vector<cmsvd_block>& bl, c
     {
         StageMark mark(h, ST_PREP);
         sumsq_batched(reinterpret_cast<const NormDesc*>(db + o_nd), (int)nd.size(), h->stream);
-        run_gemm(g32, db, h->stream);
-        run_gemm(g64, db, h->stream);
+        run_gemm(h, g32, db);
+        run_gemm(h, g64, db);
     }
     HIPCHK(hipGetLastError());
     return CMSVD_OK;
@@ -951,7 +972,7 @@ cmsvd_status gemm1(cmsvd_ctx* h, bool ta, bool tb, int M, int N, int K, double a
     char* db = nullptr;
     cmsvd_status st = upload(h, stg, &db);
     if (st != CMSVD_OK) return st;
-    run_gemm(g, db, h->stream);
+    run_gemm(h, g, db);
     HIPCHK(hipGetLastError());
     return CMSVD_OK;
 }
@@ -1072,10 +1093,10 @@ cmsvd_status resid_eval(cmsvd_ctx* h, const ResidState& st, const std::vector<Re
         if (s != CMSVD_OK) return s;
         if (q > 0) {
             StageMark mark(h, ST_PROJ);
-            run_gemm(gP32, db, h->stream);
-            run_gemm(gP64, db, h->stream);
+            run_gemm(h, gP32, db);
+            run_gemm(h, gP64, db);
             copy_f64_batched(reinterpret_cast<const CopyDesc*>(db + o_cd), (int)cd.size(), kmax, h->stream);
-            run_gemm(gS, db, h->stream);
+            run_gemm(h, gS, db);
         }
         {
             StageMark mark(h, ST_CORE);
@@ -1088,13 +1109,13 @@ cmsvd_status resid_eval(cmsvd_ctx* h, const ResidState& st, const std::vector<Re
     return CMSVD_OK;
 }
 
-// ||Q^T B_j||_F^2 for every candidate (the residual ordering of a pass: the residual
-// energy is ||B_j||^2 minus this).
-cmsvd_status resid_proj_norms(cmsvd_ctx* h, const ResidState& st, const std::vector<cmsvd_block>& bl,
-                              const std::vector<double*>& out) {
+// out[j] = ||Q^T B_j||_F^2 for a list of blocks (Q m x q, row-major, row stride ldq):
+// one grouped projection GEMM per 8 GiB of products, then column-block sums of squares.
+cmsvd_status proj_sumsq(cmsvd_ctx* h, const double* Q, long ldq, int q, int m, const std::vector<cmsvd_block>& bl,
+                        const std::vector<double*>& out) {
     const size_t total = bl.size();
     if (total == 0) return CMSVD_OK;
-    if (st.q == 0) {
+    if (q == 0) {
         for (double* o : out) fill_f64(o, 1, 0.0, h->stream);
         HIPCHK(hipGetLastError());
         return CMSVD_OK;
@@ -1103,14 +1124,14 @@ cmsvd_status resid_proj_norms(cmsvd_ctx* h, const ResidState& st, const std::vec
     while (b0 < total) {
         size_t b1 = b0, bytes = 0;
         while (b1 < total) {
-            const size_t need = align256((size_t)st.q * bl[b1].cols * 8);
+            const size_t need = align256((size_t)q * bl[b1].cols * 8);
             if (b1 > b0 && bytes + need > ((size_t)8 << 30)) break;
             bytes += need;
             ++b1;
         }
         Plan pl;
         std::vector<size_t> oP(b1 - b0);
-        for (size_t i = b0; i < b1; ++i) oP[i - b0] = pl.add((size_t)st.q * bl[i].cols * 8);
+        for (size_t i = b0; i < b1; ++i) oP[i - b0] = pl.add((size_t)q * bl[i].cols * 8);
         cmsvd_status s = ensure(h, h->ws, h->ws_cap, pl.off);
         if (s != CMSVD_OK) return s;
         GemmGroup g32, g64;
@@ -1119,9 +1140,9 @@ cmsvd_status resid_proj_norms(cmsvd_ctx* h, const ResidState& st, const std::vec
         std::vector<ColNormDesc> cn;
         for (size_t i = b0; i < b1; ++i) {
             double* P = reinterpret_cast<double*>(h->ws + oP[i - b0]);
-            GemmDesc g{st.Q, bl[i].ptr, P, st.q, (int)bl[i].cols, st.m, (long)st.qcap, (long)bl[i].ld, (long)st.q};
+            GemmDesc g{Q, bl[i].ptr, P, q, (int)bl[i].cols, m, ldq, (long)bl[i].ld, (long)q};
             (bl[i].dtype == CMSVD_F32 ? g32 : g64).push(g);
-            cn.push_back(ColNormDesc{P, st.q, (int)bl[i].cols, (long)st.q, out[i]});
+            cn.push_back(ColNormDesc{P, q, (int)bl[i].cols, (long)q, out[i]});
         }
         Stage stg;
         g32.off = stg.add(g32.d);
@@ -1132,14 +1153,21 @@ cmsvd_status resid_proj_norms(cmsvd_ctx* h, const ResidState& st, const std::vec
         if (s != CMSVD_OK) return s;
         {
             StageMark mark(h, ST_PROJ);
-            run_gemm(g32, db, h->stream);
-            run_gemm(g64, db, h->stream);
+            run_gemm(h, g32, db);
+            run_gemm(h, g64, db);
         }
         colblock_sumsq_batched(reinterpret_cast<const ColNormDesc*>(db + oc), (int)cn.size(), h->stream);
         HIPCHK(hipGetLastError());
         b0 = b1;
     }
     return CMSVD_OK;
+}
+
+// ||Q^T B_j||_F^2 for every candidate (the residual ordering of a pass: the residual
+// energy is ||B_j||^2 minus this).
+cmsvd_status resid_proj_norms(cmsvd_ctx* h, const ResidState& st, const std::vector<cmsvd_block>& bl,
+                              const std::vector<double*>& out) {
+    return proj_sumsq(h, st.Q, (long)st.qcap, st.q, st.m, bl, out);
 }
 
 // Accepts a block whose residual spectrum `lam` (nk values) was computed against the
@@ -1206,16 +1234,16 @@ cmsvd_status resid_accept_block(cmsvd_ctx* h, ResidState& st, const cmsvd_block&
     {
         StageMark mark(h, ST_COMMIT);
         copy_f64_batched(reinterpret_cast<const CopyDesc*>(db + o_cd), 1, m, s);
-        run_gemm(gP, db, s);
-        run_gemm(gR1, db, s);
-        run_gemm(gP2, db, s);
-        run_gemm(gR2, db, s);
-        run_gemm(gG1, db, s);
-        cp1.run(db, s);
-        run_gemm(gQ1, db, s);
-        run_gemm(gG2, db, s);
-        cp2.run(db, s);
-        run_gemm(gQr, db, s);
+        run_gemm(h, gP, db);
+        run_gemm(h, gR1, db);
+        run_gemm(h, gP2, db);
+        run_gemm(h, gR2, db);
+        run_gemm(h, gG1, db);
+        cp1.run(h, db);
+        run_gemm(h, gQ1, db);
+        run_gemm(h, gG2, db);
+        cp2.run(h, db);
+        run_gemm(h, gQr, db);
         append_kept_columns(D(oQr), m, k, D(oL2), (long)k, st.Q, (long)st.qcap, q, st.qcap - q, st.map, st.count, s);
     }
     HIPCHK(hipGetLastError());
@@ -1420,8 +1448,8 @@ cmsvd_status resid_scan(cmsvd_ctx* h, ResidBuffers& rb, const cmsvd_block* block
             if (stt != CMSVD_OK) return stt;
             if (q > 0) {
                 StageMark mark(h, ST_PROJ);
-                run_gemm(g32, db, s);
-                run_gemm(g64, db, s);
+                run_gemm(h, g32, db);
+                run_gemm(h, g64, db);
                 colblock_sumsq_batched(reinterpret_cast<const ColNormDesc*>(db + o_cn), (int)cn.size(), s);
             } else {
                 fill_f64(rb.pn + b0, nj, 0.0, s);
@@ -1487,7 +1515,7 @@ cmsvd_status resid_scan(cmsvd_ctx* h, ResidBuffers& rb, const cmsvd_block* block
             if (q > 0) {
                 StageMark mark(h, ST_PROJ);
                 copy_f64_batched(reinterpret_cast<const CopyDesc*>(db + o_cd), (int)cd.size(), kneed, s);
-                run_gemm(gS, db, s);
+                run_gemm(h, gS, db);
             }
             {
                 StageMark mark(h, ST_CORE);
@@ -1652,7 +1680,7 @@ cmsvd_status gemm_entry(cmsvd_handle h, const char* who, int bf16, int32_t trans
     char* db = nullptr;
     cmsvd_status st = upload(h, stg, &db);
     if (st != CMSVD_OK) return st;
-    run_gemm(g, db, h->stream);
+    run_gemm(h, g, db);
     HIPCHK(hipGetLastError());
     return CMSVD_OK;
 }
@@ -1697,6 +1725,7 @@ cmsvd_status cmsvd_destroy(cmsvd_handle h) {
     (void)hipStreamSynchronize(h->stream);
     if (h->ws) (void)hipFree(h->ws);
     if (h->dsc) (void)hipFree(h->dsc);
+    if (h->gsk) (void)hipFree(h->gsk);
     if (h->pin) (void)hipHostFree(h->pin);
     if (h->pin_ev) (void)hipEventDestroy(h->pin_ev);
     for (auto& v : h->marks)
@@ -2067,7 +2096,6 @@ cmsvd_status cmsvd_cluster(cmsvd_handle h, const cmsvd_block* blocks, int64_t nb
     const size_t o_err = pl.add((size_t)N * 8), o_rel = pl.add((size_t)N * 8);
     const size_t o_first = pl.add(8);
     const size_t o_pn = pl.add((size_t)N * 8);  // ||Q^T A_j||^2 (residual sort)
-    const size_t o_P = pl.add((size_t)r * kmax * 8);
     DevBuf keep;
     if (hipMalloc((void**)&keep.p, pl.off) != hipSuccess) {
         (void)hipGetLastError();
@@ -2113,24 +2141,18 @@ cmsvd_status cmsvd_cluster(cmsvd_handle h, const cmsvd_block* blocks, int64_t nb
                     return n2[a] < n2[b] || (n2[a] == n2[b] && a < b);
                 });
             } else if (!order.empty()) {
-                // residual norms ||A_j||^2 - ||U^T A_j||^2 against the pass-start state
+                // residual norms ||A_j||^2 - ||U^T A_j||^2 against the pass-start state,
+                // all remaining candidates in one grouped projection
                 std::vector<double> res(N, 0.0);
-                for (size_t c = 0; c < order.size(); ++c) {
-                    const int j = order[c];
-                    GemmGroup g;
-                    g.tb = true;
-                    g.bf32 = blocks[j].dtype == CMSVD_F32;
-                    g.push(GemmDesc{K(o_U[cur]), blocks[j].ptr, K(o_P), (int)r, (int)blocks[j].cols, (int)m, (long)r,
-                                    (long)blocks[j].ld, (long)r});
-                    ColNormDesc cn{K(o_P), (int)r, (int)blocks[j].cols, (long)r, K(o_pn) + j};
-                    Stage stg;
-                    g.off = stg.add(g.d);
-                    const size_t oc = stg.add(&cn, sizeof(cn));
-                    char* db = nullptr;
-                    st = upload(h, stg, &db);
+                {
+                    std::vector<cmsvd_block> bl;
+                    std::vector<double*> outp;
+                    for (const int j : order) {
+                        bl.push_back(blocks[j]);
+                        outp.push_back(K(o_pn) + j);
+                    }
+                    st = proj_sumsq(h, K(o_U[cur]), (long)r, (int)r, (int)m, bl, outp);
                     if (st != CMSVD_OK) return st;
-                    run_gemm(g, db, h->stream);
-                    colblock_sumsq_batched(reinterpret_cast<const ColNormDesc*>(db + oc), 1, h->stream);
                 }
                 std::vector<double> pn(N);
                 HIPCHK(hipMemcpyAsync(pn.data(), K(o_pn), (size_t)N * 8, hipMemcpyDeviceToHost, h->stream));
@@ -2465,7 +2487,7 @@ cmsvd_status cmsvd_exact_tail(cmsvd_handle h, const cmsvd_block* blocks, int64_t
     if (st != CMSVD_OK) return st;
     pack_batched(reinterpret_cast<const PackDesc*>(db + o_pk), N, h->stream);
     sumsq_batched(reinterpret_cast<const NormDesc*>(db + o_nd), N, h->stream);
-    run_gemm(g, db, h->stream);
+    run_gemm(h, g, db);
     sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), 1, (int)n, 1, D(o_eig), 1, h->stream);
     energy_minus(D(o_a2), N, D(o_top), D(o_out), h->stream);
     HIPCHK(hipGetLastError());
@@ -2560,18 +2582,18 @@ cmsvd_status cmsvd_compress(cmsvd_handle h, const cmsvd_block* blocks, int64_t n
     hipStream_t s = h->stream;
     pack_batched(reinterpret_cast<const PackDesc*>(db + o_pk), N, s);
     sumsq_batched(reinterpret_cast<const NormDesc*>(db + o_nd), N, s);
-    run_gemm(gG, db, s);
+    run_gemm(h, gG, db);
     sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), 1, (int)n, 1, D(o_eig), 1, s);
-    bp.run(db, s);
+    bp.run(h, db);
     // directions below the Gram's resolution (8 n u lam_1) are stored as zero columns
     const double cut_rel = 8.0 * (double)n * EPS;
     if (cols_side) {
         scale_cols(Vt, (int)ncol, rc, (long)ldv, D(o_lam), 0, cut_rel, s);
     } else {
-        run_gemm(gV, db, s);
+        run_gemm(h, gV, db);
         scale_cols(Vt, (int)ncol, rc, (long)ldv, D(o_lam), 1, cut_rel, s);
     }
-    run_gemm(gU, db, s);
+    run_gemm(h, gU, db);
     energy_minus(D(o_a2), N, D(o_top), D(o_out), s);
     fill_f64(D(o_zero), 2, 0.0, s);
     energy_minus(D(o_a2), N, D(o_zero), D(o_out) + 1, s);  // ||M_C||_F^2

@@ -59,15 +59,27 @@ __device__ __forceinline__ void store_tile_lds(double (*S)[GBM + GPAD], const do
     }
 }
 
+// Split K (ksplit > 1): blockIdx.x = split * maxTiles + tile; the workgroup contracts the
+// K range [split * Kc, (split + 1) * Kc) (Kc a multiple of 16) and writes its unscaled
+// partial tile to part (ksplit partials of maxM x maxN per problem, column-major);
+// gemm_splitk_reduce then sums the partials in split order and applies alpha and beta.
 template <typename TA, typename TB, bool TA_T, bool TB_T>
 __global__ void __launch_bounds__(256) gemm_f64_kernel(const GemmDesc* __restrict__ descs, int base,
-                                                       double alpha, double beta) {
+                                                       double alpha, double beta, int ksplit, int maxTiles,
+                                                       int maxM, int maxN, double* __restrict__ part) {
     const GemmDesc d = descs[base + blockIdx.y];
     const int tilesM = (d.M + GBM - 1) / GBM;
     const int tilesN = (d.N + GBN - 1) / GBN;
-    if ((int)blockIdx.x >= tilesM * tilesN) return;
-    const int tm = blockIdx.x % tilesM, tn = blockIdx.x / tilesM;
+    const int split = (int)blockIdx.x / maxTiles, tile = (int)blockIdx.x % maxTiles;
+    if (tile >= tilesM * tilesN) return;
+    const int tm = tile % tilesM, tn = tile / tilesM;
     const int m0 = tm * GBM, n0 = tn * GBN;
+    int kbeg = 0, kend = d.K;
+    if (ksplit > 1) {
+        const int kc = ((d.K + ksplit - 1) / ksplit + GBK - 1) / GBK * GBK;
+        kbeg = split * kc < d.K ? split * kc : d.K;
+        kend = kbeg + kc < d.K ? kbeg + kc : d.K;
+    }
     const TA* __restrict__ A = static_cast<const TA*>(d.A);
     const TB* __restrict__ B = static_cast<const TB*>(d.B);
 
@@ -85,17 +97,17 @@ __global__ void __launch_bounds__(256) gemm_f64_kernel(const GemmDesc* __restric
     // op(A) is M x K; op(B) is K x N, staged as its transpose (N x K) so that both
     // operands share the (free index, contraction index) slab loader.
     double ra[4], rb[4];
-    const int nk = (d.K + GBK - 1) / GBK;
-    load_tile_regs<TA, TA_T>(A, d.lda, d.M, d.K, m0, 0, ra, t);
-    load_tile_regs<TB, !TB_T>(B, d.ldb, d.N, d.K, n0, 0, rb, t);
+    const int nk = (kend - kbeg + GBK - 1) / GBK;
+    load_tile_regs<TA, TA_T>(A, d.lda, d.M, kend, m0, kbeg, ra, t);
+    load_tile_regs<TB, !TB_T>(B, d.ldb, d.N, kend, n0, kbeg, rb, t);
     store_tile_lds<TA_T>(As[0], ra, t);
     store_tile_lds<!TB_T>(Bs[0], rb, t);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
         if (kt + 1 < nk) {
-            load_tile_regs<TA, TA_T>(A, d.lda, d.M, d.K, m0, (kt + 1) * GBK, ra, t);
-            load_tile_regs<TB, !TB_T>(B, d.ldb, d.N, d.K, n0, (kt + 1) * GBK, rb, t);
+            load_tile_regs<TA, TA_T>(A, d.lda, d.M, kend, m0, kbeg + (kt + 1) * GBK, ra, t);
+            load_tile_regs<TB, !TB_T>(B, d.ldb, d.N, kend, n0, kbeg + (kt + 1) * GBK, rb, t);
         }
 #pragma unroll
         for (int k4 = 0; k4 < GBK / 4; ++k4) {
@@ -116,6 +128,7 @@ __global__ void __launch_bounds__(256) gemm_f64_kernel(const GemmDesc* __restric
         __syncthreads();
     }
     // D[i][j] of a 16x16 FP64 block sits in lane j + 16*(i%4), element i/4.
+    double* pt = part ? part + ((long)(base + blockIdx.y) * ksplit + split) * (long)maxM * maxN : nullptr;
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -125,35 +138,65 @@ __global__ void __launch_bounds__(256) gemm_f64_kernel(const GemmDesc* __restric
                 const int row = m0 + wm * 32 + bi * 16 + (lane >> 4) + 4 * v;
                 const int col = n0 + wn * 32 + bj * 16 + (lane & 15);
                 if (row < d.M && col < d.N) {
-                    double* c = d.C + (long)row + (long)col * d.ldc;
-                    double val = alpha * acc[bi][bj][v];
-                    if (beta != 0.0) val += beta * (*c);
-                    *c = val;
+                    if (pt) {
+                        pt[(long)row + (long)col * maxM] = acc[bi][bj][v];
+                    } else {
+                        double* c = d.C + (long)row + (long)col * d.ldc;
+                        double val = alpha * acc[bi][bj][v];
+                        if (beta != 0.0) val += beta * (*c);
+                        *c = val;
+                    }
                 }
             }
 }
 
+// C = alpha * (sum of the ksplit partials, in split order) + beta * C, per problem.
+__global__ void __launch_bounds__(256) gemm_splitk_reduce(const GemmDesc* __restrict__ descs, int base, double alpha,
+                                                          double beta, int ksplit, int maxM, int maxN,
+                                                          const double* __restrict__ part) {
+    const GemmDesc d = descs[base + blockIdx.y];
+    const long tot = (long)d.M * d.N;
+    const double* pb = part + (long)(base + blockIdx.y) * ksplit * (long)maxM * maxN;
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < tot; e += (long)gridDim.x * 256) {
+        const int col = (int)(e / d.M), row = (int)(e - (long)col * d.M);
+        double sum = 0.0;
+        for (int sp = 0; sp < ksplit; ++sp) sum += pb[(long)sp * maxM * maxN + row + (long)col * maxM];
+        double* c = d.C + (long)row + (long)col * d.ldc;
+        double val = alpha * sum;
+        if (beta != 0.0) val += beta * (*c);
+        *c = val;
+    }
+}
+
 template <typename TA, typename TB>
 static void launch_typed(const GemmDesc* descs, int count, int maxM, int maxN, bool ta, bool tb,
-                         double alpha, double beta, hipStream_t s) {
+                         double alpha, double beta, int ksplit, double* part, hipStream_t s) {
     const int tiles = ((maxM + GBM - 1) / GBM) * ((maxN + GBN - 1) / GBN);
+    const int ks = part ? ksplit : 1;
     for (int base = 0; base < count; base += 65535) {
         const int n = count - base < 65535 ? count - base : 65535;
-        dim3 grid(tiles, n), block(256);
-        if (!ta && !tb) hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, false, false>), grid, block, 0, s, descs, base, alpha, beta);
-        if (!ta && tb) hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, false, true>), grid, block, 0, s, descs, base, alpha, beta);
-        if (ta && !tb) hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, true, false>), grid, block, 0, s, descs, base, alpha, beta);
-        if (ta && tb) hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, true, true>), grid, block, 0, s, descs, base, alpha, beta);
+        dim3 grid(tiles * ks, n), block(256);
+        if (!ta && !tb) hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, false, false>), grid, block, 0, s, descs, base, alpha, beta, ks, tiles, maxM, maxN, part);
+        if (!ta && tb) hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, false, true>), grid, block, 0, s, descs, base, alpha, beta, ks, tiles, maxM, maxN, part);
+        if (ta && !tb) hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, true, false>), grid, block, 0, s, descs, base, alpha, beta, ks, tiles, maxM, maxN, part);
+        if (ta && tb) hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, true, true>), grid, block, 0, s, descs, base, alpha, beta, ks, tiles, maxM, maxN, part);
+        if (part) {
+            const long el = (long)maxM * maxN;
+            const int g = (int)((el + 255) / 256 < 64 ? (el + 255) / 256 : 64);
+            hipLaunchKernelGGL(gemm_splitk_reduce, dim3(g, n), dim3(256), 0, s, descs, base, alpha, beta, ks, maxM, maxN,
+                               (const double*)part);
+        }
     }
 }
 
 void gemm_f64_batched(const GemmDesc* d_descs, int count, int maxM, int maxN, bool transA, bool transB,
-                      bool a_f32, bool b_f32, double alpha, double beta, hipStream_t s) {
+                      bool a_f32, bool b_f32, double alpha, double beta, hipStream_t s, int ksplit, double* part) {
     if (count <= 0 || maxM <= 0 || maxN <= 0) return;
-    if (a_f32 && b_f32) launch_typed<float, float>(d_descs, count, maxM, maxN, transA, transB, alpha, beta, s);
-    else if (a_f32) launch_typed<float, double>(d_descs, count, maxM, maxN, transA, transB, alpha, beta, s);
-    else if (b_f32) launch_typed<double, float>(d_descs, count, maxM, maxN, transA, transB, alpha, beta, s);
-    else launch_typed<double, double>(d_descs, count, maxM, maxN, transA, transB, alpha, beta, s);
+    if (ksplit <= 1) part = nullptr;
+    if (a_f32 && b_f32) launch_typed<float, float>(d_descs, count, maxM, maxN, transA, transB, alpha, beta, ksplit, part, s);
+    else if (a_f32) launch_typed<float, double>(d_descs, count, maxM, maxN, transA, transB, alpha, beta, ksplit, part, s);
+    else if (b_f32) launch_typed<double, float>(d_descs, count, maxM, maxN, transA, transB, alpha, beta, ksplit, part, s);
+    else launch_typed<double, double>(d_descs, count, maxM, maxN, transA, transB, alpha, beta, ksplit, part, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -14,8 +14,12 @@ struct GemmDesc {
     long lda, ldb, ldc;
 };
 
+// ksplit > 1 with part != nullptr splits every problem's K range over ksplit workgroups
+// per tile (for launches with few tiles and long K); part holds count * ksplit * maxM *
+// maxN doubles of partial products, summed in a fixed order by a second kernel.
 void gemm_f64_batched(const GemmDesc* d_descs, int count, int maxM, int maxN, bool transA, bool transB,
-                      bool a_f32, bool b_f32, double alpha, double beta, hipStream_t s);
+                      bool a_f32, bool b_f32, double alpha, double beta, hipStream_t s, int ksplit = 1,
+                      double* part = nullptr);
 // Same descriptors and semantics with the operands rounded to BF16 (through FP32, both
 // round-to-nearest-even) and FP32 accumulation on the matrix cores; C stays FP64.
 // passes = 1: hi parts only; 3: lo_A hi_B + hi_A lo_B + hi_A hi_B (split operands).
