@@ -35,9 +35,11 @@
  *     runtime failure.  cmsvd_last_error() gives a thread-local message.
  *   - Every symmetric eigenproblem the library solves has order at most 2016: the
  *     core of an update (r_in + n_i), of a candidate merge (r + n_j), a block's or
- *     residual's Gram (n_j) and an explicit Gram (min(m, sum n_j)).  Larger orders
- *     return CMSVD_EUNSUPPORTED; append wider blocks as column panels (concatenation
- *     is associative, so the same matrix results).
+ *     residual's Gram (n_j) and the explicit Gram of cmsvd_exact_tail (min(m, sum
+ *     n_j)).  Larger orders return CMSVD_EUNSUPPORTED; append wider blocks as column
+ *     panels (concatenation is associative, so the same matrix results).
+ *     cmsvd_compress handles larger Grams by subspace iteration (its rank r_C is
+ *     limited to 2016).
  *   - NaN/Inf in the data propagate into the affected results; they are not errors.
  *     A rank-deficient residual is not an error either: its numerically absent
  *     directions are dropped (their energy stays in the error estimate).
@@ -235,9 +237,15 @@ cmsvd_status cmsvd_exact_tail(cmsvd_handle handle, const cmsvd_block* blocks, in
    U~ = U S (m x r_C) and V (N_C x r_C), N_C = sum_j n_j, r_C = min(r, m, N_C).  Block j
    is recovered as U~ V_j^T with V_j its n_j rows of V; the error of the cluster is
    sum_{l > r_C} sigma_l^2 (Eckart-Young) and its memory r_C (m + N_C).  Computed from
-   the eigenpairs of the explicit Gram (M^T M or M M^T, whichever is smaller);
-   directions whose Gram eigenvalue is at most 8 n u lambda_1 (the Gram's resolution)
-   are stored as zero columns.
+   the eigenpairs of the explicit Gram (M^T M or M M^T, whichever is smaller, order
+   n = min(m, N_C)); directions whose Gram eigenvalue is at most 8 n u lambda_1 (the
+   Gram's resolution) are stored as zero columns.  For n above 2016 the top r_C
+   eigenpairs come from subspace iteration on p = min(2016, max(2 r_C, r_C + 32))
+   columns (CholeskyQR2 between products, Rayleigh-Ritz on X^T G X every step) until
+   the sum of the top r_C Ritz values changes by at most 1e-14 relative, or after 60
+   steps; the factors are then the Ritz projection, so tail2 is exactly their error and
+   never below the optimum (Ky Fan), and the gap to it is the iteration's convergence.
+   r_C above 2016 returns CMSVD_EUNSUPPORTED.
      Ut      DEVICE out, row-major m x r_C FP64, row stride ldu >= r_C: U S
      Vt      DEVICE out, row-major r_C x N_C FP64, row stride ldv >= N_C: V^T (block j
              occupies its n_j columns, in the order given)

@@ -2514,19 +2514,38 @@ cmsvd_status cmsvd_compress(cmsvd_handle h, const cmsvd_block* blocks, int64_t n
         ncol += blocks[i].cols;
     }
     const int64_t n = std::min(m, ncol);
-    cmsvd_status so = check_order(n, "cmsvd_compress");
-    if (so != CMSVD_OK) return so;
-    if (ncol > INT32_MAX / 2 || m > INT32_MAX / 2) return fail(CMSVD_EUNSUPPORTED, "cmsvd_compress: too large");
+    if (ncol > INT32_MAX / 2 || m > INT32_MAX / 2 || (double)n * (double)n > 4e9)
+        return fail(CMSVD_EUNSUPPORTED, "cmsvd_compress: too large");
     const int rc = (int)std::min<int64_t>(r, n);
+    if (rc > sym_eig_nmax()) return fail(CMSVD_EUNSUPPORTED, "cmsvd_compress: rank %d exceeds %d", rc, sym_eig_nmax());
     if (ldu < rc || ldv < ncol) return fail(CMSVD_ESHAPE, "cmsvd_compress: ldu < rank or ldv < total columns");
     const bool cols_side = ncol <= m;  // Gram M^T M (else M M^T)
+    // Above the eigen kernels' order the top eigenpairs of the Gram come from subspace
+    // iteration with Rayleigh-Ritz on p columns (the Ritz problem has order p).
+    const bool large = n > sym_eig_nmax();
+    const int p = large ? (int)std::min<int64_t>({n, (int64_t)sym_eig_nmax(), std::max<int64_t>(2 * rc, rc + 32)})
+                        : (int)n;
+    const int ne = p;  // order of the eigenproblem solved
     Plan pl;
     const size_t o_M = pl.add((size_t)m * ncol * 8), o_G = pl.add((size_t)n * n * 8), o_a2 = pl.add((size_t)N * 16),
-                 o_top = pl.add(16), o_lam = pl.add((size_t)rc * 8), o_d = pl.add((size_t)n * 8),
-                 o_e = pl.add((size_t)n * 8), o_V = pl.add((size_t)n * n * 8), o_tau = pl.add((size_t)n * 8),
-                 o_vs = pl.add((size_t)6 * n * rc * 8), o_Z = pl.add(cols_side ? 8 : (size_t)n * rc * 8),
-                 o_out = pl.add(16), o_zero = pl.add(16), o_eig = pl.add(sym_eig_workspace_doubles((int)n, 1) * 8),
-                 o_bs = pl.add(BackPlan::scratch_doubles((int)n, rc) * 8);
+                 o_top = pl.add(16), o_lam = pl.add((size_t)rc * 8), o_d = pl.add((size_t)ne * 8),
+                 o_e = pl.add((size_t)ne * 8), o_V = pl.add((size_t)ne * ne * 8), o_tau = pl.add((size_t)ne * 8),
+                 o_vs = pl.add((size_t)6 * ne * rc * 8), o_Z = pl.add(cols_side ? 8 : (size_t)n * rc * 8),
+                 o_out = pl.add(16), o_zero = pl.add(16), o_eig = pl.add(sym_eig_workspace_doubles(ne, 1) * 8),
+                 o_bs = pl.add(BackPlan::scratch_doubles(ne, rc) * 8);
+    size_t o_X = 0, o_Y = 0, o_X1 = 0, o_G1 = 0, o_G2 = 0, o_L1 = 0, o_L2 = 0, o_Zt = 0, o_yn = 0, o_cs = 0;
+    if (large) {
+        o_X = pl.add((size_t)n * p * 8);
+        o_Y = pl.add((size_t)n * p * 8);
+        o_X1 = pl.add((size_t)n * p * 8);
+        o_G1 = pl.add((size_t)p * p * 8);
+        o_G2 = pl.add((size_t)p * p * 8);
+        o_L1 = pl.add((size_t)p * p * 8);
+        o_L2 = pl.add((size_t)p * p * 8);
+        o_Zt = pl.add((size_t)p * rc * 8);
+        o_yn = pl.add(16);
+        o_cs = pl.add(CholPlan::scratch_doubles(p) * 8);
+    }
     cmsvd_status st = ensure(h, h->ws, h->ws_cap, pl.off);
     if (st != CMSVD_OK) return st;
     auto D = [&](size_t off) { return reinterpret_cast<double*>(h->ws + off); };
@@ -2555,27 +2574,58 @@ cmsvd_status cmsvd_compress(cmsvd_handle h, const cmsvd_block* blocks, int64_t n
     gU.push(GemmDesc{Vt, D(o_M), Ut, rc, (int)m, (int)ncol, (long)ldv, (long)ncol, (long)ldu});
     double* Z = cols_side ? Vt : D(o_Z);
     const long ldz = cols_side ? (long)ldv : (long)n;
+    // the eigenproblem: the Gram itself, or the Ritz matrix T = X^T G X of the subspace
+    double* Zeig = large ? D(o_Zt) : Z;
+    const long ldze = large ? (long)p : ldz;
     EigDesc e{};
-    e.n = (int)n;
+    e.n = ne;
     e.n1 = 0;
     e.nkeep = rc;
-    e.Y = D(o_G);
-    e.ldy = (long)n;
+    e.Y = large ? D(o_G2) : D(o_G);  // T lives in the G2 buffer between orthonormalisations
+    e.ldy = (long)ne;
     e.lam = D(o_lam);
     e.d = D(o_d);
     e.e = D(o_e);
     e.V = D(o_V);
-    e.ldv = (long)n;
+    e.ldv = (long)ne;
     e.tau = D(o_tau);
     e.sum_top = D(o_top);
     std::vector<EigDesc> ed{e};
-    std::vector<VecDesc> vd{VecDesc{(int)n, rc, D(o_lam), D(o_d), D(o_e), D(o_V), (long)n, D(o_tau), Z, ldz, D(o_vs)}};
+    std::vector<VecDesc> vd{VecDesc{ne, rc, D(o_lam), D(o_d), D(o_e), D(o_V), (long)ne, D(o_tau), Zeig, ldze, D(o_vs)}};
     BackPlan bp;
     bp.build(vd, {D(o_bs)});
+    // subspace iteration on Xt (p x n column-major: the columns of X as rows):
+    //   Yt = Xt G;  T = Xt Yt^T;  Xt = CholQR2(Yt) = L2^-1 L1^-1 Yt.
+    GemmGroup gY, gT, gG1, gQ1, gG2, gQ2, gZ;
+    CholPlan cp1, cp2;
+    std::vector<NormDesc> yn;
+    if (large) {
+        gY.push(GemmDesc{D(o_X), D(o_G), D(o_Y), p, (int)n, (int)n, (long)p, (long)n, (long)p});
+        gT.tb = true;
+        gT.push(GemmDesc{D(o_X), D(o_Y), D(o_G2), p, p, (int)n, (long)p, (long)p, (long)p});
+        gG1.tb = true;
+        gG1.push(GemmDesc{D(o_Y), D(o_Y), D(o_G1), p, p, (int)n, (long)p, (long)p, (long)p});
+        gQ1.push(GemmDesc{D(o_L1), D(o_Y), D(o_X1), p, (int)n, p, (long)p, (long)p, (long)p});
+        gG2.tb = true;
+        gG2.push(GemmDesc{D(o_X1), D(o_X1), D(o_G2), p, p, (int)n, (long)p, (long)p, (long)p});
+        gQ2.push(GemmDesc{D(o_L2), D(o_X1), D(o_X), p, (int)n, p, (long)p, (long)p, (long)p});
+        // Z (n x rc) = X Zt
+        gZ.ta = true;
+        gZ.push(GemmDesc{D(o_X), Zeig, Z, (int)n, rc, p, (long)p, (long)p, ldz});
+        // pivot thresholds: u ||Y||_F^2 for the first Gram, p^2 u for the nearly orthonormal second
+        cp1.build({CholDesc{p, D(o_G1), (long)p, D(o_L1), (long)p, EPS, D(o_yn), nullptr}}, {D(o_cs)});
+        cp2.build({CholDesc{p, D(o_G2), (long)p, D(o_L2), (long)p, (double)p * p * EPS, nullptr, nullptr}}, {D(o_cs)});
+        yn.push_back(NormDesc{D(o_Y), (int)n, p, (long)p, 0, D(o_yn)});
+    }
     Stage stg;
     const size_t o_pk = stg.add(pk), o_nd = stg.add(nd), o_ed = stg.add(ed);
+    const size_t o_yd = large ? stg.add(yn) : 0;
     bp.stage(stg);
-    for (GemmGroup* g : {&gG, &gV, &gU}) g->off = stg.add(g->d);
+    if (large) {
+        cp1.stage(stg);
+        cp2.stage(stg);
+    }
+    for (GemmGroup* g : {&gG, &gV, &gU, &gY, &gT, &gG1, &gQ1, &gG2, &gQ2, &gZ}) g->off = stg.add(g->d);
     char* db = nullptr;
     st = upload(h, stg, &db);
     if (st != CMSVD_OK) return st;
@@ -2583,8 +2633,39 @@ cmsvd_status cmsvd_compress(cmsvd_handle h, const cmsvd_block* blocks, int64_t n
     pack_batched(reinterpret_cast<const PackDesc*>(db + o_pk), N, s);
     sumsq_batched(reinterpret_cast<const NormDesc*>(db + o_nd), N, s);
     run_gemm(h, gG, db);
-    sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), 1, (int)n, 1, D(o_eig), 1, s);
-    bp.run(h, db);
+    if (!large) {
+        sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), 1, ne, 1, D(o_eig), 1, s);
+        bp.run(h, db);
+    } else {
+        auto orth = [&]() {  // Xt = CholQR2(Yt)
+            sumsq_batched(reinterpret_cast<const NormDesc*>(db + o_yd), 1, s);
+            run_gemm(h, gG1, db);
+            cp1.run(h, db);
+            run_gemm(h, gQ1, db);
+            run_gemm(h, gG2, db);
+            cp2.run(h, db);
+            run_gemm(h, gQ2, db);
+        };
+        fill_hash(D(o_Y), (long)n * p, 0x5EEDull, s);
+        orth();
+        double prev = -1.0;
+        for (int it = 0; it < 60; ++it) {
+            run_gemm(h, gY, db);
+            run_gemm(h, gT, db);
+            sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), 1, ne, 1, D(o_eig), 1, s);
+            double top[2] = {0.0, 0.0};
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(top, D(o_top), 16, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            const double sum = top[0] + top[1];
+            if (!(sum == sum)) break;  // NaN data: the outputs carry it
+            if (it > 0 && std::fabs(sum - prev) <= 1e-14 * std::fabs(sum)) break;
+            prev = sum;
+            orth();
+        }
+        bp.run(h, db);  // Ritz vectors of the last T: Zt
+        run_gemm(h, gZ, db);
+    }
     // directions below the Gram's resolution (8 n u lam_1) are stored as zero columns
     const double cut_rel = 8.0 * (double)n * EPS;
     if (cols_side) {

@@ -236,6 +236,8 @@ void resid_accept(const double* L, int r, const double* lam, int nk, const doubl
 void append_kept_columns(const double* Qr, int m, int k, const double* Li, long ldl, double* Q, long ldq, int q0,
                          int room, int* map, int* count, hipStream_t s);
 void fill_f64(double* x, long n, double v, hipStream_t s);
+// x[i] uniform in [-1, 1) from a counter-based hash of (seed, i).
+void fill_hash(double* x, long n, unsigned long long seed, hipStream_t s);
 // Eigenvalue-free settling of candidates: with b_C^2 = S - sum L,
 //   b_C^2 + ||P||^2 <= b^2 <= b_C^2 + ||B||^2;
 // flag = 0 (rejected), 2 (accepted) or 1 (needs the certificate).  pn = ||Q^T B||_F^2.

@@ -274,4 +274,22 @@ void fill_f64(double* x, long n, double v, hipStream_t s) {
     hipLaunchKernelGGL(fill_f64_kernel, dim3((int)(g > 1024 ? 1024 : g)), dim3(CT), 0, s, x, n, v);
 }
 
+// x[i] uniform in [-1, 1) from a counter-based hash of (seed, i) (SplitMix64 finaliser):
+// a reproducible start basis for subspace iteration.
+__global__ void fill_hash_kernel(double* __restrict__ x, long n, unsigned long long seed) {
+    for (long i = (long)blockIdx.x * CT + threadIdx.x; i < n; i += (long)gridDim.x * CT) {
+        unsigned long long z = seed + 0x9E3779B97F4A7C15ull * (unsigned long long)(i + 1);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        x[i] = (double)(z >> 11) * 0x1p-52 - 1.0;
+    }
+}
+
+void fill_hash(double* x, long n, unsigned long long seed, hipStream_t s) {
+    if (n <= 0) return;
+    const long g = (n + CT - 1) / CT;
+    hipLaunchKernelGGL(fill_hash_kernel, dim3((int)(g > 1024 ? 1024 : g)), dim3(CT), 0, s, x, n, seed);
+}
+
 }  // namespace cmsvd

@@ -102,12 +102,51 @@ def test_partition_summary_matches_oracle(cm):
     assert summary["rel_error"] <= 0.05 + 1e-9
 
 
+def large_cluster(seed, m, widths, rank, noise):
+    rng = np.random.default_rng(seed)
+    Q = workloads.orthonormal(rng, m, rank)
+    sv = np.linspace(10.0, 2.0, rank)
+    return [(Q * sv) @ rng.standard_normal((rank, k)) / np.sqrt(k) + noise * rng.standard_normal((m, k))
+            for k in widths]
+
+
+@pytest.mark.parametrize("m,widths,rank,noise,r", [
+    (2100, [100] * 22, 40, 1e-3, 32),   # both Gram orders above 2016: M M^T of order 2100
+    (2300, [150] * 15, 40, 1e-3, 48),   # rank above the signal: the Ritz problem meets flat noise
+    (4000, [700, 700, 700], 24, 0.0, 16),  # exactly low rank, N = 2100 < m: M^T M of order 2100
+])
+def test_large_order_cluster(cm, m, widths, rank, noise, r):
+    # Gram order above the eigen kernels' limit: subspace iteration with Rayleigh-Ritz.
+    # The stored factors are a rank-r_C projection, so their error is exactly the
+    # reported tail (checked), which is never below the Eckart-Young optimum (Ky Fan)
+    # and matches it to the convergence tolerance.
+    blocks = large_cluster(m + r, m, widths, rank, noise)
+    M = np.concatenate(blocks, axis=1)
+    e2 = float(np.sum(M * M))
+    s = np.linalg.svd(M, compute_uv=False)
+    exact = float(np.sum(s[r:] ** 2))
+    say(f"compress large order m={m} N={M.shape[1]} r={r}")
+    Ut, Vt, t2 = cm.cmsvd_compress(dev(blocks), r)
+    Ut, Vt = Ut.cpu().numpy(), Vt.cpu().numpy()
+    assert Ut.shape == (m, r) and Vt.shape == (r, M.shape[1])
+    assert t2 >= exact - 1e-10 * e2
+    assert t2 - exact <= 1e-6 * max(exact, 1e-3 * e2)
+    R = Ut @ Vt
+    assert abs(float(np.sum((M - R) ** 2)) - t2) <= 1e-9 * e2
+    G = Vt @ Vt.T
+    d = np.diag(G)
+    assert np.all((np.abs(d - 1) < 1e-9) | (d < 1e-20))
+    assert np.max(np.abs(G - np.diag(d))) < 1e-9
+
+
 def test_order_limit_is_reported(cm):
     big = torch.zeros((2100, 2100), dtype=torch.float64, device="cuda")
     with pytest.raises(cm.CmsvdError):
-        cm.cmsvd_compress([big], 8)
-    with pytest.raises(cm.CmsvdError):
         cm.cmsvd_exact_tail([big], 8)
+    with pytest.raises(cm.CmsvdError):  # the Ritz problem too has order at most 2016
+        cm.cmsvd_compress([big], 2017)
+    Ut, Vt, t2 = cm.cmsvd_compress([big], 8)  # a zero cluster above the kernels' order
+    assert t2 == 0.0 and float(torch.abs(Ut).max()) == 0.0
     st = cm.State(2100, 8, "cuda")
     with pytest.raises(cm.CmsvdError):
         cm.cmsvd_update(st, big, 8)
