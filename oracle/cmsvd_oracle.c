@@ -254,6 +254,16 @@ int oracle_update(int m, int rho, const double* U, int ldu, const double* sigma,
     double* Ul = (double*)malloc(sizeof(double) * (size_t)nr * (size_t)nc);
     int sweeps = oracle_jacobi_svd(nr, nc, K, nr, sK, Ul, nr, 60);
     int ro = nr < r ? nr : r;
+    /* Lemma 1 needs an orthonormal basis: directions whose singular value is at or below
+       the Jacobi routine's negligibility (n_c u ||K||_F; it never rotates such columns,
+       so their normalised vectors are not orthogonal to the rest) are numerically absent
+       and are dropped from the state; their energy joins the discarded tally. */
+    {
+        csum_t f = {0.0, 0.0};
+        for (int c = 0; c < nc; ++c) csum_add(&f, sK[c] * sK[c]);
+        const double thr = (double)(nc > 1 ? nc : 1) * DBL_EPSILON * sqrt(csum_val(&f));
+        while (ro > 0 && !(sK[ro - 1] > thr)) --ro;
+    }
     /* U_out = [U, Qres] * Ul(:, :ro) */
     for (int c = 0; c < ro; ++c) {
         for (int i = 0; i < m; ++i) {

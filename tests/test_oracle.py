@@ -340,3 +340,25 @@ def test_alg3_extremes():
     assert len(clusters) == 6
     labels, clusters, _ = oracle.cluster(blocks, 8, 1.0)
     assert len(clusters) == 1
+
+
+@pytest.mark.parametrize("r", [4, 8, 20])
+def test_rank_deficient_anchor_state_is_orthonormal(r):
+    # A rank-3 anchor truncated at r > 3 keeps only its numerically present directions:
+    # the state's basis is orthonormal, the plug-in estimate equals the discarded-energy
+    # tally (Corollary 2 both ways) and, when the merge has rank <= r, LAPACK's exact
+    # tail (zero).
+    rng = np.random.default_rng(31 + r)
+    m = 80
+    Q = workloads.orthonormal(rng, m, 20)
+    A = Q[:, :3] @ rng.standard_normal((3, 9))
+    b = Q[:, :15] @ rng.standard_normal((15, 1))
+    st = oracle.update(oracle.State(m), A, r)
+    assert st.rho == min(3, r)
+    np.testing.assert_allclose(st.U.T @ st.U, np.eye(st.rho), atol=1e-12)
+    st2 = oracle.update(st, b, r)
+    np.testing.assert_allclose(st2.U.T @ st2.U, np.eye(st2.rho), atol=1e-12)
+    e2 = float(np.sum(A * A) + np.sum(b * b))
+    assert abs(st2.estimate2() - st2.disc) <= 1e-12 * e2
+    s = np.linalg.svd(np.hstack([A, b]), compute_uv=False)
+    assert abs(st2.estimate2() - float(np.sum(s[r:] ** 2))) <= 1e-12 * e2
