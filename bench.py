@@ -506,10 +506,89 @@ def table2(args, cm, workloads, torch):
     print(json.dumps(out), flush=True)
 
 
+def smallk_vectors(args, cm, workloads, torch):
+    """The one-column SmolVLM shape at full size: 333,760 candidate blocks of 768 x 1 and
+    r = 32.  A pair of single vectors has rank 2 <= r (an exact zero error), so the unit
+    measured is Algorithm 3's scan step once a cluster holds more than r vectors: every
+    candidate against 64 cluster matrices of 64 vectors each (one per latent subspace,
+    768 x 64, truncated to rank 32 inside the call), 21,360,640 merges in one
+    cmsvd_merge_errors call per step.  Values from the Table 2 recipe (64 latent 16-dim
+    subspaces, noise-to-signal energy 1e-2); the candidates live in one device matrix and
+    are passed as column views.  Sampled parity against the FP64 oracle."""
+    nb, m, r, na, per = 333760, 768, 32, 64, 64
+    noise = TABLE2["smolvlm"][5]
+    t0 = time.time()
+    vecs = workloads.table1_like(seed=0, nblocks=na * per + nb, m=m, k=1, noise=noise)
+    anchors_np = [np.hstack([vecs[g + na * i] for i in range(per)]) for g in range(na)]
+    cand_np = np.hstack(vecs[na * per:])
+    del vecs
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    anchors = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in anchors_np]
+    cand = torch.from_numpy(np.ascontiguousarray(cand_np)).to(dev)
+    blocks = cm.BlockArray(anchors + [cand[:, j:j + 1] for j in range(nb)])  # marshalled once
+    pairs = np.empty((na * nb, 2), dtype=np.int32)
+    pairs[:, 0] = np.repeat(np.arange(na, dtype=np.int32), nb)
+    pairs[:, 1] = np.tile(np.arange(na, na + nb, dtype=np.int32), na)
+    torch.cuda.synchronize()
+    log(f"generated {na} cluster matrices {m}x{per} and {nb} candidates {m}x1 in {time.time() - t0:.1f}s")
+    h = cm.Handle(dev)
+    for w in range(args.warmup):
+        err, rel = cm.cmsvd_merge_errors(blocks, pairs, r, handle=h)
+        torch.cuda.synchronize()
+        log(f"warmup {w + 1}/{args.warmup}")
+    h.profile(True)
+    h.profile_read()
+    t1 = time.perf_counter()
+    for st in range(args.steps):
+        err, rel = cm.cmsvd_merge_errors(blocks, pairs, r, handle=h)
+        torch.cuda.synchronize()
+        log(f"step {st + 1}/{args.steps}")
+    el = time.perf_counter() - t1
+    stages = h.profile_read()
+    h.profile(False)
+    err_h = err.cpu().numpy()
+    rel_h = rel.cpu().numpy()
+    parity = None
+    if not args.no_cpu:
+        import oracle
+
+        rng = np.random.default_rng(4)
+        cs = rng.choice(len(pairs), size=min(args.cpu_pairs, len(pairs)), replace=False)
+        sub = [anchors_np[a] for a in range(na)] + [cand_np[:, j - na:j - na + 1] for j in pairs[cs, 1]]
+        sp = np.stack([pairs[cs, 0], na + np.arange(len(cs))], axis=1).astype(np.int32)
+        e_o, _ = oracle.merge_errors(sub, sp, r, nthreads=max(1, min(16, len(os.sched_getaffinity(0)))))
+        dev_rel = np.abs(err_h[cs] - e_o) / e_o
+        parity = {"pairs": int(len(cs)), "max_rel_dev": float(dev_rel.max())}
+        log(f"parity {parity}")
+    out = {
+        "metric": "candidate merges evaluated/sec (every candidate against every cluster matrix, one call per step)",
+        "value": round(len(pairs) * args.steps / el, 2),
+        "unit": "merges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * el / args.steps, 3),
+        "higher_is_better": True,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"table1_like/smolvlm: {nb} FP32 candidates {m}x1 against {na} cluster matrices "
+                               f"{m}x{per}, 64 latent 16-dim subspaces, noise {noise:.3g}, r={r}",
+                   "candidates": nb, "clusters": na, "m": m, "k": 1, "r": r, "pairs": int(len(pairs))},
+        "stages_ms_per_step": {n: round(stages[n][0] / args.steps, 3) for n in stages},
+        "parity": parity,
+        "mean_rel": float(np.mean(rel_h)),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def smallk(args, cm, workloads, torch):
     """All anchor-first pairs of a collection with the paper's shapes (Table 1: many thin
     blocks) and synthetic values (64 latent 16-dim subspaces + noise 0.05), evaluated in
-    one cmsvd_merge_errors call per step; sampled parity against the FP64 oracle."""
+    one cmsvd_merge_errors call per step; sampled parity against the FP64 oracle.  The
+    one-column SmolVLM shape runs smallk_vectors instead."""
+    if args.preset == "smolvlm":
+        return smallk_vectors(args, cm, workloads, torch)
     if args.preset not in SMALLK:
         raise SystemExit(f"--preset {args.preset} is a --workload table2 shape")
     nb, m, k, r = SMALLK[args.preset]

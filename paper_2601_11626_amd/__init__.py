@@ -174,11 +174,34 @@ def _block(t: torch.Tensor) -> Block:
     return Block(t.data_ptr(), t.shape[0], t.shape[1], t.stride(0), dt)
 
 
-def _blocks(ts: Sequence[torch.Tensor]):
+def _blocks(ts):
+    if isinstance(ts, BlockArray):
+        return ts.arr
     arr = (Block * len(ts))()
     for i, t in enumerate(ts):
         arr[i] = _block(t)
     return arr
+
+
+class BlockArray:
+    """The descriptors of a list of device blocks, marshalled once: pass it wherever a
+    list of blocks is taken, for calls repeated over the same collection.  It keeps the
+    tensors alive; they must not be resized or freed while it is in use."""
+
+    def __init__(self, ts: Sequence[torch.Tensor]):
+        self.tensors = list(ts)
+        self.arr = (Block * len(self.tensors))()
+        for i, t in enumerate(self.tensors):
+            self.arr[i] = _block(t)
+
+    def __len__(self):
+        return len(self.tensors)
+
+    def __getitem__(self, i):
+        return self.tensors[i]
+
+    def __iter__(self):
+        return iter(self.tensors)
 
 
 class State:
@@ -497,7 +520,7 @@ def _gemm(fn, opA, opB, C, alpha, beta, handle):
     return C
 
 
-__all__ = ["cmsvd_gemm_f64", "cmsvd_gemm_bf16", "PROJECTIONS", "Handle", "State", "Block", "CmsvdError", "cmsvd_update", "cmsvd_update_batch",
+__all__ = ["cmsvd_gemm_f64", "cmsvd_gemm_bf16", "PROJECTIONS", "BlockArray", "Handle", "State", "Block", "CmsvdError", "cmsvd_update", "cmsvd_update_batch",
            "cmsvd_merge_errors", "cmsvd_cluster", "cmsvd_cluster_residual", "cmsvd_residual_bound",
            "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail", "cmsvd_compress", "compress_partition",
            "cmsvd_sym_eigvals", "cmsvd_tail_energy_grad", "TailEnergy", "tail_energy", "default_handle",

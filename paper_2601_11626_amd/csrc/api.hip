@@ -818,8 +818,11 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
         }
         {
             StageMark mark(h, ST_CORE);
-            sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), (int)nj, nmax, 0,
-                            reinterpret_cast<double*>(W + eig_off), nslots, h->stream);
+            if (kmax == 1 && rmax <= 256)  // one-column candidates: arrowhead cores
+                arrow_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), (int)nj, h->stream);
+            else
+                sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), (int)nj, nmax, 0,
+                                reinterpret_cast<double*>(W + eig_off), nslots, h->stream);
         }
         HIPCHK(hipGetLastError());
     }
@@ -913,7 +916,10 @@ cmsvd_status eval_dense(cmsvd_ctx* h, const DenseEval& de, const std::vector<Pai
         expand_dense_descs(dP + pos, (int)nj, dA, dC, r, a0, C, ldc, cmin, err, rel, ed, h->stream);
         {
             StageMark mark(h, ST_CORE);
-            sym_eig_batched(ed, (int)nj, nmax, 0, reinterpret_cast<double*>(h->ws + eig_off), nslots, h->stream);
+            if (kmax == 1 && r <= 256)  // one-column candidates: arrowhead cores
+                arrow_eig_batched(ed, (int)nj, h->stream);
+            else
+                sym_eig_batched(ed, (int)nj, nmax, 0, reinterpret_cast<double*>(h->ws + eig_off), nslots, h->stream);
         }
         HIPCHK(hipGetLastError());
     }
@@ -1296,8 +1302,9 @@ cmsvd_status resid_setup(cmsvd_ctx* h, const cmsvd_block* blocks, int N, int64_t
     rb.nkcap = (int)std::min<int64_t>(r, kmax);
     Plan pl;
     std::vector<size_t> o_n(N), o_g(N);
+    const size_t o_nall = pl.add(16 * (size_t)N);  // norms side by side: one read-back
     for (int i = 0; i < N; ++i) {
-        o_n[i] = pl.add(16);
+        o_n[i] = o_nall + 16 * (size_t)i;
         o_g[i] = pl.add((size_t)blocks[i].cols * blocks[i].cols * 8);
     }
     const size_t o_Q = pl.add((size_t)m * qcap * 8);
@@ -1893,10 +1900,13 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
     // persistent per-call buffers: norms + grams (all involved), anchor states
     Plan pl;
     std::vector<size_t> o_n(cands.size()), o_g(cands.size());
+    const size_t o_nall = pl.add(16 * cands.size());  // norms side by side: one read-back
     for (size_t c = 0; c < cands.size(); ++c) {
         const int i = cands[c];
-        o_n[c] = pl.add(16);
-        o_g[c] = is_cand[i] ? pl.add((size_t)blocks[i].cols * blocks[i].cols * 8) : (size_t)-1;
+        o_n[c] = o_nall + 16 * c;
+        // a one-column candidate's Gram is its squared norm: the leading part of the
+        // double-double norm serves as the 1 x 1 Gram (no GEMM)
+        o_g[c] = !is_cand[i] ? (size_t)-1 : blocks[i].cols == 1 ? o_n[c] : pl.add((size_t)blocks[i].cols * blocks[i].cols * 8);
     }
     std::vector<size_t> o_U(anchors.size()), o_S(anchors.size()), o_acc(anchors.size());
     const long ldu_a = dense ? (long)anchors.size() * r : (long)r;  // anchors side by side when dense
@@ -1918,7 +1928,7 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
     for (size_t c = 0; c < cands.size(); ++c) {
         bl.push_back(blocks[cands[c]]);
         nrm.push_back(K(o_n[c]));
-        gram.push_back(o_g[c] == (size_t)-1 ? nullptr : K(o_g[c]));
+        gram.push_back(o_g[c] == (size_t)-1 || o_g[c] == o_n[c] ? nullptr : K(o_g[c]));
     }
     cmsvd_status st = norms_and_grams(h, bl, nrm, gram);
     if (st != CMSVD_OK) return st;
@@ -1927,8 +1937,7 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
         // usual anchor-first pair lists a chunk of anchors then pairs with a suffix of
         // the packed candidates, and its GEMM covers only that column range.
         std::vector<double> nh(2 * cands.size());
-        for (size_t c = 0; c < cands.size(); ++c)
-            HIPCHK(hipMemcpyAsync(&nh[2 * c], K(o_n[c]), 16, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(nh.data(), K(o_nall), 16 * cands.size(), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
         std::vector<double> n2(nblocks, 0.0);
         for (size_t c = 0; c < cands.size(); ++c) n2[cands[c]] = nh[2 * c] + nh[2 * c + 1];
@@ -2081,8 +2090,9 @@ cmsvd_status cmsvd_cluster(cmsvd_handle h, const cmsvd_block* blocks, int64_t nb
     Plan pl;
     std::vector<size_t> o_n(N), o_g(N);
     size_t kmax = 0;
+    const size_t o_nall = pl.add(16 * (size_t)N);  // norms side by side: one read-back
     for (int i = 0; i < N; ++i) {
-        o_n[i] = pl.add(16);
+        o_n[i] = o_nall + 16 * (size_t)i;
         o_g[i] = pl.add((size_t)blocks[i].cols * blocks[i].cols * 8);
         kmax = std::max(kmax, (size_t)blocks[i].cols);
     }
@@ -2113,7 +2123,7 @@ cmsvd_status cmsvd_cluster(cmsvd_handle h, const cmsvd_block* blocks, int64_t nb
         if (st != CMSVD_OK) return st;
     }
     std::vector<double> n2h(2 * (size_t)N);
-    for (int i = 0; i < N; ++i) HIPCHK(hipMemcpyAsync(&n2h[2 * i], K(o_n[i]), 16, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(n2h.data(), K(o_nall), 16 * (size_t)N, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     std::vector<double> n2(N);
     for (int i = 0; i < N; ++i) n2[i] = n2h[2 * i] + n2h[2 * i + 1];
@@ -2234,8 +2244,8 @@ cmsvd_status cmsvd_cluster_residual(cmsvd_handle h, const cmsvd_block* blocks, i
     ResidBuffers rb;
     cmsvd_status st = resid_setup(h, blocks, N, r, "cmsvd_cluster_residual", rb);
     if (st != CMSVD_OK) return st;
-    std::vector<double> n2h(2 * (size_t)N);
-    for (int i = 0; i < N; ++i) HIPCHK(hipMemcpyAsync(&n2h[2 * i], rb.nrm[i], 16, hipMemcpyDeviceToHost, h->stream));
+    std::vector<double> n2h(2 * (size_t)N);  // the norms are contiguous (resid_setup)
+    HIPCHK(hipMemcpyAsync(n2h.data(), rb.nrm[0], 16 * (size_t)N, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     std::vector<double> n2(N);
     for (int i = 0; i < N; ++i) n2[i] = n2h[2 * i] + n2h[2 * i + 1];

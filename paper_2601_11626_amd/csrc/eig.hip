@@ -139,6 +139,17 @@ __device__ __forceinline__ int sturm_count(const double* dd, const double* e2, i
     return c[0];
 }
 
+// (hi, lo) = trace(T) - (hi, lo): the sum of the top eigenvalues from that of the bottom
+// ones (double-double).
+__device__ __forceinline__ void top_from_trace(const double* dd, int n, double& hi, double& lo) {
+    double th = 0.0, tl = 0.0;
+    for (int i = 0; i < n; ++i) dd_add(th, tl, dd[i]);
+    double s, e;
+    two_sum(th, -hi, s, e);
+    e += tl - lo;
+    two_sum(s, e, hi, lo);
+}
+
 // 2^-k with 2^(k-1) <= tnorm < 2^k (1 for tnorm = 0): scales T to norm below 1 exactly.
 __device__ __forceinline__ double sturm_scale(double tnorm) {
     return tnorm > 0.0 && tnorm < INFINITY ? ldexp(1.0, -__builtin_amdgcn_frexp_exp(tnorm)) : 1.0;
@@ -291,9 +302,13 @@ __global__ void __launch_bounds__(NT) sym_eig_kernel(const EigDesc* __restrict__
         glo -= tol;
         ghi += tol;
         double* lamv = pw;  // free now
-        for (int q = t; q < D.nkeep; q += NT) {
+        // the error needs only the sum of the top nkeep: above half the spectrum, the
+        // bottom n - nkeep are found and subtracted from the trace (as in the small kernel)
+        const bool bottom = MODE == 0 && 2 * D.nkeep > n;
+        const int nb = bottom ? n - D.nkeep : D.nkeep;
+        for (int q = t; q < nb; q += NT) {
             double lo = glo, hi = ghi;
-            const int target = n - q;
+            const int target = bottom ? q + 1 : n - q;
             while (hi - lo > tol) {
                 const double mid = 0.5 * (lo + hi);
                 if (mid <= lo || mid >= hi) break;
@@ -305,7 +320,8 @@ __global__ void __launch_bounds__(NT) sym_eig_kernel(const EigDesc* __restrict__
         __syncthreads();
         if (t == 0) {
             double hi = 0.0, lo = 0.0;
-            for (int q = 0; q < D.nkeep; ++q) dd_add(hi, lo, lamv[q]);
+            for (int q = 0; q < nb; ++q) dd_add(hi, lo, lamv[q]);
+            if (bottom) top_from_trace(dd, n, hi, lo);
             if (MODE == 0) {
                 double eh = D.na[0], el = D.na[1];
                 if (D.nb) {
@@ -717,11 +733,15 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
         // into P + 1 parts, with P as large as the threads allow.
         constexpr int KP = 1, NPROBE = KP * RT;
         const int nk = D.nkeep;
-        const int P = nk > 0 && nk <= NPROBE ? NPROBE / nk : 1;
+        // the error needs only the sum of the top nk: above half the spectrum, the bottom
+        // n - nk are found and subtracted from the trace (as in the small kernel)
+        const bool bottom = MODE == 0 && 2 * nk > n;
+        const int nb = bottom ? n - nk : nk;
+        const int P = nb > 0 && nb <= NPROBE ? NPROBE / nb : 1;
         double* blo = pw;
         double* bhi = pw + NP;
         int* flag = reinterpret_cast<int*>(pw + 2 * NP);  // NPROBE ints
-        for (int q = t; q < nk; q += RT) {
+        for (int q = t; q < nb; q += RT) {
             blo[q] = glo;
             bhi[q] = ghi;
         }
@@ -732,14 +752,14 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
         if (width > tol) iters = (int)ceil(log(width / tol) / log((double)(P + 1)));
         __syncthreads();
         for (int it = 0; it < iters; ++it) {
-            for (int base = 0; base < nk * P; base += NPROBE) {
+            for (int base = 0; base < nb * P; base += NPROBE) {
                 double x[KP];
                 int cnt[KP];
 #pragma unroll
                 for (int k = 0; k < KP; ++k) {
                     const int u = base + t * KP + k;
                     x[k] = 0.0;
-                    if (u < nk * P) {
+                    if (u < nb * P) {
                         const int q = u / P, pi = u % P;
                         const double lo = blo[q], hi = bhi[q];
                         x[k] = lo + (hi - lo) * (double)(pi + 1) / (double)(P + 1);
@@ -749,11 +769,11 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
 #pragma unroll
                 for (int k = 0; k < KP; ++k) {
                     const int u = base + t * KP + k;
-                    if (u < nk * P) flag[u - base] = cnt[k] >= n - u / P;
+                    if (u < nb * P) flag[u - base] = cnt[k] >= (bottom ? u / P + 1 : n - u / P);
                 }
                 __syncthreads();
                 const int q = base / P + t;
-                if (t < NPROBE / P && q < nk) {
+                if (t < NPROBE / P && q < nb) {
                     const double lo = blo[q], hi = bhi[q];
                     const int* fq = flag + (q * P - base);
                     int first = P;
@@ -769,7 +789,8 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
         }
         if (t == 0) {
             double hi = 0.0, lo = 0.0;
-            for (int q = 0; q < nk; ++q) dd_add(hi, lo, 0.5 * (blo[q] + bhi[q]));
+            for (int q = 0; q < nb; ++q) dd_add(hi, lo, 0.5 * (blo[q] + bhi[q]));
+            if (bottom) top_from_trace(dd, n, hi, lo);
             if (MODE == 0) {
                 double eh = D.na[0], el = D.na[1];
                 if (D.nb) {
@@ -910,10 +931,15 @@ __global__ void __launch_bounds__(64 * SWV) sym_eig_small_kernel(const EigDesc* 
         glo -= tol;
         ghi += tol;
         const int nk = D.nkeep;
-        const int P = nk < 64 ? 64 / nk : 1;
+        // The error needs only the sum of the top nk eigenvalues; when that is more than
+        // half the spectrum the bottom n - nk are found instead and subtracted from the
+        // trace of T (sum of its diagonal, kept by the orthogonal reduction).
+        const bool bottom = MODE == 0 && 2 * nk > n;
+        const int nb = bottom ? n - nk : nk;  // eigenvalues searched
+        const int P = nb > 0 && nb < 64 ? 64 / nb : 1;
         double* blo = vv;
         double* bhi = ww;
-        if (lane < nk) {
+        if (lane < nb) {
             blo[lane] = glo;
             bhi[lane] = ghi;
         }
@@ -925,19 +951,21 @@ __global__ void __launch_bounds__(64 * SWV) sym_eig_small_kernel(const EigDesc* 
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         for (int it = 0; it < iters; ++it) {
-            for (int base = 0; base < nk * P; base += 64) {
+            for (int base = 0; base < nb * P; base += 64) {
                 const int u = base + lane;
-                if (u < nk * P) {
+                if (u < nb * P) {
                     const int q = u / P, pi = u % P;
                     const double lo = blo[q], hi = bhi[q];
                     const double x = lo + (hi - lo) * (double)(pi + 1) / (double)(P + 1);
-                    fl[u - base] = sturm_count(dd, e2, n, x, sc) >= n - q;
+                    // eigenvalue q from the top (from the bottom): x is above it iff at
+                    // least n - q (q + 1) eigenvalues lie below x
+                    fl[u - base] = sturm_count(dd, e2, n, x, sc) >= (bottom ? q + 1 : n - q);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 const int q = base / P + lane;
-                if (lane < 64 / P && q < nk) {
+                if (lane < 64 / P && q < nb) {
                     const double lo = blo[q], hi = bhi[q];
                     const int* fq = fl + (q * P - base);
                     int first = P;
@@ -953,7 +981,8 @@ __global__ void __launch_bounds__(64 * SWV) sym_eig_small_kernel(const EigDesc* 
         }
         if (lane == 0) {
             double hi = 0.0, lo = 0.0;
-            for (int q = 0; q < nk; ++q) dd_add(hi, lo, 0.5 * (blo[q] + bhi[q]));
+            for (int q = 0; q < nb; ++q) dd_add(hi, lo, 0.5 * (blo[q] + bhi[q]));
+            if (bottom) top_from_trace(dd, n, hi, lo);
             if (MODE == 0) {
                 double eh = D.na[0], el = D.na[1];
                 if (D.nb) {
@@ -982,6 +1011,98 @@ __global__ void __launch_bounds__(64 * SWV) sym_eig_small_kernel(const EigDesc* 
         }
         __builtin_amdgcn_wave_barrier();
     }
+}
+
+// ---------------------------------------------------------------------------
+// One appended column (n = n1 + 1), evaluation mode: H is an arrowhead,
+//     H = [[diag(d), z], [z^T, c]],  d = s^2, z = s .* P, c = Y (the column's energy).
+// The kept sum is the trace minus the smallest eigenvalue (nkeep = n - 1), or the whole
+// trace (nkeep >= n).  Below the smallest diagonal entry, eliminating the border gives the
+// inertia of H - x I (Sylvester): d_i - x > 0 for every i, so x lies above an eigenvalue
+// iff the Schur complement c - x - sum_i z_i^2 / (d_i - x) is negative.  Bisection on its
+// sign over [min(d, c) - ||z||, min(d, c)] (Weyl) finds the smallest eigenvalue without a
+// reduction to tridiagonal form; when a deflated entry (z_i = 0) is the smallest, the
+// bracket closes on it.  One wavefront per problem, lane i holding entries i, i + 64, ...
+// (n1 <= 256), exact divisions, one wave sum per probe.
+// ---------------------------------------------------------------------------
+constexpr int AW = 4;  // waves per workgroup
+
+__global__ void __launch_bounds__(64 * AW) arrow_eig_kernel(const EigDesc* __restrict__ descs, int count) {
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (int prob = blockIdx.x * AW + wv; prob < count; prob += gridDim.x * AW) {
+        const EigDesc D = descs[prob];
+        const int n1 = D.n1;
+        const double c = D.Y[0];
+        double d[4], z2[4];
+        double th = 0.0, tl = 0.0, dmin = INFINITY, dmax = -INFINITY, zs = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = lane + 64 * q;
+            d[q] = INFINITY;
+            z2[q] = 0.0;
+            if (i < n1) {
+                const double si = D.s[i], zi = si * D.P[i];
+                d[q] = si * si;
+                z2[q] = zi * zi;
+                dd_add(th, tl, d[q]);
+                dmin = fmin(dmin, d[q]);
+                dmax = fmax(dmax, d[q]);
+                zs += z2[q];
+            }
+        }
+        // trace (double-double over the lanes, then the corner), bounds
+        th = wave_sum(th);  // the lanes' high parts; their low parts below
+        tl = wave_sum(tl);
+        dd_add(th, tl, c);
+        dmin = fmin(-wave_max(-dmin), c);
+        dmax = fmax(wave_max(dmax), c);
+        const double zn = sqrt(wave_sum(zs));
+        double hi = th, lo = tl;  // the kept sum
+        if (D.nkeep < n1 + 1) {
+            double bhi = dmin, blo = dmin - zn;
+            const double tnorm = fmax(fabs(blo), fabs(dmax) + zn);
+            const double tol = 4.0 * DBL_EPSILON * tnorm + 2.0 * DBL_MIN;
+            blo -= tol;
+            while (bhi - blo > tol) {
+                const double x = 0.5 * (blo + bhi);
+                if (x <= blo || x >= bhi) break;
+                double acc = 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (z2[q] != 0.0) acc += z2[q] / (d[q] - x);
+                const double sch = (c - x) - wave_sum(acc);
+                if (sch < 0.0) bhi = x;
+                else blo = x;
+            }
+            const double lmin = 0.5 * (blo + bhi);
+            double s2, e2;
+            two_sum(hi, -lmin, s2, e2);
+            e2 += lo;
+            two_sum(s2, e2, hi, lo);
+        }
+        if (lane == 0) {
+            double eh = D.na[0], el = D.na[1];
+            if (D.nb) {
+                dd_add(eh, el, D.nb[0]);
+                el += D.nb[1];
+            }
+            double s2, e2;
+            two_sum(eh, -hi, s2, e2);
+            double tail = s2 + (e2 + el - lo);
+            if (tail < 0.0) tail = 0.0;  // clamp rounding below zero; NaN propagates
+            const double err = sqrt(tail);
+            const double etot = eh + el;
+            *D.out_err = err;
+            if (D.out_rel) *D.out_rel = etot != 0.0 ? err / sqrt(etot) : 0.0;
+        }
+    }
+}
+
+void arrow_eig_batched(const EigDesc* d_descs, int count, hipStream_t s) {
+    if (count <= 0) return;
+    const int g = (count + AW - 1) / AW;
+    hipLaunchKernelGGL(arrow_eig_kernel, dim3(g < 16384 ? g : 16384), dim3(64 * AW), 0, s, d_descs, count);
 }
 
 int sym_eig_nmax() {

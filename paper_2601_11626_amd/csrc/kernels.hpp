@@ -59,6 +59,10 @@ struct EigDesc {
 void sym_eig_batched(const EigDesc* d_descs, int count, int nmax, int mode, double* gws, int nslots,
                      hipStream_t s);
 size_t sym_eig_workspace_doubles(int nmax, int nslots);
+// Evaluation mode for cores of one appended column (every descriptor n = n1 + 1 with
+// n1 <= 256 and nkeep >= n1): the arrowhead's smallest eigenvalue by bisection on the
+// inertia after eliminating the border; writes out_err / out_rel as mode 0 does.
+void arrow_eig_batched(const EigDesc* d_descs, int count, hipStream_t s);
 // Largest order the eigenvalue (and eigenvector) kernels accept (2016 on gfx950).
 int sym_eig_nmax();
 

@@ -306,3 +306,74 @@ def test_gemm_f64_matches_reference(cm, ta, tb, dt, M, N, K):
     torch.cuda.synchronize()
     err = (C.cpu() - ref).abs().max().item()
     assert err <= 1e-12 * max(1.0, ref.abs().max().item()) * K, err
+
+
+def test_one_column_candidates_as_views_and_block_array(cm):
+    # One-column candidates passed as column views of one device matrix (row stride =
+    # the matrix width), through a BlockArray marshalled once, against cluster matrices
+    # wider than r: the shape of a scan step on one-column collections.
+    rng = np.random.default_rng(21)
+    m, r = 96, 8
+    Q = workloads.orthonormal(rng, m, 6)
+    anchors = [Q @ rng.standard_normal((6, 12)) + 0.02 * rng.standard_normal((m, 12)) for _ in range(3)]
+    cand = (Q @ rng.standard_normal((6, 40)) + 0.05 * rng.standard_normal((m, 40))).astype(np.float32)
+    C = torch.from_numpy(cand).cuda()
+    arr = cm.BlockArray(dev_tensors(anchors) + [C[:, j:j + 1] for j in range(40)])
+    pairs = np.array([(a, 3 + j) for a in range(3) for j in range(40)], dtype=np.int32)
+    say("one-column candidates as column views, 120 pairs")
+    e_g, _ = cm.cmsvd_merge_errors(arr, pairs, r)
+    e_l, _ = cm.cmsvd_merge_errors(list(arr), pairs, r)
+    assert torch.equal(e_g, e_l)
+    blocks = anchors + [cand[:, j:j + 1] for j in range(40)]
+    e_o, _ = oracle.merge_errors(blocks, pairs, r)
+    nrm = np.array([math.sqrt(float(np.sum(np.asarray(blocks[i], np.float64) ** 2)) +
+                              float(np.sum(np.asarray(blocks[j], np.float64) ** 2))) for i, j in pairs])
+    assert np.max(np.abs(e_g.cpu().numpy() - e_o) / np.maximum(e_o, 1e-6 * nrm)) <= 1e-9
+
+
+@pytest.mark.parametrize("m,ka,kc,r", [(200, 60, 8, 40), (300, 150, 30, 100), (400, 260, 40, 200),
+                                       (500, 400, 60, 300)])
+def test_merge_errors_rank_above_half_the_core(cm, m, ka, kc, r):
+    # r > (r + k) / 2: the error comes from the trace of the tridiagonal minus its bottom
+    # k eigenvalues; cores of order 48, 130, 240 and 360 cover the four eigen kernels.
+    rng = np.random.default_rng(m + r)
+    Q = workloads.orthonormal(rng, m, r // 2)
+    blocks = []
+    for _ in range(2):
+        blocks.append(Q @ rng.standard_normal((r // 2, ka)) * 2.0 + 0.05 * rng.standard_normal((m, ka)))
+    for _ in range(3):
+        blocks.append(Q @ rng.standard_normal((r // 2, kc)) + 0.05 * rng.standard_normal((m, kc)))
+    pairs = np.array([(a, c) for a in range(2) for c in range(2, 5)], dtype=np.int32)
+    say(f"rank above half the core: m={m} anchor {ka} candidate {kc} r={r}")
+    e_g, _ = cm.cmsvd_merge_errors(dev_tensors(blocks), pairs, r)
+    e_o, _ = oracle.merge_errors(blocks, pairs, r)
+    for (i, j), g, o in zip(pairs, e_g.cpu().numpy(), e_o):
+        nm = math.sqrt(float(np.sum(blocks[i] ** 2)) + float(np.sum(blocks[j] ** 2)))
+        assert_est(g, o, nm, f"pair {i},{j}")
+
+
+@pytest.mark.parametrize("r", [4, 8, 40])
+def test_one_column_arrowhead_edges(cm, r):
+    # One-column candidates (arrowhead cores): rank-deficient anchors (zero singular
+    # values deflate), a candidate orthogonal to every anchor (zero border), one inside an
+    # anchor's span (zero error), a tiny one and an exactly zero one; r above the anchor
+    # widths as well as below.
+    rng = np.random.default_rng(31 + r)
+    m = 80
+    Q = workloads.orthonormal(rng, m, 20)
+    anchors = [Q[:, :10] @ rng.standard_normal((10, 12)),                       # rank 10
+               Q[:, :3] @ rng.standard_normal((3, 9)),                           # rank 3
+               Q[:, 3:13] @ rng.standard_normal((10, 6)) + 1e-3 * rng.standard_normal((m, 6))]
+    cands = [Q[:, :15] @ rng.standard_normal((15, 1)),
+             Q[:, 15:20] @ rng.standard_normal((5, 1)),                          # orthogonal to anchors 0, 1
+             anchors[1][:, :2] @ rng.standard_normal((2, 1)),                    # inside anchor 1's span
+             1e-9 * rng.standard_normal((m, 1)),
+             np.zeros((m, 1))]
+    blocks = anchors + cands
+    pairs = np.array([(a, 3 + j) for a in range(3) for j in range(5)], dtype=np.int32)
+    say(f"arrowhead edges r={r}")
+    e_g, _ = cm.cmsvd_merge_errors(dev_tensors(blocks), pairs, r)
+    e_o, _ = oracle.merge_errors(blocks, pairs, r)
+    for (i, j), g, o in zip(pairs, e_g.cpu().numpy(), e_o):
+        nm = math.sqrt(float(np.sum(blocks[i] ** 2)) + float(np.sum(blocks[j] ** 2)))
+        assert_est(g, o, nm, f"pair {i},{j}")
