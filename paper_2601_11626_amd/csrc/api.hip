@@ -837,9 +837,10 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
 struct DenseEval {
     const double* Uall;  // row-major m x (na * r): anchor a's basis in columns a*r .. a*r + r
     int na, r, m;
-    const void* Ball;    // row-major m x ksum: the candidates side by side
+    const void* Ball;    // row-major m x ksum (row stride ldb): the candidates side by side
     bool ball_f32;
     long ksum;
+    long ldb;
 };
 
 cmsvd_status eval_dense(cmsvd_ctx* h, const DenseEval& de, const std::vector<PairRec>& pairs,
@@ -903,7 +904,7 @@ cmsvd_status eval_dense(cmsvd_ctx* h, const DenseEval& de, const std::vector<Pai
         g.bf16 = proj_passes(h);
         const char* Bc = static_cast<const char*>(de.Ball) + (size_t)cmin * (de.ball_f32 ? 4 : 8);
         g.push(GemmDesc{de.Uall + (size_t)a0 * r, Bc, C, (int)ldc, (int)(cmax - cmin), de.m, (long)de.na * r,
-                        de.ksum, ldc});
+                        de.ldb, ldc});
         Stage stg;
         g.off = stg.add(g.d);
         char* db = nullptr;
@@ -1897,6 +1898,30 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
         tile_work += std::ceil(k / 64.0) * 64.0 * std::ceil((double)r / 64.0) * 64.0 / (double)r;
     }
     const bool dense = pair_work < 0.5 * tile_work && (double)anchors.size() * (double)ksum <= 4.0 * pair_work;
+    // Candidates given as consecutive column ranges of one row-major matrix (in index
+    // order, one dtype and row stride) already form the packed operand: used in place.
+    bool in_place = dense;
+    {
+        const cmsvd_block* prev = nullptr;
+        for (int i = 0; i < nblocks && in_place; ++i) {
+            if (!is_cand[i]) continue;
+            const cmsvd_block& b = blocks[i];
+            if (prev) {
+                const size_t esz = prev->dtype == CMSVD_F32 ? 4 : 8;
+                in_place = b.dtype == prev->dtype && b.ld == prev->ld &&
+                           static_cast<const char*>(b.ptr) == static_cast<const char*>(prev->ptr) + prev->cols * esz;
+            }
+            prev = &b;
+        }
+    }
+    long ldball = ksum;
+    const void* ball_user = nullptr;
+    for (int i = 0; i < nblocks && in_place; ++i)
+        if (is_cand[i]) {
+            ldball = (long)blocks[i].ld;
+            ball_user = blocks[i].ptr;
+            break;
+        }
     // persistent per-call buffers: norms + grams (all involved), anchor states
     Plan pl;
     std::vector<size_t> o_n(cands.size()), o_g(cands.size());
@@ -1911,7 +1936,7 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
     std::vector<size_t> o_U(anchors.size()), o_S(anchors.size()), o_acc(anchors.size());
     const long ldu_a = dense ? (long)anchors.size() * r : (long)r;  // anchors side by side when dense
     const size_t o_Uall = dense ? pl.add((size_t)m * ldu_a * 8) : 0;
-    const size_t o_Ball = dense ? pl.add((size_t)m * ksum * (all_f32 ? 4 : 8)) : 0;
+    const size_t o_Ball = dense && !in_place ? pl.add((size_t)m * ksum * (all_f32 ? 4 : 8)) : 0;
     for (size_t a = 0; a < anchors.size(); ++a) {
         o_U[a] = dense ? o_Uall + (size_t)a * r * 8 : pl.add((size_t)m * r * 8);
         o_S[a] = pl.add((size_t)r * 8);
@@ -1944,14 +1969,16 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
         auto by_norm = [&](int a, int b) { return n2[a] > n2[b] || (n2[a] == n2[b] && a < b); };
         std::stable_sort(anchors.begin(), anchors.end(), by_norm);
         for (size_t a = 0; a < anchors.size(); ++a) aslot[anchors[a]] = (int)a;
-        std::vector<int> corder;
-        for (int i = 0; i < nblocks; ++i)
-            if (is_cand[i]) corder.push_back(i);
-        std::stable_sort(corder.begin(), corder.end(), by_norm);
-        long off = 0;
-        for (int i : corder) {
-            coff[i] = off;
-            off += blocks[i].cols;
+        if (!in_place) {  // (in place the candidates keep the caller's column order)
+            std::vector<int> corder;
+            for (int i = 0; i < nblocks; ++i)
+                if (is_cand[i]) corder.push_back(i);
+            std::stable_sort(corder.begin(), corder.end(), by_norm);
+            long off = 0;
+            for (int i : corder) {
+                coff[i] = off;
+                off += blocks[i].cols;
+            }
         }
     }
     // anchor states: the update from the empty state (Algorithm 3, step 1)
@@ -1975,7 +2002,7 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
             if (st != CMSVD_OK) return st;
         }
     }
-    if (dense) {
+    if (dense && !in_place) {
         // pack the candidates side by side
         std::vector<PackDesc> pd;
         for (int i = 0; i < nblocks; ++i)
@@ -1993,6 +2020,8 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
             pack_batched(reinterpret_cast<const PackDesc*>(db + o_pd), (int)pd.size(), h->stream);
         }
         HIPCHK(hipGetLastError());
+    }
+    if (dense) {
         std::vector<AnchorRec> arec(anchors.size());
         for (size_t a = 0; a < anchors.size(); ++a) arec[a] = AnchorRec{K(o_S[a]), K(o_n[cslot[anchors[a]]])};
         std::vector<CandRec> crec(nblocks, CandRec{nullptr, nullptr, 0, 0});
@@ -2000,7 +2029,8 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
             if (is_cand[i]) crec[i] = CandRec{K(o_n[cslot[i]]), K(o_g[cslot[i]]), coff[i], (int)blocks[i].cols};
         std::vector<PairRec> pr((size_t)npairs);
         for (int64_t p = 0; p < npairs; ++p) pr[(size_t)p] = PairRec{aslot[pairs[2 * p]], pairs[2 * p + 1], (int)p};
-        DenseEval de{K(o_Uall), (int)anchors.size(), (int)r, (int)m, keep.p + o_Ball, all_f32, ksum};
+        DenseEval de{K(o_Uall), (int)anchors.size(), (int)r, (int)m, in_place ? ball_user : keep.p + o_Ball, all_f32,
+                     ksum, ldball};
         st = eval_dense(h, de, pr, arec, crec, err, rel);
     } else {
         std::vector<EvalJob> ej;

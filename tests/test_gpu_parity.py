@@ -331,6 +331,40 @@ def test_one_column_candidates_as_views_and_block_array(cm):
     assert np.max(np.abs(e_g.cpu().numpy() - e_o) / np.maximum(e_o, 1e-6 * nrm)) <= 1e-9
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_candidates_as_consecutive_column_ranges(cm, dtype):
+    # Thin candidates of ragged widths given as consecutive column ranges of one device
+    # matrix in index order are read in place by the projection; the same columns given
+    # in another order (or as separate tensors) are packed first.  All three agree with
+    # each other and with the oracle.
+    rng = np.random.default_rng(22)
+    m, r = 130, 12
+    widths = [3, 5, 1, 7, 2, 4, 1, 6, 3, 8, 2, 5]
+    Q = workloads.orthonormal(rng, m, 10)
+    anchors = [Q @ rng.standard_normal((10, 20)) + 0.03 * rng.standard_normal((m, 20)) for _ in range(4)]
+    wide = (Q @ rng.standard_normal((10, sum(widths))) + 0.05 * rng.standard_normal((m, sum(widths)))).astype(dtype)
+    offs = np.concatenate([[0], np.cumsum(widths)])
+    W = torch.from_numpy(wide).cuda()
+    views = [W[:, offs[c]:offs[c + 1]] for c in range(len(widths))]
+    nc = len(widths)
+    pairs = np.array([(a, 4 + c) for a in range(4) for c in range(nc)], dtype=np.int32)
+    say(f"consecutive column ranges in place, {wide.dtype}, {len(pairs)} pairs")
+    e_in, _ = cm.cmsvd_merge_errors(dev_tensors(anchors) + views, pairs, r)
+    # reversed candidate order: the views are no longer consecutive in index order
+    rev = pairs.copy()
+    rev[:, 1] = 4 + (nc - 1 - (pairs[:, 1] - 4))
+    e_rev, _ = cm.cmsvd_merge_errors(dev_tensors(anchors) + views[::-1], rev, r)
+    e_sep, _ = cm.cmsvd_merge_errors(dev_tensors(anchors) + [v.contiguous() for v in views], pairs, r)
+    blocks = anchors + [wide[:, offs[c]:offs[c + 1]] for c in range(nc)]
+    e_o, _ = oracle.merge_errors(blocks, pairs, r)
+    nrm = np.array([math.sqrt(float(np.sum(np.asarray(blocks[i], np.float64) ** 2)) +
+                              float(np.sum(np.asarray(blocks[j], np.float64) ** 2))) for i, j in pairs])
+    for e in (e_in, e_rev, e_sep):
+        assert np.max(np.abs(e.cpu().numpy() - e_o) / np.maximum(e_o, 1e-6 * nrm)) <= 1e-9
+    np.testing.assert_allclose(e_in.cpu().numpy(), e_sep.cpu().numpy(), rtol=1e-12, atol=1e-14 * nrm.max())
+    np.testing.assert_allclose(e_in.cpu().numpy(), e_rev.cpu().numpy(), rtol=1e-12, atol=1e-14 * nrm.max())
+
+
 @pytest.mark.parametrize("m,ka,kc,r", [(200, 60, 8, 40), (300, 150, 30, 100), (400, 260, 40, 200),
                                        (500, 400, 60, 300)])
 def test_merge_errors_rank_above_half_the_core(cm, m, ka, kc, r):
