@@ -63,7 +63,7 @@ typedef enum { CMSVD_PROJ_F64 = 0, CMSVD_PROJ_BF16 = 1, CMSVD_PROJ_BF16X3 = 2 } 
 typedef enum {
     CMSVD_OK = 0,
     CMSVD_EINVAL = 1,      /* bad argument value (null pointer, r < 1, index out of range, ...) */
-    CMSVD_ESHAPE = 2,      /* inconsistent shapes (row counts differ, ld < cols, r > m, ...)   */
+    CMSVD_ESHAPE = 2,      /* bad shapes (row counts differ, cols < 1, ld < cols, r > m, ...)  */
     CMSVD_ENOMEM = 3,      /* workspace allocation failed                                      */
     CMSVD_EHIP = 4,        /* a HIP runtime call failed                                        */
     CMSVD_EUNSUPPORTED = 5 /* dtype or size not supported by this build                        */
@@ -146,7 +146,10 @@ cmsvd_status cmsvd_update_batch(cmsvd_handle handle, int64_t count, int64_t m, c
      r                 target rank, 1 <= r <= m
      err               DEVICE npairs FP64: plug-in error sqrt(||A_i||^2 + ||A_j||^2 -
                        sum_{l<=r} sigma_l^2)
-     rel               DEVICE npairs FP64 (may be NULL): err / ||[A_i, A_j]||_F */
+     rel               DEVICE npairs FP64 (may be NULL): err / ||[A_i, A_j]||_F
+   nblocks and npairs are at most 2^31 - 1 (else CMSVD_EUNSUPPORTED).  Thin candidates
+   given as consecutive column ranges of one row-major matrix (in index order, one
+   dtype and row stride) are read in place; others are first packed side by side. */
 cmsvd_status cmsvd_merge_errors(cmsvd_handle handle, const cmsvd_block* blocks, int64_t nblocks,
                                 const int32_t* pairs, int64_t npairs, int64_t r, double* err, double* rel);
 

@@ -93,6 +93,10 @@ struct cmsvd_ctx {
     int proj = CMSVD_PROJ_F64;  // precision of the candidate projections
     char* gsk = nullptr;        // split-K partial products of the GEMMs
     size_t gsk_cap = 0;
+    char* rec_pin = nullptr;    // pinned staging of the pair records of a dense evaluation
+    size_t rec_pin_cap = 0;
+    char* rec = nullptr;        // their device copy
+    size_t rec_cap = 0;
     // stage timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> marks[4];
@@ -104,10 +108,10 @@ namespace {
 cmsvd_status ensure(cmsvd_ctx* h, char*& buf, size_t& cap, size_t need) {
     if (need <= cap) return CMSVD_OK;
     HIPCHK(hipStreamSynchronize(h->stream));
+    const size_t want = std::max(need, cap + cap / 2);
     if (buf) HIPCHK(hipFree(buf));
     buf = nullptr;
     cap = 0;
-    size_t want = std::max(need, cap + cap / 2);
     if (hipMalloc((void**)&buf, want) != hipSuccess) {
         (void)hipGetLastError();
         buf = nullptr;
@@ -189,12 +193,13 @@ cmsvd_status check_order(int64_t n, const char* who) {
 }
 
 cmsvd_status check_block(const cmsvd_block& b, int64_t m, const char* what, int64_t idx) {
-    if (!b.ptr) return fail(CMSVD_EINVAL, "%s %lld: null data pointer", what, (long long)idx);
-    if (b.dtype != CMSVD_F32 && b.dtype != CMSVD_F64)
-        return fail(CMSVD_EUNSUPPORTED, "%s %lld: dtype %d not supported (F32 or F64)", what, (long long)idx, b.dtype);
+    // shape first: a zero-width block (whose storage may be null) is a shape error
     if (b.rows != m) return fail(CMSVD_ESHAPE, "%s %lld: rows %lld != m %lld", what, (long long)idx, (long long)b.rows, (long long)m);
     if (b.cols < 1) return fail(CMSVD_ESHAPE, "%s %lld: cols %lld < 1", what, (long long)idx, (long long)b.cols);
     if (b.ld < b.cols) return fail(CMSVD_ESHAPE, "%s %lld: ld %lld < cols %lld", what, (long long)idx, (long long)b.ld, (long long)b.cols);
+    if (!b.ptr) return fail(CMSVD_EINVAL, "%s %lld: null data pointer", what, (long long)idx);
+    if (b.dtype != CMSVD_F32 && b.dtype != CMSVD_F64)
+        return fail(CMSVD_EUNSUPPORTED, "%s %lld: dtype %d not supported (F32 or F64)", what, (long long)idx, b.dtype);
     if (b.cols > 16384 || m > (int64_t)1 << 30) return fail(CMSVD_EUNSUPPORTED, "%s %lld: size too large", what, (long long)idx);
     return CMSVD_OK;
 }
@@ -843,37 +848,54 @@ struct DenseEval {
     long ldb;
 };
 
-cmsvd_status eval_dense(cmsvd_ctx* h, const DenseEval& de, const std::vector<PairRec>& pairs,
-                        const std::vector<AnchorRec>& arec, const std::vector<CandRec>& crec, double* err,
-                        double* rel) {
-    const size_t total = pairs.size();
+// Pinned host staging for the pair records of a dense evaluation (grow-only; the
+// previous call has synchronised its stream before returning).
+cmsvd_status ensure_rec_pin(cmsvd_ctx* h, size_t need) {
+    if (need <= h->rec_pin_cap) return CMSVD_OK;
+    const size_t want = std::max(need, h->rec_pin_cap + h->rec_pin_cap / 2);
+    if (h->rec_pin) HIPCHK(hipHostFree(h->rec_pin));
+    h->rec_pin = nullptr;
+    h->rec_pin_cap = 0;
+    if (hipHostMalloc((void**)&h->rec_pin, want, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        h->rec_pin = nullptr;
+        return fail(CMSVD_ENOMEM, "hipHostMalloc(%zu bytes) for the pair records failed", want);
+    }
+    h->rec_pin_cap = want;
+    return CMSVD_OK;
+}
+
+// Layout of the staged records: anchor table, candidate table, pair records (grouped
+// by anchor slot), each 256-byte aligned; the same offsets on the host and the device.
+struct RecLayout {
+    size_t b_a, b_c, total;
+    RecLayout(size_t na, size_t nc, size_t npairs)
+        : b_a(align256(na * sizeof(AnchorRec))), b_c(align256(nc * sizeof(CandRec))),
+          total(b_a + b_c + npairs * sizeof(PairRec)) {}
+    AnchorRec* anchors(char* base) const { return reinterpret_cast<AnchorRec*>(base); }
+    CandRec* cands(char* base) const { return reinterpret_cast<CandRec*>(base + b_a); }
+    PairRec* pairs(char* base) const { return reinterpret_cast<PairRec*>(base + b_a + b_c); }
+};
+
+// The records sit in h->rec_pin (layout lay): start[s] .. start[s+1] are the pairs of
+// anchor slot s, whose packed candidate columns lie in [smin[s], smax[s]).
+cmsvd_status eval_dense(cmsvd_ctx* h, const DenseEval& de, const RecLayout& lay, size_t ncand,
+                        const std::vector<size_t>& start, const std::vector<long>& smin,
+                        const std::vector<long>& smax, double* err, double* rel) {
+    const size_t total = start[(size_t)de.na];
     if (total == 0) return CMSVD_OK;
     const int r = de.r;
-    // pairs grouped by anchor slot (counting sort, stable)
-    std::vector<size_t> start((size_t)de.na + 1, 0);
-    for (const auto& p : pairs) ++start[(size_t)p.slot + 1];
-    for (int a = 0; a < de.na; ++a) start[(size_t)a + 1] += start[(size_t)a];
-    std::vector<PairRec> sorted(total);
-    {
-        std::vector<size_t> fill(start.begin(), start.end() - 1);
-        for (const auto& p : pairs) sorted[fill[(size_t)p.slot]++] = p;
-    }
+    const CandRec* hc = lay.cands(h->rec_pin);
     int kmax = 0;
-    for (const auto& c : crec) kmax = std::max(kmax, c.k);
+    for (size_t i = 0; i < ncand; ++i) kmax = std::max(kmax, hc[i].k);
     const int nmax = r + kmax;
-    // the records live on the device for the whole call
-    DevBuf recs;
-    const size_t b_a = align256(arec.size() * sizeof(AnchorRec)), b_c = align256(crec.size() * sizeof(CandRec));
-    if (hipMalloc((void**)&recs.p, b_a + b_c + total * sizeof(PairRec)) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(CMSVD_ENOMEM, "cmsvd_merge_errors: hipMalloc of %zu pair records failed", total);
-    }
-    const AnchorRec* dA = reinterpret_cast<const AnchorRec*>(recs.p);
-    const CandRec* dC = reinterpret_cast<const CandRec*>(recs.p + b_a);
-    const PairRec* dP = reinterpret_cast<const PairRec*>(recs.p + b_a + b_c);
-    HIPCHK(hipMemcpy(recs.p, arec.data(), arec.size() * sizeof(AnchorRec), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(recs.p + b_a, crec.data(), crec.size() * sizeof(CandRec), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(recs.p + b_a + b_c, sorted.data(), total * sizeof(PairRec), hipMemcpyHostToDevice));
+    // the records live on the device for the whole call: one copy from pinned memory
+    cmsvd_status st0 = ensure(h, h->rec, h->rec_cap, lay.total);
+    if (st0 != CMSVD_OK) return st0;
+    HIPCHK(hipMemcpyAsync(h->rec, h->rec_pin, lay.total, hipMemcpyHostToDevice, h->stream));
+    const AnchorRec* dA = lay.anchors(h->rec);
+    const CandRec* dC = lay.cands(h->rec);
+    const PairRec* dP = lay.pairs(h->rec);
     const size_t row_bytes = (size_t)de.ksum * r * 8;  // C rows of one anchor
     const int achunk = (int)std::max<size_t>(1, ((size_t)8 << 30) / std::max<size_t>(row_bytes, 1));
     for (int a0 = 0; a0 < de.na; a0 += achunk) {
@@ -885,10 +907,9 @@ cmsvd_status eval_dense(cmsvd_ctx* h, const DenseEval& de, const std::vector<Pai
         const long ldc = (long)(a1 - a0) * r;
         // the packed candidate columns this chunk's pairs use
         long cmin = de.ksum, cmax = 0;
-        for (size_t i = pos; i < end; ++i) {
-            const CandRec& c = crec[(size_t)sorted[i].cand];
-            cmin = std::min(cmin, c.coff);
-            cmax = std::max(cmax, c.coff + (long)c.k);
+        for (int a = a0; a < a1; ++a) {
+            cmin = std::min(cmin, smin[(size_t)a]);
+            cmax = std::max(cmax, smax[(size_t)a]);
         }
         Plan pl;
         const size_t c_off = pl.add((size_t)ldc * (cmax - cmin) * 8);
@@ -924,7 +945,7 @@ cmsvd_status eval_dense(cmsvd_ctx* h, const DenseEval& de, const std::vector<Pai
         }
         HIPCHK(hipGetLastError());
     }
-    // the records are freed on return
+    // the staged records are rewritten by the next call
     HIPCHK(hipStreamSynchronize(h->stream));
     return CMSVD_OK;
 }
@@ -1734,6 +1755,8 @@ cmsvd_status cmsvd_destroy(cmsvd_handle h) {
     if (h->ws) (void)hipFree(h->ws);
     if (h->dsc) (void)hipFree(h->dsc);
     if (h->gsk) (void)hipFree(h->gsk);
+    if (h->rec) (void)hipFree(h->rec);
+    if (h->rec_pin) (void)hipHostFree(h->rec_pin);
     if (h->pin) (void)hipHostFree(h->pin);
     if (h->pin_ev) (void)hipEventDestroy(h->pin_ev);
     for (auto& v : h->marks)
@@ -1842,6 +1865,7 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_merge_errors: null handle");
     if (nblocks < 1 || !blocks) return fail(CMSVD_EINVAL, "cmsvd_merge_errors: no blocks");
     if (npairs < 0 || (npairs > 0 && (!pairs || !err))) return fail(CMSVD_EINVAL, "cmsvd_merge_errors: null pairs/err");
+    if (nblocks > INT32_MAX || npairs > INT32_MAX) return fail(CMSVD_EUNSUPPORTED, "cmsvd_merge_errors: too many blocks or pairs");
     const int64_t m = blocks[0].rows;
     if (m < 1) return fail(CMSVD_ESHAPE, "cmsvd_merge_errors: m < 1");
     if (r < 1 || r > m) return fail(CMSVD_ESHAPE, "cmsvd_merge_errors: need 1 <= r <= m");
@@ -1850,20 +1874,31 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
         cmsvd_status st = check_block(blocks[i], m, "block", i);
         if (st != CMSVD_OK) return st;
     }
+    // One pass over the pairs: the range check, how often each block is an anchor and a
+    // candidate, and each anchor's widest candidate (the largest eigenproblem it meets).
+    std::vector<int> colsv(nblocks), awide(nblocks, 0);
+    for (int64_t i = 0; i < nblocks; ++i) colsv[i] = (int)blocks[i].cols;
+    std::vector<int64_t> acount(nblocks, 0), ccount(nblocks, 0);
     for (int64_t p = 0; p < npairs; ++p) {
         const int32_t a = pairs[2 * p], b = pairs[2 * p + 1];
         if (a < 0 || a >= nblocks || b < 0 || b >= nblocks)
             return fail(CMSVD_EINVAL, "cmsvd_merge_errors: pair %lld = (%d, %d) out of range", (long long)p, a, b);
-        cmsvd_status st = check_order(std::max(blocks[a].cols, std::min<int64_t>(r, blocks[a].cols) + blocks[b].cols),
-                                      "cmsvd_merge_errors");
-        if (st != CMSVD_OK) return st;
+        ++acount[a];
+        ++ccount[b];
+        awide[a] = std::max(awide[a], colsv[b]);
     }
+    for (int64_t i = 0; i < nblocks; ++i)
+        if (acount[i]) {
+            cmsvd_status st = check_order(std::max<int64_t>(colsv[i], std::min<int64_t>(r, colsv[i]) + awide[i]),
+                                          "cmsvd_merge_errors");
+            if (st != CMSVD_OK) return st;
+        }
     if (npairs == 0) return CMSVD_OK;
     // anchors and candidates
     std::vector<int> is_anchor(nblocks, 0), is_cand(nblocks, 0), aslot(nblocks, -1), cslot(nblocks, -1);
-    for (int64_t p = 0; p < npairs; ++p) {
-        is_anchor[pairs[2 * p]] = 1;
-        is_cand[pairs[2 * p + 1]] = 1;
+    for (int64_t i = 0; i < nblocks; ++i) {
+        is_anchor[i] = acount[i] > 0;
+        is_cand[i] = ccount[i] > 0;
     }
     std::vector<int> anchors, cands;
     for (int i = 0; i < nblocks; ++i) {
@@ -1892,11 +1927,12 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
     // per-pair GEMMs fill 64 x 64 tiles: with r x k outputs well below whole tiles the
     // dense form (every anchor against a range of packed candidates) does less work
     double pair_work = 0.0, tile_work = 0.0;
-    for (int64_t p = 0; p < npairs; ++p) {
-        const double k = (double)blocks[pairs[2 * p + 1]].cols;
-        pair_work += k;
-        tile_work += std::ceil(k / 64.0) * 64.0 * std::ceil((double)r / 64.0) * 64.0 / (double)r;
-    }
+    for (int i = 0; i < nblocks; ++i)
+        if (ccount[i]) {
+            const double k = (double)colsv[i], c = (double)ccount[i];
+            pair_work += c * k;
+            tile_work += c * std::ceil(k / 64.0) * 64.0 * std::ceil((double)r / 64.0) * 64.0 / (double)r;
+        }
     const bool dense = pair_work < 0.5 * tile_work && (double)anchors.size() * (double)ksum <= 4.0 * pair_work;
     // Candidates given as consecutive column ranges of one row-major matrix (in index
     // order, one dtype and row stride) already form the packed operand: used in place.
@@ -2022,16 +2058,31 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
         HIPCHK(hipGetLastError());
     }
     if (dense) {
-        std::vector<AnchorRec> arec(anchors.size());
-        for (size_t a = 0; a < anchors.size(); ++a) arec[a] = AnchorRec{K(o_S[a]), K(o_n[cslot[anchors[a]]])};
-        std::vector<CandRec> crec(nblocks, CandRec{nullptr, nullptr, 0, 0});
+        // anchor and candidate tables and the pair records, grouped by anchor slot
+        // (counting sort, stable), written once into pinned memory
+        const size_t na = anchors.size();
+        const RecLayout lay(na, (size_t)nblocks, (size_t)npairs);
+        st = ensure_rec_pin(h, lay.total);
+        if (st != CMSVD_OK) return st;
+        AnchorRec* arec = lay.anchors(h->rec_pin);
+        for (size_t a = 0; a < na; ++a) arec[a] = AnchorRec{K(o_S[a]), K(o_n[cslot[anchors[a]]])};
+        CandRec* crec = lay.cands(h->rec_pin);
         for (int i = 0; i < nblocks; ++i)
-            if (is_cand[i]) crec[i] = CandRec{K(o_n[cslot[i]]), K(o_g[cslot[i]]), coff[i], (int)blocks[i].cols};
-        std::vector<PairRec> pr((size_t)npairs);
-        for (int64_t p = 0; p < npairs; ++p) pr[(size_t)p] = PairRec{aslot[pairs[2 * p]], pairs[2 * p + 1], (int)p};
-        DenseEval de{K(o_Uall), (int)anchors.size(), (int)r, (int)m, in_place ? ball_user : keep.p + o_Ball, all_f32,
-                     ksum, ldball};
-        st = eval_dense(h, de, pr, arec, crec, err, rel);
+            crec[i] = is_cand[i] ? CandRec{K(o_n[cslot[i]]), K(o_g[cslot[i]]), coff[i], colsv[i]}
+                                 : CandRec{nullptr, nullptr, 0, 0};
+        std::vector<size_t> start(na + 1, 0);
+        for (size_t a = 0; a < na; ++a) start[a + 1] = start[a] + (size_t)acount[anchors[a]];
+        std::vector<size_t> fill(start.begin(), start.end() - 1);
+        std::vector<long> smin(na, ksum), smax(na, 0);
+        PairRec* prec = lay.pairs(h->rec_pin);
+        for (int64_t p = 0; p < npairs; ++p) {
+            const int b = pairs[2 * p + 1], sl = aslot[pairs[2 * p]];
+            prec[fill[(size_t)sl]++] = PairRec{sl, b, (int)p};
+            smin[(size_t)sl] = std::min(smin[(size_t)sl], coff[b]);
+            smax[(size_t)sl] = std::max(smax[(size_t)sl], coff[b] + (long)colsv[b]);
+        }
+        DenseEval de{K(o_Uall), (int)na, (int)r, (int)m, in_place ? ball_user : keep.p + o_Ball, all_f32, ksum, ldball};
+        st = eval_dense(h, de, lay, (size_t)nblocks, start, smin, smax, err, rel);
     } else {
         std::vector<EvalJob> ej;
         ej.reserve((size_t)npairs);

@@ -257,6 +257,36 @@ def test_invalid_arguments_raise(cm):
         cm.cmsvd_cluster([a, a], 2, -1.0)
 
 
+def test_degenerate_inputs(cm):
+    # No pairs; all-zero blocks (error and relative error zero); r = m (nothing is ever
+    # discarded: zero error at any width); a zero-width block is a shape error; a single
+    # block is one cluster holding its own rank-r tail.
+    say("edge: no pairs, zero blocks, r = m, zero width, one block")
+    rng = np.random.default_rng(5)
+    m = 24
+    blocks = [rng.standard_normal((m, 10)), rng.standard_normal((m, 20))]
+    err, rel = cm.cmsvd_merge_errors(dev_tensors(blocks), np.zeros((0, 2), np.int32), 4)
+    assert err.numel() == 0 and rel.numel() == 0
+    zeros = [np.zeros((m, 6)), np.zeros((m, 3))]
+    err, rel = cm.cmsvd_merge_errors(dev_tensors(zeros), [(0, 1), (1, 0)], 4)
+    assert np.all(err.cpu().numpy() == 0.0) and np.all(rel.cpu().numpy() == 0.0)
+    err, rel = cm.cmsvd_merge_errors(dev_tensors(blocks), [(0, 1), (1, 0)], m)
+    nm = math.sqrt(sum(oracle.frob2(b) for b in blocks))
+    assert np.all(err.cpu().numpy() <= 1e-6 * nm)
+    empty = torch.zeros((m, 0), dtype=torch.float64, device="cuda")
+    with pytest.raises(cm.CmsvdError) as e:
+        cm.cmsvd_merge_errors(dev_tensors(blocks) + [empty], [(0, 2)], 4)
+    assert e.value.status == 2
+    one = [rng.standard_normal((m, 9)) * np.linspace(3.0, 0.1, 9)]
+    labels, clusters, crel = cm.cmsvd_cluster(dev_tensors(one), 4, 0.5)
+    o_labels, o_clusters, o_rel = oracle.cluster(one, 4, 0.5)
+    assert labels == [0] and clusters == [[0]] and list(o_labels) == [0]
+    s = np.linalg.svd(one[0], compute_uv=False)
+    exact = math.sqrt(float(np.sum(s[4:] ** 2)) / float(np.sum(s ** 2)))
+    assert crel[0] == pytest.approx(exact, rel=1e-9)
+    assert crel[0] == pytest.approx(o_rel[0], rel=1e-9)
+
+
 def test_cluster_matches_oracle(cm):
     blocks = workloads.tiny_groups()
     for mode in ("frobenius", "residual"):
