@@ -19,7 +19,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <exception>
+#include <new>
+#include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "cmsvd.h"
@@ -46,6 +50,22 @@ cmsvd_status fail(cmsvd_status s, const char* fmt, ...) {
         hipError_t e_ = (x);                                                               \
         if (e_ != hipSuccess) return fail(CMSVD_EHIP, "%s: %s", #x, hipGetErrorString(e_)); \
     } while (0)
+
+// The status of an exception caught at the C ABI (called from a handler): host
+// allocation failures are CMSVD_ENOMEM, anything else an internal error.
+cmsvd_status caught(const char* who) {
+    try {
+        throw;
+    } catch (const std::bad_alloc&) {
+        return fail(CMSVD_ENOMEM, "%s: host memory allocation failed", who);
+    } catch (const std::length_error&) {
+        return fail(CMSVD_ENOMEM, "%s: host buffer too large", who);
+    } catch (const std::exception& e) {
+        return fail(CMSVD_EUNSUPPORTED, "%s: internal error: %s", who, e.what());
+    } catch (...) {
+        return fail(CMSVD_EUNSUPPORTED, "%s: internal error", who);
+    }
+}
 
 constexpr double EPS = 2.220446049250313e-16;
 
@@ -847,6 +867,33 @@ struct DenseEval {
     long ksum;
     long ldb;
 };
+
+// Runs fn(t, lo, hi) over nt contiguous ranges of [0, n), range t on its own thread
+// (range 0 and any range whose thread cannot be started run on the calling thread).
+// fn must not throw.
+template <class F>
+void parallel_ranges(int64_t n, int nt, const F& fn) {
+    std::vector<std::thread> th;
+    int started = 1;
+    try {
+        th.reserve((size_t)nt);
+        for (; started < nt; ++started)
+            th.emplace_back(fn, started, n * started / nt, n * (started + 1) / nt);
+    } catch (...) {
+    }
+    for (int t = started; t < nt; ++t) fn(t, n * t / nt, n * (t + 1) / nt);
+    fn(0, 0, n / nt);
+    for (auto& x : th) x.join();
+}
+
+// Threads for the host passes over a pair list: none below a million pairs; at most 16,
+// and few enough that the per-thread tables (three ints per block) stay within 256 MB.
+int pair_threads(int64_t npairs, int64_t nblocks) {
+    if (npairs < ((int64_t)1 << 20)) return 1;
+    const int64_t hc = std::max<int64_t>(1, (int64_t)std::thread::hardware_concurrency());
+    const int64_t by_mem = std::max<int64_t>(1, ((int64_t)256 << 20) / (12 * std::max<int64_t>(nblocks, 1)));
+    return (int)std::max<int64_t>(1, std::min<int64_t>({16, hc, npairs >> 18, by_mem}));
+}
 
 // Pinned host staging for the pair records of a dense evaluation (grow-only; the
 // previous call has synchronised its stream before returning).
@@ -1723,7 +1770,7 @@ extern "C" {
 
 const char* cmsvd_last_error(void) { return g_err.c_str(); }
 
-cmsvd_status cmsvd_create(cmsvd_handle* handle, void* hip_stream) {
+cmsvd_status cmsvd_create(cmsvd_handle* handle, void* hip_stream) try {
     if (!handle) return fail(CMSVD_EINVAL, "cmsvd_create: null handle pointer");
     cmsvd_ctx* h = new cmsvd_ctx();
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -1747,9 +1794,11 @@ cmsvd_status cmsvd_create(cmsvd_handle* handle, void* hip_stream) {
     }
     *handle = h;
     return CMSVD_OK;
+} catch (...) {
+    return caught(__func__);
 }
 
-cmsvd_status cmsvd_destroy(cmsvd_handle h) {
+cmsvd_status cmsvd_destroy(cmsvd_handle h) try {
     if (!h) return CMSVD_OK;
     (void)hipStreamSynchronize(h->stream);
     if (h->ws) (void)hipFree(h->ws);
@@ -1767,15 +1816,19 @@ cmsvd_status cmsvd_destroy(cmsvd_handle h) {
     for (auto e : h->pool) (void)hipEventDestroy(e);
     delete h;
     return CMSVD_OK;
+} catch (...) {
+    return caught(__func__);
 }
 
-cmsvd_status cmsvd_profile(cmsvd_handle h, int32_t enable) {
+cmsvd_status cmsvd_profile(cmsvd_handle h, int32_t enable) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_profile: null handle");
     h->timing = enable != 0;
     return CMSVD_OK;
+} catch (...) {
+    return caught(__func__);
 }
 
-cmsvd_status cmsvd_profile_read(cmsvd_handle h, double* ms, int64_t* count) {
+cmsvd_status cmsvd_profile_read(cmsvd_handle h, double* ms, int64_t* count) try {
     if (!h || !ms || !count) return fail(CMSVD_EINVAL, "cmsvd_profile_read: null argument");
     HIPCHK(hipStreamSynchronize(h->stream));
     for (int st = 0; st < NSTAGE; ++st) {
@@ -1792,25 +1845,31 @@ cmsvd_status cmsvd_profile_read(cmsvd_handle h, double* ms, int64_t* count) {
         h->marks[st].clear();
     }
     return CMSVD_OK;
+} catch (...) {
+    return caught(__func__);
 }
 
-cmsvd_status cmsvd_set_projection(cmsvd_handle h, int32_t precision) {
+cmsvd_status cmsvd_set_projection(cmsvd_handle h, int32_t precision) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_set_projection: null handle");
     if (precision != CMSVD_PROJ_F64 && precision != CMSVD_PROJ_BF16 && precision != CMSVD_PROJ_BF16X3)
         return fail(CMSVD_EINVAL, "cmsvd_set_projection: precision must be CMSVD_PROJ_F64, _BF16 or _BF16X3");
     h->proj = precision;
     return CMSVD_OK;
+} catch (...) {
+    return caught(__func__);
 }
 
-cmsvd_status cmsvd_set_stream(cmsvd_handle h, void* hip_stream) {
+cmsvd_status cmsvd_set_stream(cmsvd_handle h, void* hip_stream) try {
     if (!h) return fail(CMSVD_EINVAL, "null handle");
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
     return CMSVD_OK;
+} catch (...) {
+    return caught(__func__);
 }
 
 cmsvd_status cmsvd_update(cmsvd_handle h, int64_t m, const double* U, int64_t ldu, const double* S, int64_t r_in,
                           const cmsvd_block* B, int64_t r, double* U_out, int64_t ldu_out, double* S_out, double* acc,
-                          double* est) {
+                          double* est) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_update: null handle");
     if (!B) return fail(CMSVD_EINVAL, "cmsvd_update: null block");
     if (m < 1) return fail(CMSVD_ESHAPE, "cmsvd_update: m < 1");
@@ -1828,12 +1887,14 @@ cmsvd_status cmsvd_update(cmsvd_handle h, int64_t m, const double* U, int64_t ld
     if (st != CMSVD_OK) return st;
     CommitJob j{(int)m, U, (long)ldu, S, (int)r_in, *B, (int)r, U_out, (long)ldu_out, S_out, acc, est};
     return commit_batched(h, {j});
+} catch (...) {
+    return caught(__func__);
 }
 
 cmsvd_status cmsvd_update_batch(cmsvd_handle h, int64_t count, int64_t m, const double* const* U, int64_t ldu,
                                 const double* const* S, int64_t r_in, const cmsvd_block* B, int64_t r,
                                 double* const* U_out, int64_t ldu_out, double* const* S_out, double* const* acc,
-                                double* const* est) {
+                                double* const* est) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_update_batch: null handle");
     if (count < 0) return fail(CMSVD_EINVAL, "cmsvd_update_batch: count < 0");
     if (count == 0) return CMSVD_OK;
@@ -1858,10 +1919,12 @@ cmsvd_status cmsvd_update_batch(cmsvd_handle h, int64_t count, int64_t m, const 
                                  (int)r, U_out[i], (long)ldu_out, S_out[i], acc[i], est ? est[i] : nullptr});
     }
     return commit_batched(h, jobs);
+} catch (...) {
+    return caught(__func__);
 }
 
 cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, const int32_t* pairs,
-                                int64_t npairs, int64_t r, double* err, double* rel) {
+                                int64_t npairs, int64_t r, double* err, double* rel) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_merge_errors: null handle");
     if (nblocks < 1 || !blocks) return fail(CMSVD_EINVAL, "cmsvd_merge_errors: no blocks");
     if (npairs < 0 || (npairs > 0 && (!pairs || !err))) return fail(CMSVD_EINVAL, "cmsvd_merge_errors: null pairs/err");
@@ -1876,17 +1939,51 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
     }
     // One pass over the pairs: the range check, how often each block is an anchor and a
     // candidate, and each anchor's widest candidate (the largest eigenproblem it meets).
-    std::vector<int> colsv(nblocks), awide(nblocks, 0);
+    // Long lists are split into contiguous ranges, one per thread, each with its own
+    // tables; the record pass below uses the same ranges.
+    std::vector<int> colsv(nblocks);
     for (int64_t i = 0; i < nblocks; ++i) colsv[i] = (int)blocks[i].cols;
-    std::vector<int64_t> acount(nblocks, 0), ccount(nblocks, 0);
-    for (int64_t p = 0; p < npairs; ++p) {
-        const int32_t a = pairs[2 * p], b = pairs[2 * p + 1];
-        if (a < 0 || a >= nblocks || b < 0 || b >= nblocks)
-            return fail(CMSVD_EINVAL, "cmsvd_merge_errors: pair %lld = (%d, %d) out of range", (long long)p, a, b);
-        ++acount[a];
-        ++ccount[b];
-        awide[a] = std::max(awide[a], colsv[b]);
-    }
+    const int nt = pair_threads(npairs, nblocks);
+    std::vector<std::vector<int>> tac(nt, std::vector<int>(nblocks, 0)), tcc(nt, std::vector<int>(nblocks, 0)),
+        taw(nt, std::vector<int>(nblocks, 0));
+    std::vector<int64_t> tbad(nt, -1);
+    parallel_ranges(npairs, nt, [&](int t, int64_t lo, int64_t hi) {
+        int* ac = tac[t].data();
+        int* cc = tcc[t].data();
+        int* aw = taw[t].data();
+        for (int64_t p = lo; p < hi; ++p) {
+            const int32_t a = pairs[2 * p], b = pairs[2 * p + 1];
+            if (a < 0 || a >= nblocks || b < 0 || b >= nblocks) {
+                tbad[t] = p;
+                return;
+            }
+            ++ac[a];
+            ++cc[b];
+            aw[a] = std::max(aw[a], colsv[b]);
+        }
+    });
+    for (int t = 0; t < nt; ++t)
+        if (tbad[t] >= 0) {
+            const int64_t p = tbad[t];
+            return fail(CMSVD_EINVAL, "cmsvd_merge_errors: pair %lld = (%d, %d) out of range", (long long)p,
+                        pairs[2 * p], pairs[2 * p + 1]);
+        }
+    std::vector<int> acount(nblocks), ccount(nblocks), awide(nblocks);
+    parallel_ranges(nblocks, nt, [&](int, int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) {
+            int a = 0, c = 0, w = 0;
+            for (int t = 0; t < nt; ++t) {
+                a += tac[t][i];
+                c += tcc[t][i];
+                w = std::max(w, taw[t][i]);
+            }
+            acount[i] = a;
+            ccount[i] = c;
+            awide[i] = w;
+        }
+    });
+    std::vector<std::vector<int>>().swap(tcc);
+    std::vector<std::vector<int>>().swap(taw);
     for (int64_t i = 0; i < nblocks; ++i)
         if (acount[i]) {
             cmsvd_status st = check_order(std::max<int64_t>(colsv[i], std::min<int64_t>(r, colsv[i]) + awide[i]),
@@ -2072,15 +2169,34 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
                                  : CandRec{nullptr, nullptr, 0, 0};
         std::vector<size_t> start(na + 1, 0);
         for (size_t a = 0; a < na; ++a) start[a + 1] = start[a] + (size_t)acount[anchors[a]];
-        std::vector<size_t> fill(start.begin(), start.end() - 1);
-        std::vector<long> smin(na, ksum), smax(na, 0);
-        PairRec* prec = lay.pairs(h->rec_pin);
-        for (int64_t p = 0; p < npairs; ++p) {
-            const int b = pairs[2 * p + 1], sl = aslot[pairs[2 * p]];
-            prec[fill[(size_t)sl]++] = PairRec{sl, b, (int)p};
-            smin[(size_t)sl] = std::min(smin[(size_t)sl], coff[b]);
-            smax[(size_t)sl] = std::max(smax[(size_t)sl], coff[b] + (long)colsv[b]);
+        // thread t writes its pairs of slot s after those of the earlier ranges
+        std::vector<std::vector<size_t>> tpos(nt, std::vector<size_t>(na));
+        for (size_t a = 0; a < na; ++a) {
+            size_t o = start[a];
+            for (int t = 0; t < nt; ++t) {
+                tpos[t][a] = o;
+                o += (size_t)tac[t][anchors[a]];
+            }
         }
+        std::vector<std::vector<long>> tmin(nt, std::vector<long>(na, ksum)), tmax(nt, std::vector<long>(na, 0));
+        PairRec* prec = lay.pairs(h->rec_pin);
+        parallel_ranges(npairs, nt, [&](int t, int64_t lo, int64_t hi) {
+            size_t* pos = tpos[t].data();
+            long* mn = tmin[t].data();
+            long* mx = tmax[t].data();
+            for (int64_t p = lo; p < hi; ++p) {
+                const int b = pairs[2 * p + 1], sl = aslot[pairs[2 * p]];
+                prec[pos[sl]++] = PairRec{sl, b, (int)p};
+                mn[sl] = std::min(mn[sl], coff[b]);
+                mx[sl] = std::max(mx[sl], coff[b] + (long)colsv[b]);
+            }
+        });
+        std::vector<long> smin(na, ksum), smax(na, 0);
+        for (int t = 0; t < nt; ++t)
+            for (size_t a = 0; a < na; ++a) {
+                smin[a] = std::min(smin[a], tmin[t][a]);
+                smax[a] = std::max(smax[a], tmax[t][a]);
+            }
         DenseEval de{K(o_Uall), (int)na, (int)r, (int)m, in_place ? ball_user : keep.p + o_Ball, all_f32, ksum, ldball};
         st = eval_dense(h, de, lay, (size_t)nblocks, start, smin, smax, err, rel);
     } else {
@@ -2098,10 +2214,12 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
     // the per-call buffers are freed on return: wait for the work that reads them
     HIPCHK(hipStreamSynchronize(h->stream));
     return CMSVD_OK;
+} catch (...) {
+    return caught(__func__);
 }
 
 cmsvd_status cmsvd_sym_eigvals(cmsvd_handle h, const double* A, int64_t n, int64_t lda, int64_t stride_a,
-                               int64_t count, int64_t nkeep, double* lam) {
+                               int64_t count, int64_t nkeep, double* lam) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_sym_eigvals: null handle");
     if (!A || !lam) return fail(CMSVD_EINVAL, "cmsvd_sym_eigvals: null pointer");
     if (n < 1 || lda < n || count < 0 || nkeep < 1 || nkeep > n) return fail(CMSVD_ESHAPE, "cmsvd_sym_eigvals: bad sizes");
@@ -2132,25 +2250,31 @@ cmsvd_status cmsvd_sym_eigvals(cmsvd_handle h, const double* A, int64_t n, int64
                     reinterpret_cast<double*>(h->ws + eig_off), nslots, h->stream);
     HIPCHK(hipGetLastError());
     return CMSVD_OK;
+} catch (...) {
+    return caught(__func__);
 }
 
 cmsvd_status cmsvd_gemm_f64(cmsvd_handle h, int32_t trans_a, int32_t trans_b, int64_t M, int64_t N, int64_t K,
                             double alpha, const void* A, int64_t lda, int32_t a_dtype, const void* B, int64_t ldb,
-                            int32_t b_dtype, double beta, double* C, int64_t ldc) {
+                            int32_t b_dtype, double beta, double* C, int64_t ldc) try {
     return gemm_entry(h, "cmsvd_gemm_f64", 0, trans_a, trans_b, M, N, K, alpha, A, lda, a_dtype, B, ldb, b_dtype,
                       beta, C, ldc);
+} catch (...) {
+    return caught(__func__);
 }
 
 cmsvd_status cmsvd_gemm_bf16(cmsvd_handle h, int32_t passes, int32_t trans_a, int32_t trans_b, int64_t M, int64_t N,
                              int64_t K, double alpha, const void* A, int64_t lda, int32_t a_dtype, const void* B,
-                             int64_t ldb, int32_t b_dtype, double beta, double* C, int64_t ldc) {
+                             int64_t ldb, int32_t b_dtype, double beta, double* C, int64_t ldc) try {
     if (passes != 1 && passes != 3) return fail(CMSVD_EINVAL, "cmsvd_gemm_bf16: passes must be 1 or 3");
     return gemm_entry(h, "cmsvd_gemm_bf16", passes, trans_a, trans_b, M, N, K, alpha, A, lda, a_dtype, B, ldb, b_dtype,
                       beta, C, ldc);
+} catch (...) {
+    return caught(__func__);
 }
 
 cmsvd_status cmsvd_cluster(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double eps,
-                           int32_t sort_mode, int32_t* labels, int64_t* nclusters, double* cluster_rel) {
+                           int32_t sort_mode, int32_t* labels, int64_t* nclusters, double* cluster_rel) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_cluster: null handle");
     if (nblocks < 1 || !blocks) return fail(CMSVD_EINVAL, "cmsvd_cluster: no blocks");
     if (!labels || !nclusters) return fail(CMSVD_EINVAL, "cmsvd_cluster: null output");
@@ -2309,13 +2433,15 @@ cmsvd_status cmsvd_cluster(cmsvd_handle h, const cmsvd_block* blocks, int64_t nb
     if (cluster_rel)
         for (int c = 0; c < ncl; ++c) cluster_rel[c] = crel[c];
     return CMSVD_OK;
+} catch (...) {
+    return caught(__func__);
 }
 
 
 /* Residual-certified clustering (Algorithm 2); see include/cmsvd.h. */
 
 cmsvd_status cmsvd_cluster_residual(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double eps,
-                                    int32_t sort_mode, int32_t* labels, int64_t* nclusters, double* cluster_rel) {
+                                    int32_t sort_mode, int32_t* labels, int64_t* nclusters, double* cluster_rel) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_cluster_residual: null handle");
     if (!labels || !nclusters) return fail(CMSVD_EINVAL, "cmsvd_cluster_residual: null output");
     if (!(eps >= 0.0)) return fail(CMSVD_EINVAL, "cmsvd_cluster_residual: eps must be >= 0");
@@ -2398,10 +2524,12 @@ cmsvd_status cmsvd_cluster_residual(cmsvd_handle h, const cmsvd_block* blocks, i
     if (cluster_rel)
         for (int c = 0; c < ncl; ++c) cluster_rel[c] = crel[c];
     return CMSVD_OK;
+} catch (...) {
+    return caught(__func__);
 }
 
 cmsvd_status cmsvd_residual_bound(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r,
-                                  double* bound2, double* mu) {
+                                  double* bound2, double* mu) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_residual_bound: null handle");
     if (!bound2) return fail(CMSVD_EINVAL, "cmsvd_residual_bound: null output");
     if (nblocks > INT32_MAX) return fail(CMSVD_EUNSUPPORTED, "cmsvd_residual_bound: too many blocks");
@@ -2426,11 +2554,13 @@ cmsvd_status cmsvd_residual_bound(cmsvd_handle h, const cmsvd_block* blocks, int
         for (int64_t i = 0; i < r; ++i) mu[i] = std::sqrt(std::max(L[(size_t)i], 0.0));
     }
     return CMSVD_OK;
+} catch (...) {
+    return caught(__func__);
 }
 
 
 /* Theorem 1, Algorithm 1 and the explicit tail; see include/cmsvd.h. */
-cmsvd_status cmsvd_weyl_bound(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double* bound2) {
+cmsvd_status cmsvd_weyl_bound(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double* bound2) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_weyl_bound: null handle");
     if (!bound2) return fail(CMSVD_EINVAL, "cmsvd_weyl_bound: null output");
     if (nblocks > INT32_MAX) return fail(CMSVD_EUNSUPPORTED, "cmsvd_weyl_bound: too many blocks");
@@ -2442,10 +2572,12 @@ cmsvd_status cmsvd_weyl_bound(cmsvd_handle h, const cmsvd_block* blocks, int64_t
     HIPCHK(hipMemcpyAsync(bound2, wb.rel, 8, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return CMSVD_OK;
+} catch (...) {
+    return caught(__func__);
 }
 
 cmsvd_status cmsvd_cluster_weyl(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double eps,
-                                int32_t* labels, int64_t* nclusters, double* cluster_rel) {
+                                int32_t* labels, int64_t* nclusters, double* cluster_rel) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_cluster_weyl: null handle");
     if (!labels || !nclusters) return fail(CMSVD_EINVAL, "cmsvd_cluster_weyl: null output");
     if (!(eps >= 0.0)) return fail(CMSVD_EINVAL, "cmsvd_cluster_weyl: eps must be >= 0");
@@ -2516,9 +2648,11 @@ cmsvd_status cmsvd_cluster_weyl(cmsvd_handle h, const cmsvd_block* blocks, int64
     if (cluster_rel)
         for (int c = 0; c < ncl; ++c) cluster_rel[c] = crel[c];
     return CMSVD_OK;
+} catch (...) {
+    return caught(__func__);
 }
 
-cmsvd_status cmsvd_exact_tail(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double* tail2) {
+cmsvd_status cmsvd_exact_tail(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double* tail2) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_exact_tail: null handle");
     if (!tail2) return fail(CMSVD_EINVAL, "cmsvd_exact_tail: null output");
     if (nblocks < 1 || !blocks) return fail(CMSVD_EINVAL, "cmsvd_exact_tail: no blocks");
@@ -2585,12 +2719,14 @@ cmsvd_status cmsvd_exact_tail(cmsvd_handle h, const cmsvd_block* blocks, int64_t
     HIPCHK(hipMemcpyAsync(tail2, D(o_out), 8, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return CMSVD_OK;
+} catch (...) {
+    return caught(__func__);
 }
 
 
 /* Compression back-end: the truncated SVD factors of one cluster; see include/cmsvd.h. */
 cmsvd_status cmsvd_compress(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double* Ut,
-                            int64_t ldu, double* Vt, int64_t ldv, int64_t* rank, double* tail2, double* energy) {
+                            int64_t ldu, double* Vt, int64_t ldv, int64_t* rank, double* tail2, double* energy) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_compress: null handle");
     if (!Ut || !Vt || !rank || !tail2) return fail(CMSVD_EINVAL, "cmsvd_compress: null output");
     if (nblocks < 1 || !blocks) return fail(CMSVD_EINVAL, "cmsvd_compress: no blocks");
@@ -2777,12 +2913,14 @@ cmsvd_status cmsvd_compress(cmsvd_handle h, const cmsvd_block* blocks, int64_t n
     if (energy) *energy = v[1];
     *rank = rc;
     return CMSVD_OK;
+} catch (...) {
+    return caught(__func__);
 }
 
 
 /* Tail energy of a chain and its gradient; see include/cmsvd.h. */
 cmsvd_status cmsvd_tail_energy_grad(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r,
-                                    int64_t checkpoint, double* f, double* const* grads, double* min_gap) {
+                                    int64_t checkpoint, double* f, double* const* grads, double* min_gap) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_tail_energy_grad: null handle");
     if (!blocks || nblocks < 1) return fail(CMSVD_EINVAL, "cmsvd_tail_energy_grad: no blocks");
     if (!f) return fail(CMSVD_EINVAL, "cmsvd_tail_energy_grad: null f");
@@ -2965,6 +3103,8 @@ cmsvd_status cmsvd_tail_energy_grad(cmsvd_handle h, const cmsvd_block* blocks, i
         *min_gap = g;
     }
     return CMSVD_OK;
+} catch (...) {
+    return caught(__func__);
 }
 
 }  // extern "C"

@@ -257,6 +257,43 @@ def test_invalid_arguments_raise(cm):
         cm.cmsvd_cluster([a, a], 2, -1.0)
 
 
+def test_long_pair_lists_on_host_threads(cm):
+    # A million pairs or more are checked, counted and grouped by anchor on several host
+    # threads over contiguous ranges of the list: the results equal those of the same
+    # pairs evaluated in short calls (one thread), and the first bad pair is the one
+    # reported.
+    rng = np.random.default_rng(23)
+    m, r, na, nc = 64, 8, 16, 65536
+    Q = workloads.orthonormal(rng, m, 12)
+    anchors = [Q @ rng.standard_normal((12, 14)) + 0.02 * rng.standard_normal((m, 14)) for _ in range(na)]
+    cand = (Q @ rng.standard_normal((12, nc)) + 0.05 * rng.standard_normal((m, nc))).astype(np.float32)
+    C = torch.from_numpy(cand).cuda()
+    arr = cm.BlockArray(dev_tensors(anchors) + [C[:, j:j + 1] for j in range(nc)])
+    pairs = np.stack([np.repeat(np.arange(na), nc), np.tile(np.arange(na, na + nc), na)], axis=1).astype(np.int32)
+    pairs = pairs[rng.permutation(len(pairs))]
+    say(f"{len(pairs)} pairs in one call and in calls of 100,000")
+    e_all, r_all = cm.cmsvd_merge_errors(arr, pairs, r)
+    parts = [cm.cmsvd_merge_errors(arr, pairs[i:i + 100000], r) for i in range(0, len(pairs), 100000)]
+    e_par = torch.cat([e for e, _ in parts]).cpu().numpy()
+    r_par = torch.cat([x for _, x in parts]).cpu().numpy()
+    np.testing.assert_allclose(e_all.cpu().numpy(), e_par, rtol=1e-13, atol=0.0)
+    np.testing.assert_allclose(r_all.cpu().numpy(), r_par, rtol=1e-13, atol=0.0)
+    sample = rng.choice(len(pairs), size=48, replace=False)
+    blocks = anchors + [cand[:, j - na:j - na + 1] for j in pairs[sample, 1]]
+    sp = np.stack([pairs[sample, 0], na + np.arange(len(sample))], axis=1).astype(np.int32)
+    e_o, _ = oracle.merge_errors(blocks, sp, r)
+    for (i, j), g, o in zip(sp, e_all.cpu().numpy()[sample], e_o):
+        nm = math.sqrt(float(np.sum(np.asarray(blocks[i], np.float64) ** 2)) +
+                       float(np.sum(np.asarray(blocks[j], np.float64) ** 2)))
+        assert_est(g, o, nm, f"pair {i},{j}")
+    bad = pairs.copy()
+    bad[700000, 1] = na + nc
+    bad[900000, 0] = -1
+    with pytest.raises(cm.CmsvdError) as e:
+        cm.cmsvd_merge_errors(arr, bad, r)
+    assert e.value.status == 1 and "pair 700000 " in str(e.value)
+
+
 def test_degenerate_inputs(cm):
     # No pairs; all-zero blocks (error and relative error zero); r = m (nothing is ever
     # discarded: zero error at any width); a zero-width block is a shape error; a single
