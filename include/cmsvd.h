@@ -31,8 +31,11 @@
  *     stream synchronisation.  The clustering calls are synchronous (their outputs
  *     are host memory).
  *   - Argument validation happens before any launch.  A non-OK status means no
- *     kernel was launched by that call, except CMSVD_EHIP, which reports a HIP
- *     runtime failure.  cmsvd_last_error() gives a thread-local message.
+ *     kernel was launched by that call, except CMSVD_EHIP (a HIP runtime failure)
+ *     and CMSVD_ENOMEM (a device or host allocation that failed part-way).  No C++
+ *     exception crosses the ABI: a failed host allocation returns CMSVD_ENOMEM, any
+ *     other internal exception CMSVD_EUNSUPPORTED.  cmsvd_last_error() gives a
+ *     thread-local message.
  *   - Every symmetric eigenproblem the library solves has order at most 2016: the
  *     core of an update (r_in + n_i), of a candidate merge (r + n_j), a block's or
  *     residual's Gram (n_j) and the explicit Gram of cmsvd_exact_tail (min(m, sum
@@ -147,7 +150,8 @@ cmsvd_status cmsvd_update_batch(cmsvd_handle handle, int64_t count, int64_t m, c
      err               DEVICE npairs FP64: plug-in error sqrt(||A_i||^2 + ||A_j||^2 -
                        sum_{l<=r} sigma_l^2)
      rel               DEVICE npairs FP64 (may be NULL): err / ||[A_i, A_j]||_F
-   nblocks and npairs are at most 2^31 - 1 (else CMSVD_EUNSUPPORTED).  Thin candidates
+   nblocks and npairs are at most 2^31 - 1 (else CMSVD_EUNSUPPORTED).  Lists of a
+   million pairs or more are checked and grouped on up to 16 host threads.  Thin candidates
    given as consecutive column ranges of one row-major matrix (in index order, one
    dtype and row stride) are read in place; others are first packed side by side. */
 cmsvd_status cmsvd_merge_errors(cmsvd_handle handle, const cmsvd_block* blocks, int64_t nblocks,
