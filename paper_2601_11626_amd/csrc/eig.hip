@@ -68,13 +68,15 @@ __device__ __forceinline__ double hval(const EigDesc& D, int i, int c) {
 // below 1 exactly (a power of two), and the pair (p_{i-1}, p_i) is renormalised by a
 // power of two every four steps, so nothing overflows or underflows; signs are exact.
 // An exactly zero minor stands for a negative pivot of size 2^-60 ||T||.
-template <int KP>
+// PRE: the caller's arrays already hold sc d_i and sc^2 e_i^2 (the same values, formed
+// once instead of at every probe).
+template <int KP, bool PRE>
 __device__ __forceinline__ void sturm_step(double dl, double el, const double (&xs)[KP], double sc, double (&p1)[KP],
                                            double (&p2)[KP], int (&cnt)[KP]) {
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
         const double tk = -el * p2[k];
-        double p = fma(dl * sc - xs[k], p1[k], tk);
+        double p = fma((PRE ? dl : dl * sc) - xs[k], p1[k], tk);
         if (p == 0.0) p = -0x1p-60 * p1[k];
         cnt[k] += (p < 0.0) != (p1[k] < 0.0);
         p2[k] = p1[k];
@@ -96,7 +98,7 @@ __device__ __forceinline__ void sturm_renorm(double (&p1)[KP], double (&p2)[KP])
 // Full blocks of four steps run without bounds checks, with the next block's operands
 // loaded ahead (at most three entries past n - 1 are read and not used; the callers'
 // arrays are padded past n); the last n - 1 mod 4 steps follow one by one.
-template <int KP>
+template <int KP, bool PRE = false>
 __device__ __forceinline__ void sturm_count_k(const double* dd, const double* e2, int n, const double (&x)[KP],
                                               double sc, int (&cnt)[KP]) {
     const double sc2 = sc * sc;
@@ -105,7 +107,7 @@ __device__ __forceinline__ void sturm_count_k(const double* dd, const double* e2
     for (int k = 0; k < KP; ++k) {
         xs[k] = x[k] * sc;
         p2[k] = 1.0;
-        p1[k] = dd[0] * sc - xs[k];
+        p1[k] = (PRE ? dd[0] : dd[0] * sc) - xs[k];
         if (p1[k] == 0.0) p1[k] = -0x1p-60;
         cnt[k] = p1[k] < 0.0;
     }
@@ -121,15 +123,15 @@ __device__ __forceinline__ void sturm_count_k(const double* dd, const double* e2
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             dl[m] = dn[m];
-            el[m] = en[m] * sc2;
+            el[m] = PRE ? en[m] : en[m] * sc2;
             dn[m] = dd[i + 4 + m];
             en[m] = e2[i + 3 + m];
         }
 #pragma unroll
-        for (int m = 0; m < 4; ++m) sturm_step<KP>(dl[m], el[m], xs, sc, p1, p2, cnt);
+        for (int m = 0; m < 4; ++m) sturm_step<KP, PRE>(dl[m], el[m], xs, sc, p1, p2, cnt);
         sturm_renorm<KP>(p1, p2);
     }
-    for (int m = 0; i < n; ++i, ++m) sturm_step<KP>(dn[m], en[m] * sc2, xs, sc, p1, p2, cnt);
+    for (int m = 0; i < n; ++i, ++m) sturm_step<KP, PRE>(dn[m], PRE ? en[m] : en[m] * sc2, xs, sc, p1, p2, cnt);
 }
 
 __device__ __forceinline__ int sturm_count(const double* dd, const double* e2, int n, double x, double sc) {
@@ -712,7 +714,6 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
         __syncthreads();
 
         // ---- multisection bisection for the nkeep largest eigenvalues ----
-        for (int i = t; i < npad; i += RT) xv[i] = (i < n - 1) ? ee[i] * ee[i] : 0.0;
         double glo = INFINITY, ghi = -INFINITY, em = 0.0;
         for (int i = t; i < n; i += RT) {
             const double rad = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i < n - 1 ? fabs(ee[i]) : 0.0);
@@ -727,6 +728,13 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
         const double pivmin = DBL_MIN * fmax(1.0, em);
         const double tol = 4.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
         const double sc = sturm_scale(tnorm);
+        // T scaled by sc once for all probes: diagonal into vc, squared off-diagonal into xv
+        for (int i = t; i < npad; i += RT) {
+            vc[i] = i < n ? dd[i] * sc : 0.0;
+            const double es = i < n - 1 ? ee[i] * sc : 0.0;
+            xv[i] = es * es;
+        }
+        __syncthreads();
         glo -= tol;
         ghi += tol;
         // One probe per thread; P probes per eigenvalue and round split its interval
@@ -741,14 +749,37 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
         double* blo = pw;
         double* bhi = pw + NP;
         int* flag = reinterpret_cast<int*>(pw + 2 * NP);  // NPROBE ints
-        for (int q = t; q < nb; q += RT) {
-            blo[q] = glo;
-            bhi[q] = ghi;
+        double width = ghi - glo;
+        if (nb > 1) {
+            // The first round is shared: NPROBE probes spread evenly over the Gershgorin
+            // interval (the multisection formula with P = NPROBE) leave every eigenvalue
+            // a bracket of 1/(NPROBE + 1) of it, where per-eigenvalue probes would leave
+            // 1/(P + 1).
+            {
+                const double x[1] = {glo + width * (double)(t + 1) / (double)(NPROBE + 1)};
+                int c[1];
+                sturm_count_k<1, true>(vc, xv, n, x, sc, c);
+                flag[t] = c[0];
+            }
+            __syncthreads();
+            for (int q = t; q < nb; q += RT) {
+                const int target = bottom ? q + 1 : n - q;
+                int first = NPROBE;
+                for (int pi = NPROBE - 1; pi >= 0; --pi)
+                    if (flag[pi] >= target) first = pi;
+                blo[q] = first > 0 ? glo + width * (double)first / (double)(NPROBE + 1) : glo;
+                bhi[q] = first < NPROBE ? glo + width * (double)(first + 1) / (double)(NPROBE + 1) : ghi;
+            }
+            width /= (double)(NPROBE + 1);
+        } else {
+            for (int q = t; q < nb; q += RT) {
+                blo[q] = glo;
+                bhi[q] = ghi;
+            }
         }
         // Each round divides every interval by exactly P + 1, so this many rounds
-        // bring the Gershgorin width below tol (the resolution of the Sturm count).
-        const double width = ghi - glo;
-        int iters = 1;
+        // bring the bracket width below tol (the resolution of the Sturm count).
+        int iters = nb > 1 ? 0 : 1;
         if (width > tol) iters = (int)ceil(log(width / tol) / log((double)(P + 1)));
         __syncthreads();
         for (int it = 0; it < iters; ++it) {
@@ -765,7 +796,7 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                         x[k] = lo + (hi - lo) * (double)(pi + 1) / (double)(P + 1);
                     }
                 }
-                sturm_count_k<KP>(dd, xv, n, x, sc, cnt);
+                sturm_count_k<KP, true>(vc, xv, n, x, sc, cnt);
 #pragma unroll
                 for (int k = 0; k < KP; ++k) {
                     const int u = base + t * KP + k;
