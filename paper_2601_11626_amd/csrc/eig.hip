@@ -68,15 +68,13 @@ __device__ __forceinline__ double hval(const EigDesc& D, int i, int c) {
 // below 1 exactly (a power of two), and the pair (p_{i-1}, p_i) is renormalised by a
 // power of two every four steps, so nothing overflows or underflows; signs are exact.
 // An exactly zero minor stands for a negative pivot of size 2^-60 ||T||.
-// PRE: the caller's arrays already hold sc d_i and sc^2 e_i^2 (the same values, formed
-// once instead of at every probe).
-template <int KP, bool PRE>
+template <int KP>
 __device__ __forceinline__ void sturm_step(double dl, double el, const double (&xs)[KP], double sc, double (&p1)[KP],
                                            double (&p2)[KP], int (&cnt)[KP]) {
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
         const double tk = -el * p2[k];
-        double p = fma((PRE ? dl : dl * sc) - xs[k], p1[k], tk);
+        double p = fma(dl * sc - xs[k], p1[k], tk);
         if (p == 0.0) p = -0x1p-60 * p1[k];
         cnt[k] += (p < 0.0) != (p1[k] < 0.0);
         p2[k] = p1[k];
@@ -98,7 +96,7 @@ __device__ __forceinline__ void sturm_renorm(double (&p1)[KP], double (&p2)[KP])
 // Full blocks of four steps run without bounds checks, with the next block's operands
 // loaded ahead (at most three entries past n - 1 are read and not used; the callers'
 // arrays are padded past n); the last n - 1 mod 4 steps follow one by one.
-template <int KP, bool PRE = false>
+template <int KP>
 __device__ __forceinline__ void sturm_count_k(const double* dd, const double* e2, int n, const double (&x)[KP],
                                               double sc, int (&cnt)[KP]) {
     const double sc2 = sc * sc;
@@ -107,7 +105,7 @@ __device__ __forceinline__ void sturm_count_k(const double* dd, const double* e2
     for (int k = 0; k < KP; ++k) {
         xs[k] = x[k] * sc;
         p2[k] = 1.0;
-        p1[k] = (PRE ? dd[0] : dd[0] * sc) - xs[k];
+        p1[k] = dd[0] * sc - xs[k];
         if (p1[k] == 0.0) p1[k] = -0x1p-60;
         cnt[k] = p1[k] < 0.0;
     }
@@ -123,15 +121,86 @@ __device__ __forceinline__ void sturm_count_k(const double* dd, const double* e2
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             dl[m] = dn[m];
-            el[m] = PRE ? en[m] : en[m] * sc2;
+            el[m] = en[m] * sc2;
             dn[m] = dd[i + 4 + m];
             en[m] = e2[i + 3 + m];
         }
 #pragma unroll
-        for (int m = 0; m < 4; ++m) sturm_step<KP, PRE>(dl[m], el[m], xs, sc, p1, p2, cnt);
+        for (int m = 0; m < 4; ++m) sturm_step<KP>(dl[m], el[m], xs, sc, p1, p2, cnt);
         sturm_renorm<KP>(p1, p2);
     }
-    for (int m = 0; i < n; ++i, ++m) sturm_step<KP, PRE>(dn[m], PRE ? en[m] : en[m] * sc2, xs, sc, p1, p2, cnt);
+    for (int m = 0; i < n; ++i, ++m) sturm_step<KP>(dn[m], en[m] * sc2, xs, sc, p1, p2, cnt);
+}
+
+// The same count on a tridiagonal prepared for it once: ds = sc d and, for the n - 1
+// off-diagonals, e2s = max(sc^2 e^2, 2^-120) (sc = 2^-k scales T to norm below 1).
+// Raising an off-diagonal of at most 2^-60 to 2^-60 moves no eigenvalue by more than
+// 2^-60, far below the bisection's resolution.  With every e^2 positive a zero minor
+// needs no test: p_i = 0 makes p_{i+1} = -e_i^2 p_{i-1}, of the sign opposite to
+// p_{i-1}, so the two comparisons around it count one sign change whichever sign the
+// zero is given, and no two consecutive minors vanish.  One step changes the pair's
+// larger member by a factor between about 2^-120 (cancellation) and 3, so the pair is
+// renormalised every eight steps.  Reads up to seven entries past the end of each
+// array (not used).
+template <int KP>
+__device__ __forceinline__ void sturm_count_scaled(const double* ds, const double* e2s, int n, const double (&x)[KP],
+                                                   double sc, int (&cnt)[KP]) {
+    double xs[KP], p1[KP], p2[KP];  // x sc, p_{i-1}, p_{i-2}
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        xs[k] = x[k] * sc;
+        p2[k] = 1.0;
+        p1[k] = ds[0] - xs[k];
+        cnt[k] = p1[k] < 0.0;
+    }
+    auto step = [&](double dl, double el) {
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            const double p = fma(dl - xs[k], p1[k], -el * p2[k]);
+            cnt[k] += (p < 0.0) != (p1[k] < 0.0);
+            p2[k] = p1[k];
+            p1[k] = p;
+        }
+    };
+    auto rescale = [&]() {
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            const int e = __builtin_amdgcn_frexp_exp(fmax(fabs(p1[k]), fabs(p2[k])));
+            p1[k] = ldexp(p1[k], -e);
+            p2[k] = ldexp(p2[k], -e);
+        }
+    };
+    // two operand buffers of eight steps: one is loaded while the other is used
+    double da[8], ea[8], db[8], eb[8];
+    auto load = [&](double (&d8)[8], double (&e8)[8], int at) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            d8[m] = ds[at + m];
+            e8[m] = e2s[at + m - 1];
+        }
+    };
+    int i = 1;
+    load(da, ea, i);
+    for (; i + 15 < n; i += 16) {
+        load(db, eb, i + 8);
+#pragma unroll
+        for (int m = 0; m < 8; ++m) step(da[m], ea[m]);
+        rescale();
+        load(da, ea, i + 16);
+#pragma unroll
+        for (int m = 0; m < 8; ++m) step(db[m], eb[m]);
+        rescale();
+    }
+    if (i + 7 < n) {  // da holds steps i .. i + 7
+        load(db, eb, i + 8);
+#pragma unroll
+        for (int m = 0; m < 8; ++m) step(da[m], ea[m]);
+        rescale();
+        i += 8;
+        for (int m = 0; i < n; ++i, ++m) step(db[m], eb[m]);
+    } else {
+        for (int m = 0; i < n; ++i, ++m) step(da[m], ea[m]);
+    }
 }
 
 __device__ __forceinline__ int sturm_count(const double* dd, const double* e2, int n, double x, double sc) {
@@ -728,11 +797,12 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
         const double pivmin = DBL_MIN * fmax(1.0, em);
         const double tol = 4.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
         const double sc = sturm_scale(tnorm);
-        // T scaled by sc once for all probes: diagonal into vc, squared off-diagonal into xv
+        // T prepared once for all probes (sturm_count_scaled): diagonal into vc,
+        // squared off-diagonal into xv
         for (int i = t; i < npad; i += RT) {
             vc[i] = i < n ? dd[i] * sc : 0.0;
             const double es = i < n - 1 ? ee[i] * sc : 0.0;
-            xv[i] = es * es;
+            xv[i] = i < n - 1 ? fmax(es * es, 0x1p-120) : 0.0;
         }
         __syncthreads();
         glo -= tol;
@@ -758,7 +828,7 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
             {
                 const double x[1] = {glo + width * (double)(t + 1) / (double)(NPROBE + 1)};
                 int c[1];
-                sturm_count_k<1, true>(vc, xv, n, x, sc, c);
+                sturm_count_scaled<1>(vc, xv, n, x, sc, c);
                 flag[t] = c[0];
             }
             __syncthreads();
@@ -796,7 +866,7 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                         x[k] = lo + (hi - lo) * (double)(pi + 1) / (double)(P + 1);
                     }
                 }
-                sturm_count_k<KP, true>(vc, xv, n, x, sc, cnt);
+                sturm_count_scaled<KP>(vc, xv, n, x, sc, cnt);
 #pragma unroll
                 for (int k = 0; k < KP; ++k) {
                     const int u = base + t * KP + k;
