@@ -1029,6 +1029,13 @@ __global__ void __launch_bounds__(64 * SWV) sym_eig_small_kernel(const EigDesc* 
         const double pivmin = DBL_MIN * fmax(1.0, em);
         const double tol = 4.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
         const double sc = sturm_scale(tnorm);
+        // T prepared once for all probes (sturm_count_scaled): diagonal into rb (free
+        // now), squared off-diagonal scaled in place
+        if (lane < n) rb[lane] = dd[lane] * sc;
+        if (lane < n - 1) e2[lane] = fmax(e2[lane] * (sc * sc), 0x1p-120);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         glo -= tol;
         ghi += tol;
         const int nk = D.nkeep;
@@ -1040,13 +1047,34 @@ __global__ void __launch_bounds__(64 * SWV) sym_eig_small_kernel(const EigDesc* 
         const int P = nb > 0 && nb < 64 ? 64 / nb : 1;
         double* blo = vv;
         double* bhi = ww;
-        if (lane < nb) {
+        double width = ghi - glo;
+        if (nb > 1) {
+            // first round shared by all the eigenvalues (as in the register kernel): 64
+            // probes over the Gershgorin interval
+            {
+                const double x[1] = {glo + width * (double)(lane + 1) / 65.0};
+                int c[1];
+                sturm_count_scaled<1>(rb, e2, n, x, sc, c);
+                fl[lane] = c[0];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (lane < nb) {
+                const int target = bottom ? lane + 1 : n - lane;
+                int first = 64;
+                for (int pi = 63; pi >= 0; --pi)
+                    if (fl[pi] >= target) first = pi;
+                blo[lane] = first > 0 ? glo + width * (double)first / 65.0 : glo;
+                bhi[lane] = first < 64 ? glo + width * (double)(first + 1) / 65.0 : ghi;
+            }
+            width /= 65.0;
+        } else if (lane < nb) {
             blo[lane] = glo;
             bhi[lane] = ghi;
         }
         // Each round divides every interval by exactly P + 1 (see the register kernel).
-        const double width = ghi - glo;
-        int iters = 1;
+        int iters = nb > 1 ? 0 : 1;
         if (width > tol) iters = (int)ceil(log(width / tol) / log((double)(P + 1)));
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -1060,7 +1088,10 @@ __global__ void __launch_bounds__(64 * SWV) sym_eig_small_kernel(const EigDesc* 
                     const double x = lo + (hi - lo) * (double)(pi + 1) / (double)(P + 1);
                     // eigenvalue q from the top (from the bottom): x is above it iff at
                     // least n - q (q + 1) eigenvalues lie below x
-                    fl[u - base] = sturm_count(dd, e2, n, x, sc) >= (bottom ? q + 1 : n - q);
+                    const double xk[1] = {x};
+                    int c[1];
+                    sturm_count_scaled<1>(rb, e2, n, xk, sc, c);
+                    fl[u - base] = c[0] >= (bottom ? q + 1 : n - q);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
