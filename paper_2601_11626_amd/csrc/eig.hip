@@ -1151,11 +1151,22 @@ __global__ void __launch_bounds__(64 * SWV) sym_eig_small_kernel(const EigDesc* 
 // The kept sum is the trace minus the smallest eigenvalue (nkeep = n - 1), or the whole
 // trace (nkeep >= n).  Below the smallest diagonal entry, eliminating the border gives the
 // inertia of H - x I (Sylvester): d_i - x > 0 for every i, so x lies above an eigenvalue
-// iff the Schur complement c - x - sum_i z_i^2 / (d_i - x) is negative.  Bisection on its
-// sign over [min(d, c) - ||z||, min(d, c)] (Weyl) finds the smallest eigenvalue without a
+// iff the Schur complement phi(x) = c - x - sum_i z_i^2 / (d_i - x) is negative.  The
+// smallest eigenvalue is found in the Weyl bracket [min(d, c) - ||z||, min(d, c)] without a
 // reduction to tridiagonal form; when a deflated entry (z_i = 0) is the smallest, the
-// bracket closes on it.  One wavefront per problem, lane i holding entries i, i + 64, ...
-// (n1 <= 256), exact divisions, one wave sum per probe.
+// bracket closes on it.  The bracket is narrowed by the sign of phi as in bisection; the
+// probes come from a model that keeps the smallest pole exact: with p the smallest d_i
+// with z_i != 0 and R the sum of z_i^2 over the entries at p, phi = g - R / (p - x),
+// where g (the other terms) is decreasing and concave left of p.  Replacing g by its
+// tangent at the probe gives a quadratic in u = p - x with one positive root; since the
+// tangent lies above g, that root is never left of the eigenvalue.  The first probe sits
+// one tolerance below the bracket's top (which settles a deflated smallest entry at
+// once); a model step that does not halve the previous one gives way to the midpoint;
+// once a step falls below the tolerance the next probe lies one tolerance across, which
+// closes the bracket.  Plain bisection finishes if the capped loop has not.  The result
+// is the midpoint of a bracket of width at most the tolerance whose ends have the signs
+// bisection would have checked.  One wavefront per problem, lane i holding entries i,
+// i + 64, ... (n1 <= 256), two wave sums per probe (g and its derivative).
 // ---------------------------------------------------------------------------
 constexpr int AW = 4;  // waves per workgroup
 
@@ -1190,12 +1201,51 @@ __global__ void __launch_bounds__(64 * AW) arrow_eig_kernel(const EigDesc* __res
         dmin = fmin(-wave_max(-dmin), c);
         dmax = fmax(wave_max(dmax), c);
         const double zn = sqrt(wave_sum(zs));
+        // the smallest pole and its residue
+        double pl = INFINITY;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (z2[q] != 0.0) pl = fmin(pl, d[q]);
+        const double pole = -wave_max(-pl);
+        double rs = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (z2[q] != 0.0 && d[q] == pole) rs += z2[q];
+        const double res = wave_sum(rs);
         double hi = th, lo = tl;  // the kept sum
         if (D.nkeep < n1 + 1) {
             double bhi = dmin, blo = dmin - zn;
             const double tnorm = fmax(fabs(blo), fabs(dmax) + zn);
             const double tol = 4.0 * DBL_EPSILON * tnorm + 2.0 * DBL_MIN;
             blo -= tol;
+            double next = bhi - tol, prev = INFINITY;
+            for (int it = 0; it < 120 && bhi - blo > tol; ++it) {
+                double x = next;
+                if (!(x > blo && x < bhi)) x = 0.5 * (blo + bhi);
+                if (x <= blo || x >= bhi) break;  // no representable point inside
+                double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double inv = 1.0 / (d[q] - x);
+                    const double tq = z2[q] != 0.0 && d[q] != pole ? z2[q] * inv : 0.0;
+                    s1 += tq;
+                    s2 += tq * inv;
+                }
+                const double g = (c - x) - wave_sum(s1);
+                const double dg = -1.0 - wave_sum(s2);
+                const double u0 = pole - x;  // > 0: x lies below the bracket's top
+                const double phi = g - res / u0;
+                if (phi < 0.0) bhi = x;
+                else blo = x;
+                // root of g + dg (x' - x) = R / (p - x'), as A u^2 + B u - R = 0
+                const double A = -dg, B = g + dg * u0;
+                const double disc = sqrt(B * B + 4.0 * A * res);
+                const double u = B >= 0.0 ? 2.0 * res / (B + disc) : (disc - B) / (2.0 * A);
+                const double step = fabs(x - (pole - u));
+                next = step <= tol ? (phi < 0.0 ? x - tol : x + tol)
+                                   : (step <= 0.5 * prev ? pole - u : 0.5 * (blo + bhi));
+                prev = step;
+            }
             while (bhi - blo > tol) {
                 const double x = 0.5 * (blo + bhi);
                 if (x <= blo || x >= bhi) break;
