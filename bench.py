@@ -8,7 +8,8 @@ projections, core eigenvalues and plug-in errors.  Inputs are resident in HBM be
 the timed region.
 
 Also reported on the same GPU: the plain per-pair method (one cmsvd_merge_errors call
-per pair, serialised, no reuse across pairs), the roofline position of the dominant
+per pair, serialised, no reuse across pairs), the same per-pair math in library form
+(torch FP64 SVDs, for context), the roofline position of the dominant
 stage (timed with HIP events on the library's stream during the timed steps), the FP64
 CPU oracle timed on a bounded sample of the same pairs, and the deviation of the GPU
 results from the oracle on that sample.
@@ -707,6 +708,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--plain-pairs", type=int, default=48, help="0 skips the plain per-pair leg")
+    ap.add_argument("--library-pairs", type=int, default=16,
+                    help="pairs of the library-form context leg (torch FP64 SVDs); 0 skips it")
     ap.add_argument("--cpu-pairs", type=int, default=448, help="oracle sample size (about 17 s on 16 cores)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--groups", type=int, default=16)
@@ -835,6 +838,30 @@ def main():
                  "max_rel_diff_vs_batched": plain_dev}
         log(f"plain: {plain_rate:.1f} merges/s over {len(sample)} pairs")
 
+    # The same per-pair math in library form, for context: the anchor's truncation from
+    # torch's FP64 SVD, then the singular values of [U_r S_r, A_j] (rocSOLVER/rocBLAS).
+    library = None
+    if args.library_pairs > 0:
+        sample = rng.choice(npairs, size=min(args.library_pairs, npairs), replace=False)
+        torch.cuda.synchronize()
+        tl = time.perf_counter()
+        lib_err = []
+        for p in sample:
+            i, j = int(pairs[p, 0]), int(pairs[p, 1])
+            A = blocks[i].double()
+            B = blocks[j].double()
+            U, S, _ = torch.linalg.svd(A, full_matrices=False)
+            sv = torch.linalg.svdvals(torch.cat([U[:, :r] * S[:r], B], dim=1))
+            e2 = torch.sum(S * S) + torch.sum(B * B) - torch.sum(sv[:r] ** 2)
+            lib_err.append(torch.sqrt(torch.clamp(e2, min=0.0)))
+        lib_err = torch.stack(lib_err).cpu().numpy()
+        lib_rate = len(sample) / (time.perf_counter() - tl)
+        lib_dev = float(np.max(np.abs(lib_err - err_h[sample]) / np.maximum(err_h[sample], 1e-300)))
+        library = {"value": round(lib_rate, 3), "unit": "merges/s", "pairs": int(len(sample)),
+                   "kind": "torch FP64 per pair: svd of the anchor, svdvals of [U_r S_r, A_j]",
+                   "max_rel_diff_vs_batched": lib_dev}
+        log(f"library: {lib_rate:.1f} merges/s over {len(sample)} pairs")
+
     # dominant stage and its roofline position
     flops = {
         "projection": 2.0 * r * k * m * npairs * args.steps,
@@ -914,6 +941,7 @@ def main():
         },
         "plain": plain,
         "speedup_vs_plain": round(value / plain["value"], 2) if plain else None,
+        "library": library,
         "stages_ms_per_step": {n: round(stages[n][0] / args.steps, 3) for n in stages},
         "roofline": roof,
         "cpu_baseline": cpu,
