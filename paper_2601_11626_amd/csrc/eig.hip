@@ -1377,55 +1377,92 @@ __global__ void __launch_bounds__(ET) sym_vectors_kernel(const VecDesc* __restri
     for (int i = 0; i < n; ++i) tn = fmax(tn, fabs(D.d[i]) + (i > 0 ? fabs(D.e[i - 1]) : 0.0) + (i < n - 1 ? fabs(D.e[i]) : 0.0));
     const double tiny = DBL_EPSILON * fmax(tn, DBL_MIN);
 
-    // (1) independent inverse iteration, one thread per eigenvalue
+    // (1) independent inverse iteration, one thread per eigenvalue.  The LU factors of
+    // T - lam I (partial pivoting; L multipliers, diagonal, two superdiagonals, pivot
+    // flags) and the iterate live in the scratch fields 0..5; the sequential recurrences
+    // carry their running values in registers and load each step's operands one step
+    // ahead, so no step waits on its predecessor's store.
     for (int q = t; q < nk; q += ET) {
         const double lam = D.lam[q];
-        for (int i = 0; i < n; ++i) {
-            at(0, i, q) = i < n - 1 ? D.e[i] : 0.0;  // dl
-            at(1, i, q) = D.d[i] - lam;              // dd
-            at(2, i, q) = i < n - 1 ? D.e[i] : 0.0;  // du
-            at(3, i, q) = 0.0;                       // du2
-            at(5, i, q) = 0.0;                       // pivot flag
-            at(4, i, q) = 1.0 + 0.5 * hash_unit((unsigned)q, (unsigned)i);
-        }
-        // LU with partial pivoting of the tridiagonal T - lam I
+        // LU: row i is (dcur, ucur) after the earlier eliminations; row i + 1 starts as
+        // the original (d_{i+1} - lam, e_{i+1})
+        double dcur = D.d[0] - lam, ucur = n > 1 ? D.e[0] : 0.0;
+        double dn = n > 1 ? D.d[1] : 0.0, en = n > 1 ? D.e[0] : 0.0, un = n > 2 ? D.e[1] : 0.0;
         for (int i = 0; i < n - 1; ++i) {
-            double di = at(1, i, q), li = at(0, i, q);
-            if (fabs(di) >= fabs(li)) {
-                if (di == 0.0) { di = tiny; at(1, i, q) = di; }
-                const double fact = li / di;
+            const double li = en, dnext0 = dn - lam, unext0 = un;
+            if (i + 2 < n) {  // operands of the next step
+                dn = D.d[i + 2];
+                en = D.e[i + 1];
+                un = i + 3 < n ? D.e[i + 2] : 0.0;
+            }
+            double dnext = dnext0, unext = unext0;
+            if (fabs(dcur) >= fabs(li)) {
+                if (dcur == 0.0) dcur = tiny;
+                const double fact = li / dcur;
                 at(0, i, q) = fact;
-                at(1, i + 1, q) -= fact * at(2, i, q);
+                at(1, i, q) = dcur;
+                at(2, i, q) = ucur;
+                at(3, i, q) = 0.0;
+                at(5, i, q) = 0.0;
+                dnext -= fact * ucur;
             } else {
-                const double fact = di / li;
-                at(1, i, q) = li;
+                const double fact = dcur / li;
                 at(0, i, q) = fact;
-                const double temp = at(2, i, q);
-                at(2, i, q) = at(1, i + 1, q);
-                at(1, i + 1, q) = temp - fact * at(1, i + 1, q);
-                if (i < n - 2) {
-                    at(3, i, q) = at(2, i + 1, q);
-                    at(2, i + 1, q) = -fact * at(2, i + 1, q);
-                }
+                at(1, i, q) = li;
+                at(2, i, q) = dnext0;
+                at(3, i, q) = i < n - 2 ? unext0 : 0.0;
                 at(5, i, q) = 1.0;
+                dnext = ucur - fact * dnext0;
+                unext = -fact * unext0;
             }
+            dcur = dnext;
+            ucur = unext;
         }
-        if (at(1, n - 1, q) == 0.0) at(1, n - 1, q) = tiny;
+        if (dcur == 0.0) dcur = tiny;
+        at(1, n - 1, q) = dcur;
+        at(2, n - 1, q) = 0.0;
+        at(3, n - 1, q) = 0.0;
+        at(5, n - 1, q) = 0.0;
+        for (int i = 0; i < n; ++i) at(4, i, q) = 1.0 + 0.5 * hash_unit((unsigned)q, (unsigned)i);
         for (int it = 0; it < 3; ++it) {
-            // L solve
+            // L solve (row interchanges as recorded)
+            double xi = at(4, 0, q);
+            double xn = n > 1 ? at(4, 1, q) : 0.0, l = at(0, 0, q), pv = at(5, 0, q);
             for (int i = 0; i < n - 1; ++i) {
-                if (at(5, i, q) == 0.0) at(4, i + 1, q) -= at(0, i, q) * at(4, i, q);
-                else {
-                    const double temp = at(4, i, q);
-                    at(4, i, q) = at(4, i + 1, q);
-                    at(4, i + 1, q) = temp - at(0, i, q) * at(4, i, q);
+                const double xnext = xn, li = l, pi = pv;
+                if (i + 2 < n) xn = at(4, i + 2, q);
+                if (i + 1 < n - 1) {
+                    l = at(0, i + 1, q);
+                    pv = at(5, i + 1, q);
+                }
+                if (pi == 0.0) {
+                    at(4, i, q) = xi;
+                    xi = xnext - li * xi;
+                } else {
+                    at(4, i, q) = xnext;
+                    xi = xi - li * xnext;
                 }
             }
-            // U solve
-            at(4, n - 1, q) /= at(1, n - 1, q);
-            if (n > 1) at(4, n - 2, q) = (at(4, n - 2, q) - at(2, n - 2, q) * at(4, n - 1, q)) / at(1, n - 2, q);
-            for (int i = n - 3; i >= 0; --i)
-                at(4, i, q) = (at(4, i, q) - at(2, i, q) * at(4, i + 1, q) - at(3, i, q) * at(4, i + 2, q)) / at(1, i, q);
+            at(4, n - 1, q) = xi;
+            // U solve, backwards with x_{i+1}, x_{i+2} in registers
+            double x1 = at(4, n - 1, q) / at(1, n - 1, q), x2 = 0.0;
+            at(4, n - 1, q) = x1;
+            if (n > 1) {
+                double b = at(4, n - 2, q), dg = at(1, n - 2, q), u1 = at(2, n - 2, q), u2 = 0.0;
+                for (int i = n - 2; i >= 0; --i) {
+                    const double bi = b, di = dg, ui = u1, wi = u2;
+                    if (i > 0) {
+                        b = at(4, i - 1, q);
+                        dg = at(1, i - 1, q);
+                        u1 = at(2, i - 1, q);
+                        u2 = at(3, i - 1, q);
+                    }
+                    const double xv = (bi - ui * x1 - wi * x2) / di;
+                    at(4, i, q) = xv;
+                    x2 = x1;
+                    x1 = xv;
+                }
+            }
             double nrm = 0.0;
             for (int i = 0; i < n; ++i) nrm += at(4, i, q) * at(4, i, q);
             nrm = sqrt(nrm);
@@ -1439,15 +1476,20 @@ __global__ void __launch_bounds__(ET) sym_vectors_kernel(const VecDesc* __restri
     // products and updates keep 8 independent loads and partial sums in flight.
     for (int q = 0; q < nk; ++q) {
         for (int pass = 0; pass < 2; ++pass) {
-            for (int qq = t; qq < q; qq += ET) {
-                double sp[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                int i = 0;
-                for (; i + 8 <= n; i += 8) {
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) sp[u] = fma(at(4, i + u, qq), at(4, i + u, q), sp[u]);
+            // coefficients: eight lanes per earlier vector, each over every eighth row
+            for (int base = 0; base < q; base += ET / 8) {
+                const int qq = base + (t >> 3), part = t & 7;
+                double s0 = 0.0, s1 = 0.0;
+                if (qq < q) {
+                    int i = part;
+                    for (; i + 8 < n; i += 16) {
+                        s0 = fma(at(4, i, qq), at(4, i, q), s0);
+                        s1 = fma(at(4, i + 8, qq), at(4, i + 8, q), s1);
+                    }
+                    if (i < n) s0 = fma(at(4, i, qq), at(4, i, q), s0);
                 }
-                for (; i < n; ++i) sp[0] = fma(at(4, i, qq), at(4, i, q), sp[0]);
-                coef[qq] = ((sp[0] + sp[1]) + (sp[2] + sp[3])) + ((sp[4] + sp[5]) + (sp[6] + sp[7]));
+                const double sum = sum_lanes8(s0 + s1);
+                if (qq < q && part == 0) coef[qq] = sum;
             }
             __syncthreads();
             for (int i = t; i < n; i += ET) {

@@ -68,7 +68,7 @@ int sym_eig_nmax();
 
 // Inverse iteration on the tridiagonal (lam, d, e) for the nkeep top eigenvectors,
 // orthonormalised, then back-transformed by the stored Householder vectors.  Z is
-// n x nkeep column-major (ldz).  scratch: per problem 4 * n * nkeep doubles.
+// n x nkeep column-major (ldz).  scratch: per problem 6 * n * nkeep doubles.
 struct VecDesc {
     int n, nkeep;
     const double* lam;
