@@ -398,6 +398,40 @@ def test_one_column_candidates_as_views_and_block_array(cm):
     assert np.max(np.abs(e_g.cpu().numpy() - e_o) / np.maximum(e_o, 1e-6 * nrm)) <= 1e-9
 
 
+@pytest.mark.parametrize("r", [64, 129, 256])
+def test_one_column_wide_anchors(cm, r):
+    # Arrowhead cores with up to 256 anchor singular values (four entries per lane):
+    # anchors wider than r with repeated, graded and clustered spectra, candidates mostly
+    # inside the anchors' spans, across them, and tiny; all against the oracle.  (The
+    # stated relative bar needs the error well above the FP64 cancellation floor of the
+    # plug-in, about sqrt(n u) ||M||_F for a core of order n: a spectrum graded down to
+    # 1e-6 puts the r = 256 tail at 2e-6 ||M||_F, where two FP64 evaluations differ by
+    # about 1e-3 relative.)
+    rng = np.random.default_rng(41 + r)
+    m, w = 320, 290
+    Q = workloads.orthonormal(rng, m, w)
+    V = workloads.orthonormal(rng, w, w)
+    # repeated values in groups that end at every r tested (the kept subspace is unique)
+    bounds = [0, 32, 64, 129, 200, 256, w]
+    rep = np.concatenate([np.full(b - a, v) for a, b, v in zip(bounds, bounds[1:], [4.0, 3.0, 2.0, 1.0, 0.5, 0.25])])
+    spectra = [rep,
+               np.logspace(0, -2, w),                                   # graded
+               np.concatenate([1.0 + 1e-9 * np.arange(40), 0.5 * np.logspace(0, -3, w - 40)])]  # tight top cluster
+    anchors = [(Q * s) @ V.T for s in spectra]
+    cands = [Q[:, :40] @ rng.standard_normal((40, 1)) + 1e-4 * rng.standard_normal((m, 1)),
+             Q[:, r - 2:r + 2] @ rng.standard_normal((4, 1)),           # around the cut
+             rng.standard_normal((m, 1)),
+             1e-7 * rng.standard_normal((m, 1))]
+    blocks = anchors + cands
+    pairs = np.array([(a, 3 + j) for a in range(3) for j in range(4)], dtype=np.int32)
+    say(f"one-column candidates, anchors {m}x{w}, r={r}")
+    e_g, _ = cm.cmsvd_merge_errors(dev_tensors(blocks), pairs, r)
+    e_o, _ = oracle.merge_errors(blocks, pairs, r)
+    for (i, j), g, o in zip(pairs, e_g.cpu().numpy(), e_o):
+        nm = math.sqrt(float(np.sum(blocks[i] ** 2)) + float(np.sum(blocks[j] ** 2)))
+        assert_est(g, o, nm, f"pair {i},{j}")
+
+
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_candidates_as_consecutive_column_ranges(cm, dtype):
     # Thin candidates of ragged widths given as consecutive column ranges of one device
