@@ -530,6 +530,47 @@ __device__ __forceinline__ void tile_step_racc(double (&a)[16], int R, int C, co
     }
 }
 
+// The same step on a tile held in LDS (plane order: element s*4 + q of lane at
+// tp[(s*4 + q) * 64 + lane]), one of its four rows at a time, so that only four of its
+// elements occupy registers beside the resident tiles (more would spill those).
+__device__ __forceinline__ void tile_step_lds(double* tp, int lane, int R, int C, const double* __restrict__ vc,
+                                              const double* __restrict__ vp, const double* __restrict__ wp,
+                                              double* pww, int ly, int lx, double (&racc)[4]) {
+    const int gi0 = R * TILE + 4 * ly, gc0 = C * TILE + 4 * lx;
+    double vq[4], wq[4], cq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        vq[q] = vp[gc0 + q];
+        wq[q] = wp[gc0 + q];
+        cq[q] = vc[gc0 + q];
+    }
+    double cp[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        double a[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = tp[((4 * s + q) << 6) + lane];
+        const double vr = vp[gi0 + s], wr = wp[gi0 + s], cr = vc[gi0 + s];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double x = fma(-vr, wq[q], a[q]);
+            x = fma(-wr, vq[q], x);
+            a[q] = x;
+            racc[s] = fma(x, cq[q], racc[s]);
+            cp[q] = fma(x, cr, cp[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tp[((4 * s + q) << 6) + lane] = a[q];
+    }
+    if (R != C) {
+        const double s01 = add_swap32(cp[0], cp[1]);
+        const double s23 = add_swap32(cp[2], cp[3]);
+        double t = add_swap16(s01, s23);
+        t += dpp_move<0x128>(t);
+        if ((ly & 1) == 0) unsafeAtomicAdd(&pww[gc0 + (ly >> 2) + 2 * ((ly >> 1) & 1)], t);
+    }
+}
+
 __device__ __forceinline__ void flush_rows(int R, double (&racc)[4], double* pww, int ly, int lx) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -718,13 +759,8 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                         if (curR >= 0) flush_rows(curR, racc, pww, ly, lx);
                         curR = R;
                     }
-                    double* tp = lt + (size_t)lds_tile_index(R, C, c0, TL) * TILE_EL;
-                    double a[16];
-#pragma unroll
-                    for (int e = 0; e < 16; ++e) a[e] = tp[(e << 6) + lane];
-                    tile_step_racc(a, R, C, vc, vp, wp, pww, ly, lx, racc);
-#pragma unroll
-                    for (int e = 0; e < 16; ++e) tp[(e << 6) + lane] = a[e];
+                    tile_step_lds(lt + (size_t)lds_tile_index(R, C, c0, TL) * TILE_EL, lane, R, C, vc, vp, wp, pww, ly,
+                                  lx, racc);
                     if (++C > R) {
                         ++R;
                         C = cl;
