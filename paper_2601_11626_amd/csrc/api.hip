@@ -117,6 +117,8 @@ struct cmsvd_ctx {
     size_t rec_pin_cap = 0;
     char* rec = nullptr;        // their device copy
     size_t rec_cap = 0;
+    hipStream_t side = nullptr;  // uploads that overlap work on the handle's stream
+    hipEvent_t rec_ev = nullptr;
     // stage timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> marks[4];
@@ -924,76 +926,66 @@ struct RecLayout {
     PairRec* pairs(char* base) const { return reinterpret_cast<PairRec*>(base + b_a + b_c); }
 };
 
-// The records sit in h->rec_pin (layout lay): start[s] .. start[s+1] are the pairs of
-// anchor slot s, whose packed candidate columns lie in [smin[s], smax[s]).
-cmsvd_status eval_dense(cmsvd_ctx* h, const DenseEval& de, const RecLayout& lay, size_t ncand,
-                        const std::vector<size_t>& start, const std::vector<long>& smin,
-                        const std::vector<long>& smax, double* err, double* rel) {
-    const size_t total = start[(size_t)de.na];
-    if (total == 0) return CMSVD_OK;
+// One chunk [a0, a1) of anchor slots of a dense evaluation: its pairs are records
+// pos .. pos + nj of the grouped list, its packed candidate columns [cmin, cmax).
+struct DenseChunk {
+    int a0, a1;
+    size_t pos, nj;
+    long cmin, cmax;
+    int nslots;
+    double* C = nullptr;         // the chunk's products, (a1 - a0) r rows
+    EigDesc* ed = nullptr;       // its eigenproblem descriptors
+    double* eig_ws = nullptr;    // eigen kernel scratch
+};
+
+// Plans the chunk's workspace and launches its projection
+// C = [U_a0 .. U_a1-1]^T B[:, cmin:cmax) on the handle's stream.
+cmsvd_status dense_project(cmsvd_ctx* h, const DenseEval& de, int nmax, DenseChunk& ch) {
     const int r = de.r;
-    const CandRec* hc = lay.cands(h->rec_pin);
-    int kmax = 0;
-    for (size_t i = 0; i < ncand; ++i) kmax = std::max(kmax, hc[i].k);
-    const int nmax = r + kmax;
-    // the records live on the device for the whole call: one copy from pinned memory
-    cmsvd_status st0 = ensure(h, h->rec, h->rec_cap, lay.total);
-    if (st0 != CMSVD_OK) return st0;
-    HIPCHK(hipMemcpyAsync(h->rec, h->rec_pin, lay.total, hipMemcpyHostToDevice, h->stream));
-    const AnchorRec* dA = lay.anchors(h->rec);
-    const CandRec* dC = lay.cands(h->rec);
-    const PairRec* dP = lay.pairs(h->rec);
-    const size_t row_bytes = (size_t)de.ksum * r * 8;  // C rows of one anchor
-    const int achunk = (int)std::max<size_t>(1, ((size_t)8 << 30) / std::max<size_t>(row_bytes, 1));
-    for (int a0 = 0; a0 < de.na; a0 += achunk) {
-        const int a1 = std::min(de.na, a0 + achunk);
-        const size_t pos = start[(size_t)a0], end = start[(size_t)a1];
-        if (end == pos) continue;
-        const size_t nj = end - pos;
-        const int nslots = (int)std::min<size_t>(nj, (size_t)h->ncu);
-        const long ldc = (long)(a1 - a0) * r;
-        // the packed candidate columns this chunk's pairs use
-        long cmin = de.ksum, cmax = 0;
-        for (int a = a0; a < a1; ++a) {
-            cmin = std::min(cmin, smin[(size_t)a]);
-            cmax = std::max(cmax, smax[(size_t)a]);
-        }
-        Plan pl;
-        const size_t c_off = pl.add((size_t)ldc * (cmax - cmin) * 8);
-        const size_t d_off = pl.add(nj * sizeof(EigDesc));
-        const size_t eig_off = pl.add(sym_eig_workspace_doubles(nmax, nslots) * 8);
-        cmsvd_status st = ensure(h, h->ws, h->ws_cap, pl.off);
-        if (st != CMSVD_OK) return st;
-        double* C = reinterpret_cast<double*>(h->ws + c_off);
-        EigDesc* ed = reinterpret_cast<EigDesc*>(h->ws + d_off);
-        GemmGroup g;
-        g.tb = true;
-        g.bf32 = de.ball_f32;
-        g.bf16 = proj_passes(h);
-        const char* Bc = static_cast<const char*>(de.Ball) + (size_t)cmin * (de.ball_f32 ? 4 : 8);
-        g.push(GemmDesc{de.Uall + (size_t)a0 * r, Bc, C, (int)ldc, (int)(cmax - cmin), de.m, (long)de.na * r,
-                        de.ldb, ldc});
-        Stage stg;
-        g.off = stg.add(g.d);
-        char* db = nullptr;
-        st = upload(h, stg, &db);
-        if (st != CMSVD_OK) return st;
-        {
-            StageMark mark(h, ST_PROJ);
-            run_gemm(h, g, db);
-        }
-        expand_dense_descs(dP + pos, (int)nj, dA, dC, r, a0, C, ldc, cmin, err, rel, ed, h->stream);
-        {
-            StageMark mark(h, ST_CORE);
-            if (kmax == 1 && r <= 256)  // one-column candidates: arrowhead cores
-                arrow_eig_batched(ed, (int)nj, h->stream);
-            else
-                sym_eig_batched(ed, (int)nj, nmax, 0, reinterpret_cast<double*>(h->ws + eig_off), nslots, h->stream);
-        }
-        HIPCHK(hipGetLastError());
+    const long ldc = (long)(ch.a1 - ch.a0) * r;
+    Plan pl;
+    const size_t c_off = pl.add((size_t)ldc * (ch.cmax - ch.cmin) * 8);
+    const size_t d_off = pl.add(ch.nj * sizeof(EigDesc));
+    const size_t eig_off = pl.add(sym_eig_workspace_doubles(nmax, ch.nslots) * 8);
+    cmsvd_status st = ensure(h, h->ws, h->ws_cap, pl.off);
+    if (st != CMSVD_OK) return st;
+    ch.C = reinterpret_cast<double*>(h->ws + c_off);
+    ch.ed = reinterpret_cast<EigDesc*>(h->ws + d_off);
+    ch.eig_ws = reinterpret_cast<double*>(h->ws + eig_off);
+    GemmGroup g;
+    g.tb = true;
+    g.bf32 = de.ball_f32;
+    g.bf16 = proj_passes(h);
+    const char* Bc = static_cast<const char*>(de.Ball) + (size_t)ch.cmin * (de.ball_f32 ? 4 : 8);
+    g.push(GemmDesc{de.Uall + (size_t)ch.a0 * r, Bc, ch.C, (int)ldc, (int)(ch.cmax - ch.cmin), de.m, (long)de.na * r,
+                    de.ldb, ldc});
+    Stage stg;
+    g.off = stg.add(g.d);
+    char* db = nullptr;
+    st = upload(h, stg, &db);
+    if (st != CMSVD_OK) return st;
+    {
+        StageMark mark(h, ST_PROJ);
+        run_gemm(h, g, db);
     }
-    // the staged records are rewritten by the next call
-    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipGetLastError());
+    return CMSVD_OK;
+}
+
+// Expands the chunk's pair records (on the device) into eigenproblem descriptors next to
+// its products and evaluates the cores; arrow: one-column candidates (arrowhead cores).
+cmsvd_status dense_cores(cmsvd_ctx* h, const DenseEval& de, int nmax, bool arrow, const DenseChunk& ch,
+                         const AnchorRec* dA, const CandRec* dC, const PairRec* dP, double* err, double* rel) {
+    const long ldc = (long)(ch.a1 - ch.a0) * de.r;
+    expand_dense_descs(dP + ch.pos, (int)ch.nj, dA, dC, de.r, ch.a0, ch.C, ldc, ch.cmin, err, rel, ch.ed, h->stream);
+    {
+        StageMark mark(h, ST_CORE);
+        if (arrow)
+            arrow_eig_batched(ch.ed, (int)ch.nj, h->stream);
+        else
+            sym_eig_batched(ch.ed, (int)ch.nj, nmax, 0, ch.eig_ws, ch.nslots, h->stream);
+    }
+    HIPCHK(hipGetLastError());
     return CMSVD_OK;
 }
 
@@ -1788,9 +1780,13 @@ cmsvd_status cmsvd_create(cmsvd_handle* handle, void* hip_stream) try {
         return fail(CMSVD_EUNSUPPORTED, "device %s is not gfx950", prop.gcnArchName);
     }
     h->ncu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-    if (hipEventCreateWithFlags(&h->pin_ev, hipEventDisableTiming) != hipSuccess) {
+    if (hipEventCreateWithFlags(&h->pin_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->rec_ev, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) {
+        if (h->pin_ev) (void)hipEventDestroy(h->pin_ev);
+        if (h->rec_ev) (void)hipEventDestroy(h->rec_ev);
         delete h;
-        return fail(CMSVD_EHIP, "hipEventCreate failed");
+        return fail(CMSVD_EHIP, "hipEventCreate / hipStreamCreate failed");
     }
     *handle = h;
     return CMSVD_OK;
@@ -1808,6 +1804,11 @@ cmsvd_status cmsvd_destroy(cmsvd_handle h) try {
     if (h->rec_pin) (void)hipHostFree(h->rec_pin);
     if (h->pin) (void)hipHostFree(h->pin);
     if (h->pin_ev) (void)hipEventDestroy(h->pin_ev);
+    if (h->side) {
+        (void)hipStreamSynchronize(h->side);
+        (void)hipStreamDestroy(h->side);
+    }
+    if (h->rec_ev) (void)hipEventDestroy(h->rec_ev);
     for (auto& v : h->marks)
         for (auto& pr : v) {
             (void)hipEventDestroy(pr.first);
@@ -2155,9 +2156,22 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
         HIPCHK(hipGetLastError());
     }
     if (dense) {
+        const size_t na = anchors.size();
+        const int nmax = (int)r + kmax_c;
+        const bool arrow = kmax_c == 1 && r <= 256;
+        DenseEval de{K(o_Uall), (int)na, (int)r, (int)m, in_place ? ball_user : keep.p + o_Ball, all_f32, ksum, ldball};
+        // chunks of anchors bound the products to about 8 GiB; with one chunk (every
+        // candidate column in use) the product needs no pair record, so it runs while the
+        // records are built and uploaded
+        const size_t achunk = std::max<size_t>(1, ((size_t)8 << 30) / std::max<size_t>((size_t)ksum * r * 8, 1));
+        DenseChunk whole{0, (int)na, 0, (size_t)npairs, 0, ksum, (int)std::min<int64_t>(npairs, h->ncu)};
+        const bool early = na <= achunk;
+        if (early) {
+            st = dense_project(h, de, nmax, whole);
+            if (st != CMSVD_OK) return st;
+        }
         // anchor and candidate tables and the pair records, grouped by anchor slot
         // (counting sort, stable), written once into pinned memory
-        const size_t na = anchors.size();
         const RecLayout lay(na, (size_t)nblocks, (size_t)npairs);
         st = ensure_rec_pin(h, lay.total);
         if (st != CMSVD_OK) return st;
@@ -2197,8 +2211,31 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
                 smin[a] = std::min(smin[a], tmin[t][a]);
                 smax[a] = std::max(smax[a], tmax[t][a]);
             }
-        DenseEval de{K(o_Uall), (int)na, (int)r, (int)m, in_place ? ball_user : keep.p + o_Ball, all_f32, ksum, ldball};
-        st = eval_dense(h, de, lay, (size_t)nblocks, start, smin, smax, err, rel);
+        // one upload on the side stream; the handle's stream waits for it before expanding
+        st = ensure(h, h->rec, h->rec_cap, lay.total);
+        if (st != CMSVD_OK) return st;
+        HIPCHK(hipMemcpyAsync(h->rec, h->rec_pin, lay.total, hipMemcpyHostToDevice, h->side));
+        HIPCHK(hipEventRecord(h->rec_ev, h->side));
+        HIPCHK(hipStreamWaitEvent(h->stream, h->rec_ev, 0));
+        const AnchorRec* dA = lay.anchors(h->rec);
+        const CandRec* dC = lay.cands(h->rec);
+        const PairRec* dP = lay.pairs(h->rec);
+        if (early) {
+            st = dense_cores(h, de, nmax, arrow, whole, dA, dC, dP, err, rel);
+        } else {
+            for (size_t a0 = 0; a0 < na && st == CMSVD_OK; a0 += achunk) {
+                const size_t a1 = std::min(na, a0 + achunk);
+                if (start[a1] == start[a0]) continue;
+                DenseChunk ch{(int)a0, (int)a1, start[a0], start[a1] - start[a0], ksum, 0, 0};
+                ch.nslots = (int)std::min<size_t>(ch.nj, (size_t)h->ncu);
+                for (size_t a = a0; a < a1; ++a) {
+                    ch.cmin = std::min(ch.cmin, smin[a]);
+                    ch.cmax = std::max(ch.cmax, smax[a]);
+                }
+                st = dense_project(h, de, nmax, ch);
+                if (st == CMSVD_OK) st = dense_cores(h, de, nmax, arrow, ch, dA, dC, dP, err, rel);
+            }
+        }
     } else {
         std::vector<EvalJob> ej;
         ej.reserve((size_t)npairs);
