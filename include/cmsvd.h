@@ -24,7 +24,9 @@
  *     acc[4] = {E_tot hi, E_tot lo, D hi, D lo}: the block energy sum_i ||A_i||_F^2
  *     and the energy discarded by truncation, each as a double-double.
  *   - The caller owns every input and output buffer; the handle owns only its
- *     workspace (grown on demand with hipMalloc, freed by cmsvd_destroy).
+ *     workspace (grown on demand with hipMalloc, freed by cmsvd_destroy), pinned
+ *     staging buffers and one internal stream for uploads (default priority), whose
+ *     work is ordered by an event before any dependent work on the handle's stream.
  *   - All calls are ordered on the handle's HIP stream.  cmsvd_update and
  *     cmsvd_merge_errors return once their work is enqueued (the host may block
  *     briefly while descriptor tables are uploaded); results are valid after a
