@@ -1512,20 +1512,15 @@ __global__ void __launch_bounds__(ET) sym_vectors_kernel(const VecDesc* __restri
     // products and updates keep 8 independent loads and partial sums in flight.
     for (int q = 0; q < nk; ++q) {
         for (int pass = 0; pass < 2; ++pass) {
-            // coefficients: eight lanes per earlier vector, each over every eighth row
-            for (int base = 0; base < q; base += ET / 8) {
-                const int qq = base + (t >> 3), part = t & 7;
-                double s0 = 0.0, s1 = 0.0;
-                if (qq < q) {
-                    int i = part;
-                    for (; i + 8 < n; i += 16) {
-                        s0 = fma(at(4, i, qq), at(4, i, q), s0);
-                        s1 = fma(at(4, i + 8, qq), at(4, i + 8, q), s1);
-                    }
-                    if (i < n) s0 = fma(at(4, i, qq), at(4, i, q), s0);
+            for (int qq = t; qq < q; qq += ET) {
+                double sp[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                int i = 0;
+                for (; i + 8 <= n; i += 8) {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) sp[u] = fma(at(4, i + u, qq), at(4, i + u, q), sp[u]);
                 }
-                const double sum = sum_lanes8(s0 + s1);
-                if (qq < q && part == 0) coef[qq] = sum;
+                for (; i < n; ++i) sp[0] = fma(at(4, i, qq), at(4, i, q), sp[0]);
+                coef[qq] = ((sp[0] + sp[1]) + (sp[2] + sp[3])) + ((sp[4] + sp[5]) + (sp[6] + sp[7]));
             }
             __syncthreads();
             for (int i = t; i < n; i += ET) {
