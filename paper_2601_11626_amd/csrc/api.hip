@@ -846,7 +846,7 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
         {
             StageMark mark(h, ST_CORE);
             if (kmax == 1 && rmax <= 256)  // one-column candidates: arrowhead cores
-                arrow_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), (int)nj, h->stream);
+                arrow_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), (int)nj, rmax, h->stream);
             else
                 sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), (int)nj, nmax, 0,
                                 reinterpret_cast<double*>(W + eig_off), nslots, h->stream);
@@ -981,7 +981,7 @@ cmsvd_status dense_cores(cmsvd_ctx* h, const DenseEval& de, int nmax, bool arrow
     {
         StageMark mark(h, ST_CORE);
         if (arrow)
-            arrow_eig_batched(ch.ed, (int)ch.nj, h->stream);
+            arrow_eig_batched(ch.ed, (int)ch.nj, de.r, h->stream);
         else
             sym_eig_batched(ch.ed, (int)ch.nj, nmax, 0, ch.eig_ws, ch.nslots, h->stream);
     }

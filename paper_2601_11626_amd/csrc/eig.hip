@@ -1317,8 +1317,128 @@ __global__ void __launch_bounds__(64 * AW) arrow_eig_kernel(const EigDesc* __res
     }
 }
 
-void arrow_eig_batched(const EigDesc* d_descs, int count, hipStream_t s) {
+// Sums and maxima over each 32-lane half of the wavefront (every lane of the half gets it).
+__device__ __forceinline__ double half_sum(double v) {
+    v = sum_lanes8(v);
+    v += dpp_move<0x128>(v);
+    return add_swap16(v);
+}
+__device__ __forceinline__ double half_max(double v) {
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) v = fmax(v, shfl_xor_d(v, o));
+    return v;
+}
+
+// The same evaluation for n1 <= 32, two problems per wavefront: lanes 0-31 hold one
+// problem's entries (one each), lanes 32-63 the next problem's.  Every quantity above
+// is formed per half, each half keeps its own bracket, and the probe loop runs until
+// both halves have closed theirs (a finished half computes along and discards).
+__global__ void __launch_bounds__(64 * AW) arrow_eig_pair_kernel(const EigDesc* __restrict__ descs, int count) {
+    const int lane = threadIdx.x & 63, hl = lane & 31;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (int pp = blockIdx.x * AW + wv; 2 * pp < count; pp += gridDim.x * AW) {
+        const int prob = 2 * pp + (lane >> 5);
+        const bool active = prob < count;
+        EigDesc D{};
+        if (active) D = descs[prob];
+        const int n1 = active ? D.n1 : 0;
+        const double c = active ? D.Y[0] : 0.0;
+        double d = INFINITY, z2 = 0.0;
+        double th = 0.0, tl = 0.0, dmin = INFINITY, dmax = -INFINITY, zs = 0.0;
+        if (hl < n1) {
+            const double si = D.s[hl], zi = si * D.P[hl];
+            d = si * si;
+            z2 = zi * zi;
+            dd_add(th, tl, d);
+            dmin = d;
+            dmax = d;
+            zs = z2;
+        }
+        th = half_sum(th);
+        tl = half_sum(tl);
+        dd_add(th, tl, c);
+        dmin = fmin(-half_max(-dmin), c);
+        dmax = fmax(half_max(dmax), c);
+        const double zn = sqrt(half_sum(zs));
+        const double pole = -half_max(-(z2 != 0.0 ? d : INFINITY));
+        const double res = half_sum(z2 != 0.0 && d == pole ? z2 : 0.0);
+        double hi = th, lo = tl;  // the kept sum
+        const bool solve = active && D.nkeep < n1 + 1;
+        double bhi = dmin, blo = dmin - zn;
+        const double tnorm = fmax(fabs(blo), fabs(dmax) + zn);
+        const double tol = 4.0 * DBL_EPSILON * tnorm + 2.0 * DBL_MIN;
+        blo -= tol;
+        double next = bhi - tol, prev = INFINITY;
+        bool run = solve && bhi - blo > tol;
+        for (int it = 0; it < 120; ++it) {
+            double x = next;
+            if (!(x > blo && x < bhi)) x = 0.5 * (blo + bhi);
+            if (x <= blo || x >= bhi) run = false;  // no representable point inside
+            if (!__any(run)) break;
+            const double inv = 1.0 / (d - x);
+            const double tq = z2 != 0.0 && d != pole ? z2 * inv : 0.0;
+            const double g = (c - x) - half_sum(tq);
+            const double dg = -1.0 - half_sum(tq * inv);
+            if (run) {
+                const double u0 = pole - x;
+                const double phi = g - res / u0;
+                if (phi < 0.0) bhi = x;
+                else blo = x;
+                const double A = -dg, B = g + dg * u0;
+                const double disc = sqrt(B * B + 4.0 * A * res);
+                const double u = B >= 0.0 ? 2.0 * res / (B + disc) : (disc - B) / (2.0 * A);
+                const double step = fabs(x - (pole - u));
+                next = step <= tol ? (phi < 0.0 ? x - tol : x + tol)
+                                   : (step <= 0.5 * prev ? pole - u : 0.5 * (blo + bhi));
+                prev = step;
+                run = bhi - blo > tol;
+            }
+        }
+        run = solve && bhi - blo > tol;
+        for (;;) {
+            const double x = 0.5 * (blo + bhi);
+            if (x <= blo || x >= bhi) run = false;
+            if (!__any(run)) break;
+            const double sch = (c - x) - half_sum(z2 != 0.0 ? z2 / (d - x) : 0.0);
+            if (run) {
+                if (sch < 0.0) bhi = x;
+                else blo = x;
+                run = bhi - blo > tol;
+            }
+        }
+        if (solve) {
+            const double lmin = 0.5 * (blo + bhi);
+            double s2, e2;
+            two_sum(hi, -lmin, s2, e2);
+            e2 += lo;
+            two_sum(s2, e2, hi, lo);
+        }
+        if (active && hl == 0) {
+            double eh = D.na[0], el = D.na[1];
+            if (D.nb) {
+                dd_add(eh, el, D.nb[0]);
+                el += D.nb[1];
+            }
+            double s2, e2;
+            two_sum(eh, -hi, s2, e2);
+            double tail = s2 + (e2 + el - lo);
+            if (tail < 0.0) tail = 0.0;  // clamp rounding below zero; NaN propagates
+            const double err = sqrt(tail);
+            const double etot = eh + el;
+            *D.out_err = err;
+            if (D.out_rel) *D.out_rel = etot != 0.0 ? err / sqrt(etot) : 0.0;
+        }
+    }
+}
+
+void arrow_eig_batched(const EigDesc* d_descs, int count, int n1max, hipStream_t s) {
     if (count <= 0) return;
+    if (n1max <= 32) {
+        const int pairs = (count + 1) / 2;
+        const int g = (pairs + AW - 1) / AW;
+        hipLaunchKernelGGL(arrow_eig_pair_kernel, dim3(g < 16384 ? g : 16384), dim3(64 * AW), 0, s, d_descs, count);
+        return;
+    }
     const int g = (count + AW - 1) / AW;
     hipLaunchKernelGGL(arrow_eig_kernel, dim3(g < 16384 ? g : 16384), dim3(64 * AW), 0, s, d_descs, count);
 }

@@ -62,7 +62,8 @@ size_t sym_eig_workspace_doubles(int nmax, int nslots);
 // Evaluation mode for cores of one appended column (every descriptor n = n1 + 1 with
 // n1 <= 256 and nkeep >= n1): the arrowhead's smallest eigenvalue by bisection on the
 // inertia after eliminating the border; writes out_err / out_rel as mode 0 does.
-void arrow_eig_batched(const EigDesc* d_descs, int count, hipStream_t s);
+// n1max: the largest n1 of the batch (at most 32: two problems per wavefront).
+void arrow_eig_batched(const EigDesc* d_descs, int count, int n1max, hipStream_t s);
 // Largest order the eigenvalue (and eigenvector) kernels accept (2016 on gfx950).
 int sym_eig_nmax();
 
