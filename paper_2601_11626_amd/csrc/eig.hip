@@ -974,7 +974,9 @@ constexpr int SN = 64;
 constexpr int SWV = 4;
 constexpr int S_LDS = 7 * SN + 8;
 
-template <int MODE>
+// SNT: the width of each lane's row in registers (the largest order served); the LDS
+// vectors keep 64 entries, one per lane.
+template <int MODE, int SNT>
 __global__ void __launch_bounds__(64 * SWV) sym_eig_small_kernel(const EigDesc* __restrict__ descs, int count) {
     __shared__ double sh[SWV][S_LDS];
     const int lane = threadIdx.x & 63;
@@ -990,14 +992,14 @@ __global__ void __launch_bounds__(64 * SWV) sym_eig_small_kernel(const EigDesc* 
     for (int prob = blockIdx.x * SWV + wv; prob < count; prob += gridDim.x * SWV) {
         const EigDesc D = descs[prob];
         const int n = D.n;
-        double a[SN];
+        double a[SNT];
 #pragma unroll
-        for (int c = 0; c < SN; ++c) a[c] = (lane < n && c < n) ? hval(D, lane, c) : 0.0;
+        for (int c = 0; c < SNT; ++c) a[c] = (lane < n && c < n) ? hval(D, lane, c) : 0.0;
         for (int j = 0; j + 1 < n; ++j) {
             // column j of A = row j: lane j publishes its row
             if (lane == j) {
 #pragma unroll
-                for (int c = 0; c < SN; ++c) rb[c] = a[c];
+                for (int c = 0; c < SNT; ++c) rb[c] = a[c];
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -1026,7 +1028,7 @@ __global__ void __launch_bounds__(64 * SWV) sym_eig_small_kernel(const EigDesc* 
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             double acc = 0.0;
 #pragma unroll
-            for (int c = 0; c < SN; ++c) acc = fma(a[c], vv[c], acc);  // a, v vanish beyond n
+            for (int c = 0; c < SNT; ++c) acc = fma(a[c], vv[c], acc);  // a, v vanish beyond n
             const double pi = tau * acc;
             const double K = -0.5 * tau * wave_sum(pi * vi);
             const double wi = pi + K * vi;
@@ -1035,12 +1037,12 @@ __global__ void __launch_bounds__(64 * SWV) sym_eig_small_kernel(const EigDesc* 
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-            for (int c = 0; c < SN; ++c) a[c] = fma(-vi, ww[c], fma(-wi, vv[c], a[c]));
+            for (int c = 0; c < SNT; ++c) a[c] = fma(-vi, ww[c], fma(-wi, vv[c], a[c]));
             __builtin_amdgcn_wave_barrier();
         }
         if (lane == n - 1) {
 #pragma unroll
-            for (int c = 0; c < SN; ++c) rb[c] = a[c];
+            for (int c = 0; c < SNT; ++c) rb[c] = a[c];
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -1460,8 +1462,14 @@ void sym_eig_batched(const EigDesc* d_descs, int count, int nmax, int mode, doub
     if (nmax <= SN) {
         int grid = (count + SWV - 1) / SWV;
         if (grid > 16384) grid = 16384;
-        if (mode == 0) hipLaunchKernelGGL(sym_eig_small_kernel<0>, dim3(grid), dim3(64 * SWV), 0, s, d_descs, count);
-        else hipLaunchKernelGGL(sym_eig_small_kernel<1>, dim3(grid), dim3(64 * SWV), 0, s, d_descs, count);
+        // orders up to 48: shorter rows in registers, so more wavefronts per SIMD
+        if (nmax <= 48) {
+            if (mode == 0) hipLaunchKernelGGL((sym_eig_small_kernel<0, 48>), dim3(grid), dim3(64 * SWV), 0, s, d_descs, count);
+            else hipLaunchKernelGGL((sym_eig_small_kernel<1, 48>), dim3(grid), dim3(64 * SWV), 0, s, d_descs, count);
+        } else {
+            if (mode == 0) hipLaunchKernelGGL((sym_eig_small_kernel<0, SN>), dim3(grid), dim3(64 * SWV), 0, s, d_descs, count);
+            else hipLaunchKernelGGL((sym_eig_small_kernel<1, SN>), dim3(grid), dim3(64 * SWV), 0, s, d_descs, count);
+        }
         return;
     }
     if (T <= THIN_TMAX) {
