@@ -52,7 +52,7 @@ def assert_est(e_gpu, e_ref, norm_m, what=""):
     assert abs(e_gpu ** 2 - e_ref ** 2) <= 1e-9 * e_ref ** 2 + 1e-12 * norm_m ** 2, (what, e_gpu, e_ref, norm_m)
 
 
-@pytest.mark.parametrize("n", [1, 2, 5, 31, 32, 33, 40, 64, 100, 161, 200, 320, 353])
+@pytest.mark.parametrize("n", [1, 2, 5, 31, 32, 33, 40, 48, 49, 64, 100, 161, 200, 320, 353])
 def test_sym_eigvals_against_oracle_svd(cm, n):
     say(f"sym_eigvals n={n}")
     rng = np.random.default_rng(n)
@@ -396,6 +396,21 @@ def test_one_column_candidates_as_views_and_block_array(cm):
     nrm = np.array([math.sqrt(float(np.sum(np.asarray(blocks[i], np.float64) ** 2)) +
                               float(np.sum(np.asarray(blocks[j], np.float64) ** 2))) for i, j in pairs])
     assert np.max(np.abs(e_g.cpu().numpy() - e_o) / np.maximum(e_o, 1e-6 * nrm)) <= 1e-9
+
+
+def test_single_one_column_pair(cm):
+    # One pair of a one-column candidate at r <= 32: the arrowhead kernel that pairs
+    # problems per wavefront runs with one half idle.
+    rng = np.random.default_rng(43)
+    m = 64
+    Q = workloads.orthonormal(rng, m, 12)
+    blocks = [Q @ rng.standard_normal((12, 10)) + 0.01 * rng.standard_normal((m, 10)),
+              Q[:, :6] @ rng.standard_normal((6, 1)) + 0.01 * rng.standard_normal((m, 1))]
+    say("single one-column pair, r=6")
+    e_g, _ = cm.cmsvd_merge_errors(dev_tensors(blocks), [(0, 1)], 6)
+    e_o, _ = oracle.merge_errors(blocks, np.array([[0, 1]], np.int32), 6)
+    nm = math.sqrt(sum(float(np.sum(b ** 2)) for b in blocks))
+    assert_est(e_g.cpu().numpy()[0], e_o[0], nm, "pair 0,1")
 
 
 @pytest.mark.parametrize("r", [64, 129, 256])
