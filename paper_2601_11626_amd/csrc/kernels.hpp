@@ -60,9 +60,10 @@ void sym_eig_batched(const EigDesc* d_descs, int count, int nmax, int mode, doub
                      hipStream_t s);
 size_t sym_eig_workspace_doubles(int nmax, int nslots);
 // Evaluation mode for cores of one appended column (every descriptor n = n1 + 1 with
-// n1 <= 256 and nkeep >= n1): the arrowhead's smallest eigenvalue by bisection on the
-// inertia after eliminating the border; writes out_err / out_rel as mode 0 does.
-// n1max: the largest n1 of the batch (at most 32: two problems per wavefront).
+// n1 <= 256 and nkeep >= n1): the arrowhead's smallest eigenvalue, bracketed by the sign
+// of the Schur complement of the border (the inertia) with model-based probes; writes
+// out_err / out_rel as mode 0 does.  n1max: the largest n1 of the batch (at most 32:
+// two problems per wavefront).
 void arrow_eig_batched(const EigDesc* d_descs, int count, int n1max, hipStream_t s);
 // Largest order the eigenvalue (and eigenvector) kernels accept (2016 on gfx950).
 int sym_eig_nmax();
