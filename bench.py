@@ -748,8 +748,8 @@ def main():
         print(json.dumps(rec, indent=1))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "layout is a design note, not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding the pair "
+              "list across GPUs is described in the design notes but not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -71,7 +71,7 @@ typedef enum {
     CMSVD_ESHAPE = 2,      /* bad shapes (row counts differ, cols < 1, ld < cols, r > m, ...)  */
     CMSVD_ENOMEM = 3,      /* workspace allocation failed                                      */
     CMSVD_EHIP = 4,        /* a HIP runtime call failed                                        */
-    CMSVD_EUNSUPPORTED = 5 /* dtype or size not supported by this build                        */
+    CMSVD_EUNSUPPORTED = 5 /* dtype or size not supported by this library                      */
 } cmsvd_status;
 
 typedef struct {

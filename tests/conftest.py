@@ -13,8 +13,8 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # GPU tests are skipped (not failed) where no GPU is visible; the full test run
-    # selects them with -m gpu on a GPU machine.
+    # GPU tests are skipped (not failed) where no GPU is visible; on a machine with an
+    # MI355X they are selected with -m gpu.
     try:
         import torch
 
