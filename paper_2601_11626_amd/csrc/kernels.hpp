@@ -211,7 +211,7 @@ struct PackDesc {
     const void* src;
     int rows, cols;
     long lds;
-    int f32_in;
+    int f32_in;  // source dtype: 0 FP64, 1 FP32, 2 BF16
     void* dst;
     long ldd;
     int f32_out;

@@ -35,32 +35,47 @@ void assemble_kt_batched(const KtDesc* d_descs, int count, int nmax, hipStream_t
     }
 }
 
+// Numerically present directions: eigenvalue above the eigensolver's rounding level
+// (n eps ||S||); the others are stored as sigma = 0 with a zero basis column.
+__device__ __forceinline__ bool fin_keep(const FinDesc& D, int q, double cut) {
+    return q < D.nkeep && D.lam[q] > cut;
+}
+
 __global__ void __launch_bounds__(256) finalize_state_kernel(const FinDesc* __restrict__ descs) {
     const FinDesc D = descs[blockIdx.x];
-    __shared__ double sq[1024];
-    __shared__ int keep[1024];
+    __shared__ double red_h[256], red_l[256];
     const int t = threadIdx.x;
-    double lmax = 0.0;
-    for (int q = 0; q < D.nkeep; ++q) lmax = fmax(lmax, D.lam[q]);
-    // eigenvalues at the eigensolver's rounding level (n eps ||S||) are numerically zero
+    double lm = 0.0;
+    for (int q = t; q < D.nkeep; q += 256) lm = fmax(lm, D.lam[q]);
+    __shared__ double redm[4];
+    const double lmax = block_max(lm, redm);
     const double cut = (double)D.nc * 8.0 * 2.220446049250313e-16 * lmax;
+    // kept values and their energy, over every one of the r columns
+    double kh = 0.0, kl = 0.0;
     for (int q = t; q < D.r; q += 256) {
-        const double l = q < D.nkeep ? D.lam[q] : 0.0;
-        const int k = (q < D.nkeep && l > cut) ? 1 : 0;
-        const double sv = k ? sqrt(l) : 0.0;
+        const bool k = fin_keep(D, q, cut);
+        const double sv = k ? sqrt(D.lam[q]) : 0.0;
         D.s_out[q] = sv;
-        if (q < 1024) {
-            sq[q] = sv * sv;
-            keep[q] = k;
-        }
+        if (k) dd_add(kh, kl, sv * sv);
     }
-    __syncthreads();
     // zero the basis columns of dropped directions (row-major m x r)
     for (long e = t; e < (long)D.m * D.r; e += 256) {
         const int q = (int)(e % D.r);
         const long row = e / D.r;
-        const int k = q < 1024 ? keep[q] : (q < D.nkeep);
-        if (!k) D.U_out[row * D.ldu + q] = 0.0;
+        if (!fin_keep(D, q, cut)) D.U_out[row * D.ldu + q] = 0.0;
+    }
+    // double-double tree sum of the kept energy (fixed order: reproducible)
+    red_h[t] = kh;
+    red_l[t] = kl;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) {
+            double h = red_h[t], l = red_l[t];
+            dd_add(h, l, red_h[t + o]);
+            red_h[t] = h;
+            red_l[t] = l + red_l[t + o];
+        }
+        __syncthreads();
     }
     if (t == 0) {
         // energies (double-double)
@@ -83,11 +98,10 @@ __global__ void __launch_bounds__(256) finalize_state_kernel(const FinDesc* __re
         D.acc[2] = dh;
         D.acc[3] = dl;
         if (D.est) {
-            double kh = 0.0, kl = 0.0;
-            for (int q = 0; q < D.r && q < 1024; ++q) dd_add(kh, kl, sq[q]);
+            const double kth = red_h[0], ktl = red_l[0];
             double s, e;
-            two_sum(eh, -kh, s, e);
-            double tail = s + (e + el - kl);
+            two_sum(eh, -kth, s, e);
+            double tail = s + (e + el - ktl);
             D.est[0] = sqrt(tail < 0.0 ? 0.0 : tail);
             const double dtot = dh + dl;
             D.est[1] = sqrt(dtot < 0.0 ? 0.0 : dtot);
@@ -230,8 +244,11 @@ __global__ void __launch_bounds__(256) pack_kernel(const PackDesc* __restrict__ 
             r = e / D.cols;
             c = e - r * D.cols;
         }
-        const double v = D.f32_in ? (double)static_cast<const float*>(D.src)[r * D.lds + c]
-                                  : static_cast<const double*>(D.src)[r * D.lds + c];
+        double v;
+        if (D.f32_in == 1) v = (double)static_cast<const float*>(D.src)[r * D.lds + c];
+        else if (D.f32_in == 2)  // BF16: the high half of an FP32 word (exact widening)
+            v = (double)__uint_as_float((unsigned)static_cast<const unsigned short*>(D.src)[r * D.lds + c] << 16);
+        else v = static_cast<const double*>(D.src)[r * D.lds + c];
         if (D.f32_out) static_cast<float*>(D.dst)[r * D.ldd + c] = (float)v;
         else static_cast<double*>(D.dst)[r * D.ldd + c] = v;
     }
