@@ -37,6 +37,38 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+CPU_SHARE_PER_GPU = 16
+
+
+def host_cpus():
+    """The host cores the CPU oracle runs on: the process's affinity set, bounded by the
+    job's share of the host (the cgroup CPU quota when one is set, else the 16 host cores
+    that the GPU hosts give each GPU), with the machine's logical CPU count and model for
+    the record."""
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        affinity = os.cpu_count() or 1
+    quota = None
+    try:
+        q, per = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if q != "max":
+            quota = max(1, int(int(q) // int(per)))
+    except (OSError, ValueError):
+        pass
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    threads = min(affinity, quota if quota else CPU_SHARE_PER_GPU)
+    return {"threads": max(1, threads), "affinity": affinity, "cgroup_quota": quota,
+            "host_logical_cpus": os.cpu_count(), "model": model}
+
+
 def kernel_source_hash():
     import hashlib
 
@@ -238,7 +270,7 @@ def cluster(args, cm, workloads, torch):
         err, rel = cm.cmsvd_merge_errors(blocks, pairs[cs], r, handle=h)
         err = err.cpu().numpy()
         tc = time.perf_counter()
-        e_o, rel_o = oracle.merge_errors(blocks_np, pairs[cs], r, nthreads=max(1, min(16, len(os.sched_getaffinity(0)))))
+        e_o, rel_o = oracle.merge_errors(blocks_np, pairs[cs], r, nthreads=host_cpus()["threads"])
         ct = time.perf_counter() - tc
         dev_rel = np.abs(err - e_o) / e_o
         k = int(np.argmax(dev_rel))
@@ -558,7 +590,7 @@ def smallk_vectors(args, cm, workloads, torch):
         cs = rng.choice(len(pairs), size=min(args.cpu_pairs, len(pairs)), replace=False)
         sub = [anchors_np[a] for a in range(na)] + [cand_np[:, j - na:j - na + 1] for j in pairs[cs, 1]]
         sp = np.stack([pairs[cs, 0], na + np.arange(len(cs))], axis=1).astype(np.int32)
-        e_o, _ = oracle.merge_errors(sub, sp, r, nthreads=max(1, min(16, len(os.sched_getaffinity(0)))))
+        e_o, _ = oracle.merge_errors(sub, sp, r, nthreads=host_cpus()["threads"])
         dev_rel = np.abs(err_h[cs] - e_o) / e_o
         parity = {"pairs": int(len(cs)), "max_rel_dev": float(dev_rel.max())}
         log(f"parity {parity}")
@@ -622,7 +654,7 @@ def smallk(args, cm, workloads, torch):
 
         rng = np.random.default_rng(4)
         cs = rng.choice(len(pairs), size=min(args.cpu_pairs, len(pairs)), replace=False)
-        e_o, _ = oracle.merge_errors(blocks_np, pairs[cs], r, nthreads=max(1, min(16, len(os.sched_getaffinity(0)))))
+        e_o, _ = oracle.merge_errors(blocks_np, pairs[cs], r, nthreads=host_cpus()["threads"])
         nrm = np.array([math.sqrt(float(np.sum(blocks_np[i].astype(np.float64) ** 2)) +
                                   float(np.sum(blocks_np[j].astype(np.float64) ** 2))) for i, j in pairs[cs]])
         dev_rel = np.abs(err_h[cs] - e_o) / np.maximum(e_o, 1e-6 * nrm)
@@ -895,11 +927,8 @@ def main():
     if not args.no_cpu:
         import oracle
 
-        try:
-            ncores = len(os.sched_getaffinity(0))
-        except AttributeError:  # pragma: no cover
-            ncores = os.cpu_count() or 1
-        nthreads = max(1, min(16, ncores))
+        hc = host_cpus()
+        nthreads = hc["threads"]
         cs = rng.choice(npairs, size=min(args.cpu_pairs, npairs), replace=False)
         tc = time.perf_counter()
         e_o, rel_o = oracle.merge_errors(blocks_np, pairs[cs], r, nthreads=nthreads)
@@ -908,6 +937,7 @@ def main():
             "value": round(len(cs) / ct, 4),
             "unit": "merges/s",
             "cores": nthreads,
+            "host": hc,
             "kind": "oracle",
             "sample": f"{len(cs)} random anchor-first pairs of the same 256-block collection "
                       f"(each with its own anchor truncation), {ct:.1f}s wall",
