@@ -25,6 +25,9 @@ projection Y enters H directly, so the precision of Y is what the option changes
                      and lo = BF16(x32 - hi); Y = lo_U^T hi_B + hi_U^T lo_B + hi_U^T hi_B
                      (the lo_U^T lo_B term is dropped), summed in FP64 here and in FP32
                      on the device.
+  projection "f32":  every element of U and of B is rounded to FP32 (round-to-nearest-
+                     even) and Y is the FP64 sum of the (exact) products of the rounded
+                     values; the device sums them in FP32.
 
 B^T B, sigma, E_tot and the eigenvalues stay FP64.  The eigenvalues of the symmetric H
 are the singular values of H + c I minus c with c = ||H||_F (which makes H + c I
@@ -47,6 +50,11 @@ def round_bf16(x) -> np.ndarray:
     keep_odd = (bits >> 16) & 1
     rounded = ((bits + 0x7FFF + keep_odd) >> 16) << 16
     return rounded.astype(np.uint32).view(np.float32).astype(np.float64).reshape(np.shape(x))
+
+
+def round_f32(x) -> np.ndarray:
+    """Each element rounded to FP32 (round-to-nearest-even), returned as FP64."""
+    return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
 
 
 def split_bf16(x):
@@ -82,7 +90,9 @@ def projection(U, B, mode: str = "f64") -> np.ndarray:
         uh, ul = split_bf16(U)
         bh, bl = split_bf16(B)
         return ul.T @ bh + uh.T @ bl + uh.T @ bh
-    raise ValueError("projection must be 'f64', 'bf16' or 'bf16x3'")
+    if mode == "f32":
+        return round_f32(U).T @ round_f32(B)
+    raise ValueError("projection must be 'f64', 'bf16', 'bf16x3' or 'f32'")
 
 
 def candidate_estimate2(state, B, r: int, mode: str = "f64"):

@@ -22,6 +22,10 @@
   that its estimate deviates from the FP64 one by far less than the plain BF16 one.
 * Algorithm 3 with projection "f64" routed through the Gram form equals the default
   path; with "bf16" on well-separated data the partition is unchanged.
+* The FP32 projection: its rounding is numpy's own float32 conversion; on operands
+  that FP32 represents exactly (the Hadamard basis, small integers) it equals the FP64
+  estimate; and its deviation obeys the Ky Fan bound with u = 2^-24, far below the BF16
+  one on the same pairs.
 """
 import math
 
@@ -154,3 +158,50 @@ def test_split_projection_bound_and_gain(seed):
         e_1, _ = lowprec.candidate_estimate2(st, B, r, "bf16")
         e_3, _ = lowprec.candidate_estimate2(st, B, r, "bf16x3")
         assert abs(e_3 - e_f) <= 0.02 * abs(e_1 - e_f) + 1e-12 * st.etot
+
+
+def test_round_f32_is_the_library_conversion():
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal(20000) * np.exp(rng.uniform(-30, 30, 20000))
+    ref = torch.from_numpy(x).to(torch.float32).to(torch.float64).numpy()
+    assert np.array_equal(lowprec.round_f32(x), ref)
+    # a tie of the FP32 grid at 1 goes to the even neighbour
+    assert lowprec.round_f32(1 + 2.0 ** -24) == 1.0
+    assert lowprec.round_f32(1 + 3 * 2.0 ** -24) == 1 + 2.0 ** -22
+
+
+def test_f32_exact_on_representable_operands():
+    m, r = 64, 4
+    Hd = hadamard(m) / 8.0
+    s = np.array([3.1, 2.7, 1.3, 0.9, 0.45, 0.2])
+    rng = np.random.default_rng(2)
+    V = np.linalg.qr(rng.standard_normal((6, 6)))[0]
+    A = Hd[:, :6] @ np.diag(s) @ V.T
+    st = oracle.update(oracle.State(m), A, r)
+    B = rng.integers(-8, 9, size=(m, 5)).astype(np.float64)
+    st.U = np.round(st.U * 8) / 8  # the basis is the Hadamard columns up to sign
+    e_f, _ = lowprec.candidate_estimate2(st, B, r, "f64")
+    e_3, _ = lowprec.candidate_estimate2(st, B, r, "f32")
+    assert e_3 == e_f
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_f32_deviation_within_ky_fan_bound(seed):
+    blocks = workloads.latent_uneven(seed=seed, m=256, nblocks=6, latents=2, d=12, nmin=8, nmax=40, noise=1e-2)
+    r, m = 16, 256
+    u = 2.0 ** -24
+    for i, j in ((0, 2), (1, 3), (0, 1)):
+        st = oracle.update(oracle.State(m), blocks[i], r)
+        B = np.asarray(blocks[j], dtype=np.float64)
+        e_f, _ = lowprec.candidate_estimate2(st, B, r, "f64")
+        e_3, _ = lowprec.candidate_estimate2(st, B, r, "f32")
+        e_b, _ = lowprec.candidate_estimate2(st, B, r, "bf16")
+        dY = (2 * u + u * u) * (np.abs(st.U).T @ np.abs(B))
+        k = B.shape[1]
+        rho = st.rho
+        E = np.zeros((rho + k, rho + k))
+        E[:rho, rho:] = st.sigma[:, None] * dY
+        E[rho:, :rho] = E[:rho, rho:].T
+        bound = float(np.sum(np.linalg.svd(E, compute_uv=False)[:r]))
+        assert abs(e_3 - e_f) <= bound * (1 + 1e-9) + 1e-12 * st.etot
+        assert abs(e_3 - e_f) <= 1e-3 * abs(e_b - e_f) + 1e-12 * st.etot
