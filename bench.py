@@ -31,6 +31,10 @@ if ROOT not in sys.path:
 
 METRIC = "candidate merges evaluated/sec (batched vs plain, same GPU) at ≤1e-5 rel error"
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 (vector and matrix), 256 CU x 2.4 GHz
+# dense matrix-core peaks of MI355X per projection operand type, and the kernel name
+PROJ_PEAK = {"f64": (78.6, "gemm_f64_kernel (Y = U^T B)"), "f32": (157.3, "gemm_f32_kernel (Y = U^T B)"),
+             "bf16": (2500.0, "gemm_bf16_kernel (Y = U^T B, one BF16 pass)"),
+             "bf16x3": (2500.0, "gemm_bf16_kernel (Y = U^T B, three BF16 passes)")}
 
 
 def log(msg):
@@ -285,7 +289,8 @@ def cluster(args, cm, workloads, torch):
         "n_gpus": 1,
         "higher_is_better": False,
         "dtype": {"f64": "f64", "bf16": "bf16 projections (fp32 accumulate), f64 core",
-                  "bf16x3": "split bf16 projections (fp32 accumulate), f64 core"}[args.projection],
+                  "bf16x3": "split bf16 projections (fp32 accumulate), f64 core",
+                  "f32": "fp32 projections (fp32 accumulate), f64 core"}[args.projection],
         "data": "synthetic",
         "config": {"workload": f"latent_uneven: {len(blocks)} FP32 blocks 4096 x U{{64..1024}}, 32 latent 48-dim "
                                f"subspaces, noise 1e-2, r={r}, eps=0.1, frobenius order",
@@ -763,7 +768,7 @@ def main():
     ap.add_argument("--sort-mode", default="frobenius", choices=("frobenius", "residual"),
                     help="cluster_residual: candidate order of a pass")
     ap.add_argument("--cpu-chains", type=int, default=6, help="cluster_residual: oracle sample (narrow pairs)")
-    ap.add_argument("--projection", default="f64", choices=("f64", "bf16", "bf16x3"),
+    ap.add_argument("--projection", default="f64", choices=("f64", "bf16", "bf16x3", "f32"),
                     help="pairs, cluster: precision of the candidate projections")
     ap.add_argument("--compare-f64", action="store_true", help="cluster: also run the FP64 clustering")
     ap.add_argument("--parity-pairs", type=int, default=48, help="cluster: oracle sample (narrow pairs)")
@@ -922,6 +927,15 @@ def main():
     if roof.get("achieved") is not None:
         roof["traffic"] = measured_traffic(EIG_KERNEL if dom == "core_eig" else "gemm_f64_kernel", npairs)
 
+    # the projection GEMMs against the matrix-core peak of their own operand type
+    proj_roof = None
+    if timed["projection"] > 0:
+        pk, kern = PROJ_PEAK[args.projection]
+        ach = flops["projection"] / (timed["projection"] * 1e-3) / 1e12
+        proj_roof = {"kernel": kern, "bound": "mfma", "achieved": round(ach, 3), "peak": pk, "unit": "TFLOP/s",
+                     "frac": round(ach / pk, 4), "launches": int(stages["projection"][1]),
+                     "avg_launch_ms": round(timed["projection"] / max(stages["projection"][1], 1), 3)}
+
     cpu = None
     parity = None
     if not args.no_cpu:
@@ -974,6 +988,7 @@ def main():
         "library": library,
         "stages_ms_per_step": {n: round(stages[n][0] / args.steps, 3) for n in stages},
         "roofline": roof,
+        "projection_roofline": proj_roof,
         "cpu_baseline": cpu,
         "parity": parity,
         "mean_rel": float(np.mean(rel_h)),

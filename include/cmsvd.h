@@ -24,14 +24,18 @@
  *     acc[4] = {E_tot hi, E_tot lo, D hi, D lo}: the block energy sum_i ||A_i||_F^2
  *     and the energy discarded by truncation, each as a double-double.
  *   - The caller owns every input and output buffer; the handle owns only its
- *     workspace (grown on demand with hipMalloc, freed by cmsvd_destroy), pinned
- *     staging buffers and one internal stream for uploads (default priority), whose
- *     work is ordered by an event before any dependent work on the handle's stream.
- *   - All calls are ordered on the handle's HIP stream.  cmsvd_update and
- *     cmsvd_merge_errors return once their work is enqueued (the host may block
- *     briefly while descriptor tables are uploaded); results are valid after a
- *     stream synchronisation.  The clustering calls are synchronous (their outputs
- *     are host memory).
+ *     workspace (grown on demand, freed by cmsvd_destroy), pinned staging buffers and
+ *     one internal stream for uploads (default priority), whose work is ordered by
+ *     events against the handle's stream in both directions.  Device memory comes
+ *     from the allocator callbacks given to cmsvd_create_ex (for example PyTorch's
+ *     caching allocator), else from hipMalloc; growing a workspace synchronises the
+ *     handle's stream first.
+ *   - All calls are ordered on the handle's HIP stream.  cmsvd_update,
+ *     cmsvd_update_batch, cmsvd_merge_errors and cmsvd_sym_eigvals return once their
+ *     work is enqueued (the host may block briefly while descriptor tables are
+ *     uploaded, and cmsvd_merge_errors reads the block norms back once when its
+ *     candidates are thin enough for the dense projection); results are valid after
+ *     a stream synchronisation.  The other calls are synchronous.
  *   - Argument validation happens before any launch.  A non-OK status means no
  *     kernel was launched by that call, except CMSVD_EHIP (a HIP runtime failure)
  *     and CMSVD_ENOMEM (a device or host allocation that failed part-way).  No C++
@@ -52,6 +56,7 @@
 #ifndef CMSVD_H
 #define CMSVD_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -63,7 +68,7 @@ typedef struct cmsvd_ctx* cmsvd_handle;
 typedef enum { CMSVD_F32 = 0, CMSVD_F64 = 2 } cmsvd_dtype;
 
 /* Precision of the candidate projections Y = U_r^T A_j (see cmsvd_set_projection). */
-typedef enum { CMSVD_PROJ_F64 = 0, CMSVD_PROJ_BF16 = 1, CMSVD_PROJ_BF16X3 = 2 } cmsvd_projection;
+typedef enum { CMSVD_PROJ_F64 = 0, CMSVD_PROJ_BF16 = 1, CMSVD_PROJ_BF16X3 = 2, CMSVD_PROJ_F32 = 3 } cmsvd_projection;
 
 typedef enum {
     CMSVD_OK = 0,
@@ -82,9 +87,41 @@ typedef struct {
     int32_t dtype;   /* cmsvd_dtype                                     */
 } cmsvd_block;
 
+/* Options of a handle (cmsvd_create_ex).  A zero-filled struct gives the defaults.
+     projection   precision of the candidate projections (cmsvd_projection; see
+                  cmsvd_set_projection, which can change it later)
+     chol_tau     c in the pivot threshold c u ||B||_F^2 (u = 2^-52) of the first
+                  Cholesky factorisation of CholeskyQR2 in every committed step (Lemma
+                  1's thin QR of the residual): a pivot at or below it drops its
+                  direction, whose energy stays in the error estimate.  0 = the block
+                  width k (the default); at most 1e12.
+     panel_cols   cmsvd_update and cmsvd_update_batch append a block wider than this as
+                  consecutive column panels of this width (the last one narrower): the
+                  same concatenation, truncated after every panel (Lemma 1 holds for any
+                  blocking), so results depend on it.  0 = whole blocks (the default).
+   CholeskyQR always takes two passes. */
+typedef struct {
+    int32_t projection;
+    double chol_tau;
+    int64_t panel_cols;
+} cmsvd_options;
+
 /* Creates a handle bound to a HIP stream (NULL = the default stream).  The current
-   HIP device at creation time is the device used by every call on the handle. */
+   HIP device at creation time is the device used by every call on the handle.
+   Default options; device memory from hipMalloc. */
 cmsvd_status cmsvd_create(cmsvd_handle* handle, void* hip_stream);
+
+/* cmsvd_create with options (NULL = defaults) and, optionally, the caller's device
+   allocator: alloc(bytes, alloc_ctx) returns device memory of the handle's device (NULL
+   on failure, reported as CMSVD_ENOMEM) and release(ptr, alloc_ctx) returns it; give
+   both or neither (CMSVD_EINVAL).  The library calls them from the thread that makes
+   the call, for its workspaces (grown on demand, released by cmsvd_destroy) and the
+   per-call buffers of the synchronous calls (released before they return).  A buffer
+   is released only after the work that reads it has completed or, for a grown
+   workspace, after the handle's stream has been synchronised.  Out-of-range options
+   give CMSVD_EINVAL. */
+cmsvd_status cmsvd_create_ex(cmsvd_handle* handle, void* hip_stream, const cmsvd_options* options,
+                             void* (*alloc)(size_t, void*), void (*release)(void*, void*), void* alloc_ctx);
 cmsvd_status cmsvd_destroy(cmsvd_handle handle);
 cmsvd_status cmsvd_set_stream(cmsvd_handle handle, void* hip_stream);
 
@@ -99,6 +136,10 @@ cmsvd_status cmsvd_set_stream(cmsvd_handle handle, void* hip_stream);
      CMSVD_PROJ_BF16X3 the same with lo = BF16(x32 - hi) staged too, summing
                        lo_U hi_A + hi_U lo_A + hi_U hi_A in FP32: three BF16 matrix-core
                        passes that carry about 16 significant bits per operand.
+     CMSVD_PROJ_F32    every element of U_r and of A_j is rounded to FP32 (round-to-
+                       nearest-even; FP32 data is unchanged) and the products are summed
+                       in FP32 on the matrix cores (v_mfma_f32_16x16x4f32), then widened
+                       to FP64.
    Everything else stays FP64: block norms and Grams A_j^T A_j, the anchors'
    truncations and every state update of the clustering (an accepted candidate is
    committed in FP64), the residual ordering of sort_mode 1, the core eigenvalues and
@@ -118,7 +159,8 @@ const char* cmsvd_last_error(void);
      S            current singular values, r_in FP64 (ignored when r_in == 0)
      r_in         current state width (0 = empty state: the update then computes the
                   rank-r truncated SVD of B, Algorithm 3 step 1)
-     B            the appended block (rows == m)
+     B            the appended block (rows == m); wider than the handle's panel_cols
+                  option, it is appended as consecutive column panels (cmsvd_options)
      r            target rank, 1 <= r <= m
      U_out, ldu_out  new basis, m x r row-major FP64 (must not alias U)
      S_out        new singular values, r FP64 (must not alias S)
@@ -265,6 +307,26 @@ cmsvd_status cmsvd_exact_tail(cmsvd_handle handle, const cmsvd_block* blocks, in
 cmsvd_status cmsvd_compress(cmsvd_handle handle, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double* Ut,
                             int64_t ldu, double* Vt, int64_t ldv, int64_t* rank, double* tail2, double* energy);
 
+/* The compression back-end over a whole partition (Problem Formulation; the
+   compression ratio and realised error of the Experiments): for every cluster c =
+   0 .. K-1 of labels (K = max label + 1; every id must have a block), cmsvd_compress
+   of its blocks in index order, and the partition's summary
+     ratio      = (sum over blocks of m n_i) / (sum over clusters of r_c (m + N_c)),
+                  the stored entries of the blocks over those of the factors
+     rel_error  = sqrt(sum_c tail2_c / sum_c ||M_c||_F^2)
+     labels     HOST nblocks int32, cluster id per block (as the clustering calls return)
+     Ut, ldu, Vt, ldv  HOST arrays of K entries (all four NULL: the factors are formed
+                  in a scratch buffer and only the summary is returned): cluster c's
+                  factors as in cmsvd_compress (Ut[c] m x r_c, Vt[c] r_c x N_c, DEVICE)
+     ranks, tail2, energy  HOST arrays of K entries (each may be NULL): r_c, the
+                  cluster's optimal rank-r_c error squared and ||M_c||_F^2
+     nclusters, ratio, rel_error  HOST out
+   Synchronous. */
+cmsvd_status cmsvd_compress_partition(cmsvd_handle handle, const cmsvd_block* blocks, int64_t nblocks,
+                                      const int32_t* labels, int64_t r, double* const* Ut, const int64_t* ldu,
+                                      double* const* Vt, const int64_t* ldv, int64_t* ranks, double* tail2,
+                                      double* energy, int64_t* nclusters, double* ratio, double* rel_error);
+
 /* Tail energy of a chain and its gradient with respect to every block.
    The chain folds the blocks in order (the incremental state of Lemma 1 and
    Corollary 3, starting from the empty state); the tail energy is Corollary 2's
@@ -291,7 +353,8 @@ cmsvd_status cmsvd_compress(cmsvd_handle handle, const cmsvd_block* blocks, int6
      min_gap           HOST out (may be NULL): min over steps of
                        (lam_r - lam_{r+1}) / lam_1 of the step's core spectrum; the
                        gradient does not exist where this is 0 (a tie at the cut)
-   Synchronous.  The workspace for states and factors is allocated per call. */
+   Synchronous.  The device memory for states and factors is allocated per call (through
+   the handle's allocator) and released before it returns. */
 cmsvd_status cmsvd_tail_energy_grad(cmsvd_handle handle, const cmsvd_block* blocks, int64_t nblocks, int64_t r,
                                     int64_t checkpoint, double* f, double* const* grads, double* min_gap);
 
@@ -333,6 +396,14 @@ cmsvd_status cmsvd_gemm_f64(cmsvd_handle handle, int32_t trans_a, int32_t trans_
 cmsvd_status cmsvd_gemm_bf16(cmsvd_handle handle, int32_t passes, int32_t trans_a, int32_t trans_b, int64_t M,
                              int64_t N, int64_t K, double alpha, const void* A, int64_t lda, int32_t a_dtype,
                              const void* B, int64_t ldb, int32_t b_dtype, double beta, double* C, int64_t ldc);
+
+/* The same GEMM with FP32 operands, the kernel of CMSVD_PROJ_F32: every element of
+   op(A) and op(B) is rounded to FP32 (round-to-nearest-even) as it is staged, products
+   are summed in FP32 on the matrix cores (v_mfma_f32_16x16x4f32), and alpha, beta and C
+   are FP64.  Otherwise the same arguments and errors as cmsvd_gemm_f64. */
+cmsvd_status cmsvd_gemm_f32(cmsvd_handle handle, int32_t trans_a, int32_t trans_b, int64_t M, int64_t N, int64_t K,
+                            double alpha, const void* A, int64_t lda, int32_t a_dtype, const void* B, int64_t ldb,
+                            int32_t b_dtype, double beta, double* C, int64_t ldc);
 
 #ifdef __cplusplus
 }

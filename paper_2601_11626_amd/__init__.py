@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 from typing import Sequence
 
 import torch
@@ -39,6 +40,7 @@ def _load():
     lib = ctypes.CDLL(LIB_PATH)
     vp, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     lib.cmsvd_create.argtypes = [ctypes.POINTER(vp), vp]
+    lib.cmsvd_create_ex.argtypes = [ctypes.POINTER(vp), vp, vp, vp, vp, vp]
     lib.cmsvd_destroy.argtypes = [vp]
     lib.cmsvd_set_stream.argtypes = [vp, vp]
     lib.cmsvd_last_error.restype = ctypes.c_char_p
@@ -48,6 +50,7 @@ def _load():
     lib.cmsvd_sym_eigvals.argtypes = [vp, vp, i64, i64, i64, i64, i64, vp]
     lib.cmsvd_gemm_f64.argtypes = [vp, i32, i32, i64, i64, i64, d, vp, i64, i32, vp, i64, i32, d, vp, i64]
     lib.cmsvd_gemm_bf16.argtypes = [vp, i32, i32, i32, i64, i64, i64, d, vp, i64, i32, vp, i64, i32, d, vp, i64]
+    lib.cmsvd_gemm_f32.argtypes = [vp, i32, i32, i64, i64, i64, d, vp, i64, i32, vp, i64, i32, d, vp, i64]
     lib.cmsvd_set_projection.argtypes = [vp, i32]
     lib.cmsvd_profile.argtypes = [vp, i32]
     lib.cmsvd_profile_read.argtypes = [vp, vp, vp]
@@ -59,13 +62,16 @@ def _load():
     lib.cmsvd_exact_tail.argtypes = [vp, ctypes.POINTER(Block), i64, i64, ctypes.POINTER(d)]
     lib.cmsvd_compress.argtypes = [vp, ctypes.POINTER(Block), i64, i64, vp, i64, vp, i64, ctypes.POINTER(i64),
                                    ctypes.POINTER(d), ctypes.POINTER(d)]
+    lib.cmsvd_compress_partition.argtypes = [vp, ctypes.POINTER(Block), i64, vp, i64, vp, vp, vp, vp, vp, vp, vp,
+                                             ctypes.POINTER(i64), ctypes.POINTER(d), ctypes.POINTER(d)]
     lib.cmsvd_tail_energy_grad.argtypes = [vp, ctypes.POINTER(Block), i64, i64, i64, ctypes.POINTER(d), vp,
                                            ctypes.POINTER(d)]
     for f in ("cmsvd_create", "cmsvd_destroy", "cmsvd_set_stream", "cmsvd_update", "cmsvd_merge_errors",
               "cmsvd_cluster", "cmsvd_sym_eigvals", "cmsvd_gemm_f64", "cmsvd_profile", "cmsvd_profile_read",
               "cmsvd_tail_energy_grad", "cmsvd_update_batch", "cmsvd_cluster_residual", "cmsvd_residual_bound",
               "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail", "cmsvd_compress", "cmsvd_gemm_bf16",
-              "cmsvd_set_projection"):
+              "cmsvd_set_projection", "cmsvd_gemm_f32", "cmsvd_create_ex",
+              "cmsvd_compress_partition"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -76,9 +82,10 @@ EXPORTS = ("cmsvd_create", "cmsvd_destroy", "cmsvd_set_stream", "cmsvd_last_erro
            "cmsvd_merge_errors", "cmsvd_cluster", "cmsvd_sym_eigvals", "cmsvd_gemm_f64", "cmsvd_profile",
            "cmsvd_profile_read", "cmsvd_tail_energy_grad", "cmsvd_update_batch", "cmsvd_cluster_residual",
            "cmsvd_residual_bound", "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail", "cmsvd_compress",
-           "cmsvd_gemm_bf16", "cmsvd_set_projection")
+           "cmsvd_gemm_bf16", "cmsvd_set_projection", "cmsvd_gemm_f32",
+           "cmsvd_create_ex", "cmsvd_compress_partition")
 
-PROJECTIONS = {"f64": 0, "bf16": 1, "bf16x3": 2}  # cmsvd_projection
+PROJECTIONS = {"f64": 0, "bf16": 1, "bf16x3": 2, "f32": 3}  # cmsvd_projection
 
 STAGES = ("norms_grams", "commit", "projection", "core_eig")
 
@@ -92,15 +99,54 @@ def _stream_ptr(device=None):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
-class Handle:
-    """Owns a cmsvd handle bound to the current torch stream of ``device``."""
+class Options(ctypes.Structure):
+    """cmsvd_options (zero = the defaults)."""
+    _fields_ = [("projection", ctypes.c_int32), ("chol_tau", ctypes.c_double), ("panel_cols", ctypes.c_int64)]
 
-    def __init__(self, device=None):
+
+_ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_RELEASE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+def _torch_allocator(device_index: int, stream):
+    """The allocator callbacks of cmsvd_create_ex on PyTorch's caching allocator (blocks
+    tied to the handle's stream)."""
+
+    def alloc(nbytes, _ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device_index, stream)
+        except Exception:  # out of memory: the library reports CMSVD_ENOMEM
+            return None
+
+    def release(ptr, _ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return _ALLOC_T(alloc), _RELEASE_T(release)
+
+
+class Handle:
+    """Owns a cmsvd handle bound to the current torch stream of ``device``.
+
+    ``projection``, ``chol_tau`` and ``panel_cols`` are the handle options
+    (cmsvd_options); with ``torch_allocator`` (the default) the library's device memory
+    comes from PyTorch's caching allocator."""
+
+    def __init__(self, device=None, projection: str = "f64", chol_tau: float = 0.0, panel_cols: int = 0,
+                 torch_allocator: bool = True):
         self._h = ctypes.c_void_p()
-        self.projection = "f64"
+        self._cb = None
+        self.projection = projection
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else torch.device(device).index)
+        opts = Options(PROJECTIONS[projection], float(chol_tau), int(panel_cols))
         with torch.cuda.device(self.device):
-            _check(_lib.cmsvd_create(ctypes.byref(self._h), _stream_ptr(self.device)))
+            stream = torch.cuda.current_stream(self.device)
+            if torch_allocator:
+                self._cb = _torch_allocator(self.device.index, stream)
+                alloc, release = self._cb
+            else:
+                alloc, release = _ALLOC_T(), _RELEASE_T()
+            _check(_lib.cmsvd_create_ex(ctypes.byref(self._h), ctypes.c_void_p(stream.cuda_stream),
+                                        ctypes.byref(opts), alloc, release, None))
 
     def sync_stream(self):
         _check(_lib.cmsvd_set_stream(self._h, _stream_ptr(self.device)))
@@ -110,7 +156,9 @@ class Handle:
             _lib.cmsvd_destroy(self._h)
             self._h = ctypes.c_void_p()
 
-    def __del__(self):  # pragma: no cover
+    def __del__(self, _finalizing=sys.is_finalizing):  # pragma: no cover
+        if _finalizing():  # the allocator callbacks cannot run any more: leave it to the process exit
+            return
         try:
             self.close()
         except Exception:
@@ -121,7 +169,7 @@ class Handle:
         return self._h
 
     def set_projection(self, precision: str):
-        """'f64' (default), 'bf16' or 'bf16x3': precision of the candidate projections
+        """'f64' (default), 'bf16', 'bf16x3' or 'f32': precision of the candidate projections
         Y = U_r^T A_j."""
         _check(_lib.cmsvd_set_projection(self._h, PROJECTIONS[precision]))
         self.projection = precision
@@ -271,7 +319,7 @@ def cmsvd_update_batch(states: Sequence[State], blocks: Sequence[torch.Tensor], 
 def cmsvd_merge_errors(blocks: Sequence[torch.Tensor], pairs, r: int, handle: Handle | None = None,
                        projection: str | None = None):
     """Returns (err, rel) device FP64 tensors for the ordered pairs (i, j).  projection:
-    'f64', 'bf16' or 'bf16x3' for this call (None: the handle's setting)."""
+    'f64', 'bf16', 'bf16x3' or 'f32' for this call (None: the handle's setting)."""
     dev = blocks[0].device
     h = handle or default_handle(dev)
     if isinstance(pairs, torch.Tensor):
@@ -293,7 +341,7 @@ def cmsvd_merge_errors(blocks: Sequence[torch.Tensor], pairs, r: int, handle: Ha
 def cmsvd_cluster(blocks: Sequence[torch.Tensor], r: int, eps: float, sort_mode: str = "frobenius",
                   handle: Handle | None = None, projection: str | None = None):
     """Algorithm 3 on the device.  Returns (labels list, clusters list, cluster_rel list).
-    projection: 'f64', 'bf16' or 'bf16x3' for the candidate evaluations of this call
+    projection: 'f64', 'bf16', 'bf16x3' or 'f32' for the candidate evaluations of this call
     (None: the handle's setting)."""
     dev = blocks[0].device
     h = handle or default_handle(dev)
@@ -395,23 +443,32 @@ def cmsvd_compress(blocks: Sequence[torch.Tensor], r: int, handle: Handle | None
 
 def compress_partition(blocks: Sequence[torch.Tensor], labels, r: int, handle: Handle | None = None):
     """Factors of every cluster of a partition (labels as returned by the clustering
-    calls) and the summary: compression ratio (stored entries of the blocks over those of
-    the factors) and the relative error sqrt(sum of the cluster tails) / ||all blocks||_F.
+    calls) and the summary computed by cmsvd_compress_partition: compression ratio
+    (stored entries of the blocks over those of the factors) and the relative error
+    sqrt(sum of the cluster tails) / ||all blocks||_F.
     Returns (factors: list of (members, Ut, Vt, tail2), summary dict)."""
+    h = handle or default_handle(blocks[0].device)
     m = blocks[0].shape[0]
-    ncl = max(labels) + 1
-    members = [[i for i, c in enumerate(labels) if c == k] for k in range(ncl)]
-    factors, before, after, tails, total = [], 0, 0, 0.0, 0.0
+    lab = [int(c) for c in labels]
+    ncl = max(lab) + 1
+    members = [[i for i, c in enumerate(lab) if c == k] for k in range(ncl)]
+    uts, vts = [], []
     for mem in members:
-        Ut, Vt, t2, e2 = cmsvd_compress([blocks[i] for i in mem], r, handle, with_energy=True)
         N = sum(int(blocks[i].shape[1]) for i in mem)
-        before += m * N
-        after += Ut.shape[1] * (m + N)
-        tails += t2
-        total += e2
-        factors.append((mem, Ut, Vt, t2))
-    return factors, {"compression_ratio": before / after, "rel_error": (tails / total) ** 0.5 if total > 0 else 0.0,
-                     "clusters": ncl}
+        rc = min(r, m, N)
+        uts.append(torch.empty((m, rc), dtype=torch.float64, device=blocks[0].device))
+        vts.append(torch.empty((rc, N), dtype=torch.float64, device=blocks[0].device))
+    P = ctypes.c_void_p * ncl
+    L = ctypes.c_int64 * ncl
+    ranks, t2 = L(), (ctypes.c_double * ncl)()
+    lab_c = (ctypes.c_int32 * len(lab))(*lab)
+    k, ratio, rel = ctypes.c_int64(0), ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(_lib.cmsvd_compress_partition(
+        h.ptr, _blocks(blocks), len(blocks), lab_c, r, P(*[u.data_ptr() for u in uts]), L(*[u.shape[1] for u in uts]),
+        P(*[v.data_ptr() for v in vts]), L(*[v.shape[1] for v in vts]), ranks, t2, None, ctypes.byref(k),
+        ctypes.byref(ratio), ctypes.byref(rel)))
+    factors = [(mem, uts[c], vts[c], t2[c]) for c, mem in enumerate(members)]
+    return factors, {"compression_ratio": ratio.value, "rel_error": rel.value, "clusters": int(k.value)}
 
 
 def cmsvd_tail_energy_grad(blocks: Sequence[torch.Tensor], r: int, checkpoint: int | None = None,
@@ -493,6 +550,12 @@ def cmsvd_gemm_bf16(opA: torch.Tensor, opB: torch.Tensor, C: torch.Tensor | None
     return _gemm(lambda *a: _lib.cmsvd_gemm_bf16(a[0], passes, *a[1:]), opA, opB, C, alpha, beta, handle)
 
 
+def cmsvd_gemm_f32(opA: torch.Tensor, opB: torch.Tensor, C: torch.Tensor | None = None, alpha: float = 1.0,
+                   beta: float = 0.0, handle: Handle | None = None) -> torch.Tensor:
+    """As cmsvd_gemm_f64 with the operands rounded to FP32 and FP32 accumulation."""
+    return _gemm(_lib.cmsvd_gemm_f32, opA, opB, C, alpha, beta, handle)
+
+
 def _gemm(fn, opA, opB, C, alpha, beta, handle):
     h = handle or default_handle(opA.device)
 
@@ -520,7 +583,7 @@ def _gemm(fn, opA, opB, C, alpha, beta, handle):
     return C
 
 
-__all__ = ["cmsvd_gemm_f64", "cmsvd_gemm_bf16", "PROJECTIONS", "BlockArray", "Handle", "State", "Block", "CmsvdError", "cmsvd_update", "cmsvd_update_batch",
+__all__ = ["cmsvd_gemm_f64", "cmsvd_gemm_bf16", "cmsvd_gemm_f32", "PROJECTIONS", "BlockArray", "Handle", "State", "Block", "CmsvdError", "cmsvd_update", "cmsvd_update_batch",
            "cmsvd_merge_errors", "cmsvd_cluster", "cmsvd_cluster_residual", "cmsvd_residual_bound",
            "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail", "cmsvd_compress", "compress_partition",
            "cmsvd_sym_eigvals", "cmsvd_tail_energy_grad", "TailEnergy", "tail_energy", "default_handle",

@@ -119,6 +119,19 @@ struct cmsvd_ctx {
     size_t rec_cap = 0;
     hipStream_t side = nullptr;  // uploads that overlap work on the handle's stream
     hipEvent_t rec_ev = nullptr;
+    // device memory: the caller's allocator when given (cmsvd_create_ex), else hipMalloc
+    void* (*alloc_fn)(size_t, void*) = nullptr;
+    void (*release_fn)(void*, void*) = nullptr;
+    void* alloc_ctx = nullptr;
+    char* keep = nullptr;        // per-call tables of cmsvd_merge_errors (norms, Grams, anchor states)
+    size_t keep_cap = 0;
+    char* pan = nullptr;         // intermediate states of panelled updates
+    size_t pan_cap = 0;
+    bool rec_ev_armed = false;   // an upload of pair records may still read rec_pin
+    hipEvent_t tail_ev = nullptr;  // end of the handle stream's enqueued work (orders the side stream)
+    // options (cmsvd_create_ex)
+    double chol_c = 0.0;         // pivot threshold factor of the first Cholesky (<= 0: the block width)
+    int64_t panel_cols = 0;      // cmsvd_update(_batch): widest block appended in one step (0: any)
     // stage timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> marks[4];
@@ -127,18 +140,41 @@ struct cmsvd_ctx {
 
 namespace {
 
+// Device memory of a handle: through the caller's allocator when one was given at
+// creation, otherwise hipMalloc / hipFree.  Every device buffer of the library (the
+// grow-on-demand workspaces and the per-call buffers) goes through these two.
+cmsvd_status dev_alloc(cmsvd_ctx* h, size_t bytes, char** out) {
+    *out = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (h->alloc_fn) {
+        void* p = h->alloc_fn(bytes, h->alloc_ctx);
+        if (!p) return fail(CMSVD_ENOMEM, "allocator callback returned null for %zu bytes", bytes);
+        *out = static_cast<char*>(p);
+        return CMSVD_OK;
+    }
+    if (hipMalloc((void**)out, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *out = nullptr;
+        return fail(CMSVD_ENOMEM, "hipMalloc(%zu bytes) failed", bytes);
+    }
+    return CMSVD_OK;
+}
+
+void dev_free(cmsvd_ctx* h, char* p) {
+    if (!p) return;
+    if (h->release_fn) h->release_fn(p, h->alloc_ctx);
+    else (void)hipFree(p);
+}
+
 cmsvd_status ensure(cmsvd_ctx* h, char*& buf, size_t& cap, size_t need) {
     if (need <= cap) return CMSVD_OK;
     HIPCHK(hipStreamSynchronize(h->stream));
     const size_t want = std::max(need, cap + cap / 2);
-    if (buf) HIPCHK(hipFree(buf));
+    dev_free(h, buf);
     buf = nullptr;
     cap = 0;
-    if (hipMalloc((void**)&buf, want) != hipSuccess) {
-        (void)hipGetLastError();
-        buf = nullptr;
-        return fail(CMSVD_ENOMEM, "hipMalloc(%zu bytes) failed", want);
-    }
+    cmsvd_status st = dev_alloc(h, want, &buf);
+    if (st != CMSVD_OK) return st;
     cap = want;
     return CMSVD_OK;
 }
@@ -168,9 +204,14 @@ cmsvd_status upload(cmsvd_ctx* h, const Stage& st, char** dbase) {
 
 // A device allocation owned by one call (separate from the workspace arena).
 struct DevBuf {
+    cmsvd_ctx* h = nullptr;
     char* p = nullptr;
+    cmsvd_status get(cmsvd_ctx* h_, size_t bytes) {
+        h = h_;
+        return dev_alloc(h, bytes, &p);
+    }
     ~DevBuf() {
-        if (p) (void)hipFree(p);
+        if (p) dev_free(h, p);
     }
 };
 
@@ -229,15 +270,24 @@ cmsvd_status check_block(const cmsvd_block& b, int64_t m, const char* what, int6
 // ---------------------------------------------------------------------------
 // Batched GEMM helper: groups problems that share (transA, transB, types).
 // ---------------------------------------------------------------------------
-// BF16 passes of the candidate projections (0 = the FP64 kernel).
-int proj_passes(const cmsvd_ctx* h) {
-    return h->proj == CMSVD_PROJ_BF16 ? 1 : h->proj == CMSVD_PROJ_BF16X3 ? 3 : 0;
+// Operand precision of a GEMM group: the FP64 kernel, BF16 with one or three operand
+// passes, or FP32 (the last three accumulate in FP32 on the matrix cores).
+enum { PREC_F64 = 0, PREC_BF16 = 1, PREC_BF16X3 = 3, PREC_F32 = 32 };
+
+// The kernel precision of the candidate projections.
+int proj_prec(const cmsvd_ctx* h) {
+    switch (h->proj) {
+        case CMSVD_PROJ_BF16: return PREC_BF16;
+        case CMSVD_PROJ_BF16X3: return PREC_BF16X3;
+        case CMSVD_PROJ_F32: return PREC_F32;
+        default: return PREC_F64;
+    }
 }
 
 struct GemmGroup {
     std::vector<GemmDesc> d;
     bool ta = false, tb = false, af32 = false, bf32 = false;
-    int bf16 = 0;  // 0: FP64 kernel; 1 or 3: BF16 operand passes, FP32 accumulation
+    int prec = PREC_F64;  // operand precision (PREC_*)
     double alpha = 1.0, beta = 0.0;
     size_t off = 0;
     int maxM = 0, maxN = 0;
@@ -255,8 +305,12 @@ struct GemmGroup {
 void run_gemm(cmsvd_ctx* h, const GemmGroup& g, char* dbase) {
     if (g.d.empty()) return;
     const GemmDesc* dd = reinterpret_cast<const GemmDesc*>(dbase + g.off);
-    if (g.bf16) {
-        gemm_bf16_batched(dd, (int)g.d.size(), g.maxM, g.maxN, g.ta, g.tb, g.af32, g.bf32, g.bf16, g.alpha, g.beta,
+    if (g.prec == PREC_F32) {
+        gemm_f32_batched(dd, (int)g.d.size(), g.maxM, g.maxN, g.ta, g.tb, g.af32, g.bf32, g.alpha, g.beta, h->stream);
+        return;
+    }
+    if (g.prec != PREC_F64) {
+        gemm_bf16_batched(dd, (int)g.d.size(), g.maxM, g.maxN, g.ta, g.tb, g.af32, g.bf32, g.prec, g.alpha, g.beta,
                           h->stream);
         return;
     }
@@ -660,7 +714,8 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
             gR2.push(GemmDesc{D(q.P2), c.U, D(q.Rt), k, m, c.r_in, (long)c.r_in, c.ldu, (long)k});
         }
         gG1.push(GemmDesc{D(q.Rt), D(q.Rt), D(q.G1), k, k, m, (long)k, (long)k, (long)k});
-        ch1[j] = CholDesc{k, D(q.G1), (long)k, D(q.Li1), (long)k, (double)k * EPS, pnb[j], nullptr};
+        ch1[j] = CholDesc{k, D(q.G1), (long)k, D(q.Li1), (long)k, (h->chol_c > 0.0 ? h->chol_c : (double)k) * EPS,
+                          pnb[j], nullptr};
         gQ1.push(GemmDesc{D(q.Li1), D(q.Rt), D(q.Q1), k, m, k, (long)k, (long)k, (long)k});
         gG2.push(GemmDesc{D(q.Q1), D(q.Q1), D(q.G2), k, k, m, (long)k, (long)k, (long)k});
         ch2[j] = CholDesc{k, D(q.G2), (long)k, D(q.Li2), (long)k, (double)k * k * EPS, nullptr, nullptr};
@@ -808,7 +863,7 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
         GemmGroup g32, g64;
         g32.tb = g64.tb = true;
         g32.bf32 = true;
-        g32.bf16 = g64.bf16 = proj_passes(h);
+        g32.prec = g64.prec = proj_prec(h);
         std::vector<EigDesc> ed(nj);
         for (size_t i = 0; i < nj; ++i) {
             const EvalJob& j = jobs[b0 + i];
@@ -897,9 +952,14 @@ int pair_threads(int64_t npairs, int64_t nblocks) {
     return (int)std::max<int64_t>(1, std::min<int64_t>({16, hc, npairs >> 18, by_mem}));
 }
 
-// Pinned host staging for the pair records of a dense evaluation (grow-only; the
-// previous call has synchronised its stream before returning).
+// Pinned host staging for the pair records of a dense evaluation (grow-only).  The
+// previous call's upload from it may still be in flight: wait for it before the
+// staging is rewritten or replaced.
 cmsvd_status ensure_rec_pin(cmsvd_ctx* h, size_t need) {
+    if (h->rec_ev_armed) {
+        HIPCHK(hipEventSynchronize(h->rec_ev));
+        h->rec_ev_armed = false;
+    }
     if (need <= h->rec_pin_cap) return CMSVD_OK;
     const size_t want = std::max(need, h->rec_pin_cap + h->rec_pin_cap / 2);
     if (h->rec_pin) HIPCHK(hipHostFree(h->rec_pin));
@@ -955,7 +1015,7 @@ cmsvd_status dense_project(cmsvd_ctx* h, const DenseEval& de, int nmax, DenseChu
     GemmGroup g;
     g.tb = true;
     g.bf32 = de.ball_f32;
-    g.bf16 = proj_passes(h);
+    g.prec = proj_prec(h);
     const char* Bc = static_cast<const char*>(de.Ball) + (size_t)ch.cmin * (de.ball_f32 ? 4 : 8);
     g.push(GemmDesc{de.Uall + (size_t)ch.a0 * r, Bc, ch.C, (int)ldc, (int)(ch.cmax - ch.cmin), de.m, (long)de.na * r,
                     de.ldb, ldc});
@@ -1377,9 +1437,9 @@ cmsvd_status resid_setup(cmsvd_ctx* h, const cmsvd_block* blocks, int N, int64_t
     const size_t o_lam = pl.add((size_t)N * rb.nkcap * 8), o_rel = pl.add((size_t)N * 8), o_err = pl.add((size_t)N * 8),
                  o_pn = pl.add((size_t)N * 8), o_first = pl.add(8), o_cnt = pl.add(8), o_map = pl.add((size_t)kmax * 4),
                  o_flags = pl.add((size_t)N * 4), o_own = pl.add((size_t)N * rb.nkcap * 8);
-    if (hipMalloc((void**)&rb.keep.p, pl.off) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(CMSVD_ENOMEM, "%s: hipMalloc(%zu) failed", who, pl.off);
+    {
+        const cmsvd_status sa = rb.keep.get(h, pl.off);
+        if (sa != CMSVD_OK) return sa;
     }
     char* base = rb.keep.p;
     auto K = [&](size_t off) { return reinterpret_cast<double*>(base + off); };
@@ -1662,9 +1722,9 @@ cmsvd_status weyl_setup(cmsvd_ctx* h, const cmsvd_block* blocks, int N, int64_t 
     Plan pl;
     const size_t o_a2 = pl.add((size_t)N * 16), o_top = pl.add((size_t)N * 16), o_h = pl.add((size_t)N * 8),
                  o_st = pl.add(24), o_rel = pl.add(8), o_first = pl.add(8);
-    if (hipMalloc((void**)&wb.keep.p, pl.off) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(CMSVD_ENOMEM, "%s: hipMalloc(%zu) failed", who, pl.off);
+    {
+        const cmsvd_status sa = wb.keep.get(h, pl.off);
+        if (sa != CMSVD_OK) return sa;
     }
     char* base = wb.keep.p;
     wb.a2 = reinterpret_cast<double*>(base + o_a2);
@@ -1721,7 +1781,7 @@ cmsvd_status weyl_setup(cmsvd_ctx* h, const cmsvd_block* blocks, int N, int64_t 
     return CMSVD_OK;
 }
 
-cmsvd_status gemm_entry(cmsvd_handle h, const char* who, int bf16, int32_t trans_a, int32_t trans_b, int64_t M,
+cmsvd_status gemm_entry(cmsvd_handle h, const char* who, int prec, int32_t trans_a, int32_t trans_b, int64_t M,
                         int64_t N, int64_t K, double alpha, const void* A, int64_t lda, int32_t a_dtype, const void* B,
                         int64_t ldb, int32_t b_dtype, double beta, double* C, int64_t ldc) {
     if (!h) return fail(CMSVD_EINVAL, "%s: null handle", who);
@@ -1735,7 +1795,7 @@ cmsvd_status gemm_entry(cmsvd_handle h, const char* who, int bf16, int32_t trans
         return fail(CMSVD_ESHAPE, "%s: leading dimension too small", who);
     if (M == 0 || N == 0) return CMSVD_OK;
     GemmGroup g;
-    g.bf16 = bf16;
+    g.prec = prec;
     g.ta = trans_a != 0;
     g.tb = trans_b != 0;
     g.af32 = a_dtype == CMSVD_F32;
@@ -1758,14 +1818,99 @@ cmsvd_status gemm_entry(cmsvd_handle h, const char* who, int bf16, int32_t trans
 // ===========================================================================
 // Public C ABI
 // ===========================================================================
+namespace {
+
+// Width of the i-th column panel of a block under the handle's panel_cols option.
+int64_t panel_count(const cmsvd_ctx* h, int64_t cols) {
+    return h->panel_cols > 0 && cols > h->panel_cols ? (cols + h->panel_cols - 1) / h->panel_cols : 1;
+}
+
+// The largest core order of a panelled step sequence: r_in + first panel, then r + panel.
+int64_t panelled_order(const cmsvd_ctx* h, int64_t r_in, int64_t r, int64_t cols) {
+    if (panel_count(h, cols) == 1) return r_in + cols;
+    return std::max(r_in, r) + h->panel_cols;
+}
+
+// Runs the incremental steps of `jobs` (one per independent state).  A block wider than
+// the handle's panel_cols is appended as consecutive column panels of that width (the
+// last one narrower): the same concatenation (Lemma 1 holds for any blocking) with a
+// truncation after every panel.  Intermediate states (row-major m x r bases and their r
+// singular values) alternate between two slots per state in the handle's buffer; the
+// last panel writes the caller's outputs and est.
+cmsvd_status commit_panelled(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
+    int64_t npmax = 1;
+    for (const auto& j : jobs) npmax = std::max(npmax, panel_count(h, j.B.cols));
+    if (npmax == 1) return commit_batched(h, jobs);
+    const size_t J = jobs.size();
+    size_t per = 0;  // doubles of one state slot
+    for (const auto& j : jobs) per = std::max(per, (size_t)j.m * j.r + (size_t)j.r);
+    cmsvd_status st = ensure(h, h->pan, h->pan_cap, 2 * J * align256(per * 8));
+    if (st != CMSVD_OK) return st;
+    auto slot = [&](size_t i, int64_t p) {
+        return reinterpret_cast<double*>(h->pan + (2 * i + (size_t)(p & 1)) * align256(per * 8));
+    };
+    for (int64_t p = 0; p < npmax; ++p) {
+        std::vector<CommitJob> step;
+        for (size_t i = 0; i < J; ++i) {
+            const CommitJob& c = jobs[i];
+            const int64_t np = panel_count(h, c.B.cols);
+            if (p >= np) continue;
+            CommitJob q = c;
+            const size_t esz = c.B.dtype == CMSVD_F32 ? 4 : 8;
+            const int64_t c0 = p * h->panel_cols;
+            q.B.ptr = static_cast<const char*>(c.B.ptr) + (size_t)c0 * esz;
+            q.B.cols = np == 1 ? c.B.cols : std::min<int64_t>(h->panel_cols, c.B.cols - c0);
+            if (p > 0) {  // the state the previous panel left
+                double* prev = slot(i, p - 1);
+                q.U = prev;
+                q.ldu = c.r;
+                q.S = prev + (size_t)c.m * c.r;
+                q.r_in = c.r;
+            }
+            if (p + 1 < np) {  // not the last panel: write an intermediate state
+                double* nxt = slot(i, p);
+                q.U_out = nxt;
+                q.ldu_out = c.r;
+                q.S_out = nxt + (size_t)c.m * c.r;
+                q.est = nullptr;
+            }
+            step.push_back(q);
+        }
+        st = commit_batched(h, step);
+        if (st != CMSVD_OK) return st;
+    }
+    return CMSVD_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* cmsvd_last_error(void) { return g_err.c_str(); }
 
-cmsvd_status cmsvd_create(cmsvd_handle* handle, void* hip_stream) try {
+cmsvd_status cmsvd_create_ex(cmsvd_handle* handle, void* hip_stream, const cmsvd_options* options,
+                             void* (*alloc)(size_t, void*), void (*release)(void*, void*), void* alloc_ctx) try {
     if (!handle) return fail(CMSVD_EINVAL, "cmsvd_create: null handle pointer");
+    if ((alloc == nullptr) != (release == nullptr))
+        return fail(CMSVD_EINVAL, "cmsvd_create_ex: give both allocator callbacks or neither");
+    if (options) {
+        const int p = options->projection;
+        if (p != CMSVD_PROJ_F64 && p != CMSVD_PROJ_BF16 && p != CMSVD_PROJ_BF16X3 && p != CMSVD_PROJ_F32)
+            return fail(CMSVD_EINVAL, "cmsvd_create_ex: unknown projection %d", p);
+        if (options->panel_cols < 0) return fail(CMSVD_EINVAL, "cmsvd_create_ex: panel_cols < 0");
+        if (!(options->chol_tau >= 0.0) || options->chol_tau > 1e12)
+            return fail(CMSVD_EINVAL, "cmsvd_create_ex: chol_tau must be in [0, 1e12]");
+    }
     cmsvd_ctx* h = new cmsvd_ctx();
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    h->alloc_fn = alloc;
+    h->release_fn = release;
+    h->alloc_ctx = alloc_ctx;
+    if (options) {
+        h->proj = options->projection;
+        h->chol_c = options->chol_tau;
+        h->panel_cols = options->panel_cols;
+    }
     if (hipGetDevice(&h->device) != hipSuccess) {
         delete h;
         return fail(CMSVD_EHIP, "hipGetDevice failed");
@@ -1782,9 +1927,11 @@ cmsvd_status cmsvd_create(cmsvd_handle* handle, void* hip_stream) try {
     h->ncu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     if (hipEventCreateWithFlags(&h->pin_ev, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&h->rec_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->tail_ev, hipEventDisableTiming) != hipSuccess ||
         hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) {
         if (h->pin_ev) (void)hipEventDestroy(h->pin_ev);
         if (h->rec_ev) (void)hipEventDestroy(h->rec_ev);
+        if (h->tail_ev) (void)hipEventDestroy(h->tail_ev);
         delete h;
         return fail(CMSVD_EHIP, "hipEventCreate / hipStreamCreate failed");
     }
@@ -1794,13 +1941,23 @@ cmsvd_status cmsvd_create(cmsvd_handle* handle, void* hip_stream) try {
     return caught(__func__);
 }
 
+cmsvd_status cmsvd_create(cmsvd_handle* handle, void* hip_stream) try {
+    return cmsvd_create_ex(handle, hip_stream, nullptr, nullptr, nullptr, nullptr);
+} catch (...) {
+    return caught(__func__);
+}
+
 cmsvd_status cmsvd_destroy(cmsvd_handle h) try {
     if (!h) return CMSVD_OK;
     (void)hipStreamSynchronize(h->stream);
-    if (h->ws) (void)hipFree(h->ws);
-    if (h->dsc) (void)hipFree(h->dsc);
-    if (h->gsk) (void)hipFree(h->gsk);
-    if (h->rec) (void)hipFree(h->rec);
+    if (h->side) (void)hipStreamSynchronize(h->side);
+    dev_free(h, h->ws);
+    dev_free(h, h->dsc);
+    dev_free(h, h->gsk);
+    dev_free(h, h->rec);
+    dev_free(h, h->keep);
+    dev_free(h, h->pan);
+    if (h->tail_ev) (void)hipEventDestroy(h->tail_ev);
     if (h->rec_pin) (void)hipHostFree(h->rec_pin);
     if (h->pin) (void)hipHostFree(h->pin);
     if (h->pin_ev) (void)hipEventDestroy(h->pin_ev);
@@ -1852,8 +2009,9 @@ cmsvd_status cmsvd_profile_read(cmsvd_handle h, double* ms, int64_t* count) try 
 
 cmsvd_status cmsvd_set_projection(cmsvd_handle h, int32_t precision) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_set_projection: null handle");
-    if (precision != CMSVD_PROJ_F64 && precision != CMSVD_PROJ_BF16 && precision != CMSVD_PROJ_BF16X3)
-        return fail(CMSVD_EINVAL, "cmsvd_set_projection: precision must be CMSVD_PROJ_F64, _BF16 or _BF16X3");
+    if (precision != CMSVD_PROJ_F64 && precision != CMSVD_PROJ_BF16 && precision != CMSVD_PROJ_BF16X3 &&
+        precision != CMSVD_PROJ_F32)
+        return fail(CMSVD_EINVAL, "cmsvd_set_projection: precision must be CMSVD_PROJ_F64, _BF16, _BF16X3 or _F32");
     h->proj = precision;
     return CMSVD_OK;
 } catch (...) {
@@ -1884,10 +2042,10 @@ cmsvd_status cmsvd_update(cmsvd_handle h, int64_t m, const double* U, int64_t ld
     if (U_out == U || S_out == S) return fail(CMSVD_EINVAL, "cmsvd_update: outputs alias inputs");
     cmsvd_status st = check_block(*B, m, "block", 0);
     if (st != CMSVD_OK) return st;
-    st = check_order(r_in + B->cols, "cmsvd_update");
+    st = check_order(panelled_order(h, r_in, r, B->cols), "cmsvd_update");
     if (st != CMSVD_OK) return st;
     CommitJob j{(int)m, U, (long)ldu, S, (int)r_in, *B, (int)r, U_out, (long)ldu_out, S_out, acc, est};
-    return commit_batched(h, {j});
+    return commit_panelled(h, {j});
 } catch (...) {
     return caught(__func__);
 }
@@ -1910,7 +2068,7 @@ cmsvd_status cmsvd_update_batch(cmsvd_handle h, int64_t count, int64_t m, const 
     for (int64_t i = 0; i < count; ++i) {
         cmsvd_status st = check_block(B[i], m, "block", i);
         if (st != CMSVD_OK) return st;
-        st = check_order(r_in + B[i].cols, "cmsvd_update_batch");
+        st = check_order(panelled_order(h, r_in, r, B[i].cols), "cmsvd_update_batch");
         if (st != CMSVD_OK) return st;
         if (!U_out[i] || !S_out[i] || !acc[i]) return fail(CMSVD_EINVAL, "cmsvd_update_batch: null output %lld", (long long)i);
         if (r_in > 0 && (!U[i] || !S[i])) return fail(CMSVD_EINVAL, "cmsvd_update_batch: null state %lld", (long long)i);
@@ -1919,7 +2077,7 @@ cmsvd_status cmsvd_update_batch(cmsvd_handle h, int64_t count, int64_t m, const 
         jobs.push_back(CommitJob{(int)m, r_in > 0 ? U[i] : nullptr, (long)ldu, r_in > 0 ? S[i] : nullptr, (int)r_in, B[i],
                                  (int)r, U_out[i], (long)ldu_out, S_out[i], acc[i], est ? est[i] : nullptr});
     }
-    return commit_batched(h, jobs);
+    return commit_panelled(h, jobs);
 } catch (...) {
     return caught(__func__);
 }
@@ -2076,12 +2234,14 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
         o_S[a] = pl.add((size_t)r * 8);
         o_acc[a] = pl.add(4 * 8);
     }
-    DevBuf keep;
-    if (hipMalloc((void**)&keep.p, pl.off) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(CMSVD_ENOMEM, "cmsvd_merge_errors: hipMalloc(%zu) failed", pl.off);
+    // the handle's grow-on-demand buffer: its previous contents are read only by work
+    // enqueued earlier on the same stream
+    {
+        const cmsvd_status sa = ensure(h, h->keep, h->keep_cap, pl.off);
+        if (sa != CMSVD_OK) return sa;
     }
-    auto K = [&](size_t off) { return reinterpret_cast<double*>(keep.p + off); };
+    char* const kp = h->keep;
+    auto K = [&](size_t off) { return reinterpret_cast<double*>(kp + off); };
     std::vector<cmsvd_block> bl;
     std::vector<double*> nrm, gram;
     for (size_t c = 0; c < cands.size(); ++c) {
@@ -2143,7 +2303,7 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
             if (is_cand[i])
                 pd.push_back(PackDesc{blocks[i].ptr, (int)m, (int)blocks[i].cols, (long)blocks[i].ld,
                                       blocks[i].dtype == CMSVD_F32 ? 1 : 0,
-                                      keep.p + o_Ball + (size_t)coff[i] * (all_f32 ? 4 : 8), ksum, all_f32 ? 1 : 0});
+                                      kp + o_Ball + (size_t)coff[i] * (all_f32 ? 4 : 8), ksum, all_f32 ? 1 : 0});
         Stage stg;
         const size_t o_pd = stg.add(pd);
         char* db = nullptr;
@@ -2159,7 +2319,7 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
         const size_t na = anchors.size();
         const int nmax = (int)r + kmax_c;
         const bool arrow = kmax_c == 1 && r <= 256;
-        DenseEval de{K(o_Uall), (int)na, (int)r, (int)m, in_place ? ball_user : keep.p + o_Ball, all_f32, ksum, ldball};
+        DenseEval de{K(o_Uall), (int)na, (int)r, (int)m, in_place ? ball_user : kp + o_Ball, all_f32, ksum, ldball};
         // chunks of anchors bound the products to about 8 GiB; with one chunk (every
         // candidate column in use) the product needs no pair record, so it runs while the
         // records are built and uploaded
@@ -2211,11 +2371,16 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
                 smin[a] = std::min(smin[a], tmin[t][a]);
                 smax[a] = std::max(smax[a], tmax[t][a]);
             }
-        // one upload on the side stream; the handle's stream waits for it before expanding
+        // one upload on the side stream; the handle's stream waits for it before expanding,
+        // and the side stream waits for the work already enqueued on the handle's stream
+        // (earlier calls may still read the previous records)
         st = ensure(h, h->rec, h->rec_cap, lay.total);
         if (st != CMSVD_OK) return st;
+        HIPCHK(hipEventRecord(h->tail_ev, h->stream));
+        HIPCHK(hipStreamWaitEvent(h->side, h->tail_ev, 0));
         HIPCHK(hipMemcpyAsync(h->rec, h->rec_pin, lay.total, hipMemcpyHostToDevice, h->side));
         HIPCHK(hipEventRecord(h->rec_ev, h->side));
+        h->rec_ev_armed = true;
         HIPCHK(hipStreamWaitEvent(h->stream, h->rec_ev, 0));
         const AnchorRec* dA = lay.anchors(h->rec);
         const CandRec* dC = lay.cands(h->rec);
@@ -2247,10 +2412,7 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
         }
         st = eval_batched(h, ej, (int)m);
     }
-    if (st != CMSVD_OK) return st;
-    // the per-call buffers are freed on return: wait for the work that reads them
-    HIPCHK(hipStreamSynchronize(h->stream));
-    return CMSVD_OK;
+    return st;
 } catch (...) {
     return caught(__func__);
 }
@@ -2310,6 +2472,15 @@ cmsvd_status cmsvd_gemm_bf16(cmsvd_handle h, int32_t passes, int32_t trans_a, in
     return caught(__func__);
 }
 
+cmsvd_status cmsvd_gemm_f32(cmsvd_handle h, int32_t trans_a, int32_t trans_b, int64_t M, int64_t N, int64_t K,
+                            double alpha, const void* A, int64_t lda, int32_t a_dtype, const void* B, int64_t ldb,
+                            int32_t b_dtype, double beta, double* C, int64_t ldc) try {
+    return gemm_entry(h, "cmsvd_gemm_f32", PREC_F32, trans_a, trans_b, M, N, K, alpha, A, lda, a_dtype, B, ldb,
+                      b_dtype, beta, C, ldc);
+} catch (...) {
+    return caught(__func__);
+}
+
 cmsvd_status cmsvd_cluster(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double eps,
                            int32_t sort_mode, int32_t* labels, int64_t* nclusters, double* cluster_rel) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_cluster: null handle");
@@ -2349,9 +2520,9 @@ cmsvd_status cmsvd_cluster(cmsvd_handle h, const cmsvd_block* blocks, int64_t nb
     const size_t o_first = pl.add(8);
     const size_t o_pn = pl.add((size_t)N * 8);  // ||Q^T A_j||^2 (residual sort)
     DevBuf keep;
-    if (hipMalloc((void**)&keep.p, pl.off) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(CMSVD_ENOMEM, "cmsvd_cluster: hipMalloc(%zu) failed", pl.off);
+    {
+        const cmsvd_status sa = keep.get(h, pl.off);
+        if (sa != CMSVD_OK) return sa;
     }
     auto K = [&](size_t off) { return reinterpret_cast<double*>(keep.p + off); };
     {
@@ -2956,6 +3127,76 @@ cmsvd_status cmsvd_compress(cmsvd_handle h, const cmsvd_block* blocks, int64_t n
 
 
 /* Tail energy of a chain and its gradient; see include/cmsvd.h. */
+cmsvd_status cmsvd_compress_partition(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks,
+                                      const int32_t* labels, int64_t r, double* const* Ut, const int64_t* ldu,
+                                      double* const* Vt, const int64_t* ldv, int64_t* ranks, double* tail2,
+                                      double* energy, int64_t* nclusters, double* ratio, double* rel_error) try {
+    if (!h) return fail(CMSVD_EINVAL, "cmsvd_compress_partition: null handle");
+    if (nblocks < 1 || !blocks || !labels) return fail(CMSVD_EINVAL, "cmsvd_compress_partition: no blocks or labels");
+    if (!nclusters || !ratio || !rel_error) return fail(CMSVD_EINVAL, "cmsvd_compress_partition: null output");
+    if (nblocks > INT32_MAX) return fail(CMSVD_EUNSUPPORTED, "cmsvd_compress_partition: too many blocks");
+    if ((Ut == nullptr) != (Vt == nullptr) || (Ut && (!ldu || !ldv)))
+        return fail(CMSVD_EINVAL, "cmsvd_compress_partition: give Ut, ldu, Vt and ldv together or none");
+    if (r < 1) return fail(CMSVD_ESHAPE, "cmsvd_compress_partition: r < 1");
+    const int64_t m = blocks[0].rows;
+    int32_t kmax = -1;
+    for (int64_t i = 0; i < nblocks; ++i) {
+        cmsvd_status s = check_block(blocks[i], m, "block", i);
+        if (s != CMSVD_OK) return s;
+        if (labels[i] < 0 || labels[i] >= nblocks)
+            return fail(CMSVD_EINVAL, "cmsvd_compress_partition: label %d of block %lld out of range", labels[i],
+                        (long long)i);
+        kmax = std::max(kmax, labels[i]);
+    }
+    const int K = kmax + 1;
+    std::vector<std::vector<cmsvd_block>> members((size_t)K);
+    for (int64_t i = 0; i < nblocks; ++i) members[(size_t)labels[i]].push_back(blocks[i]);
+    for (int c = 0; c < K; ++c)
+        if (members[(size_t)c].empty())
+            return fail(CMSVD_EINVAL, "cmsvd_compress_partition: cluster %d has no block (ids must be 0..K-1)", c);
+    // Without caller buffers the factors go to one scratch buffer sized for the largest
+    // cluster, reused cluster after cluster (each cmsvd_compress call is synchronous).
+    DevBuf tmp;
+    if (!Ut) {
+        size_t need = 0;
+        for (const auto& mem : members) {
+            int64_t N = 0;
+            for (const auto& b : mem) N += b.cols;
+            const int64_t rc = std::min<int64_t>({r, m, N});
+            need = std::max(need, (size_t)(rc * m + rc * N) * 8);
+        }
+        const cmsvd_status sa = tmp.get(h, need);
+        if (sa != CMSVD_OK) return sa;
+    }
+    double before = 0.0, after = 0.0, tails = 0.0, total = 0.0;
+    for (int c = 0; c < K; ++c) {
+        const auto& mem = members[(size_t)c];
+        int64_t N = 0;
+        for (const auto& b : mem) N += b.cols;
+        const int64_t rc = std::min<int64_t>({r, m, N});
+        double* u = Ut ? Ut[c] : reinterpret_cast<double*>(tmp.p);
+        double* v = Ut ? Vt[c] : reinterpret_cast<double*>(tmp.p) + (size_t)rc * m;
+        const int64_t lu = Ut ? ldu[c] : rc, lv = Ut ? ldv[c] : N;
+        int64_t rank = 0;
+        double t2 = 0.0, e2 = 0.0;
+        const cmsvd_status st = cmsvd_compress(h, mem.data(), (int64_t)mem.size(), r, u, lu, v, lv, &rank, &t2, &e2);
+        if (st != CMSVD_OK) return st;
+        if (ranks) ranks[c] = rank;
+        if (tail2) tail2[c] = t2;
+        if (energy) energy[c] = e2;
+        before += (double)m * (double)N;
+        after += (double)rank * (double)(m + N);
+        tails += t2;
+        total += e2;
+    }
+    *nclusters = K;
+    *ratio = after > 0.0 ? before / after : 0.0;
+    *rel_error = total > 0.0 ? std::sqrt(tails / total) : 0.0;
+    return CMSVD_OK;
+} catch (...) {
+    return caught(__func__);
+}
+
 cmsvd_status cmsvd_tail_energy_grad(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r,
                                     int64_t checkpoint, double* f, double* const* grads, double* min_gap) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_tail_energy_grad: null handle");
@@ -2989,10 +3230,9 @@ cmsvd_status cmsvd_tail_energy_grad(cmsvd_handle h, const cmsvd_block* blocks, i
                              + (size_t)kmax * M + T + 8               // residual basis, gaps, scratch acc
                              + (size_t)R * M;                         // U_{t+1} across a segment boundary
     DevBuf mem;
-    if (hipMalloc((void**)&mem.p, n_doubles * 8) != hipSuccess) {
-        (void)hipGetLastError();
-        mem.p = nullptr;
-        return fail(CMSVD_ENOMEM, "cmsvd_tail_energy_grad: hipMalloc(%zu bytes) failed", n_doubles * 8);
+    {
+        const cmsvd_status sa = mem.get(h, n_doubles * 8);
+        if (sa != CMSVD_OK) return sa;
     }
     double* base = reinterpret_cast<double*>(mem.p);
     double* ckp = base;

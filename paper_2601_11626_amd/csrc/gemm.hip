@@ -375,4 +375,138 @@ void gemm_bf16_batched(const GemmDesc* d_descs, int count, int maxM, int maxN, b
     else launch_bf16_types<false>(d_descs, count, maxM, maxN, transA, transB, a_f32, b_f32, alpha, beta, s);
 }
 
+// ---------------------------------------------------------------------------
+// Grouped batched GEMM with FP32 operands and FP32 accumulation on the CDNA4 matrix
+// cores (v_mfma_f32_16x16x4f32), for the FP32 projection option.
+//
+//   C_b = alpha * op(A_b) * op(B_b) + beta * C_b      (C FP64, column-major)
+//
+// Every operand element is rounded to FP32 (round-to-nearest-even; FP32 data stays as
+// it is) while it is staged into LDS; the matrix cores sum the products in FP32 and C
+// receives the sums widened to FP64.  Tiling as the FP64 kernel (a 64 x 64 C tile per
+// 256-thread workgroup, a 32 x 32 quadrant of 2 x 2 MFMA blocks per wave), with K
+// slabs of 32 (half the LDS bytes per element, so twice the depth per barrier),
+// double-buffered.
+// ---------------------------------------------------------------------------
+constexpr int FBK = 32;
+constexpr int FPAD = 4;  // LDS row padding (floats)
+
+template <bool TRANS>
+__device__ __forceinline__ void store_tile_lds_f32(float (*S)[GBM + FPAD], const double (&reg)[4], int t, int k0) {
+    if (!TRANS) {
+        const int kk = t >> 4, i0 = (t & 15) * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) S[k0 + kk][i0 + q] = (float)reg[q];
+    } else {
+        const int i = t >> 2, kq = (t & 3) * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) S[k0 + kq + q][i] = (float)reg[q];
+    }
+}
+
+template <typename TA, typename TB, bool TA_T, bool TB_T>
+__global__ void __launch_bounds__(256) gemm_f32_kernel(const GemmDesc* __restrict__ descs, int base,
+                                                       double alpha, double beta) {
+    const GemmDesc d = descs[base + blockIdx.y];
+    const int tilesM = (d.M + GBM - 1) / GBM;
+    const int tilesN = (d.N + GBN - 1) / GBN;
+    if ((int)blockIdx.x >= tilesM * tilesN) return;
+    const int tm = blockIdx.x % tilesM, tn = blockIdx.x / tilesM;
+    const int m0 = tm * GBM, n0 = tn * GBN;
+    const TA* __restrict__ A = static_cast<const TA*>(d.A);
+    const TB* __restrict__ B = static_cast<const TB*>(d.B);
+
+    __shared__ float As[2][FBK][GBM + FPAD];
+    __shared__ float Bs[2][FBK][GBN + FPAD];
+
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    f4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
+
+    // a slab of 32 K values is two 64 x 16 half-slabs of the FP64 kernel's loader (the
+    // values are exact in FP64 and rounded once, to FP32, when stored)
+    double ra[2][4], rb[2][4];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int hs = 0; hs < 2; ++hs) {
+            load_tile_regs<TA, TA_T>(A, d.lda, d.M, d.K, m0, k0 + 16 * hs, ra[hs], t);
+            load_tile_regs<TB, !TB_T>(B, d.ldb, d.N, d.K, n0, k0 + 16 * hs, rb[hs], t);
+        }
+    };
+    auto stage = [&](int buf) {
+#pragma unroll
+        for (int hs = 0; hs < 2; ++hs) {
+            store_tile_lds_f32<TA_T>(As[buf], ra[hs], t, 16 * hs);
+            store_tile_lds_f32<!TB_T>(Bs[buf], rb[hs], t, 16 * hs);
+        }
+    };
+    const int nk = (d.K + FBK - 1) / FBK;
+    fetch(0);
+    stage(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) fetch((kt + 1) * FBK);
+        // A operand: lane holds row (lane % 16), K value lane / 16 of the 4-deep step;
+        // B operand: column (lane % 16), the same K value.
+#pragma unroll
+        for (int k4 = 0; k4 < FBK / 4; ++k4) {
+            const int krow = k4 * 4 + (lane >> 4);
+            const float a0 = As[cur][krow][wm * 32 + (lane & 15)];
+            const float a1 = As[cur][krow][wm * 32 + 16 + (lane & 15)];
+            const float b0 = Bs[cur][krow][wn * 32 + (lane & 15)];
+            const float b1 = Bs[cur][krow][wn * 32 + 16 + (lane & 15)];
+            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        if (kt + 1 < nk) stage(cur ^ 1);
+        __syncthreads();
+    }
+    // D[i][j] of a 16x16 FP32 block sits in lane j + 16*(i/4), element i%4.
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + wm * 32 + bi * 16 + (lane >> 4) * 4 + v;
+                const int col = n0 + wn * 32 + bj * 16 + (lane & 15);
+                if (row < d.M && col < d.N) {
+                    double* c = d.C + (long)row + (long)col * d.ldc;
+                    double val = alpha * (double)acc[bi][bj][v];
+                    if (beta != 0.0) val += beta * (*c);
+                    *c = val;
+                }
+            }
+}
+
+template <typename TA, typename TB>
+static void launch_f32(const GemmDesc* descs, int count, int maxM, int maxN, bool ta, bool tb, double alpha,
+                       double beta, hipStream_t s) {
+    const int tiles = ((maxM + GBM - 1) / GBM) * ((maxN + GBN - 1) / GBN);
+    for (int base = 0; base < count; base += 65535) {
+        const int n = count - base < 65535 ? count - base : 65535;
+        dim3 grid(tiles, n), block(256);
+        if (!ta && !tb) hipLaunchKernelGGL((gemm_f32_kernel<TA, TB, false, false>), grid, block, 0, s, descs, base, alpha, beta);
+        if (!ta && tb) hipLaunchKernelGGL((gemm_f32_kernel<TA, TB, false, true>), grid, block, 0, s, descs, base, alpha, beta);
+        if (ta && !tb) hipLaunchKernelGGL((gemm_f32_kernel<TA, TB, true, false>), grid, block, 0, s, descs, base, alpha, beta);
+        if (ta && tb) hipLaunchKernelGGL((gemm_f32_kernel<TA, TB, true, true>), grid, block, 0, s, descs, base, alpha, beta);
+    }
+}
+
+void gemm_f32_batched(const GemmDesc* d_descs, int count, int maxM, int maxN, bool transA, bool transB,
+                      bool a_f32, bool b_f32, double alpha, double beta, hipStream_t s) {
+    if (count <= 0 || maxM <= 0 || maxN <= 0) return;
+    if (a_f32 && b_f32) launch_f32<float, float>(d_descs, count, maxM, maxN, transA, transB, alpha, beta, s);
+    else if (a_f32) launch_f32<float, double>(d_descs, count, maxM, maxN, transA, transB, alpha, beta, s);
+    else if (b_f32) launch_f32<double, float>(d_descs, count, maxM, maxN, transA, transB, alpha, beta, s);
+    else launch_f32<double, double>(d_descs, count, maxM, maxN, transA, transB, alpha, beta, s);
+}
+
 }  // namespace cmsvd

@@ -25,6 +25,10 @@ void gemm_f64_batched(const GemmDesc* d_descs, int count, int maxM, int maxN, bo
 // passes = 1: hi parts only; 3: lo_A hi_B + hi_A lo_B + hi_A hi_B (split operands).
 void gemm_bf16_batched(const GemmDesc* d_descs, int count, int maxM, int maxN, bool transA, bool transB,
                        bool a_f32, bool b_f32, int passes, double alpha, double beta, hipStream_t s);
+// Same descriptors and semantics with the operands rounded to FP32 (round-to-nearest-
+// even) and FP32 accumulation on the matrix cores; C stays FP64.
+void gemm_f32_batched(const GemmDesc* d_descs, int count, int maxM, int maxN, bool transA, bool transB,
+                      bool a_f32, bool b_f32, double alpha, double beta, hipStream_t s);
 
 // One symmetric eigenvalue problem of order n, given in block-arrow form
 //     H = [[ diag(s)^2        , diag(s) P ],
