@@ -365,6 +365,27 @@ cmsvd_status cmsvd_tail_energy_grad(cmsvd_handle handle, const cmsvd_block* bloc
 cmsvd_status cmsvd_sym_eigvals(cmsvd_handle handle, const double* A, int64_t n, int64_t lda, int64_t stride_a,
                                int64_t count, int64_t nkeep, double* lam);
 
+/* Size in bytes of the fixed device scratch of cmsvd_sym_eigvals_noalloc. */
+#define CMSVD_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory: code under HIP graph capture, tight
+   serving loops, harnesses that forbid hipMalloc.  The same computation and kernels as
+   cmsvd_sym_eigvals (same arguments, layout, results and errors), but it calls no
+   hipMalloc, hipFree, host staging copy or other allocating routine: the per-problem
+   descriptors are written by a kernel, and they and the eigen kernel's tile slots live
+   in a fixed array of CMSVD_NOALLOC_SCRATCH_BYTES in the library's code object (one
+   copy per device, held until the process ends, its address looked up when a handle is
+   created on that device).  Orders above 320 keep T (T + 1) / 2 tiles of 32 x 32
+   doubles per workgroup slot (T = ceil(n / 32)); the call runs as many slots as fit
+   beside the descriptors (at least one, so order 2016 runs on 3 workgroups: correct but
+   slow).  A count or order whose descriptors and one slot do not fit returns
+   CMSVD_EUNSUPPORTED before any launch.  Every call on a device shares that device's
+   scratch and leaves its contents behind: calls that overlap on one device (several
+   handles or streams) race and must be ordered by the caller.  Asynchronous on the
+   handle's stream. */
+cmsvd_status cmsvd_sym_eigvals_noalloc(cmsvd_handle handle, const double* A, int64_t n, int64_t lda,
+                                       int64_t stride_a, int64_t count, int64_t nkeep, double* lam);
+
 /* Stage timing for measurement (off by default).  When enabled, every pipeline stage
    launched on the handle's stream is bracketed by HIP events recorded on that same
    stream.  Stages: 0 = block norms and Grams B^T B, 1 = commit pipeline (anchor

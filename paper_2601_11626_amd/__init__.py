@@ -48,6 +48,7 @@ def _load():
     lib.cmsvd_merge_errors.argtypes = [vp, ctypes.POINTER(Block), i64, vp, i64, i64, vp, vp]
     lib.cmsvd_cluster.argtypes = [vp, ctypes.POINTER(Block), i64, i64, d, i32, vp, ctypes.POINTER(i64), vp]
     lib.cmsvd_sym_eigvals.argtypes = [vp, vp, i64, i64, i64, i64, i64, vp]
+    lib.cmsvd_sym_eigvals_noalloc.argtypes = [vp, vp, i64, i64, i64, i64, i64, vp]
     lib.cmsvd_gemm_f64.argtypes = [vp, i32, i32, i64, i64, i64, d, vp, i64, i32, vp, i64, i32, d, vp, i64]
     lib.cmsvd_gemm_bf16.argtypes = [vp, i32, i32, i32, i64, i64, i64, d, vp, i64, i32, vp, i64, i32, d, vp, i64]
     lib.cmsvd_gemm_f32.argtypes = [vp, i32, i32, i64, i64, i64, d, vp, i64, i32, vp, i64, i32, d, vp, i64]
@@ -70,7 +71,7 @@ def _load():
               "cmsvd_cluster", "cmsvd_sym_eigvals", "cmsvd_gemm_f64", "cmsvd_profile", "cmsvd_profile_read",
               "cmsvd_tail_energy_grad", "cmsvd_update_batch", "cmsvd_cluster_residual", "cmsvd_residual_bound",
               "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail", "cmsvd_compress", "cmsvd_gemm_bf16",
-              "cmsvd_set_projection", "cmsvd_gemm_f32", "cmsvd_create_ex",
+              "cmsvd_set_projection", "cmsvd_sym_eigvals_noalloc", "cmsvd_gemm_f32", "cmsvd_create_ex",
               "cmsvd_compress_partition"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
@@ -82,7 +83,7 @@ EXPORTS = ("cmsvd_create", "cmsvd_destroy", "cmsvd_set_stream", "cmsvd_last_erro
            "cmsvd_merge_errors", "cmsvd_cluster", "cmsvd_sym_eigvals", "cmsvd_gemm_f64", "cmsvd_profile",
            "cmsvd_profile_read", "cmsvd_tail_energy_grad", "cmsvd_update_batch", "cmsvd_cluster_residual",
            "cmsvd_residual_bound", "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail", "cmsvd_compress",
-           "cmsvd_gemm_bf16", "cmsvd_set_projection", "cmsvd_gemm_f32",
+           "cmsvd_gemm_bf16", "cmsvd_set_projection", "cmsvd_sym_eigvals_noalloc", "cmsvd_gemm_f32",
            "cmsvd_create_ex", "cmsvd_compress_partition")
 
 PROJECTIONS = {"f64": 0, "bf16": 1, "bf16x3": 2, "f32": 3}  # cmsvd_projection
@@ -536,6 +537,23 @@ def cmsvd_sym_eigvals(A: torch.Tensor, nkeep: int, handle: Handle | None = None)
     return lam.reshape(*A.shape[:-2], nkeep)
 
 
+def cmsvd_sym_eigvals_noalloc(A: torch.Tensor, nkeep: int, lam: torch.Tensor,
+                              handle: Handle | None = None) -> torch.Tensor:
+    """cmsvd_sym_eigvals into a caller-provided output (lam, (..., nkeep) FP64) through
+    the entry point that allocates nothing: A must already be a contiguous CUDA float64
+    batch (..., n, n), so that no copy is made here either."""
+    if A.dtype != torch.float64 or not A.is_cuda or not A.is_contiguous():
+        raise ValueError("A must be a contiguous CUDA float64 tensor")
+    n = A.shape[-1]
+    count = A.numel() // (n * n) if n else 0
+    if lam.dtype != torch.float64 or not lam.is_contiguous() or lam.numel() != count * nkeep:
+        raise ValueError("lam must be a contiguous float64 tensor of count x nkeep entries")
+    h = handle or default_handle(A.device)
+    _check(_lib.cmsvd_sym_eigvals_noalloc(h.ptr, ctypes.c_void_p(A.data_ptr()), n, n, n * n, count, nkeep,
+                                          ctypes.c_void_p(lam.data_ptr())))
+    return lam
+
+
 def cmsvd_gemm_f64(opA: torch.Tensor, opB: torch.Tensor, C: torch.Tensor | None = None, alpha: float = 1.0,
                    beta: float = 0.0, handle: Handle | None = None) -> torch.Tensor:
     """C = alpha opA @ opB + beta C on the matrix cores.  opA (M x K) and opB (K x N) may be
@@ -586,5 +604,5 @@ def _gemm(fn, opA, opB, C, alpha, beta, handle):
 __all__ = ["cmsvd_gemm_f64", "cmsvd_gemm_bf16", "cmsvd_gemm_f32", "PROJECTIONS", "BlockArray", "Handle", "State", "Block", "CmsvdError", "cmsvd_update", "cmsvd_update_batch",
            "cmsvd_merge_errors", "cmsvd_cluster", "cmsvd_cluster_residual", "cmsvd_residual_bound",
            "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail", "cmsvd_compress", "compress_partition",
-           "cmsvd_sym_eigvals", "cmsvd_tail_energy_grad", "TailEnergy", "tail_energy", "default_handle",
+           "cmsvd_sym_eigvals", "cmsvd_sym_eigvals_noalloc", "cmsvd_tail_energy_grad", "TailEnergy", "tail_energy", "default_handle",
            "LIB_PATH", "EXPORTS"]

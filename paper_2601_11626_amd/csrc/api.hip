@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -119,6 +120,7 @@ struct cmsvd_ctx {
     size_t rec_cap = 0;
     hipStream_t side = nullptr;  // uploads that overlap work on the handle's stream
     hipEvent_t rec_ev = nullptr;
+    char* scratch = nullptr;     // this device's copy of the fixed no-allocation scratch
     // device memory: the caller's allocator when given (cmsvd_create_ex), else hipMalloc
     void* (*alloc_fn)(size_t, void*) = nullptr;
     void (*release_fn)(void*, void*) = nullptr;
@@ -138,7 +140,49 @@ struct cmsvd_ctx {
     std::vector<hipEvent_t> pool;
 };
 
+// Fixed device scratch of the no-allocation entry point: an array in the code object,
+// one copy per device the library runs on, held until the process ends.  Host code
+// never passes the array's name to a kernel or a copy: it uses the device address that
+// hipGetSymbolAddress returns for the current device, looked up once per device when a
+// handle is created there.
+__device__ __align__(256) char scratch[CMSVD_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+std::mutex g_scratch_mu;
+std::vector<char*> g_scratch_addr;  // per device ordinal; null until looked up
+
+cmsvd_status scratch_address(int device, char** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_addr.size() <= device) g_scratch_addr.resize((size_t)device + 1, nullptr);
+    if (!g_scratch_addr[(size_t)device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(CMSVD_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", device,
+                        hipGetErrorString(e));
+        }
+        g_scratch_addr[(size_t)device] = static_cast<char*>(p);
+    }
+    *out = g_scratch_addr[(size_t)device];
+    return CMSVD_OK;
+}
+
+// The descriptors of cmsvd_sym_eigvals_noalloc, written on the device (no host staging).
+__global__ void eigvals_descs_kernel(EigDesc* __restrict__ out, const double* A, int n, long lda, long stride_a,
+                                     long count, int nkeep, double* lam) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long)gridDim.x * blockDim.x) {
+        EigDesc e{};
+        e.n = n;
+        e.n1 = 0;
+        e.nkeep = nkeep;
+        e.Y = A + i * stride_a;
+        e.ldy = lda;
+        e.lam = lam + i * nkeep;
+        out[i] = e;
+    }
+}
 
 // Device memory of a handle: through the caller's allocator when one was given at
 // creation, otherwise hipMalloc / hipFree.  Every device buffer of the library (the
@@ -1925,6 +1969,13 @@ cmsvd_status cmsvd_create_ex(cmsvd_handle* handle, void* hip_stream, const cmsvd
         return fail(CMSVD_EUNSUPPORTED, "device %s is not gfx950", prop.gcnArchName);
     }
     h->ncu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    {
+        const cmsvd_status ss = scratch_address(h->device, &h->scratch);
+        if (ss != CMSVD_OK) {
+            delete h;
+            return ss;
+        }
+    }
     if (hipEventCreateWithFlags(&h->pin_ev, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&h->rec_ev, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&h->tail_ev, hipEventDisableTiming) != hipSuccess ||
@@ -2447,6 +2498,40 @@ cmsvd_status cmsvd_sym_eigvals(cmsvd_handle h, const double* A, int64_t n, int64
     if (st != CMSVD_OK) return st;
     sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o), (int)count, (int)n, 1,
                     reinterpret_cast<double*>(h->ws + eig_off), nslots, h->stream);
+    HIPCHK(hipGetLastError());
+    return CMSVD_OK;
+} catch (...) {
+    return caught(__func__);
+}
+
+cmsvd_status cmsvd_sym_eigvals_noalloc(cmsvd_handle h, const double* A, int64_t n, int64_t lda, int64_t stride_a,
+                                       int64_t count, int64_t nkeep, double* lam) try {
+    if (!h) return fail(CMSVD_EINVAL, "cmsvd_sym_eigvals_noalloc: null handle");
+    if (!A || !lam) return fail(CMSVD_EINVAL, "cmsvd_sym_eigvals_noalloc: null pointer");
+    if (n < 1 || lda < n || count < 0 || nkeep < 1 || nkeep > n)
+        return fail(CMSVD_ESHAPE, "cmsvd_sym_eigvals_noalloc: bad sizes");
+    if (n > sym_eig_nmax()) return fail(CMSVD_EUNSUPPORTED, "cmsvd_sym_eigvals_noalloc: n > %d", sym_eig_nmax());
+    if (count == 0) return CMSVD_OK;
+    const size_t cap = (size_t)CMSVD_NOALLOC_SCRATCH_BYTES;
+    if (count > (int64_t)(cap / sizeof(EigDesc)))
+        return fail(CMSVD_EUNSUPPORTED, "cmsvd_sym_eigvals_noalloc: %lld problems exceed the %zu-byte scratch",
+                    (long long)count, cap);
+    const size_t dbytes = align256((size_t)count * sizeof(EigDesc));
+    const size_t slot = sym_eig_slot_doubles((int)n) * 8;
+    int64_t nslots = std::min<int64_t>(count, h->ncu);
+    if (slot > 0) nslots = std::min<int64_t>(nslots, dbytes < cap ? (int64_t)((cap - dbytes) / slot) : 0);
+    if (nslots < 1)
+        return fail(CMSVD_EUNSUPPORTED,
+                    "cmsvd_sym_eigvals_noalloc: %lld problems of order %lld exceed the %zu-byte scratch",
+                    (long long)count, (long long)n, cap);
+    // scratch: [descriptors][eigen kernel slots], at this device's address of the array
+    EigDesc* descs = reinterpret_cast<EigDesc*>(h->scratch);
+    double* gws = reinterpret_cast<double*>(h->scratch + dbytes);
+    const int grid = (int)std::min<int64_t>((count + 255) / 256, 1024);
+    hipLaunchKernelGGL(eigvals_descs_kernel, dim3(grid), dim3(256), 0, h->stream, descs, A, (int)n, (long)lda,
+                       (long)stride_a, (long)count, (int)nkeep, lam);
+    HIPCHK(hipGetLastError());
+    sym_eig_batched(descs, (int)count, (int)n, 1, gws, (int)nslots, h->stream);
     HIPCHK(hipGetLastError());
     return CMSVD_OK;
 } catch (...) {

@@ -1455,6 +1455,12 @@ size_t sym_eig_workspace_doubles(int nmax, int nslots) {
     return (size_t)nslots * (size_t)T * (size_t)(T + 1) / 2 * TILE_EL;
 }
 
+size_t sym_eig_slot_doubles(int nmax) {
+    // only the general kernel (more than REG_TMAX tile rows) keeps tiles in global slots
+    const int T = (nmax + TILE - 1) / TILE;
+    return T <= REG_TMAX ? 0 : (size_t)T * (size_t)(T + 1) / 2 * TILE_EL;
+}
+
 void sym_eig_batched(const EigDesc* d_descs, int count, int nmax, int mode, double* gws, int nslots,
                      hipStream_t s) {
     if (count <= 0) return;

@@ -63,6 +63,9 @@ struct EigDesc {
 void sym_eig_batched(const EigDesc* d_descs, int count, int nmax, int mode, double* gws, int nslots,
                      hipStream_t s);
 size_t sym_eig_workspace_doubles(int nmax, int nslots);
+// Doubles of global scratch one workgroup slot of sym_eig_batched needs for order nmax
+// (0 when the kernel chosen for that order keeps every tile on chip).
+size_t sym_eig_slot_doubles(int nmax);
 // Evaluation mode for cores of one appended column (every descriptor n = n1 + 1 with
 // n1 <= 256 and nkeep >= n1): the arrowhead's smallest eigenvalue, bracketed by the sign
 // of the Schur complement of the border (the inertia) with model-based probes; writes
