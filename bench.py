@@ -4,8 +4,10 @@ Workload: 256 FP32 blocks of 1024 x 256 in 16 groups (shared 1024 x 32 bases rot
 per block by principal angles ~U(0, 0.3)), rank r = 64, all 32,640 anchor-first pairs
 in one batched evaluation.  One step = one cmsvd_merge_errors call over all pairs:
 block norms and Grams, anchor initialisation (rank-64 truncated SVD of every anchor),
-projections, core eigenvalues and plug-in errors.  Inputs are resident in HBM before
-the timed region.
+projections (FP32 operands on the FP32 matrix cores by default, --projection), core
+eigenvalues and plug-in errors (FP64).  Inputs are resident in HBM before the timed
+region.  The same steps are then replayed from a captured HIP graph (the `graph` field,
+capture time apart).
 
 Also reported on the same GPU: the plain per-pair method (one cmsvd_merge_errors call
 per pair, serialised, no reuse across pairs), the same per-pair math in library form
@@ -110,7 +112,9 @@ def _pmc_rows(path):
     return rows  # (dispatch, kernel) -> counter summed over its instances (KiB)
 
 
-EIG_KERNEL = "sym_eig_reg_kernel<0, 512, 5, 5, 10>"  # the headline launch (n = 320: 5 x 64 tiles)
+# the headline's dominant launch: the register-resident tridiagonalisation of the split
+# evaluation (n = 320: 10 tile rows of 32), whose bisection runs in tri_bisect_kernel
+EIG_KERNEL = "sym_eig_reg_kernel<2, 512, 5, 5, 10>"
 
 
 def pmc_summary(fetch_csv, write_csv, copy_mib, kernel=EIG_KERNEL):
@@ -216,6 +220,73 @@ def chain_grad(args, cm, workloads, torch):
     print(json.dumps(out), flush=True)
 
 
+def decision_replay(cm, h, blocks, blocks_np, clusters, r, eps, args):
+    """Re-takes a seeded sample of the clustering's decisions with the oracle, in the same
+    projection precision, on the device's own states: each cluster's anchor and
+    acceptances are committed again in the recorded order (cmsvd_cluster_trace), an
+    accepted candidate must have rel <= eps (1 + 1e-3) against the state before it, and
+    a block of a later cluster rel > eps (1 - 1e-3) against the cluster's final state
+    (its last pass rejected every remaining block).  Narrow candidates (<= 256 columns)
+    keep the oracle's eigenvalue problems small."""
+    import math
+
+    import oracle
+    from oracle import lowprec
+
+    trace = cm.cmsvd_cluster_trace(h)
+    m = int(blocks_np[0].shape[0])
+    rng = np.random.default_rng(7)
+    seq, off = [], 0
+    for mem in clusters:
+        seq.append(trace[off:off + len(mem)])
+        off += len(mem)
+
+    def ostate(st):
+        S = st.S.cpu().numpy()
+        keep = S > 0
+        o = oracle.State(m)
+        o.U = np.asfortranarray(st.U.cpu().numpy()[:, keep])
+        o.sigma = S[keep].copy()
+        o.energy_terms = [float(x) for x in st.acc.cpu().numpy()[:2]]
+        return o
+
+    def orel(o, j):
+        e2, et = lowprec.candidate_estimate2(o, blocks_np[j], r, args.projection)
+        return math.sqrt(e2 / et)
+
+    t0 = time.perf_counter()
+    acc, rej, bad = [], [], []
+    later = set(range(len(blocks_np)))
+    multi = [c for c, part in enumerate(seq) if len(part) > 1]
+    want = set(rng.permutation(multi)[:args.replay].tolist())
+    for c, part in enumerate(seq):
+        later -= set(part)
+        if c not in want:
+            continue
+        st = cm.State(m, r, blocks[0].device)
+        states = []
+        for j in part:
+            states.append(st)
+            st = cm.cmsvd_update(st, blocks[j], handle=h)
+        narrow = [t for t in range(1, len(part)) if blocks_np[part[t]].shape[1] <= 256]
+        for t in rng.permutation(narrow)[:1]:
+            v = orel(ostate(states[t]), part[t])
+            acc.append(v)
+            if v > eps * (1 + 1e-3):
+                bad.append(("accept", c, part[t], v))
+        cand = [j for j in sorted(later) if blocks_np[j].shape[1] <= 256]
+        for j in rng.permutation(cand)[:1]:
+            v = orel(ostate(st), j)
+            rej.append(v)
+            if v <= eps * (1 - 1e-3):
+                bad.append(("reject", c, j, v))
+    out = {"acceptances": len(acc), "rejections": len(rej), "disagreements": len(bad),
+           "max_accepted_rel": max(acc) if acc else None, "min_rejected_rel": min(rej) if rej else None,
+           "seconds": round(time.perf_counter() - t0, 1)}
+    log(f"decision replay {out} {bad[:3]}")
+    return out
+
+
 def cluster(args, cm, workloads, torch):
     """Algorithm 3 on 512 FP32 blocks with 4096 rows and widths U{64..1024} from 32
     latent 4096 x 48 subspaces (noise 1e-2), relative threshold 0.1, norm-ordered scan,
@@ -235,6 +306,13 @@ def cluster(args, cm, workloads, torch):
     log(f"generated {len(blocks)} blocks, widths {min(widths)}..{max(widths)} in {time.time() - t0:.1f}s")
     h = cm.default_handle(dev)
     h.set_projection(args.projection)
+    tuned = None
+    if args.autotune:
+        # the scan schedule for the median candidate width, measured (or loaded) first
+        ta = time.perf_counter()
+        chunk = h.autotune(int(blocks_np[0].shape[0]), int(np.median(widths)), r, args.autotune)
+        tuned = {"scan_chunk": chunk, "seconds": round(time.perf_counter() - ta, 3), "cache": args.autotune}
+        log(f"autotuned scan chunk {tuned}")
     h.profile(True)
     h.profile_read()
     t1 = time.perf_counter()
@@ -245,6 +323,7 @@ def cluster(args, cm, workloads, torch):
     h.profile(False)
     log(f"clustered into {len(cl)} clusters in {el:.1f}s ({args.projection} projections); stages {stages}")
     sizes = sorted((len(c) for c in cl), reverse=True)
+    replay = decision_replay(cm, h, blocks, blocks_np, cl, r, 0.1, args) if args.replay > 0 else None
     versus = None
     if args.compare_f64 and args.projection != "f64":
         h.set_projection("f64")
@@ -296,6 +375,8 @@ def cluster(args, cm, workloads, torch):
                                f"subspaces, noise 1e-2, r={r}, eps=0.1, frobenius order",
                    "r": r, "eps": 0.1, "projection": args.projection},
         "clusters": len(cl),
+        "autotune": tuned,
+        "decision_replay": replay,
         "largest_clusters": sizes[:8],
         "max_cluster_rel": max(crel) if crel else None,
         "stages_ms_launches": {k: [round(v[0], 1), v[1]] for k, v in stages.items()},
@@ -768,7 +849,13 @@ def main():
     ap.add_argument("--sort-mode", default="frobenius", choices=("frobenius", "residual"),
                     help="cluster_residual: candidate order of a pass")
     ap.add_argument("--cpu-chains", type=int, default=6, help="cluster_residual: oracle sample (narrow pairs)")
-    ap.add_argument("--projection", default="f64", choices=("f64", "bf16", "bf16x3", "f32"),
+    ap.add_argument("--graph-steps", type=int, default=5,
+                    help="pairs: steps replayed from a captured HIP graph after the timed eager steps (0: none)")
+    ap.add_argument("--autotune", default=None, metavar="CACHE",
+                    help="cluster: tune the scan schedule first (JSON cache path; loaded when present)")
+    ap.add_argument("--replay", type=int, default=0,
+                    help="cluster: clusters whose decisions the oracle re-takes on the device states")
+    ap.add_argument("--projection", default="f32", choices=("f64", "bf16", "bf16x3", "f32"),
                     help="pairs, cluster: precision of the candidate projections")
     ap.add_argument("--compare-f64", action="store_true", help="cluster: also run the FP64 clustering")
     ap.add_argument("--parity-pairs", type=int, default=48, help="cluster: oracle sample (narrow pairs)")
@@ -856,6 +943,30 @@ def main():
     err_h = err.cpu().numpy()
     rel_h = rel.cpu().numpy()
 
+    # The same step replayed from a captured HIP graph (cmsvd_options.graphs): the first
+    # call runs eagerly, the second is captured (its wall time reported apart), and the
+    # timed replays launch the graph on the same stream.
+    graph = None
+    if args.graph_steps > 0:
+        hg = cm.Handle(dev, projection=args.projection, graphs=True)
+        out = (torch.empty(npairs, dtype=torch.float64, device=dev), torch.empty(npairs, dtype=torch.float64, device=dev))
+        barr = cm.BlockArray(blocks)
+        for _ in range(2):
+            cm.cmsvd_merge_errors(barr, pairs, r, handle=hg, out=out)
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(args.graph_steps):
+            cm.cmsvd_merge_errors(barr, pairs, r, handle=hg, out=out)
+        torch.cuda.synchronize()
+        gel = time.perf_counter() - tg
+        gs = hg.graph_stats()
+        gdev = float(np.max(np.abs(out[0].cpu().numpy() - err_h) / np.maximum(err_h, 1e-300)))
+        graph = {"value": round(npairs * args.graph_steps / gel, 2), "unit": "merges/s", "steps": args.graph_steps,
+                 "ms_per_step": round(1000.0 * gel / args.graph_steps, 3), "capture_ms": round(gs["last_capture_ms"], 3),
+                 "captures": gs["captures"], "replays": gs["replays"], "max_rel_diff_vs_eager": gdev}
+        log(f"graph replays: {graph}")
+        hg.close()
+
     # plain per-pair method on a sample of the same pairs
     rng = np.random.default_rng(1)
     plain = None
@@ -904,13 +1015,13 @@ def main():
         "projection": 2.0 * r * k * m * npairs * args.steps,
         "core_eig": (4.0 / 3.0) * float(r + k) ** 3 * npairs * args.steps,
     }
-    timed = {n: stages[n][0] for n in ("commit", "projection", "core_eig")}
+    timed = {n: stages[n][0] for n in ("commit", "projection", "core_eig", "core_bisect")}
     dom = max(timed, key=timed.get)
     roof = None
     if dom in flops and timed[dom] > 0:
         ach = flops[dom] / (timed[dom] * 1e-3) / 1e12
         roof = {
-            "kernel": (EIG_KERNEL + " (tridiagonalisation + bisection)") if dom == "core_eig" else "gemm_f64_kernel (Y = U^T B)",
+            "kernel": (EIG_KERNEL + " (tridiagonalisation)") if dom == "core_eig" else "gemm_f64_kernel (Y = U^T B)",
             "bound": "alu" if dom == "core_eig" else "mfma",
             "achieved": round(ach, 3),
             "peak": PEAK_FP64_TFLOPS,
@@ -985,6 +1096,7 @@ def main():
         },
         "plain": plain,
         "speedup_vs_plain": round(value / plain["value"], 2) if plain else None,
+        "graph": graph,
         "library": library,
         "stages_ms_per_step": {n: round(stages[n][0] / args.steps, 3) for n in stages},
         "roofline": roof,

@@ -99,11 +99,23 @@ typedef struct {
                   consecutive column panels of this width (the last one narrower): the
                   same concatenation, truncated after every panel (Lemma 1 holds for any
                   blocking), so results depend on it.  0 = whole blocks (the default).
+     graphs       nonzero: repeated cmsvd_merge_errors calls are replayed from a captured
+                  HIP graph.  The first call with a given set of arguments (block
+                  descriptors, pair list, r, output pointers, projection) runs eagerly and
+                  sizes the workspaces; the second captures its launch sequence (kernel
+                  nodes only: descriptor tables go to a buffer the graph owns, copied once
+                  after the capture) and launches it; later ones launch the graph.  A graph
+                  is dropped when a workspace it refers to is reallocated (it is then
+                  captured again), and the four most recently used are kept.  A replay
+                  reads the blocks' current contents.  Calls whose candidates take the
+                  dense projection (thin blocks) are never captured.  Not used while stage
+                  timing is on.  0 (the default): every call runs eagerly.
    CholeskyQR always takes two passes. */
 typedef struct {
     int32_t projection;
     double chol_tau;
     int64_t panel_cols;
+    int32_t graphs;
 } cmsvd_options;
 
 /* Creates a handle bound to a HIP stream (NULL = the default stream).  The current
@@ -215,6 +227,33 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle handle, const cmsvd_block* blocks, 
 cmsvd_status cmsvd_cluster(cmsvd_handle handle, const cmsvd_block* blocks, int64_t nblocks, int64_t r,
                            double eps, int32_t sort_mode, int32_t* labels, int64_t* nclusters,
                            double* cluster_rel);
+
+/* Autotuner of the scan schedule of Algorithm 3 (cmsvd_cluster): after an acceptance
+   the scan evaluates the rest of the pass in chunks, the first of `chunk` candidates,
+   doubling while none is feasible.  For candidates of width k (bucketed to the next
+   power of two, at least 16) appended to rank-r states of m rows, with the handle's
+   projection precision, it times one evaluation launch sequence of c synthetic
+   candidates for c = 16, 32, .., 1024 (HIP events, best of three after a warm-up) and
+   picks the largest c that costs at most 15 % more than c = 16: the candidates the
+   device evaluates side by side for about the price of the smallest chunk.  The choice
+   is kept in the handle (cmsvd_cluster uses the entry of the median remaining width;
+   shapes without one start at a quarter of the compute units) and in cache_path (may be
+   NULL), a JSON object with one entry per line keyed "gfx950 m=.. k=.. r=.. proj=..",
+   holding the chosen chunk and the measured times.  An entry already in the cache is
+   loaded instead of measured unless force is nonzero.
+     chunk_out   HOST out (may be NULL): the chunk chosen
+   Synchronous; uses about (2 m k + m r + k^2) doubles of device memory while it runs. */
+cmsvd_status cmsvd_autotune(cmsvd_handle handle, int64_t m, int64_t k, int64_t r, const char* cache_path,
+                            int32_t force, int64_t* chunk_out);
+
+/* The decisions of the last cmsvd_cluster call on this handle, for replaying them:
+   for every cluster in creation order, its anchor and then the blocks it accepted, in
+   the order of acceptance (each was evaluated against the state left by the previous
+   entry of its cluster).  Every block appears once.
+     order  HOST cap int32 (may be NULL with cap 0: *n is set and nothing copied)
+     n      HOST out: the number of entries (nblocks of that call; 0 before any call)
+   CMSVD_ESHAPE when cap < *n and order is given. */
+cmsvd_status cmsvd_cluster_trace(cmsvd_handle handle, int32_t* order, int64_t cap, int64_t* n);
 
 /* Algorithm 2 (residual-based clustering, Appendix E) with the certificate of
    Corollary 1: a cluster C keeps an orthonormal basis Q_C of the span of its blocks,
@@ -386,15 +425,23 @@ cmsvd_status cmsvd_sym_eigvals(cmsvd_handle handle, const double* A, int64_t n, 
 cmsvd_status cmsvd_sym_eigvals_noalloc(cmsvd_handle handle, const double* A, int64_t n, int64_t lda,
                                        int64_t stride_a, int64_t count, int64_t nkeep, double* lam);
 
+/* Graph use of the handle so far (cmsvd_options.graphs): sequences captured, graph
+   replays, and the wall time of the last capture in milliseconds (capture,
+   instantiation and the copy of its descriptor tables; excluded from the replays).
+   Each output may be NULL. */
+cmsvd_status cmsvd_graph_stats(cmsvd_handle handle, int64_t* captures, int64_t* replays, double* last_capture_ms);
+
 /* Stage timing for measurement (off by default).  When enabled, every pipeline stage
    launched on the handle's stream is bracketed by HIP events recorded on that same
    stream.  Stages: 0 = block norms and Grams B^T B, 1 = commit pipeline (anchor
    initialisation and state updates), 2 = projection GEMM Y = U^T B of candidate
    evaluation, 3 = core eigenvalue kernel of candidate evaluation (tridiagonalisation,
-   bisection, plug-in error; one launch per evaluation chunk).
-   cmsvd_profile_read synchronises the handle's stream, writes for each of the 4
+   and for all but cores of order 161..320 also bisection and the plug-in error; one
+   launch per evaluation chunk), 4 = the bisection kernel that finishes the evaluation
+   of cores of order 161..320 (eigenvalues of their tridiagonals, plug-in error).
+   cmsvd_profile_read synchronises the handle's stream, writes for each of the 5
    stages the summed milliseconds and the number of bracketed launches, and resets
-   the counters.  ms and count are HOST arrays of 4 entries. */
+   the counters.  ms and count are HOST arrays of 5 entries. */
 cmsvd_status cmsvd_profile(cmsvd_handle handle, int32_t enable);
 cmsvd_status cmsvd_profile_read(cmsvd_handle handle, double* ms, int64_t* count);
 

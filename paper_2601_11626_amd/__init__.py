@@ -63,6 +63,9 @@ def _load():
     lib.cmsvd_exact_tail.argtypes = [vp, ctypes.POINTER(Block), i64, i64, ctypes.POINTER(d)]
     lib.cmsvd_compress.argtypes = [vp, ctypes.POINTER(Block), i64, i64, vp, i64, vp, i64, ctypes.POINTER(i64),
                                    ctypes.POINTER(d), ctypes.POINTER(d)]
+    lib.cmsvd_cluster_trace.argtypes = [vp, vp, i64, ctypes.POINTER(i64)]
+    lib.cmsvd_graph_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(d)]
+    lib.cmsvd_autotune.argtypes = [vp, i64, i64, i64, ctypes.c_char_p, i32, ctypes.POINTER(i64)]
     lib.cmsvd_compress_partition.argtypes = [vp, ctypes.POINTER(Block), i64, vp, i64, vp, vp, vp, vp, vp, vp, vp,
                                              ctypes.POINTER(i64), ctypes.POINTER(d), ctypes.POINTER(d)]
     lib.cmsvd_tail_energy_grad.argtypes = [vp, ctypes.POINTER(Block), i64, i64, i64, ctypes.POINTER(d), vp,
@@ -72,7 +75,7 @@ def _load():
               "cmsvd_tail_energy_grad", "cmsvd_update_batch", "cmsvd_cluster_residual", "cmsvd_residual_bound",
               "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail", "cmsvd_compress", "cmsvd_gemm_bf16",
               "cmsvd_set_projection", "cmsvd_sym_eigvals_noalloc", "cmsvd_gemm_f32", "cmsvd_create_ex",
-              "cmsvd_compress_partition"):
+              "cmsvd_compress_partition", "cmsvd_cluster_trace", "cmsvd_graph_stats", "cmsvd_autotune"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -84,11 +87,12 @@ EXPORTS = ("cmsvd_create", "cmsvd_destroy", "cmsvd_set_stream", "cmsvd_last_erro
            "cmsvd_profile_read", "cmsvd_tail_energy_grad", "cmsvd_update_batch", "cmsvd_cluster_residual",
            "cmsvd_residual_bound", "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail", "cmsvd_compress",
            "cmsvd_gemm_bf16", "cmsvd_set_projection", "cmsvd_sym_eigvals_noalloc", "cmsvd_gemm_f32",
-           "cmsvd_create_ex", "cmsvd_compress_partition")
+           "cmsvd_create_ex", "cmsvd_compress_partition", "cmsvd_cluster_trace", "cmsvd_graph_stats",
+           "cmsvd_autotune")
 
 PROJECTIONS = {"f64": 0, "bf16": 1, "bf16x3": 2, "f32": 3}  # cmsvd_projection
 
-STAGES = ("norms_grams", "commit", "projection", "core_eig")
+STAGES = ("norms_grams", "commit", "projection", "core_eig", "core_bisect")
 
 
 def _check(status: int):
@@ -102,7 +106,8 @@ def _stream_ptr(device=None):
 
 class Options(ctypes.Structure):
     """cmsvd_options (zero = the defaults)."""
-    _fields_ = [("projection", ctypes.c_int32), ("chol_tau", ctypes.c_double), ("panel_cols", ctypes.c_int64)]
+    _fields_ = [("projection", ctypes.c_int32), ("chol_tau", ctypes.c_double), ("panel_cols", ctypes.c_int64),
+                ("graphs", ctypes.c_int32)]
 
 
 _ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -128,17 +133,17 @@ def _torch_allocator(device_index: int, stream):
 class Handle:
     """Owns a cmsvd handle bound to the current torch stream of ``device``.
 
-    ``projection``, ``chol_tau`` and ``panel_cols`` are the handle options
+    ``projection``, ``chol_tau``, ``panel_cols`` and ``graphs`` are the handle options
     (cmsvd_options); with ``torch_allocator`` (the default) the library's device memory
     comes from PyTorch's caching allocator."""
 
     def __init__(self, device=None, projection: str = "f64", chol_tau: float = 0.0, panel_cols: int = 0,
-                 torch_allocator: bool = True):
+                 graphs: bool = False, torch_allocator: bool = True):
         self._h = ctypes.c_void_p()
         self._cb = None
         self.projection = projection
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else torch.device(device).index)
-        opts = Options(PROJECTIONS[projection], float(chol_tau), int(panel_cols))
+        opts = Options(PROJECTIONS[projection], float(chol_tau), int(panel_cols), 1 if graphs else 0)
         with torch.cuda.device(self.device):
             stream = torch.cuda.current_stream(self.device)
             if torch_allocator:
@@ -186,13 +191,27 @@ class Handle:
         finally:
             self.set_projection(prev)
 
+    def graph_stats(self) -> dict:
+        """Captured sequences, graph replays and the last capture's wall time (ms)."""
+        c, rp, ms = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_double(0.0)
+        _check(_lib.cmsvd_graph_stats(self._h, ctypes.byref(c), ctypes.byref(rp), ctypes.byref(ms)))
+        return {"captures": c.value, "replays": rp.value, "last_capture_ms": ms.value}
+
+    def autotune(self, m: int, k: int, r: int, cache_path: str | None = None, force: bool = False) -> int:
+        """Tunes (or loads from cache_path) the first scan chunk of Algorithm 3 for
+        width-k candidates on rank-r states of m rows; returns the chunk chosen."""
+        c = ctypes.c_int64(0)
+        _check(_lib.cmsvd_autotune(self._h, m, k, r, cache_path.encode() if cache_path else None,
+                                   1 if force else 0, ctypes.byref(c)))
+        return c.value
+
     def profile(self, enable: bool = True):
         _check(_lib.cmsvd_profile(self._h, 1 if enable else 0))
 
     def profile_read(self) -> dict:
         """Per-stage (milliseconds, launches) since the last read; synchronises the stream."""
-        ms = (ctypes.c_double * 4)()
-        cnt = (ctypes.c_int64 * 4)()
+        ms = (ctypes.c_double * len(STAGES))()
+        cnt = (ctypes.c_int64 * len(STAGES))()
         _check(_lib.cmsvd_profile_read(self._h, ms, cnt))
         return {name: (ms[i], cnt[i]) for i, name in enumerate(STAGES)}
 
@@ -318,9 +337,11 @@ def cmsvd_update_batch(states: Sequence[State], blocks: Sequence[torch.Tensor], 
 
 
 def cmsvd_merge_errors(blocks: Sequence[torch.Tensor], pairs, r: int, handle: Handle | None = None,
-                       projection: str | None = None):
+                       projection: str | None = None, out=None):
     """Returns (err, rel) device FP64 tensors for the ordered pairs (i, j).  projection:
-    'f64', 'bf16', 'bf16x3' or 'f32' for this call (None: the handle's setting)."""
+    'f64', 'bf16', 'bf16x3' or 'f32' for this call (None: the handle's setting).  out:
+    an (err, rel) pair of FP64 device tensors to write (repeated calls with the same
+    outputs can be replayed from a captured graph, Handle(graphs=True))."""
     dev = blocks[0].device
     h = handle or default_handle(dev)
     if isinstance(pairs, torch.Tensor):
@@ -330,8 +351,14 @@ def cmsvd_merge_errors(blocks: Sequence[torch.Tensor], pairs, r: int, handle: Ha
 
         pr = torch.from_numpy(np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2)))
     npairs = pr.shape[0]
-    err = torch.empty(npairs, dtype=torch.float64, device=dev)
-    rel = torch.empty(npairs, dtype=torch.float64, device=dev)
+    if out is not None:
+        err, rel = out
+        if err.numel() != npairs or rel.numel() != npairs or err.dtype != torch.float64 or \
+                rel.dtype != torch.float64 or not err.is_contiguous() or not rel.is_contiguous():
+            raise ValueError("out must be two contiguous float64 tensors of npairs entries")
+    else:
+        err = torch.empty(npairs, dtype=torch.float64, device=dev)
+        rel = torch.empty(npairs, dtype=torch.float64, device=dev)
     arr = _blocks(blocks)
     h.call_with_projection(projection, lambda: _check(_lib.cmsvd_merge_errors(
         h.ptr, arr, len(blocks), ctypes.c_void_p(pr.data_ptr()), npairs, r, ctypes.c_void_p(err.data_ptr()),
@@ -359,6 +386,16 @@ def cmsvd_cluster(blocks: Sequence[torch.Tensor], r: int, eps: float, sort_mode:
     for i, c in enumerate(lab):
         clusters[c].append(i)
     return lab, clusters, list(crel)[: ncl.value]
+
+
+def cmsvd_cluster_trace(handle: Handle | None = None) -> list:
+    """Anchors and acceptances of the handle's last cmsvd_cluster call, in order."""
+    h = handle or default_handle()
+    n = ctypes.c_int64(0)
+    _check(_lib.cmsvd_cluster_trace(h.ptr, None, 0, ctypes.byref(n)))
+    buf = (ctypes.c_int32 * max(n.value, 1))()
+    _check(_lib.cmsvd_cluster_trace(h.ptr, buf, n.value, ctypes.byref(n)))
+    return [int(buf[i]) for i in range(n.value)]
 
 
 def cmsvd_cluster_residual(blocks: Sequence[torch.Tensor], r: int, eps: float, sort_mode: str = "frobenius",
@@ -602,7 +639,7 @@ def _gemm(fn, opA, opB, C, alpha, beta, handle):
 
 
 __all__ = ["cmsvd_gemm_f64", "cmsvd_gemm_bf16", "cmsvd_gemm_f32", "PROJECTIONS", "BlockArray", "Handle", "State", "Block", "CmsvdError", "cmsvd_update", "cmsvd_update_batch",
-           "cmsvd_merge_errors", "cmsvd_cluster", "cmsvd_cluster_residual", "cmsvd_residual_bound",
+           "cmsvd_merge_errors", "cmsvd_cluster", "cmsvd_cluster_trace", "cmsvd_cluster_residual", "cmsvd_residual_bound",
            "cmsvd_weyl_bound", "cmsvd_cluster_weyl", "cmsvd_exact_tail", "cmsvd_compress", "compress_partition",
            "cmsvd_sym_eigvals", "cmsvd_sym_eigvals_noalloc", "cmsvd_tail_energy_grad", "TailEnergy", "tail_energy", "default_handle",
            "LIB_PATH", "EXPORTS"]

@@ -14,11 +14,15 @@
 //        eigenvalues of S+ equal those of [[diag(S)^2, diag(S) Y],[Y^T diag(S), B^T B]]
 //        (c) tridiagonalisation + bisection of that matrix, (e) plug-in error.
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <exception>
 #include <mutex>
 #include <new>
@@ -131,12 +135,39 @@ struct cmsvd_ctx {
     size_t pan_cap = 0;
     bool rec_ev_armed = false;   // an upload of pair records may still read rec_pin
     hipEvent_t tail_ev = nullptr;  // end of the handle stream's enqueued work (orders the side stream)
+    std::vector<int32_t> cluster_trace;  // anchors and acceptances of the last cmsvd_cluster, in order
+    // captured launch sequences of repeated cmsvd_merge_errors calls (cmsvd_options.graphs)
+    bool graphs = false;
+    uint64_t ws_gen = 0;           // bumped whenever a device workspace is reallocated
+    size_t call_upload = 0;        // descriptor bytes the current call has uploaded
+    struct GraphRec {              // the descriptor tables of a call being captured
+        char* dev = nullptr;       // graph-owned device copy (filled once after the capture)
+        size_t cap = 0;
+        std::vector<char> host;
+        bool overflow = false;
+    };
+    GraphRec* recording = nullptr;
+    hipStream_t cap_stream = nullptr;  // captures run here (the handle's stream may be the legacy one)
+    struct GraphEntry {
+        uint64_t key = 0;
+        uint64_t gen = 0;
+        hipGraphExec_t exec = nullptr;
+        char* dev = nullptr;       // its descriptor tables
+        uint64_t last_use = 0;
+    };
+    std::vector<GraphEntry> graph_cache;
+    std::vector<std::pair<uint64_t, size_t>> graph_seen;  // keys run once eagerly, their upload bytes
+    uint64_t graph_clock = 0;
+    double last_capture_ms = 0.0;
+    int64_t graph_replays = 0, graph_captures = 0;
+    // autotuned schedules: scan chunk of Algorithm 3 per (m, width bucket, r, projection)
+    std::map<std::string, int> tuned_chunk;
     // options (cmsvd_create_ex)
     double chol_c = 0.0;         // pivot threshold factor of the first Cholesky (<= 0: the block width)
     int64_t panel_cols = 0;      // cmsvd_update(_batch): widest block appended in one step (0: any)
     // stage timing
     bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> marks[4];
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> marks[5];
     std::vector<hipEvent_t> pool;
 };
 
@@ -212,6 +243,9 @@ void dev_free(cmsvd_ctx* h, char* p) {
 
 cmsvd_status ensure(cmsvd_ctx* h, char*& buf, size_t& cap, size_t need) {
     if (need <= cap) return CMSVD_OK;
+    if (h->recording)  // a captured sequence must not move the workspaces it refers to
+        return fail(CMSVD_EUNSUPPORTED, "workspace growth during graph capture");
+    ++h->ws_gen;
     HIPCHK(hipStreamSynchronize(h->stream));
     const size_t want = std::max(need, cap + cap / 2);
     dev_free(h, buf);
@@ -226,6 +260,21 @@ cmsvd_status ensure(cmsvd_ctx* h, char*& buf, size_t& cap, size_t need) {
 // Uploads the staged descriptor tables; returns the device base pointer.
 cmsvd_status upload(cmsvd_ctx* h, const Stage& st, char** dbase) {
     const size_t n = st.buf.size();
+    h->call_upload += align256(n);
+    if (h->recording) {
+        // capture: the tables go to the graph's own device buffer (copied once, after
+        // the capture), so that replays never depend on the staging buffers
+        auto& g = *h->recording;
+        const size_t off = g.host.size();
+        if (off + align256(n) > g.cap) {
+            g.overflow = true;
+            return fail(CMSVD_EUNSUPPORTED, "graph capture: descriptor tables larger than recorded");
+        }
+        g.host.resize(off + align256(n));
+        if (n) memcpy(g.host.data() + off, st.buf.data(), n);
+        *dbase = g.dev + off;
+        return CMSVD_OK;
+    }
     cmsvd_status s = ensure(h, h->dsc, h->dsc_cap, n);
     if (s != CMSVD_OK) return s;
     if (n > h->pin_cap) {
@@ -259,7 +308,7 @@ struct DevBuf {
     }
 };
 
-enum { ST_PREP = 0, ST_COMMIT = 1, ST_PROJ = 2, ST_CORE = 3, NSTAGE = 4 };
+enum { ST_PREP = 0, ST_COMMIT = 1, ST_PROJ = 2, ST_CORE = 3, ST_BISECT = 4, NSTAGE = 5 };
 
 hipEvent_t take_event(cmsvd_ctx* h) {
     hipEvent_t e = nullptr;
@@ -901,6 +950,8 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
         std::vector<size_t> poff(nj);
         for (size_t i = 0; i < nj; ++i) poff[i] = pl.add((size_t)jobs[b0 + i].r * jobs[b0 + i].B.cols * 8);
         const size_t eig_off = pl.add(sym_eig_workspace_doubles(nmax, nslots) * 8);
+        const size_t tri = sym_eig_tri_doubles(nmax);
+        const size_t tri_off = pl.add(nj * tri * 8);  // tridiagonals of the split evaluation
         cmsvd_status st = ensure(h, h->ws, h->ws_cap, pl.off);
         if (st != CMSVD_OK) return st;
         char* W = h->ws;
@@ -928,6 +979,8 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
             e.nb = j.nb;
             e.out_err = j.err;
             e.out_rel = j.rel;
+            e.d = reinterpret_cast<double*>(W + tri_off) + i * tri;
+            e.e = e.d + tri / 2;
             ed[i] = e;
         }
         Stage stg;
@@ -947,8 +1000,12 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
             if (kmax == 1 && rmax <= 256)  // one-column candidates: arrowhead cores
                 arrow_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), (int)nj, rmax, h->stream);
             else
-                sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), (int)nj, nmax, 0,
+                sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), (int)nj, nmax, 2,
                                 reinterpret_cast<double*>(W + eig_off), nslots, h->stream);
+        }
+        if (!(kmax == 1 && rmax <= 256) && sym_eig_split(nmax)) {
+            StageMark mark(h, ST_BISECT);
+            tri_bisect_batched(reinterpret_cast<const EigDesc*>(db + o_ed), (int)nj, nmax, h->stream);
         }
         HIPCHK(hipGetLastError());
     }
@@ -1926,6 +1983,37 @@ cmsvd_status commit_panelled(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
     return CMSVD_OK;
 }
 
+// Width bucket of the autotuner: the next power of two at or above k (at least 16).
+int64_t width_bucket(int64_t k) {
+    int64_t b = 16;
+    while (b < k) b *= 2;
+    return b;
+}
+
+std::string tune_key(const cmsvd_ctx* h, int64_t m, int64_t k, int64_t r) {
+    static const char* pn[] = {"f64", "bf16", "bf16x3", "f32"};
+    char buf[128];
+    snprintf(buf, sizeof(buf), "gfx950 m=%lld k=%lld r=%lld proj=%s", (long long)m, (long long)width_bucket(k),
+             (long long)r, pn[h->proj & 3]);
+    return buf;
+}
+
+// The first scan chunk of Algorithm 3 for candidates of width about k: the autotuned
+// value when the handle has one for this shape, else a quarter of the compute units.
+size_t scan_chunk(const cmsvd_ctx* h, int64_t m, int64_t k, int64_t r) {
+    auto it = h->tuned_chunk.find(tune_key(h, m, k, r));
+    if (it != h->tuned_chunk.end()) return (size_t)it->second;
+    return (size_t)std::max(16, h->ncu / 4);
+}
+
+// Releases captured sequence i of the handle's cache.
+void drop_graph(cmsvd_ctx* h, size_t i) {
+    auto& e = h->graph_cache[i];
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    dev_free(h, e.dev);
+    h->graph_cache.erase(h->graph_cache.begin() + (long)i);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1954,6 +2042,7 @@ cmsvd_status cmsvd_create_ex(cmsvd_handle* handle, void* hip_stream, const cmsvd
         h->proj = options->projection;
         h->chol_c = options->chol_tau;
         h->panel_cols = options->panel_cols;
+        h->graphs = options->graphs != 0;
     }
     if (hipGetDevice(&h->device) != hipSuccess) {
         delete h;
@@ -2002,6 +2091,8 @@ cmsvd_status cmsvd_destroy(cmsvd_handle h) try {
     if (!h) return CMSVD_OK;
     (void)hipStreamSynchronize(h->stream);
     if (h->side) (void)hipStreamSynchronize(h->side);
+    while (!h->graph_cache.empty()) drop_graph(h, h->graph_cache.size() - 1);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     dev_free(h, h->ws);
     dev_free(h, h->dsc);
     dev_free(h, h->gsk);
@@ -2133,8 +2224,10 @@ cmsvd_status cmsvd_update_batch(cmsvd_handle h, int64_t count, int64_t m, const 
     return caught(__func__);
 }
 
-cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, const int32_t* pairs,
-                                int64_t npairs, int64_t r, double* err, double* rel) try {
+// The body of cmsvd_merge_errors; *dense_out tells whether the dense (thin-candidate)
+// path ran, which reads the block norms back mid-call and is never captured.
+static cmsvd_status merge_errors_run(cmsvd_ctx* h, const cmsvd_block* blocks, int64_t nblocks, const int32_t* pairs,
+                                     int64_t npairs, int64_t r, double* err, double* rel, bool* dense_out) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_merge_errors: null handle");
     if (nblocks < 1 || !blocks) return fail(CMSVD_EINVAL, "cmsvd_merge_errors: no blocks");
     if (npairs < 0 || (npairs > 0 && (!pairs || !err))) return fail(CMSVD_EINVAL, "cmsvd_merge_errors: null pairs/err");
@@ -2241,6 +2334,7 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
             tile_work += c * std::ceil(k / 64.0) * 64.0 * std::ceil((double)r / 64.0) * 64.0 / (double)r;
         }
     const bool dense = pair_work < 0.5 * tile_work && (double)anchors.size() * (double)ksum <= 4.0 * pair_work;
+    if (dense_out) *dense_out = dense;
     // Candidates given as consecutive column ranges of one row-major matrix (in index
     // order, one dtype and row stride) already form the packed operand: used in place.
     bool in_place = dense;
@@ -2280,10 +2374,11 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
     const long ldu_a = dense ? (long)anchors.size() * r : (long)r;  // anchors side by side when dense
     const size_t o_Uall = dense ? pl.add((size_t)m * ldu_a * 8) : 0;
     const size_t o_Ball = dense && !in_place ? pl.add((size_t)m * ksum * (all_f32 ? 4 : 8)) : 0;
+    const size_t o_accall = pl.add(anchors.size() * 4 * 8);  // the accumulators side by side: one fill
     for (size_t a = 0; a < anchors.size(); ++a) {
         o_U[a] = dense ? o_Uall + (size_t)a * r * 8 : pl.add((size_t)m * r * 8);
         o_S[a] = pl.add((size_t)r * 8);
-        o_acc[a] = pl.add(4 * 8);
+        o_acc[a] = o_accall + a * 4 * 8;
     }
     // the handle's grow-on-demand buffer: its previous contents are read only by work
     // enqueued earlier on the same stream
@@ -2326,8 +2421,10 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
             }
         }
     }
-    // anchor states: the update from the empty state (Algorithm 3, step 1)
-    for (size_t a = 0; a < anchors.size(); ++a) HIPCHK(hipMemsetAsync(K(o_acc[a]), 0, 32, h->stream));
+    // anchor states: the update from the empty state (Algorithm 3, step 1); the
+    // accumulators are cleared by a kernel (a capturable node)
+    fill_f64(K(o_accall), (long)anchors.size() * 4, 0.0, h->stream);
+    HIPCHK(hipGetLastError());
     {
         // chunk anchors to bound the commit scratch (~ 2 k m + 8 k^2 doubles each)
         size_t per = 0;
@@ -2464,6 +2561,149 @@ cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64
         st = eval_batched(h, ej, (int)m);
     }
     return st;
+} catch (...) {
+    return caught(__func__);
+}
+
+// FNV-1a over the arguments that fix a merge_errors launch sequence (pointers, shapes,
+// the pair list, the projection precision).
+static uint64_t merge_key(const cmsvd_ctx* h, const cmsvd_block* blocks, int64_t nblocks, const int32_t* pairs,
+                          int64_t npairs, int64_t r, const double* err, const double* rel) {
+    uint64_t x = 1469598103934665603ull;
+    auto mix = [&](const void* p, size_t n) {
+        const unsigned char* c = static_cast<const unsigned char*>(p);
+        for (size_t i = 0; i < n; ++i) x = (x ^ c[i]) * 1099511628211ull;
+    };
+    auto mix64 = [&](uint64_t v) { mix(&v, 8); };
+    mix64((uint64_t)nblocks);
+    mix64((uint64_t)npairs);
+    mix64((uint64_t)r);
+    mix64((uint64_t)(uintptr_t)err);
+    mix64((uint64_t)(uintptr_t)rel);
+    mix64((uint64_t)h->proj);
+    for (int64_t i = 0; i < nblocks; ++i) {
+        mix64((uint64_t)(uintptr_t)blocks[i].ptr);
+        mix64((uint64_t)blocks[i].rows);
+        mix64((uint64_t)blocks[i].cols);
+        mix64((uint64_t)blocks[i].ld);
+        mix64((uint64_t)blocks[i].dtype);
+    }
+    if (npairs > 0) mix(pairs, (size_t)npairs * 2 * sizeof(int32_t));
+    return x;
+}
+
+cmsvd_status cmsvd_merge_errors(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, const int32_t* pairs,
+                                int64_t npairs, int64_t r, double* err, double* rel) try {
+    if (!h) return fail(CMSVD_EINVAL, "cmsvd_merge_errors: null handle");
+    if (!h->graphs || h->timing || npairs <= 0 || !blocks || !pairs || nblocks < 1)
+        return merge_errors_run(h, blocks, nblocks, pairs, npairs, r, err, rel, nullptr);
+    const uint64_t key = merge_key(h, blocks, nblocks, pairs, npairs, r, err, rel);
+    // a captured sequence for the same arguments, still valid: replay it
+    for (size_t i = 0; i < h->graph_cache.size(); ++i) {
+        if (h->graph_cache[i].key != key) continue;
+        if (h->graph_cache[i].gen == h->ws_gen) {
+            HIPCHK(hipGraphLaunch(h->graph_cache[i].exec, h->stream));
+            h->graph_cache[i].last_use = ++h->graph_clock;
+            ++h->graph_replays;
+            return CMSVD_OK;
+        }
+        drop_graph(h, i);  // a workspace it refers to has moved
+        break;
+    }
+    size_t seen = (size_t)-1;
+    for (const auto& sk : h->graph_seen)
+        if (sk.first == key) seen = sk.second;
+    if (seen == (size_t)-1) {
+        // first time: run eagerly (this also sizes every workspace) and remember the
+        // call if its sequence can be captured
+        bool dense = false;
+        h->call_upload = 0;
+        const cmsvd_status st = merge_errors_run(h, blocks, nblocks, pairs, npairs, r, err, rel, &dense);
+        if (st == CMSVD_OK && !dense) {
+            if (h->graph_seen.size() >= 16) h->graph_seen.erase(h->graph_seen.begin());
+            h->graph_seen.emplace_back(key, h->call_upload);
+        }
+        return st;
+    }
+    // second time: capture the launch sequence into a graph, then launch it
+    const auto t0 = std::chrono::steady_clock::now();
+    cmsvd_ctx::GraphRec rec;
+    rec.cap = std::max<size_t>(seen, 256);
+    {
+        const cmsvd_status sa = dev_alloc(h, rec.cap, &rec.dev);
+        if (sa != CMSVD_OK) return sa;
+    }
+    if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    // The sequence is captured on the handle's capture stream (nothing captured runs)
+    // and the graph is launched on the handle's stream.
+    hipGraph_t graph = nullptr;
+    const hipStream_t user_stream = h->stream;
+    HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    h->stream = h->cap_stream;
+    h->recording = &rec;
+    bool dense = false;
+    const uint64_t gen0 = h->ws_gen;
+    const cmsvd_status st = merge_errors_run(h, blocks, nblocks, pairs, npairs, r, err, rel, &dense);
+    h->recording = nullptr;
+    h->stream = user_stream;
+    const hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
+    hipGraphExec_t exec = nullptr;
+    // why a capture was given up (kept in cmsvd_last_error; the call itself succeeds)
+    std::string why;
+    if (st != CMSVD_OK) why = std::string("the captured call failed: ") + g_err;
+    else if (ec != hipSuccess || !graph) why = std::string("hipStreamEndCapture: ") + hipGetErrorString(ec);
+    else if (dense || rec.overflow || h->ws_gen != gen0) why = "the sequence differs from the recorded call";
+    if (why.empty()) {
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ei != hipSuccess) why = std::string("hipGraphInstantiate: ") + hipGetErrorString(ei);
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    if (why.empty() && !rec.host.empty()) {
+        const hipError_t em = hipMemcpy(rec.dev, rec.host.data(), rec.host.size(), hipMemcpyHostToDevice);
+        if (em != hipSuccess) why = std::string("hipMemcpy of the graph's tables: ") + hipGetErrorString(em);
+    }
+    const bool ok = why.empty();
+    for (size_t i = 0; i < h->graph_seen.size(); ++i)
+        if (h->graph_seen[i].first == key) {
+            h->graph_seen.erase(h->graph_seen.begin() + (long)i);
+            break;
+        }
+    if (!ok) {
+        // nothing captured ran: run the call eagerly instead
+        (void)hipGetLastError();
+        if (exec) (void)hipGraphExecDestroy(exec);
+        dev_free(h, rec.dev);
+        const cmsvd_status se = merge_errors_run(h, blocks, nblocks, pairs, npairs, r, err, rel, nullptr);
+        if (se == CMSVD_OK) (void)fail(CMSVD_OK, "cmsvd_merge_errors: graph capture given up (%s)", why.c_str());
+        return se;
+    }
+    if (h->graph_cache.size() >= 4) {  // keep the four most recently used
+        size_t lru = 0;
+        for (size_t i = 1; i < h->graph_cache.size(); ++i)
+            if (h->graph_cache[i].last_use < h->graph_cache[lru].last_use) lru = i;
+        drop_graph(h, lru);
+    }
+    cmsvd_ctx::GraphEntry e;
+    e.key = key;
+    e.gen = h->ws_gen;
+    e.exec = exec;
+    e.dev = rec.dev;
+    e.last_use = ++h->graph_clock;
+    h->graph_cache.push_back(e);
+    h->last_capture_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    ++h->graph_captures;
+    HIPCHK(hipGraphLaunch(exec, h->stream));
+    return CMSVD_OK;
+} catch (...) {
+    return caught(__func__);
+}
+
+cmsvd_status cmsvd_graph_stats(cmsvd_handle h, int64_t* captures, int64_t* replays, double* last_capture_ms) try {
+    if (!h) return fail(CMSVD_EINVAL, "cmsvd_graph_stats: null handle");
+    if (captures) *captures = h->graph_captures;
+    if (replays) *replays = h->graph_replays;
+    if (last_capture_ms) *last_capture_ms = h->last_capture_ms;
+    return CMSVD_OK;
 } catch (...) {
     return caught(__func__);
 }
@@ -2631,9 +2871,12 @@ cmsvd_status cmsvd_cluster(cmsvd_handle h, const cmsvd_block* blocks, int64_t nb
     for (int i = 0; i < N; ++i) labels[i] = -1;
     int ncl = 0;
     std::vector<double> crel;
+    h->cluster_trace.clear();
+    h->cluster_trace.reserve((size_t)N);
     while (!remaining.empty()) {
         const int anchor = remaining.front();
         remaining.erase(remaining.begin());
+        h->cluster_trace.push_back(anchor);
         int cur = 0;
         HIPCHK(hipMemsetAsync(K(o_acc[cur]), 0, 32, h->stream));
         CommitJob aj{(int)m, nullptr, (long)r, nullptr, 0, blocks[anchor], (int)r, K(o_U[cur]), (long)r, K(o_S[cur]),
@@ -2675,7 +2918,13 @@ cmsvd_status cmsvd_cluster(cmsvd_handle h, const cmsvd_block* blocks, int64_t nb
             // The scan only needs the first feasible candidate: evaluate the suffix in
             // chunks (a quarter of the compute units first, doubling while nothing in
             // the chunk is feasible) instead of all of it after every acceptance.
-            const size_t chunk0 = (size_t)std::max(16, h->ncu / 4);
+            size_t chunk0;
+            {
+                std::vector<int64_t> w;
+                for (const int j : order) w.push_back(blocks[j].cols);
+                std::nth_element(w.begin(), w.begin() + (long)(w.size() / 2), w.end());
+                chunk0 = scan_chunk(h, m, w.empty() ? 1 : w[w.size() / 2], r);
+            }
             size_t chunk = chunk0;
             while (pos < order.size()) {
                 const size_t end = std::min(order.size(), pos + chunk);
@@ -2707,6 +2956,7 @@ cmsvd_status cmsvd_cluster(cmsvd_handle h, const cmsvd_block* blocks, int64_t nb
                 if (st != CMSVD_OK) return st;
                 cur = nxt;
                 labels[jacc] = ncl;
+                h->cluster_trace.push_back(jacc);
                 remaining.erase(std::find(remaining.begin(), remaining.end(), jacc));
                 accepted_any = true;
                 pos = pos + idx + 1;
@@ -2730,6 +2980,131 @@ cmsvd_status cmsvd_cluster(cmsvd_handle h, const cmsvd_block* blocks, int64_t nb
     return caught(__func__);
 }
 
+
+cmsvd_status cmsvd_autotune(cmsvd_handle h, int64_t m, int64_t k, int64_t r, const char* cache_path,
+                            int32_t force, int64_t* chunk_out) try {
+    if (!h) return fail(CMSVD_EINVAL, "cmsvd_autotune: null handle");
+    if (m < 1 || k < 1 || r < 1 || r > m || k > 16384) return fail(CMSVD_ESHAPE, "cmsvd_autotune: bad shape");
+    const int64_t kb = std::min<int64_t>(width_bucket(k), sym_eig_nmax() - r);
+    if (kb < 1) return fail(CMSVD_EUNSUPPORTED, "cmsvd_autotune: r leaves no room for a candidate");
+    const std::string key = tune_key(h, m, k, r);
+    // the cache: one JSON object, one entry per line, written by this function only
+    std::vector<std::string> lines;
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string ln;
+        while (std::getline(in, ln))
+            if (ln.find("\"gfx950 ") != std::string::npos) lines.push_back(ln);
+    }
+    const std::string tag = "\"" + key + "\": {\"scan_chunk\": ";
+    if (!force)
+        for (const auto& ln : lines) {
+            const size_t p = ln.find(tag);
+            if (p == std::string::npos) continue;
+            const int c = std::atoi(ln.c_str() + p + tag.size());
+            if (c >= 1) {
+                h->tuned_chunk[key] = c;
+                if (chunk_out) *chunk_out = c;
+                return CMSVD_OK;
+            }
+        }
+    // Measure: a synthetic anchor state of rank r (an m x kb block committed from the
+    // empty state) and c evaluations of one synthetic m x kb candidate, for c = 16 ..
+    // 1024; time per launch sequence with HIP events (best of three after a warm-up).
+    Plan pl;
+    const size_t o_A = pl.add((size_t)m * kb * 8), o_B = pl.add((size_t)m * kb * 8), o_U = pl.add((size_t)m * r * 8),
+                 o_S = pl.add((size_t)r * 8), o_acc = pl.add(32), o_nb = pl.add(16), o_G = pl.add((size_t)kb * kb * 8),
+                 o_err = pl.add(1024 * 8), o_rel = pl.add(1024 * 8);
+    DevBuf mem;
+    {
+        const cmsvd_status sa = mem.get(h, pl.off);
+        if (sa != CMSVD_OK) return sa;
+    }
+    auto D = [&](size_t o) { return reinterpret_cast<double*>(mem.p + o); };
+    fill_hash(D(o_A), (long)m * kb, 0x5eedULL, h->stream);
+    fill_hash(D(o_B), (long)m * kb, 0xca11ULL, h->stream);
+    fill_f64(D(o_acc), 4, 0.0, h->stream);
+    HIPCHK(hipGetLastError());
+    const cmsvd_block A{D(o_A), m, kb, kb, CMSVD_F64}, B{D(o_B), m, kb, kb, CMSVD_F64};
+    cmsvd_status st = commit_batched(h, {CommitJob{(int)m, nullptr, (long)r, nullptr, 0, A, (int)r, D(o_U), (long)r,
+                                                   D(o_S), D(o_acc), nullptr}});
+    if (st != CMSVD_OK) return st;
+    st = norms_and_grams(h, {B}, {D(o_nb)}, {D(o_G)});
+    if (st != CMSVD_OK) return st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(CMSVD_EHIP, "cmsvd_autotune: hipEventCreate failed");
+    }
+    std::vector<std::pair<int, double>> ms;
+    for (int c = 16; c <= 1024 && st == CMSVD_OK; c *= 2) {
+        std::vector<EvalJob> ej((size_t)c, EvalJob{D(o_U), (long)r, D(o_S), (int)r, D(o_acc), B, D(o_nb), D(o_G),
+                                                   D(o_err), D(o_rel)});
+        for (int q = 0; q < c; ++q) {
+            ej[(size_t)q].err = D(o_err) + q;
+            ej[(size_t)q].rel = D(o_rel) + q;
+        }
+        double best = 1e300;
+        for (int rep = 0; rep < 4 && st == CMSVD_OK; ++rep) {
+            if (hipEventRecord(e0, h->stream) != hipSuccess) st = fail(CMSVD_EHIP, "hipEventRecord failed");
+            if (st == CMSVD_OK) st = eval_batched(h, ej, (int)m);
+            if (st == CMSVD_OK && (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                st = fail(CMSVD_EHIP, "hipEventRecord / hipEventSynchronize failed");
+            float t = 0.0f;
+            if (st == CMSVD_OK && hipEventElapsedTime(&t, e0, e1) == hipSuccess && rep > 0) best = std::min(best, (double)t);
+        }
+        ms.emplace_back(c, best);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != CMSVD_OK) return st;
+    // the largest chunk that costs at most 15 % more than the smallest: candidates the
+    // compute units evaluate side by side for (almost) free
+    int chunk = ms.front().first;
+    for (const auto& x : ms)
+        if (x.second <= 1.15 * ms.front().second) chunk = x.first;
+    h->tuned_chunk[key] = chunk;
+    if (chunk_out) *chunk_out = chunk;
+    if (cache_path) {
+        std::ostringstream e;
+        e << "  " << tag << chunk << ", \"ms\": [";
+        for (size_t q = 0; q < ms.size(); ++q)
+            e << (q ? ", " : "") << "[" << ms[q].first << ", " << ms[q].second << "]";
+        e << "]}";
+        std::vector<std::string> keep;
+        for (const auto& ln : lines)
+            if (ln.find(tag) == std::string::npos) keep.push_back(ln);
+        keep.push_back(e.str());
+        std::ofstream out(cache_path, std::ios::trunc);
+        if (!out) return fail(CMSVD_EINVAL, "cmsvd_autotune: cannot write %s", cache_path);
+        out << "{\n";
+        for (size_t q = 0; q < keep.size(); ++q) {
+            std::string ln = keep[q];
+            while (!ln.empty() && (ln.back() == ',' || ln.back() == ' ')) ln.pop_back();
+            out << ln << (q + 1 < keep.size() ? ",\n" : "\n");
+        }
+        out << "}\n";
+    }
+    return CMSVD_OK;
+} catch (...) {
+    return caught(__func__);
+}
+
+cmsvd_status cmsvd_cluster_trace(cmsvd_handle h, int32_t* order, int64_t cap, int64_t* n) try {
+    if (!h || !n) return fail(CMSVD_EINVAL, "cmsvd_cluster_trace: null handle or count");
+    *n = (int64_t)h->cluster_trace.size();
+    if (cap < *n) {
+        if (order) return fail(CMSVD_ESHAPE, "cmsvd_cluster_trace: %lld entries do not fit in %lld", (long long)*n,
+                               (long long)cap);
+        return CMSVD_OK;  // size query
+    }
+    if (!order && *n > 0) return fail(CMSVD_EINVAL, "cmsvd_cluster_trace: null order");
+    std::copy(h->cluster_trace.begin(), h->cluster_trace.end(), order);
+    return CMSVD_OK;
+} catch (...) {
+    return caught(__func__);
+}
 
 /* Residual-certified clustering (Algorithm 2); see include/cmsvd.h. */
 

@@ -114,8 +114,7 @@ __global__ void __launch_bounds__(CHT) chol_semidef_kernel(const CholDesc* __res
 
 void chol_semidef_batched(const CholDesc* d_descs, int count, hipStream_t s) {
     if (count <= 0) return;
-    (void)hipFuncSetAttribute((const void*)chol_semidef_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              CH_LDS * (int)sizeof(double));
+    lds_limit((const void*)chol_semidef_kernel, CH_LDS * (int)sizeof(double));
     hipLaunchKernelGGL(chol_semidef_kernel, dim3(count), dim3(CHT), CH_LDS * sizeof(double), s, d_descs);
 }
 

@@ -3,9 +3,28 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+#include <utility>
+
 #define CMSVD_WAVE 64
 
 namespace cmsvd {
+
+// Raises a kernel's dynamic-LDS limit to `bytes`, once per function and device: the
+// attribute persists, so launches recorded into a graph capture find it already set and
+// make no runtime call besides the launch.
+inline void lds_limit(const void* fn, int bytes) {
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, int> done;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lock(mu);
+    int& cur = done[{fn, dev}];
+    if (cur >= bytes) return;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess) cur = bytes;
+    else (void)hipGetLastError();
+}
 
 // ---------------------------------------------------------------------------
 // Wave / block reductions (deterministic: fixed butterfly order).

@@ -817,6 +817,16 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
             __syncthreads();  // #3
         }
         __syncthreads();
+        if (MODE == 2) {
+            // evaluation split in two launches: the tridiagonal goes to the problem's
+            // slot (D.d, D.e) and tri_bisect_kernel finishes the evaluation
+            for (int i = t; i < n; i += RT) {
+                D.d[i] = dd[i];
+                if (i < n - 1) D.e[i] = ee[i];
+            }
+            __syncthreads();
+            continue;
+        }
 
         // ---- multisection bisection for the nkeep largest eigenvalues ----
         double glo = INFINITY, ghi = -INFINITY, em = 0.0;
@@ -956,6 +966,131 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                 }
         }
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Evaluation epilogue of the register-resident kernel as a kernel of its own: the
+// eigenvalues of every problem's tridiagonal (written by sym_eig_reg_kernel<2>) by
+// bisection, one wavefront per problem and one eigenvalue per lane, then the plug-in
+// error, exactly as the in-kernel epilogue of mode 0 (same scaled Sturm count, same
+// tolerance, the top eigenvalues from the trace above half the spectrum).  A tridiagonal
+// takes 5 KB of LDS where the tridiagonalisation needed the whole compute unit, so six
+// wavefronts per SIMD take turns on the dependent Sturm recurrences, and plain bisection
+// does the fewest Sturm steps per eigenvalue.  A first round spreads the 64 lanes' probes
+// evenly over the Gershgorin interval; each eigenvalue then bisects its 1/65 of it.
+// ---------------------------------------------------------------------------
+constexpr int BIS_W = 4;  // wavefronts (problems) per workgroup
+
+template <int NPMAX>
+__global__ void __launch_bounds__(64 * BIS_W) tri_bisect_kernel(const EigDesc* __restrict__ descs, int count) {
+    constexpr int LEN = NPMAX + 8;  // the count reads up to seven entries past the end
+    __shared__ double sh[BIS_W][2 * LEN + 128];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double* ds = sh[wv];
+    double* e2s = ds + LEN;
+    double* aux = e2s + LEN;  // 64 counts of the first round, then 64 double-double partial sums
+    int* cnt0 = reinterpret_cast<int*>(aux);
+    for (int prob = blockIdx.x * BIS_W + wv; prob < count; prob += gridDim.x * BIS_W) {
+        const EigDesc D = descs[prob];
+        const int n = D.n;
+        double glo = INFINITY, ghi = -INFINITY, em = 0.0;
+        for (int i = lane; i < LEN; i += 64) {
+            const double di = i < n ? D.d[i] : 0.0;
+            const double ei = i < n - 1 ? D.e[i] : 0.0;
+            if (i < n) {
+                const double rad = (i > 0 ? fabs(D.e[i - 1]) : 0.0) + fabs(ei);
+                glo = fmin(glo, di - rad);
+                ghi = fmax(ghi, di + rad);
+            }
+            em = fmax(em, ei * ei);
+            ds[i] = di;
+            e2s[i] = ei;
+        }
+        glo = -wave_max(-glo);
+        ghi = wave_max(ghi);
+        em = wave_max(em);
+        const double tnorm = fmax(fabs(glo), fabs(ghi));
+        const double pivmin = DBL_MIN * fmax(1.0, em);
+        const double tol = 4.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
+        const double sc = sturm_scale(tnorm);
+        // trace of T (double-double, index order) for the bottom-half case
+        double th = 0.0, tl = 0.0;
+        if (lane == 0)
+            for (int i = 0; i < n; ++i) dd_add(th, tl, ds[i]);
+        for (int i = lane; i < LEN; i += 64) {
+            ds[i] *= sc;  // exact: sc is a power of two
+            const double es = e2s[i] * sc;
+            e2s[i] = i < n - 1 ? fmax(es * es, 0x1p-120) : 0.0;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        glo -= tol;
+        ghi += tol;
+        const int nk = D.nkeep;
+        const bool bottom = 2 * nk > n;
+        const int nb = bottom ? n - nk : nk;
+        const double width = ghi - glo;
+        {
+            const double x[1] = {glo + width * (double)(lane + 1) / 65.0};
+            int c[1];
+            sturm_count_scaled<1>(ds, e2s, n, x, sc, c);
+            cnt0[lane] = c[0];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const double w0 = width / 65.0;
+        const int iters = w0 > tol ? (int)ceil(log2(w0 / tol)) : 0;
+        double shi = 0.0, slo = 0.0;  // this lane's eigenvalues, in increasing q
+        for (int q = lane; q < nb; q += 64) {
+            const int target = bottom ? q + 1 : n - q;
+            int first = 64;
+            for (int pi = 63; pi >= 0; --pi)
+                if (cnt0[pi] >= target) first = pi;
+            double lo = first > 0 ? glo + width * (double)first / 65.0 : glo;
+            double hi = first < 64 ? glo + width * (double)(first + 1) / 65.0 : ghi;
+            for (int it = 0; it < iters; ++it) {
+                const double x[1] = {0.5 * (lo + hi)};
+                int c[1];
+                sturm_count_scaled<1>(ds, e2s, n, x, sc, c);
+                if (c[0] >= target) hi = x[0];
+                else lo = x[0];
+            }
+            dd_add(shi, slo, 0.5 * (lo + hi));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        aux[2 * lane] = shi;
+        aux[2 * lane + 1] = slo;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {
+            double hi = 0.0, lo = 0.0;
+            for (int l = 0; l < 64; ++l) {
+                dd_add(hi, lo, aux[2 * l]);
+                lo += aux[2 * l + 1];
+            }
+            if (bottom) {  // (hi, lo) = trace - (hi, lo)
+                double s2, e2;
+                two_sum(th, -hi, s2, e2);
+                e2 += tl - lo;
+                two_sum(s2, e2, hi, lo);
+            }
+            double eh = D.na[0], el = D.na[1];
+            if (D.nb) {
+                dd_add(eh, el, D.nb[0]);
+                el += D.nb[1];
+            }
+            double s2, e2;
+            two_sum(eh, -hi, s2, e2);
+            double tail = s2 + (e2 + el - lo);
+            if (tail < 0.0) tail = 0.0;  // clamp rounding below zero; NaN propagates
+            const double err = sqrt(tail);
+            const double etot = eh + el;
+            *D.out_err = err;
+            if (D.out_rel) *D.out_rel = etot != 0.0 ? err / sqrt(etot) : 0.0;
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -1450,6 +1585,22 @@ int sym_eig_nmax() {
     return (int)(((LDS_BYTES / 8 - 32) / 10) / TILE * TILE);
 }
 
+bool sym_eig_split(int nmax) {
+    const int T = (nmax + TILE - 1) / TILE;
+    return nmax > SN && T > THIN_TMAX && T <= REG_TMAX;
+}
+
+void tri_bisect_batched(const EigDesc* d_descs, int count, int nmax, hipStream_t s) {
+    if (count <= 0 || !sym_eig_split(nmax)) return;
+    const int grid = (count + BIS_W - 1) / BIS_W < 8192 ? (count + BIS_W - 1) / BIS_W : 8192;
+    hipLaunchKernelGGL((tri_bisect_kernel<REG_NP>), dim3(grid), dim3(64 * BIS_W), 0, s, d_descs, count);
+}
+
+size_t sym_eig_tri_doubles(int nmax) {
+    const int T = (nmax + TILE - 1) / TILE;
+    return 2 * (size_t)T * TILE;
+}
+
 size_t sym_eig_workspace_doubles(int nmax, int nslots) {
     const int T = (nmax + TILE - 1) / TILE;
     return (size_t)nslots * (size_t)T * (size_t)(T + 1) / 2 * TILE_EL;
@@ -1465,6 +1616,8 @@ void sym_eig_batched(const EigDesc* d_descs, int count, int nmax, int mode, doub
                      hipStream_t s) {
     if (count <= 0) return;
     const int T = (nmax + TILE - 1) / TILE, npad = T * TILE;
+    const bool split = mode == 2 && sym_eig_split(nmax);
+    if (mode == 2 && !split) mode = 0;  // the other kernels finish the evaluation themselves
     if (nmax <= SN) {
         int grid = (count + SWV - 1) / SWV;
         if (grid > 16384) grid = 16384;
@@ -1493,14 +1646,18 @@ void sym_eig_batched(const EigDesc* d_descs, int count, int nmax, int mode, doub
     if (T <= REG_TMAX) {
         const size_t lds = (size_t)REG_LDS_DOUBLES * 8;
         const int grid = count < nslots ? count : nslots;
+        if (split) {
+            lds_limit((const void*)sym_eig_reg_kernel<2, RT, NSLOT, RTL, REG_TMAX>, (int)lds);
+            hipLaunchKernelGGL((sym_eig_reg_kernel<2, RT, NSLOT, RTL, REG_TMAX>), dim3(grid), dim3(RT), lds, s, d_descs,
+                               count);
+            return;
+        }
         if (mode == 0) {
-            (void)hipFuncSetAttribute((const void*)sym_eig_reg_kernel<0, RT, NSLOT, RTL, REG_TMAX>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            lds_limit((const void*)sym_eig_reg_kernel<0, RT, NSLOT, RTL, REG_TMAX>, (int)lds);
             hipLaunchKernelGGL((sym_eig_reg_kernel<0, RT, NSLOT, RTL, REG_TMAX>), dim3(grid), dim3(RT), lds, s, d_descs,
                                count);
         } else {
-            (void)hipFuncSetAttribute((const void*)sym_eig_reg_kernel<1, RT, NSLOT, RTL, REG_TMAX>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            lds_limit((const void*)sym_eig_reg_kernel<1, RT, NSLOT, RTL, REG_TMAX>, (int)lds);
             hipLaunchKernelGGL((sym_eig_reg_kernel<1, RT, NSLOT, RTL, REG_TMAX>), dim3(grid), dim3(RT), lds, s, d_descs,
                                count);
         }
@@ -1511,10 +1668,10 @@ void sym_eig_batched(const EigDesc* d_descs, int count, int nmax, int mode, doub
     const long slot = (long)T * (T + 1) / 2 * TILE_EL;
     const int grid = count < nslots ? count : nslots;
     if (mode == 0) {
-        (void)hipFuncSetAttribute((const void*)sym_eig_kernel<0, GT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        lds_limit((const void*)sym_eig_kernel<0, GT>, (int)lds);
         hipLaunchKernelGGL((sym_eig_kernel<0, GT>), dim3(grid), dim3(GT), lds, s, d_descs, count, npad, TL, gws, slot);
     } else {
-        (void)hipFuncSetAttribute((const void*)sym_eig_kernel<1, GT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        lds_limit((const void*)sym_eig_kernel<1, GT>, (int)lds);
         hipLaunchKernelGGL((sym_eig_kernel<1, GT>), dim3(grid), dim3(GT), lds, s, d_descs, count, npad, TL, gws, slot);
     }
 }
@@ -1730,7 +1887,7 @@ __global__ void __launch_bounds__(ET) sym_vectors_kernel(const VecDesc* __restri
 
 void sym_vectors_batched(const VecDesc* d_descs, int count, hipStream_t s) {
     if (count <= 0) return;
-    (void)hipFuncSetAttribute((const void*)sym_vectors_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES);
+    lds_limit((const void*)sym_vectors_kernel, LDS_BYTES);
     hipLaunchKernelGGL(sym_vectors_kernel, dim3(count), dim3(ET), LDS_BYTES, s, d_descs);
 }
 

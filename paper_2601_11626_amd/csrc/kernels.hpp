@@ -59,10 +59,18 @@ struct EigDesc {
 };
 
 // Tridiagonalisation + bisection.  mode 0: evaluation (writes out_err/out_rel);
-// mode 1: vectors wanted (writes lam, d, e, V, tau, sum_top).
+// mode 1: vectors wanted (writes lam, d, e, V, tau, sum_top); mode 2: for orders where
+// sym_eig_split(nmax) holds (the register-resident orders 161..320), only the
+// tridiagonalisation, into each descriptor's d and e (sym_eig_tri_doubles(nmax) doubles
+// of scratch), and tri_bisect_batched finishes the evaluation (a high-occupancy
+// bisection kernel); for other orders mode 2 is mode 0.
 void sym_eig_batched(const EigDesc* d_descs, int count, int nmax, int mode, double* gws, int nslots,
                      hipStream_t s);
 size_t sym_eig_workspace_doubles(int nmax, int nslots);
+// Scratch doubles per problem for the tridiagonal of mode 2 (d at 0, e at half of it).
+size_t sym_eig_tri_doubles(int nmax);
+bool sym_eig_split(int nmax);
+void tri_bisect_batched(const EigDesc* d_descs, int count, int nmax, hipStream_t s);
 // Doubles of global scratch one workgroup slot of sym_eig_batched needs for order nmax
 // (0 when the kernel chosen for that order keeps every tile on chip).
 size_t sym_eig_slot_doubles(int nmax);

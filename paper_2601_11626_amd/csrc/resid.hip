@@ -126,8 +126,7 @@ __global__ void __launch_bounds__(CT) resid_cert_kernel(const CertDesc* __restri
 void resid_cert_batched(const CertDesc* d_descs, int count, int r, int nkmax, hipStream_t s) {
     if (count <= 0) return;
     const size_t lds = (size_t)(r + nkmax + 2 * CT) * sizeof(double);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(resid_cert_kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    lds_limit(reinterpret_cast<const void*>(resid_cert_kernel), (int)lds);
     for (int base = 0; base < count; base += 65535) {
         const int n = count - base < 65535 ? count - base : 65535;
         hipLaunchKernelGGL(resid_cert_kernel, dim3(n), dim3(CT), lds, s, d_descs + base, r, nkmax);
@@ -161,8 +160,7 @@ __global__ void __launch_bounds__(CT) resid_accept_kernel(const double* __restri
 void resid_accept(const double* L, int r, const double* lam, int nk, const double* S, const double* nb, double* Lout,
                   double* Sout, hipStream_t s) {
     const size_t lds = (size_t)(r + nk + CT) * sizeof(double);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(resid_accept_kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    lds_limit(reinterpret_cast<const void*>(resid_accept_kernel), (int)lds);
     hipLaunchKernelGGL(resid_accept_kernel, dim3(1), dim3(CT), lds, s, L, r, lam, nk, S, nb, Lout, Sout);
 }
 
