@@ -203,6 +203,41 @@ __device__ __forceinline__ void sturm_count_scaled(const double* ds, const doubl
     }
 }
 
+// The count of sturm_count_scaled<1> (the same steps in the same order, renormalised
+// after every eight, so the same result) with one operand buffer instead of two: fewer
+// registers, for kernels that hide latency with many wavefronts rather than loads ahead.
+__device__ __forceinline__ int sturm_count_lean(const double* ds, const double* e2s, int n, double x, double sc) {
+    const double xs = x * sc;
+    double p2 = 1.0, p1 = ds[0] - xs;
+    int cnt = p1 < 0.0;
+    int i = 1;
+    for (; i + 7 < n; i += 8) {
+        double d8[8], e8[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            d8[m] = ds[i + m];
+            e8[m] = e2s[i + m - 1];
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const double p = fma(d8[m] - xs, p1, -e8[m] * p2);
+            cnt += (p < 0.0) != (p1 < 0.0);
+            p2 = p1;
+            p1 = p;
+        }
+        const int e = __builtin_amdgcn_frexp_exp(fmax(fabs(p1), fabs(p2)));
+        p1 = ldexp(p1, -e);
+        p2 = ldexp(p2, -e);
+    }
+    for (; i < n; ++i) {
+        const double p = fma(ds[i] - xs, p1, -e2s[i - 1] * p2);
+        cnt += (p < 0.0) != (p1 < 0.0);
+        p2 = p1;
+        p1 = p;
+    }
+    return cnt;
+}
+
 __device__ __forceinline__ int sturm_count(const double* dd, const double* e2, int n, double x, double sc) {
     const double xs[1] = {x};
     int c[1];
@@ -978,12 +1013,14 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
 // takes 5 KB of LDS where the tridiagonalisation needed the whole compute unit, so six
 // wavefronts per SIMD take turns on the dependent Sturm recurrences, and plain bisection
 // does the fewest Sturm steps per eigenvalue.  A first round spreads the 64 lanes' probes
-// evenly over the Gershgorin interval; each eigenvalue then bisects its 1/65 of it.
+// evenly over the Gershgorin interval; each eigenvalue then bisects its 1/65 of it.  The
+// count is the register-lean form of the same recurrence (sturm_count_lean), so that four
+// workgroups of four wavefronts (four per SIMD) fit on each compute unit without spills.
 // ---------------------------------------------------------------------------
 constexpr int BIS_W = 4;  // wavefronts (problems) per workgroup
 
 template <int NPMAX>
-__global__ void __launch_bounds__(64 * BIS_W) tri_bisect_kernel(const EigDesc* __restrict__ descs, int count) {
+__global__ void __launch_bounds__(64 * BIS_W, 4) tri_bisect_kernel(const EigDesc* __restrict__ descs, int count) {
     constexpr int LEN = NPMAX + 8;  // the count reads up to seven entries past the end
     __shared__ double sh[BIS_W][2 * LEN + 128];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1031,12 +1068,7 @@ __global__ void __launch_bounds__(64 * BIS_W) tri_bisect_kernel(const EigDesc* _
         const bool bottom = 2 * nk > n;
         const int nb = bottom ? n - nk : nk;
         const double width = ghi - glo;
-        {
-            const double x[1] = {glo + width * (double)(lane + 1) / 65.0};
-            int c[1];
-            sturm_count_scaled<1>(ds, e2s, n, x, sc, c);
-            cnt0[lane] = c[0];
-        }
+        cnt0[lane] = sturm_count_lean(ds, e2s, n, glo + width * (double)(lane + 1) / 65.0, sc);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         const double w0 = width / 65.0;
@@ -1050,11 +1082,9 @@ __global__ void __launch_bounds__(64 * BIS_W) tri_bisect_kernel(const EigDesc* _
             double lo = first > 0 ? glo + width * (double)first / 65.0 : glo;
             double hi = first < 64 ? glo + width * (double)(first + 1) / 65.0 : ghi;
             for (int it = 0; it < iters; ++it) {
-                const double x[1] = {0.5 * (lo + hi)};
-                int c[1];
-                sturm_count_scaled<1>(ds, e2s, n, x, sc, c);
-                if (c[0] >= target) hi = x[0];
-                else lo = x[0];
+                const double x = 0.5 * (lo + hi);
+                if (sturm_count_lean(ds, e2s, n, x, sc) >= target) hi = x;
+                else lo = x;
             }
             dd_add(shi, slo, 0.5 * (lo + hi));
         }
