@@ -16,8 +16,11 @@
  *   - Blocks A_i are real m x n_i matrices with a common row count m (Problem
  *     Formulation).  They are passed as cmsvd_block: a DEVICE pointer to a
  *     row-major matrix (element (i, c) at ptr[i * ld + c]), ld >= cols, dtype
- *     CMSVD_F32 or CMSVD_F64.  FP32 data is promoted to FP64 exactly; all
- *     arithmetic is FP64.
+ *     CMSVD_F32, CMSVD_BF16 or CMSVD_F64.  FP32 data is promoted to FP64 exactly;
+ *     BF16 blocks are first widened to FP32 (exact) in a buffer of the handle, which
+ *     holds 4 bytes per element of every BF16 block of the call until the next call
+ *     that widens; all arithmetic is FP64 except the optional low-precision
+ *     projections (cmsvd_set_projection).
  *   - A state of rank r (the state Algorithm 3 maintains) is a DEVICE basis U
  *     (m x r, row-major FP64, orthonormal or zero columns), DEVICE singular values
  *     S (r FP64, descending, zero-padded), and DEVICE accumulators
@@ -37,8 +40,10 @@
  *     candidates are thin enough for the dense projection); results are valid after
  *     a stream synchronisation.  The other calls are synchronous.
  *   - Argument validation happens before any launch.  A non-OK status means no
- *     kernel was launched by that call, except CMSVD_EHIP (a HIP runtime failure)
- *     and CMSVD_ENOMEM (a device or host allocation that failed part-way).  No C++
+ *     kernel was launched by that call, except CMSVD_EHIP (a HIP runtime failure),
+ *     CMSVD_ENOMEM (a device or host allocation that failed part-way), and the
+ *     widening of BF16 blocks, which follows the checks of the blocks themselves and
+ *     precedes those of the other arguments (it writes only the handle's buffer).  No C++
  *     exception crosses the ABI: a failed host allocation returns CMSVD_ENOMEM, any
  *     other internal exception CMSVD_EUNSUPPORTED.  cmsvd_last_error() gives a
  *     thread-local message.
@@ -65,7 +70,7 @@ extern "C" {
 
 typedef struct cmsvd_ctx* cmsvd_handle;
 
-typedef enum { CMSVD_F32 = 0, CMSVD_F64 = 2 } cmsvd_dtype;
+typedef enum { CMSVD_F32 = 0, CMSVD_BF16 = 1, CMSVD_F64 = 2 } cmsvd_dtype;
 
 /* Precision of the candidate projections Y = U_r^T A_j (see cmsvd_set_projection). */
 typedef enum { CMSVD_PROJ_F64 = 0, CMSVD_PROJ_BF16 = 1, CMSVD_PROJ_BF16X3 = 2, CMSVD_PROJ_F32 = 3 } cmsvd_projection;
@@ -235,11 +240,16 @@ cmsvd_status cmsvd_cluster(cmsvd_handle handle, const cmsvd_block* blocks, int64
    projection precision, it times one evaluation launch sequence of c synthetic
    candidates for c = 16, 32, .., 1024 (HIP events, best of three after a warm-up) and
    picks the largest c that costs at most 15 % more than c = 16: the candidates the
-   device evaluates side by side for about the price of the smallest chunk.  The choice
-   is kept in the handle (cmsvd_cluster uses the entry of the median remaining width;
-   shapes without one start at a quarter of the compute units) and in cache_path (may be
-   NULL), a JSON object with one entry per line keyed "gfx950 m=.. k=.. r=.. proj=..",
-   holding the chosen chunk and the measured times.  An entry already in the cache is
+   device evaluates side by side for about the price of the smallest chunk.  When the
+   cores (order r + k) exceed 320, the general eigen kernel's workgroup is measured the
+   same way with 1024 and with 512 threads per problem, and the size with the lower time
+   per candidate at its own chunk is kept for candidate evaluations (cmsvd_merge_errors
+   and the scan) whose core order falls in the same power-of-two bucket as r + k.  The
+   choices are kept in the handle (cmsvd_cluster uses the chunk of the median remaining
+   width; shapes without one start at a quarter of the compute units) and in cache_path
+   (may be NULL), a JSON object with one entry per line keyed "gfx950 m=.. k=.. r=..
+   proj=..", holding the chosen chunk, the workgroup size (0: not applicable) and the
+   measured times.  An entry already in the cache is
    loaded instead of measured unless force is nonzero.
      chunk_out   HOST out (may be NULL): the chunk chosen
    Synchronous; uses about (2 m k + m r + k^2) doubles of device memory while it runs. */

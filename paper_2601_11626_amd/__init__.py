@@ -19,6 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcmsvd.so")
 
 CMSVD_F32 = 0
+CMSVD_BF16 = 1
 CMSVD_F64 = 2
 _STATUS = {0: "OK", 1: "EINVAL", 2: "ESHAPE", 3: "ENOMEM", 4: "EHIP", 5: "EUNSUPPORTED"}
 
@@ -237,6 +238,8 @@ def _block(t: torch.Tensor) -> Block:
         dt = CMSVD_F32
     elif t.dtype == torch.float64:
         dt = CMSVD_F64
+    elif t.dtype == torch.bfloat16:
+        dt = CMSVD_BF16
     else:
         raise ValueError(f"unsupported dtype {t.dtype}")
     return Block(t.data_ptr(), t.shape[0], t.shape[1], t.stride(0), dt)

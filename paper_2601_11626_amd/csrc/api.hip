@@ -133,6 +133,8 @@ struct cmsvd_ctx {
     size_t keep_cap = 0;
     char* pan = nullptr;         // intermediate states of panelled updates
     size_t pan_cap = 0;
+    char* wide = nullptr;        // FP32 copies of the BF16 blocks of the current call
+    size_t wide_cap = 0;
     bool rec_ev_armed = false;   // an upload of pair records may still read rec_pin
     hipEvent_t tail_ev = nullptr;  // end of the handle stream's enqueued work (orders the side stream)
     std::vector<int32_t> cluster_trace;  // anchors and acceptances of the last cmsvd_cluster, in order
@@ -160,8 +162,11 @@ struct cmsvd_ctx {
     uint64_t graph_clock = 0;
     double last_capture_ms = 0.0;
     int64_t graph_replays = 0, graph_captures = 0;
-    // autotuned schedules: scan chunk of Algorithm 3 per (m, width bucket, r, projection)
+    // autotuned schedules: scan chunk of Algorithm 3 per (m, width bucket, r, projection),
+    // and the general eigen kernel's workgroup per power-of-two order bucket
     std::map<std::string, int> tuned_chunk;
+    std::map<int64_t, int> tuned_threads;
+    int force_threads = 0;  // set by the autotuner while it measures
     // options (cmsvd_create_ex)
     double chol_c = 0.0;         // pivot threshold factor of the first Cholesky (<= 0: the block width)
     int64_t panel_cols = 0;      // cmsvd_update(_batch): widest block appended in one step (0: any)
@@ -917,6 +922,21 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
 // ---------------------------------------------------------------------------
 // Evaluation pipeline: err/rel of candidate merges against given states.
 // ---------------------------------------------------------------------------
+// Width bucket of the autotuner: the next power of two at or above k (at least 16).
+int64_t width_bucket(int64_t k) {
+    int64_t b = 16;
+    while (b < k) b *= 2;
+    return b;
+}
+
+// Workgroup size of the general eigen kernel for candidate cores of order n: what the
+// autotuner measured for n's power-of-two bucket, else the default (0).
+int eig_threads(const cmsvd_ctx* h, int64_t n) {
+    if (h->force_threads) return h->force_threads;
+    auto it = h->tuned_threads.find(width_bucket(n));
+    return it == h->tuned_threads.end() ? 0 : it->second;
+}
+
 struct EvalJob {
     const double* U;  // row-major m x r (ld ldu)
     long ldu;
@@ -1001,7 +1021,7 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
                 arrow_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), (int)nj, rmax, h->stream);
             else
                 sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), (int)nj, nmax, 2,
-                                reinterpret_cast<double*>(W + eig_off), nslots, h->stream);
+                                reinterpret_cast<double*>(W + eig_off), nslots, h->stream, eig_threads(h, nmax));
         }
         if (!(kmax == 1 && rmax <= 256) && sym_eig_split(nmax)) {
             StageMark mark(h, ST_BISECT);
@@ -1983,13 +2003,6 @@ cmsvd_status commit_panelled(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
     return CMSVD_OK;
 }
 
-// Width bucket of the autotuner: the next power of two at or above k (at least 16).
-int64_t width_bucket(int64_t k) {
-    int64_t b = 16;
-    while (b < k) b *= 2;
-    return b;
-}
-
 std::string tune_key(const cmsvd_ctx* h, int64_t m, int64_t k, int64_t r) {
     static const char* pn[] = {"f64", "bf16", "bf16x3", "f32"};
     char buf[128];
@@ -2004,6 +2017,76 @@ size_t scan_chunk(const cmsvd_ctx* h, int64_t m, int64_t k, int64_t r) {
     auto it = h->tuned_chunk.find(tune_key(h, m, k, r));
     if (it != h->tuned_chunk.end()) return (size_t)it->second;
     return (size_t)std::max(16, h->ncu / 4);
+}
+
+// BF16 blocks are widened to FP32 (exactly: a BF16 value is an FP32 value with the low
+// 16 bits zero) into the handle's buffer before a call uses them.
+struct WidenDesc {
+    const uint16_t* src;  // row-major BF16, row stride ld
+    int rows, cols;
+    long ld;
+    float* dst;           // row-major FP32, row stride cols
+};
+
+__global__ void __launch_bounds__(256) widen_bf16_kernel(const WidenDesc* __restrict__ descs) {
+    const WidenDesc D = descs[blockIdx.y];
+    const long tot = (long)D.rows * D.cols;
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < tot; e += (long)gridDim.x * 256) {
+        const long r = e / D.cols, c = e - r * D.cols;
+        D.dst[e] = __uint_as_float((uint32_t)D.src[r * D.ld + c] << 16);
+    }
+}
+
+// When any of the n blocks is BF16: checks all of them as check_block does (with BF16
+// allowed), widens the BF16 ones into h->wide and returns in `out` the descriptors the
+// call goes on with (FP32 copies in place of BF16 blocks).  `out` stays empty when no
+// block is BF16.  The copies live until the next call widens blocks on this handle;
+// everything that reads them is ordered before that on the handle's stream.
+cmsvd_status widen_blocks(cmsvd_ctx* h, const cmsvd_block* in, int64_t n, std::vector<cmsvd_block>& out,
+                          const char* who) {
+    out.clear();
+    if (!in || n < 1) return CMSVD_OK;
+    bool any = false;
+    for (int64_t i = 0; i < n; ++i) any |= in[i].dtype == CMSVD_BF16;
+    if (!any) return CMSVD_OK;
+    const int64_t m = in[0].rows;
+    size_t bytes = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        cmsvd_block b = in[i];
+        if (b.dtype == CMSVD_BF16) b.dtype = CMSVD_F32;  // same shape rules
+        const cmsvd_status st = check_block(b, m, "block", i);
+        if (st != CMSVD_OK) return st;
+        if (in[i].dtype == CMSVD_BF16) bytes += align256((size_t)b.rows * b.cols * 4);
+    }
+    cmsvd_status st = ensure(h, h->wide, h->wide_cap, bytes);
+    if (st != CMSVD_OK) return st;
+    out.assign(in, in + n);
+    std::vector<WidenDesc> wd;
+    size_t off = 0;
+    long maxel = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (in[i].dtype != CMSVD_BF16) continue;
+        float* dst = reinterpret_cast<float*>(h->wide + off);
+        wd.push_back(WidenDesc{static_cast<const uint16_t*>(in[i].ptr), (int)in[i].rows, (int)in[i].cols,
+                               (long)in[i].ld, dst});
+        maxel = std::max(maxel, (long)in[i].rows * in[i].cols);
+        out[(size_t)i] = cmsvd_block{dst, in[i].rows, in[i].cols, in[i].cols, CMSVD_F32};
+        off += align256((size_t)in[i].rows * in[i].cols * 4);
+    }
+    Stage stg;
+    const size_t o = stg.add(wd);
+    char* db = nullptr;
+    st = upload(h, stg, &db);
+    if (st != CMSVD_OK) return st;
+    const WidenDesc* dd = reinterpret_cast<const WidenDesc*>(db + o);
+    const int gx = (int)std::min<long>((maxel + 255) / 256, 1024);
+    for (size_t b0 = 0; b0 < wd.size(); b0 += 65535) {
+        const int nb = (int)std::min<size_t>(65535, wd.size() - b0);
+        hipLaunchKernelGGL(widen_bf16_kernel, dim3(gx, nb), dim3(256), 0, h->stream, dd + b0);
+    }
+    HIPCHK(hipGetLastError());
+    (void)who;
+    return CMSVD_OK;
 }
 
 // Releases captured sequence i of the handle's cache.
@@ -2099,6 +2182,7 @@ cmsvd_status cmsvd_destroy(cmsvd_handle h) try {
     dev_free(h, h->rec);
     dev_free(h, h->keep);
     dev_free(h, h->pan);
+    dev_free(h, h->wide);
     if (h->tail_ev) (void)hipEventDestroy(h->tail_ev);
     if (h->rec_pin) (void)hipHostFree(h->rec_pin);
     if (h->pin) (void)hipHostFree(h->pin);
@@ -2173,6 +2257,12 @@ cmsvd_status cmsvd_update(cmsvd_handle h, int64_t m, const double* U, int64_t ld
                           double* est) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_update: null handle");
     if (!B) return fail(CMSVD_EINVAL, "cmsvd_update: null block");
+    std::vector<cmsvd_block> wide_;
+    {
+        const cmsvd_status sw = widen_blocks(h, B, 1, wide_, "cmsvd_update");
+        if (sw != CMSVD_OK) return sw;
+        if (!wide_.empty()) B = wide_.data();
+    }
     if (m < 1) return fail(CMSVD_ESHAPE, "cmsvd_update: m < 1");
     if (r < 1 || r > m) return fail(CMSVD_ESHAPE, "cmsvd_update: need 1 <= r <= m (r=%lld, m=%lld)", (long long)r, (long long)m);
     if (r > 4096) return fail(CMSVD_EUNSUPPORTED, "cmsvd_update: r > 4096");
@@ -2200,6 +2290,12 @@ cmsvd_status cmsvd_update_batch(cmsvd_handle h, int64_t count, int64_t m, const 
     if (count < 0) return fail(CMSVD_EINVAL, "cmsvd_update_batch: count < 0");
     if (count == 0) return CMSVD_OK;
     if (!B || !U_out || !S_out || !acc) return fail(CMSVD_EINVAL, "cmsvd_update_batch: null array");
+    std::vector<cmsvd_block> wide_;
+    {
+        const cmsvd_status sw = widen_blocks(h, B, count, wide_, "cmsvd_update_batch");
+        if (sw != CMSVD_OK) return sw;
+        if (!wide_.empty()) B = wide_.data();
+    }
     if (m < 1) return fail(CMSVD_ESHAPE, "cmsvd_update_batch: m < 1");
     if (r < 1 || r > m) return fail(CMSVD_ESHAPE, "cmsvd_update_batch: need 1 <= r <= m");
     if (r > 4096) return fail(CMSVD_EUNSUPPORTED, "cmsvd_update_batch: r > 4096");
@@ -2232,6 +2328,12 @@ static cmsvd_status merge_errors_run(cmsvd_ctx* h, const cmsvd_block* blocks, in
     if (nblocks < 1 || !blocks) return fail(CMSVD_EINVAL, "cmsvd_merge_errors: no blocks");
     if (npairs < 0 || (npairs > 0 && (!pairs || !err))) return fail(CMSVD_EINVAL, "cmsvd_merge_errors: null pairs/err");
     if (nblocks > INT32_MAX || npairs > INT32_MAX) return fail(CMSVD_EUNSUPPORTED, "cmsvd_merge_errors: too many blocks or pairs");
+    std::vector<cmsvd_block> wide_;
+    {
+        const cmsvd_status sw = widen_blocks(h, blocks, nblocks, wide_, "cmsvd_merge_errors");
+        if (sw != CMSVD_OK) return sw;
+        if (!wide_.empty()) blocks = wide_.data();
+    }
     const int64_t m = blocks[0].rows;
     if (m < 1) return fail(CMSVD_ESHAPE, "cmsvd_merge_errors: m < 1");
     if (r < 1 || r > m) return fail(CMSVD_ESHAPE, "cmsvd_merge_errors: need 1 <= r <= m");
@@ -2809,6 +2911,12 @@ cmsvd_status cmsvd_gemm_f32(cmsvd_handle h, int32_t trans_a, int32_t trans_b, in
 cmsvd_status cmsvd_cluster(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double eps,
                            int32_t sort_mode, int32_t* labels, int64_t* nclusters, double* cluster_rel) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_cluster: null handle");
+    std::vector<cmsvd_block> wide_;
+    {
+        const cmsvd_status sw = widen_blocks(h, blocks, nblocks, wide_, "cmsvd_cluster");
+        if (sw != CMSVD_OK) return sw;
+        if (!wide_.empty()) blocks = wide_.data();
+    }
     if (nblocks < 1 || !blocks) return fail(CMSVD_EINVAL, "cmsvd_cluster: no blocks");
     if (!labels || !nclusters) return fail(CMSVD_EINVAL, "cmsvd_cluster: null output");
     if (!(eps >= 0.0)) return fail(CMSVD_EINVAL, "cmsvd_cluster: eps must be >= 0");
@@ -2997,13 +3105,17 @@ cmsvd_status cmsvd_autotune(cmsvd_handle h, int64_t m, int64_t k, int64_t r, con
             if (ln.find("\"gfx950 ") != std::string::npos) lines.push_back(ln);
     }
     const std::string tag = "\"" + key + "\": {\"scan_chunk\": ";
+    const int64_t ob = width_bucket(r + k);  // order bucket of the cores the entry serves
     if (!force)
         for (const auto& ln : lines) {
             const size_t p = ln.find(tag);
             if (p == std::string::npos) continue;
             const int c = std::atoi(ln.c_str() + p + tag.size());
+            const size_t q = ln.find("\"eig_threads\": ", p);
+            const int th = q == std::string::npos ? 0 : std::atoi(ln.c_str() + q + 15);
             if (c >= 1) {
                 h->tuned_chunk[key] = c;
+                if (th > 0) h->tuned_threads[ob] = th;
                 if (chunk_out) *chunk_out = c;
                 return CMSVD_OK;
             }
@@ -3037,7 +3149,16 @@ cmsvd_status cmsvd_autotune(cmsvd_handle h, int64_t m, int64_t k, int64_t r, con
         (void)hipEventDestroy(e0);
         return fail(CMSVD_EHIP, "cmsvd_autotune: hipEventCreate failed");
     }
-    std::vector<std::pair<int, double>> ms;
+    // orders above 320 run the general kernel: its workgroup (1024 or 512 threads per
+    // problem) is measured too, each with its own best chunk
+    const bool general = r + kb > 320;
+    std::vector<int> variants = general ? std::vector<int>{1024, 512} : std::vector<int>{0};
+    std::vector<std::pair<int, double>> ms, best_ms;
+    int best_threads = 0, chunk = 16;
+    double best_rate = 1e300;
+    for (const int v : variants) {
+    ms.clear();
+    h->force_threads = v;
     for (int c = 16; c <= 1024 && st == CMSVD_OK; c *= 2) {
         std::vector<EvalJob> ej((size_t)c, EvalJob{D(o_U), (long)r, D(o_S), (int)r, D(o_acc), B, D(o_nb), D(o_G),
                                                    D(o_err), D(o_rel)});
@@ -3056,19 +3177,35 @@ cmsvd_status cmsvd_autotune(cmsvd_handle h, int64_t m, int64_t k, int64_t r, con
         }
         ms.emplace_back(c, best);
     }
+    if (st != CMSVD_OK) break;
+    // the largest chunk that costs at most 15 % more than the smallest: candidates the
+    // compute units evaluate side by side for (almost) free; between workgroup sizes,
+    // the one with the lower time per candidate at its own chunk
+    int cv = ms.front().first;
+    double tv = ms.front().second;
+    for (const auto& x : ms)
+        if (x.second <= 1.15 * ms.front().second) {
+            cv = x.first;
+            tv = x.second;
+        }
+    if (tv / cv < best_rate) {
+        best_rate = tv / cv;
+        chunk = cv;
+        best_threads = v;
+        best_ms = ms;
+    }
+    }
+    h->force_threads = 0;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != CMSVD_OK) return st;
-    // the largest chunk that costs at most 15 % more than the smallest: candidates the
-    // compute units evaluate side by side for (almost) free
-    int chunk = ms.front().first;
-    for (const auto& x : ms)
-        if (x.second <= 1.15 * ms.front().second) chunk = x.first;
+    ms = best_ms;
     h->tuned_chunk[key] = chunk;
+    if (best_threads > 0) h->tuned_threads[ob] = best_threads;
     if (chunk_out) *chunk_out = chunk;
     if (cache_path) {
         std::ostringstream e;
-        e << "  " << tag << chunk << ", \"ms\": [";
+        e << "  " << tag << chunk << ", \"eig_threads\": " << best_threads << ", \"ms\": [";
         for (size_t q = 0; q < ms.size(); ++q)
             e << (q ? ", " : "") << "[" << ms[q].first << ", " << ms[q].second << "]";
         e << "]}";
@@ -3111,6 +3248,12 @@ cmsvd_status cmsvd_cluster_trace(cmsvd_handle h, int32_t* order, int64_t cap, in
 cmsvd_status cmsvd_cluster_residual(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double eps,
                                     int32_t sort_mode, int32_t* labels, int64_t* nclusters, double* cluster_rel) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_cluster_residual: null handle");
+    std::vector<cmsvd_block> wide_;
+    {
+        const cmsvd_status sw = widen_blocks(h, blocks, nblocks, wide_, "cmsvd_cluster_residual");
+        if (sw != CMSVD_OK) return sw;
+        if (!wide_.empty()) blocks = wide_.data();
+    }
     if (!labels || !nclusters) return fail(CMSVD_EINVAL, "cmsvd_cluster_residual: null output");
     if (!(eps >= 0.0)) return fail(CMSVD_EINVAL, "cmsvd_cluster_residual: eps must be >= 0");
     if (sort_mode != 0 && sort_mode != 1) return fail(CMSVD_EINVAL, "cmsvd_cluster_residual: sort_mode must be 0 or 1");
@@ -3199,6 +3342,12 @@ cmsvd_status cmsvd_cluster_residual(cmsvd_handle h, const cmsvd_block* blocks, i
 cmsvd_status cmsvd_residual_bound(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r,
                                   double* bound2, double* mu) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_residual_bound: null handle");
+    std::vector<cmsvd_block> wide_;
+    {
+        const cmsvd_status sw = widen_blocks(h, blocks, nblocks, wide_, "cmsvd_residual_bound");
+        if (sw != CMSVD_OK) return sw;
+        if (!wide_.empty()) blocks = wide_.data();
+    }
     if (!bound2) return fail(CMSVD_EINVAL, "cmsvd_residual_bound: null output");
     if (nblocks > INT32_MAX) return fail(CMSVD_EUNSUPPORTED, "cmsvd_residual_bound: too many blocks");
     const int N = (int)nblocks;
@@ -3230,6 +3379,12 @@ cmsvd_status cmsvd_residual_bound(cmsvd_handle h, const cmsvd_block* blocks, int
 /* Theorem 1, Algorithm 1 and the explicit tail; see include/cmsvd.h. */
 cmsvd_status cmsvd_weyl_bound(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double* bound2) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_weyl_bound: null handle");
+    std::vector<cmsvd_block> wide_;
+    {
+        const cmsvd_status sw = widen_blocks(h, blocks, nblocks, wide_, "cmsvd_weyl_bound");
+        if (sw != CMSVD_OK) return sw;
+        if (!wide_.empty()) blocks = wide_.data();
+    }
     if (!bound2) return fail(CMSVD_EINVAL, "cmsvd_weyl_bound: null output");
     if (nblocks > INT32_MAX) return fail(CMSVD_EUNSUPPORTED, "cmsvd_weyl_bound: too many blocks");
     WeylBuffers wb;
@@ -3247,6 +3402,12 @@ cmsvd_status cmsvd_weyl_bound(cmsvd_handle h, const cmsvd_block* blocks, int64_t
 cmsvd_status cmsvd_cluster_weyl(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double eps,
                                 int32_t* labels, int64_t* nclusters, double* cluster_rel) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_cluster_weyl: null handle");
+    std::vector<cmsvd_block> wide_;
+    {
+        const cmsvd_status sw = widen_blocks(h, blocks, nblocks, wide_, "cmsvd_cluster_weyl");
+        if (sw != CMSVD_OK) return sw;
+        if (!wide_.empty()) blocks = wide_.data();
+    }
     if (!labels || !nclusters) return fail(CMSVD_EINVAL, "cmsvd_cluster_weyl: null output");
     if (!(eps >= 0.0)) return fail(CMSVD_EINVAL, "cmsvd_cluster_weyl: eps must be >= 0");
     if (nblocks > INT32_MAX) return fail(CMSVD_EUNSUPPORTED, "cmsvd_cluster_weyl: too many blocks");
@@ -3322,6 +3483,12 @@ cmsvd_status cmsvd_cluster_weyl(cmsvd_handle h, const cmsvd_block* blocks, int64
 
 cmsvd_status cmsvd_exact_tail(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double* tail2) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_exact_tail: null handle");
+    std::vector<cmsvd_block> wide_;
+    {
+        const cmsvd_status sw = widen_blocks(h, blocks, nblocks, wide_, "cmsvd_exact_tail");
+        if (sw != CMSVD_OK) return sw;
+        if (!wide_.empty()) blocks = wide_.data();
+    }
     if (!tail2) return fail(CMSVD_EINVAL, "cmsvd_exact_tail: null output");
     if (nblocks < 1 || !blocks) return fail(CMSVD_EINVAL, "cmsvd_exact_tail: no blocks");
     if (nblocks > INT32_MAX) return fail(CMSVD_EUNSUPPORTED, "cmsvd_exact_tail: too many blocks");
@@ -3396,6 +3563,12 @@ cmsvd_status cmsvd_exact_tail(cmsvd_handle h, const cmsvd_block* blocks, int64_t
 cmsvd_status cmsvd_compress(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r, double* Ut,
                             int64_t ldu, double* Vt, int64_t ldv, int64_t* rank, double* tail2, double* energy) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_compress: null handle");
+    std::vector<cmsvd_block> wide_;
+    {
+        const cmsvd_status sw = widen_blocks(h, blocks, nblocks, wide_, "cmsvd_compress");
+        if (sw != CMSVD_OK) return sw;
+        if (!wide_.empty()) blocks = wide_.data();
+    }
     if (!Ut || !Vt || !rank || !tail2) return fail(CMSVD_EINVAL, "cmsvd_compress: null output");
     if (nblocks < 1 || !blocks) return fail(CMSVD_EINVAL, "cmsvd_compress: no blocks");
     if (nblocks > INT32_MAX) return fail(CMSVD_EUNSUPPORTED, "cmsvd_compress: too many blocks");
@@ -3592,6 +3765,12 @@ cmsvd_status cmsvd_compress_partition(cmsvd_handle h, const cmsvd_block* blocks,
                                       double* const* Vt, const int64_t* ldv, int64_t* ranks, double* tail2,
                                       double* energy, int64_t* nclusters, double* ratio, double* rel_error) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_compress_partition: null handle");
+    std::vector<cmsvd_block> wide_;
+    {
+        const cmsvd_status sw = widen_blocks(h, blocks, nblocks, wide_, "cmsvd_compress_partition");
+        if (sw != CMSVD_OK) return sw;
+        if (!wide_.empty()) blocks = wide_.data();
+    }
     if (nblocks < 1 || !blocks || !labels) return fail(CMSVD_EINVAL, "cmsvd_compress_partition: no blocks or labels");
     if (!nclusters || !ratio || !rel_error) return fail(CMSVD_EINVAL, "cmsvd_compress_partition: null output");
     if (nblocks > INT32_MAX) return fail(CMSVD_EUNSUPPORTED, "cmsvd_compress_partition: too many blocks");
@@ -3660,6 +3839,12 @@ cmsvd_status cmsvd_compress_partition(cmsvd_handle h, const cmsvd_block* blocks,
 cmsvd_status cmsvd_tail_energy_grad(cmsvd_handle h, const cmsvd_block* blocks, int64_t nblocks, int64_t r,
                                     int64_t checkpoint, double* f, double* const* grads, double* min_gap) try {
     if (!h) return fail(CMSVD_EINVAL, "cmsvd_tail_energy_grad: null handle");
+    std::vector<cmsvd_block> wide_;
+    {
+        const cmsvd_status sw = widen_blocks(h, blocks, nblocks, wide_, "cmsvd_tail_energy_grad");
+        if (sw != CMSVD_OK) return sw;
+        if (!wide_.empty()) blocks = wide_.data();
+    }
     if (!blocks || nblocks < 1) return fail(CMSVD_EINVAL, "cmsvd_tail_energy_grad: no blocks");
     if (!f) return fail(CMSVD_EINVAL, "cmsvd_tail_energy_grad: null f");
     if (checkpoint < 1) return fail(CMSVD_EINVAL, "cmsvd_tail_energy_grad: checkpoint must be >= 1");

@@ -1643,7 +1643,7 @@ size_t sym_eig_slot_doubles(int nmax) {
 }
 
 void sym_eig_batched(const EigDesc* d_descs, int count, int nmax, int mode, double* gws, int nslots,
-                     hipStream_t s) {
+                     hipStream_t s, int threads) {
     if (count <= 0) return;
     const int T = (nmax + TILE - 1) / TILE, npad = T * TILE;
     const bool split = mode == 2 && sym_eig_split(nmax);
@@ -1697,6 +1697,18 @@ void sym_eig_batched(const EigDesc* d_descs, int count, int nmax, int mode, doub
     const size_t lds = (size_t)(10L * npad + 32) * 8 + (size_t)TL * (TL + 1) / 2 * TILE_EL * 8;
     const long slot = (long)T * (T + 1) / 2 * TILE_EL;
     const int grid = count < nslots ? count : nslots;
+    if (threads == GT / 2) {  // eight waves per problem instead of sixteen (an autotuner choice)
+        if (mode == 0) {
+            lds_limit((const void*)sym_eig_kernel<0, GT / 2>, (int)lds);
+            hipLaunchKernelGGL((sym_eig_kernel<0, GT / 2>), dim3(grid), dim3(GT / 2), lds, s, d_descs, count, npad, TL,
+                               gws, slot);
+        } else {
+            lds_limit((const void*)sym_eig_kernel<1, GT / 2>, (int)lds);
+            hipLaunchKernelGGL((sym_eig_kernel<1, GT / 2>), dim3(grid), dim3(GT / 2), lds, s, d_descs, count, npad, TL,
+                               gws, slot);
+        }
+        return;
+    }
     if (mode == 0) {
         lds_limit((const void*)sym_eig_kernel<0, GT>, (int)lds);
         hipLaunchKernelGGL((sym_eig_kernel<0, GT>), dim3(grid), dim3(GT), lds, s, d_descs, count, npad, TL, gws, slot);

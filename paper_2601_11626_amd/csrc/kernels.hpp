@@ -64,8 +64,10 @@ struct EigDesc {
 // tridiagonalisation, into each descriptor's d and e (sym_eig_tri_doubles(nmax) doubles
 // of scratch), and tri_bisect_batched finishes the evaluation (a high-occupancy
 // bisection kernel); for other orders mode 2 is mode 0.
+// threads: 0 for the default workgroup of the general kernel (orders above 320: 1024
+// threads), or 512 (eight waves per problem); other orders ignore it.
 void sym_eig_batched(const EigDesc* d_descs, int count, int nmax, int mode, double* gws, int nslots,
-                     hipStream_t s);
+                     hipStream_t s, int threads = 0);
 size_t sym_eig_workspace_doubles(int nmax, int nslots);
 // Scratch doubles per problem for the tridiagonal of mode 2 (d at 0, e at half of it).
 size_t sym_eig_tri_doubles(int nmax);

@@ -9,6 +9,7 @@ by a handle without graphs, with eager work and synchronisations between replays
   with the old arguments is captured again and still correct;
 * the dense (thin-candidate) path is never captured.
 """
+import math
 import sys
 
 import numpy as np
@@ -157,3 +158,34 @@ def test_autotuned_scan_chunk_is_cached_and_keeps_the_partition(cm, tmp_path):
     assert len(json.load(open(cache))) == 2
     h.close()
     h2.close()
+
+
+def test_autotuned_general_kernel_workgroup(cm, tmp_path):
+    """For cores above order 320 the autotuner also picks the general eigen kernel's
+    workgroup (1024 or 512 threads per problem); candidate evaluations with either size
+    match the FP64 oracle."""
+    import json
+
+    import oracle
+
+    host = workloads.latent_uneven(seed=46, m=700, nblocks=5, latents=2, d=24, nmin=300, nmax=400, noise=1e-2)
+    pairs = workloads.anchor_ordered_pairs(host)
+    blocks = dev(host)
+    cache = str(tmp_path / "tune.json")
+    h = cm.Handle()
+    h.autotune(700, 350, 64, cache)
+    (key, entry), = json.load(open(cache)).items()
+    say(f"autotune {key}: chunk {entry['scan_chunk']}, eig_threads {entry['eig_threads']}")
+    assert entry["eig_threads"] in (512, 1024)
+    e_o, _ = oracle.merge_errors(host, pairs, 64)
+    for threads in (512, 1024):  # both sizes, through a cache entry naming each
+        text = open(cache).read().replace(f'"eig_threads": {entry["eig_threads"]}', f'"eig_threads": {threads}')
+        open(cache, "w").write(text)
+        h2 = cm.Handle()
+        h2.autotune(700, 350, 64, cache)  # loaded, not measured
+        e_g = cm.cmsvd_merge_errors(blocks, pairs, 64, handle=h2)[0].cpu().numpy()
+        for p, (i, j) in enumerate(pairs.tolist()):
+            nm = math.sqrt(oracle.frob2(host[i]) + oracle.frob2(host[j]))
+            assert abs(e_g[p] ** 2 - e_o[p] ** 2) <= 1e-9 * e_o[p] ** 2 + 1e-12 * nm ** 2, (threads, i, j)
+        h2.close()
+    h.close()
