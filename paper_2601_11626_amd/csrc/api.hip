@@ -430,9 +430,10 @@ void run_gemm(cmsvd_ctx* h, const GemmGroup& g, char* dbase) {
 // ---------------------------------------------------------------------------
 // Semidefinite Cholesky + restricted inverse for a list of Grams.
 //
-// Many problems: one workgroup each (chol_semidef_batched).  A few large ones (where
-// one workgroup per matrix would leave the chip idle and run the factorisation and
-// the inverse row by row): right-looking by 64-column panels -- the panel's diagonal
+// Orders below 192: one workgroup per problem (chol_semidef_batched).  Larger ones
+// (where one workgroup per matrix runs the factorisation and the inverse row by row,
+// with a barrier per row, and a few problems leave the chip idle): right-looking by
+// 64-column panels -- the panel's diagonal
 // block is factored by the same kernel (pivot threshold, zeroed columns, inverse on
 // the kept pivots), the panel below becomes A21 Dinv^T and the trailing matrix is
 // updated by A22 -= L21 L21^T, both on the matrix cores; the inverse is then merged
@@ -464,7 +465,7 @@ struct CholPlan {
     static bool use_blocked(const std::vector<int>& ks) {
         int kmax = 0;
         for (int k : ks) kmax = std::max(kmax, k);
-        return kmax >= 192 && ks.size() <= 32;
+        return kmax >= 192;
     }
     // scratch doubles per problem of order k (blocked path): the panel copy (k x NB)
     // and the products of the inverse merge (k x k)
