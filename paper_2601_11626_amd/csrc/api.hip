@@ -28,6 +28,7 @@
 #include <new>
 #include <stdexcept>
 #include <string>
+#include <unordered_map>
 #include <thread>
 #include <vector>
 
@@ -458,9 +459,10 @@ struct CholPlan {
         GemmGroup t, x;
     };
     std::vector<Level> levels;
-    std::vector<double*> up;  // matrices whose strict upper triangle is zeroed at the end
-    std::vector<int> upk;
-    std::vector<long> upld;
+    // clears of the blocked path, one launch each: the inverses before the panels, the
+    // factors' strict upper triangles at the end
+    std::vector<ClearDesc> pre, post;
+    size_t o_pre = 0, o_post = 0;
 
     static bool use_blocked(const std::vector<int>& ks) {
         int kmax = 0;
@@ -526,10 +528,9 @@ struct CholPlan {
             }
             levels.push_back(std::move(L));
         }
-        for (const auto& c : js) {  // the inverse is lower triangular by construction
-            up.push_back(c.G);
-            upk.push_back(c.k);
-            upld.push_back(c.ldg);
+        for (const auto& c : js) {
+            pre.push_back(ClearDesc{c.Linv, (long)c.ldi * c.k, c.k, 0, c.ldi});
+            post.push_back(ClearDesc{c.G, 0, c.k, 1, c.ldg});  // L is lower triangular
         }
     }
 
@@ -548,6 +549,8 @@ struct CholPlan {
             L.t.off = stg.add(L.t.d);
             L.x.off = stg.add(L.x.d);
         }
+        o_pre = stg.add(pre);
+        o_post = stg.add(post);
     }
 
     void run(cmsvd_ctx* h, char* db) {
@@ -556,7 +559,7 @@ struct CholPlan {
             chol_semidef_batched(reinterpret_cast<const CholDesc*>(db + o_desc), (int)jobs.size(), s);
             return;
         }
-        for (const auto& c : jobs) fill_f64(c.Linv, (long)c.ldi * c.k, 0.0, s);
+        clear_batched(reinterpret_cast<const ClearDesc*>(db + o_pre), (int)pre.size(), s);
         for (auto& P : panels) {
             chol_semidef_batched(reinterpret_cast<const CholDesc*>(db + P.o_diag), (int)P.diag.size(), s);
             if (!P.cp.empty()) {
@@ -569,7 +572,7 @@ struct CholPlan {
             run_gemm(h, L.t, db);
             run_gemm(h, L.x, db);
         }
-        for (size_t i = 0; i < up.size(); ++i) zero_upper(up[i], upk[i], upld[i], s);
+        clear_batched(reinterpret_cast<const ClearDesc*>(db + o_post), (int)post.size(), s);
     }
 };
 
@@ -1003,6 +1006,27 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
             e.d = reinterpret_cast<double*>(W + tri_off) + i * tri;
             e.e = e.d + tri / 2;
             ed[i] = e;
+        }
+        // The eigen kernels take problems in a grid-stride order, so problems next to each
+        // other in the table run at the same time on different CUs.  Grouping them by
+        // candidate lets the CUs of one XCD share the candidate's Gram in its L2 instead
+        // of fetching it once per problem (results do not depend on the order).
+        {
+            std::unordered_map<const double*, int> gid;
+            std::vector<int> grp(nj), cnt;
+            for (size_t i = 0; i < nj; ++i) {
+                auto it = gid.emplace(ed[i].Y, (int)cnt.size()).first;
+                if (it->second == (int)cnt.size()) cnt.push_back(0);
+                grp[i] = it->second;
+                ++cnt[(size_t)it->second];
+            }
+            if (cnt.size() > 1 && cnt.size() < nj) {
+                std::vector<size_t> at(cnt.size(), 0);
+                for (size_t g = 1; g < cnt.size(); ++g) at[g] = at[g - 1] + (size_t)cnt[g - 1];
+                std::vector<EigDesc> grouped(nj);
+                for (size_t i = 0; i < nj; ++i) grouped[at[(size_t)grp[i]]++] = ed[i];
+                ed.swap(grouped);
+            }
         }
         Stage stg;
         g32.off = stg.add(g32.d);

@@ -123,15 +123,26 @@ __global__ void __launch_bounds__(256) sumsq_kernel(const NormDesc* __restrict__
     const NormDesc D = descs[blockIdx.x];
     __shared__ double red_hi[256], red_lo[256];
     double hi = 0.0, lo = 0.0;
-    const long tot = (long)D.rows * D.cols;
+    const int cols = D.cols;
+    const long tot = cols > 0 ? (long)D.rows * cols : 0;
+    // element e = r * cols + c, advanced by 256 without a division per element: the step
+    // is q rows and rem columns, and the column wraps at most once
+    const int q = cols > 0 ? 256 / cols : 0, rem = cols > 0 ? 256 % cols : 0;
+    long r = cols > 0 ? (long)(threadIdx.x / cols) : 0;
+    int c = cols > 0 ? (int)(threadIdx.x % cols) : 0;
     for (long e = threadIdx.x; e < tot; e += 256) {
-        const long r = e / D.cols, c = e % D.cols;
         const double v = D.f32 ? (double)static_cast<const float*>(D.A)[r * D.ld + c]
                                : static_cast<const double*>(D.A)[r * D.ld + c];
         double p = v * v;
         double pe = fma(v, v, -p);  // exact product error
         dd_add(hi, lo, p);
         lo += pe;
+        r += q;
+        c += rem;
+        if (c >= cols) {
+            c -= cols;
+            ++r;
+        }
     }
     red_hi[threadIdx.x] = hi;
     red_lo[threadIdx.x] = lo;
@@ -161,12 +172,24 @@ void sumsq_batched(const NormDesc* d_descs, int count, hipStream_t s) {
 
 __global__ void __launch_bounds__(256) copy_f64_kernel(const CopyDesc* __restrict__ descs) {
     const CopyDesc D = descs[blockIdx.y];
+    if (D.cols <= 0) return;
     const long tot = (long)D.rows * D.cols;
-    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < tot; e += (long)gridDim.x * 256) {
-        const long r = e / D.cols, c = e % D.cols;
+    const long e0 = (long)blockIdx.x * 256 + threadIdx.x, step = (long)gridDim.x * 256;
+    // (r, c) of element e advanced by the stride without a division per element
+    const long q = step / D.cols;
+    const int rem = (int)(step % D.cols);
+    long r = e0 / D.cols;
+    int c = (int)(e0 % D.cols);
+    for (long e = e0; e < tot; e += step) {
         const double v = D.f32 ? (double)static_cast<const float*>(D.A)[r * D.lda + c]
                                : static_cast<const double*>(D.A)[r * D.lda + c];
         D.B[r * D.ldb + c] = v;
+        r += q;
+        c += rem;
+        if (c >= D.cols) {
+            c -= D.cols;
+            ++r;
+        }
     }
 }
 

@@ -211,6 +211,16 @@ void finalize_state_batched(const FinDesc* d_descs, int count, hipStream_t s);
 void add_f64(const double* x, double* y, long n, hipStream_t s);
 // zero the strictly upper triangle of a k x k column-major matrix
 void zero_upper(double* A, int k, long lda, hipStream_t s);
+// Clears of many matrices in one launch: upper == 0 zeroes A[0, n); upper == 1 zeroes
+// the strictly upper triangle of the k x k column-major matrix A (leading dimension ld).
+struct ClearDesc {
+    double* A;
+    long n;
+    int k;
+    int upper;
+    long ld;
+};
+void clear_batched(const ClearDesc* d_descs, int count, hipStream_t s);
 // index of the first i < n with rel[i] <= eps (n if none), written to *out (device int)
 void first_feasible(const double* rel, int n, double eps, int* out, hipStream_t s);
 // ||P||_F^2 per column block: out[b] = sum over the r x k_b block (column-major, ld) -- plain FP64

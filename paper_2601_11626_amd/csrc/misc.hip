@@ -132,6 +132,24 @@ __global__ void zero_upper_kernel(double* A, int k, long lda) {
     }
 }
 
+__global__ void __launch_bounds__(256) clear_kernel(const ClearDesc* __restrict__ descs) {
+    const ClearDesc D = descs[blockIdx.y];
+    if (D.upper) {
+        // column c holds c entries above the diagonal
+        for (int c = 1 + blockIdx.x; c < D.k; c += gridDim.x)
+            for (int i = threadIdx.x; i < c; i += 256) D.A[(long)i + (long)c * D.ld] = 0.0;
+    } else {
+        for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < D.n; e += (long)gridDim.x * 256) D.A[e] = 0.0;
+    }
+}
+
+void clear_batched(const ClearDesc* d_descs, int count, hipStream_t s) {
+    for (int base = 0; base < count; base += 65535) {
+        const int n = count - base < 65535 ? count - base : 65535;
+        hipLaunchKernelGGL(clear_kernel, dim3(64, n), dim3(256), 0, s, d_descs + base);
+    }
+}
+
 void zero_upper(double* A, int k, long lda, hipStream_t s) {
     if (k <= 0) return;
     long g = ((long)k * k + 255) / 256;
