@@ -114,7 +114,7 @@ def _pmc_rows(path):
 
 # the headline's dominant launch: the register-resident tridiagonalisation of the split
 # evaluation (n = 320: 10 tile rows of 32), whose bisection runs in tri_bisect_kernel
-EIG_KERNEL = "sym_eig_reg_kernel<2, 512, 5, 5, 10>"
+EIG_KERNEL = "sym_eig_reg_kernel<2, 512, 5, 5, 10, true>"
 
 
 def pmc_summary(fetch_csv, write_csv, copy_mib, kernel=EIG_KERNEL):

@@ -54,6 +54,11 @@
  *     panels (concatenation is associative, so the same matrix results).
  *     cmsvd_compress handles larger Grams by subspace iteration (its rank r_C is
  *     limited to 2016).
+ *   - Reproducibility: a call repeated on the same data returns the same bits, except
+ *     candidate evaluations whose core order r + n_j is 161..320 (their
+ *     tridiagonalisation sums A v over several wavefronts with atomic adds, in an
+ *     order that varies) and eigenproblems of order above 320; these agree from run to
+ *     run to rounding, |d(err^2)| = O((r + n_j) u ||M||^2) with u = 2^-53.
  *   - NaN/Inf in the data propagate into the affected results; they are not errors.
  *     A rank-deficient residual is not an error either: its numerically absent
  *     directions are dropped (their energy stays in the error estimate).

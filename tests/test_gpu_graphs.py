@@ -17,6 +17,7 @@ import pytest
 import torch
 
 import workloads
+from rounding import pair_norm2, same_to_rounding
 
 pytestmark = pytest.mark.gpu
 
@@ -45,8 +46,10 @@ def eager(cm, blocks, pairs, r):
     return e
 
 
-def close(a, b):
-    return torch.allclose(a, b, rtol=1e-12, atol=0)
+def close(a, b, blocks, pairs, n):
+    """Equal to rounding: cores of order 161..320 sum A v over several waves in varying
+    order, so two runs of the same merges agree to O(n u ||M||^2) in e^2."""
+    return same_to_rounding(a, b, pair_norm2([x.double().cpu().numpy() for x in blocks], pairs), n)
 
 
 def test_graph_replays_match_eager_results(cm):
@@ -62,7 +65,7 @@ def test_graph_replays_match_eager_results(cm):
         out[0].fill_(float("nan"))
         cm.cmsvd_merge_errors(blocks, pairs, r, handle=h, out=out)
         torch.cuda.synchronize()
-        assert close(out[0], ref), call
+        assert close(out[0], ref, blocks, pairs, r + 200), call
         # eager work of the program between replays
         scratch = torch.randn(1 << 20, device="cuda")
         float(scratch.sum())
@@ -76,7 +79,7 @@ def test_graph_replays_match_eager_results(cm):
         blocks[5 + step].add_(0.01)
         cm.cmsvd_merge_errors(blocks, pairs, r, handle=h, out=out)
         torch.cuda.synchronize()
-        assert close(out[0], eager(cm, blocks, pairs, r)), step
+        assert close(out[0], eager(cm, blocks, pairs, r), blocks, pairs, r + 200), step
     assert h.graph_stats()["replays"] == 6
     h.close()
 
@@ -95,16 +98,16 @@ def test_workspace_growth_drops_and_recaptures(cm):
     for _ in range(3):
         cm.cmsvd_merge_errors(small, ps, 64, handle=h, out=o_s)
     torch.cuda.synchronize()
-    assert close(o_s[0], ref_s)
+    assert close(o_s[0], ref_s, small, ps, 64 + 120)
     assert h.graph_stats()["captures"] == 1
     cm.cmsvd_merge_errors(big, pb, 64, handle=h, out=o_b)  # grows the workspaces
     torch.cuda.synchronize()
-    assert close(o_b[0], ref_b)
+    assert close(o_b[0], ref_b, big, pb, 64 + 300)
     for _ in range(3):  # the old graph is gone: captured again, then replayed
         o_s[0].zero_()
         cm.cmsvd_merge_errors(small, ps, 64, handle=h, out=o_s)
         torch.cuda.synchronize()
-        assert close(o_s[0], ref_s)
+        assert close(o_s[0], ref_s, small, ps, 64 + 120)
     st = h.graph_stats()
     say(f"graph stats {st}")
     assert st["captures"] == 2
@@ -122,7 +125,7 @@ def test_dense_path_is_not_captured(cm):
     for _ in range(3):
         cm.cmsvd_merge_errors(blocks, pairs, 20, handle=h, out=out)
         torch.cuda.synchronize()
-        assert close(out[0], ref)
+        assert close(out[0], ref, blocks, pairs, 40)
     assert h.graph_stats()["captures"] == 0
     h.close()
 
@@ -152,7 +155,7 @@ def test_autotuned_scan_chunk_is_cached_and_keeps_the_partition(cm, tmp_path):
     lab_t, _, rel_t = cm.cmsvd_cluster(blocks, 24, 0.2, handle=h2)
     lab_d, _, rel_d = cm.cmsvd_cluster(blocks, 24, 0.2, handle=cm.Handle())
     assert lab_t == lab_d
-    np.testing.assert_allclose(rel_t, rel_d, rtol=1e-10, atol=1e-7)
+    np.testing.assert_allclose(rel_t, rel_d, rtol=1e-9, atol=1e-7)  # equal to rounding
     # another shape adds a second entry
     h2.autotune(512, 300, 24, cache)
     assert len(json.load(open(cache))) == 2
