@@ -678,6 +678,7 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
             }
             geo[t] = code;
         }
+        if (SHV && t == 0) red[8] = 0.0;
         __syncthreads();
         // For each tile column c (the step's leading column), the active LDS tiles
         // (columns >= max(c, c0)) in row-major order, handed out so that every wave
@@ -724,7 +725,11 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
         }
         for (int i = t; i < PWL; i += RT) pw[i] = 0.0;
         part = wave_sum(part);
-        if (lane == 0) red[8 + w] = part;
+        if (SHV) {
+            // one norm accumulator (red[8]) for all waves; it was zeroed before the
+            // geometry barrier above
+            if (lane == 0) unsafeAtomicAdd(&red[8], part);
+        } else if (lane == 0) red[8 + w] = part;
         __syncthreads();
 
         // Step j: (H) Householder vector v_j of column j; (P) one pass over the
@@ -736,8 +741,11 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
             const int Cj = j >> 5;
             // (H) redundantly in every wave
             double xn2 = 0.0;
+            if (SHV) xn2 = red[8];
+            else {
 #pragma unroll
-            for (int q = 0; q < RW; ++q) xn2 += red[8 + q];
+                for (int q = 0; q < RW; ++q) xn2 += red[8 + q];
+            }
             const double alpha = xv[j + 1];
             double tau = 0.0, beta = alpha, scale = 0.0;
             if (xn2 > 0.0) {
@@ -760,11 +768,17 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
             // partials accumulate while consecutive tiles stay in one tile row.
             const int Cn = (j + 1) >> 5, cn = (j + 1) & 31;
             double* pww = SHV ? pw : pw + w * NP;
+            if (SHV && t == 0) red[8] = 0.0;  // every wave read it in (H); (W) adds to it
+            // the wave's slot codes and LDS share, read together (one LDS wait)
+            int codes[NSLOT];
+#pragma unroll
+            for (int sl = 0; sl < NSLOT; ++sl) codes[sl] = geo[w * NSLOT + sl];
+            const int al_v = geo[RW * NSLOT + Cj * RW + w];
             double racc[4] = {0.0, 0.0, 0.0, 0.0};
             int curR = -1;
 #pragma unroll
             for (int sl = 0; sl < NSLOT; ++sl) {
-                const int code = __builtin_amdgcn_readfirstlane(geo[w * NSLOT + sl]);
+                const int code = __builtin_amdgcn_readfirstlane(codes[sl]);
                 if (code >= 0 && (code & 255) >= Cj) {
                     const int R = code >> 8, C = code & 255;
                     if (R != curR) {
@@ -784,7 +798,7 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                 }
             }
             {
-                const int al = __builtin_amdgcn_readfirstlane(geo[RW * NSLOT + Cj * RW + w]);
+                const int al = __builtin_amdgcn_readfirstlane(al_v);
                 const int cl = Cj > c0 ? Cj : c0;
                 int f = al >> 8, k = al & 255;
                 // row-major position of the first tile of this wave's share
@@ -867,7 +881,9 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                 vp[i] = vc[i];
             }
             part = wave_sum(part);
-            if (lane == 0) red[8 + w] = part;
+            if (SHV) {
+                if (lane == 0) unsafeAtomicAdd(&red[8], part);
+            } else if (lane == 0) red[8 + w] = part;
             __syncthreads();  // #3
         }
         __syncthreads();
