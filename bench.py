@@ -34,7 +34,7 @@ if ROOT not in sys.path:
 METRIC = "candidate merges evaluated/sec (batched vs plain, same GPU) at ≤1e-5 rel error"
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 (vector and matrix), 256 CU x 2.4 GHz
 # dense matrix-core peaks of MI355X per projection operand type, and the kernel name
-PROJ_PEAK = {"f64": (78.6, "gemm_f64_kernel (Y = U^T B)"), "f32": (157.3, "gemm_f32_kernel (Y = U^T B)"),
+PROJ_PEAK = {"f64": (78.6, "gemm_f64_kernel (Y = U^T B)"), "f32": (157.3, "gemm_f32_wide_kernel (Y = U^T B)"),
              "bf16": (2500.0, "gemm_bf16_kernel (Y = U^T B, one BF16 pass)"),
              "bf16x3": (2500.0, "gemm_bf16_kernel (Y = U^T B, three BF16 passes)")}
 

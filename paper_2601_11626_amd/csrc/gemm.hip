@@ -486,9 +486,151 @@ __global__ void __launch_bounds__(256) gemm_f32_kernel(const GemmDesc* __restric
             }
 }
 
+// Wide tiles for the candidate projections Y = U^T A_j (op(A) = A and op(B) = B^T, both
+// with the free index contiguous in memory): a 512-thread workgroup owns a 64 x 256 tile
+// of C, so a 64-column basis is read once per candidate block instead of once per 64
+// columns of it; each of the eight waves owns a 32 x 64 part (2 x 4 MFMA blocks).  K
+// advances by 32 through one LDS stage while the next slab waits in registers (45 KB
+// of LDS: three workgroups per CU).  Operands are read four consecutive elements at a
+// time (one 16-byte load where the problem's pointer and leading dimension allow it),
+// rounded to FP32 as they are staged, and every lane stores its four consecutive rows
+// of C as two 16-byte stores where possible.
+constexpr int WBM = 64, WBN = 256, WBK = 32, WTH = 512;
+constexpr int WPAD = 16;  // LDS row padding (floats): rows k and k + 1 fall 16 banks apart
+
+template <typename T>
+__device__ __forceinline__ f4_t load4_f32(const T* __restrict__ P, long off, int nvalid, bool vec) {
+    f4_t r;
+    if (vec && nvalid >= 4) {
+        if constexpr (sizeof(T) == 4) {
+            r = *reinterpret_cast<const f4_t*>(P + off);
+        } else {
+            typedef double d2_t __attribute__((ext_vector_type(2)));
+            const d2_t x0 = *reinterpret_cast<const d2_t*>(P + off);
+            const d2_t x1 = *reinterpret_cast<const d2_t*>(P + off + 2);
+            r = f4_t{(float)x0[0], (float)x0[1], (float)x1[0], (float)x1[1]};
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) r[q] = q < nvalid ? (float)P[off + q] : 0.0f;
+    }
+    return r;
+}
+
+template <typename TA, typename TB>
+__global__ void __launch_bounds__(WTH) gemm_f32_wide_kernel(const GemmDesc* __restrict__ descs, int base,
+                                                            double alpha, double beta) {
+    const GemmDesc d = descs[base + blockIdx.y];
+    const int tilesM = (d.M + WBM - 1) / WBM;
+    const int tilesN = (d.N + WBN - 1) / WBN;
+    if ((int)blockIdx.x >= tilesM * tilesN) return;
+    const int tm = blockIdx.x % tilesM, tn = blockIdx.x / tilesM;
+    const int m0 = tm * WBM, n0 = tn * WBN;
+    const TA* __restrict__ A = static_cast<const TA*>(d.A);
+    const TB* __restrict__ B = static_cast<const TB*>(d.B);
+    const bool vecA = (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (d.lda & 3) == 0;
+    const bool vecB = (reinterpret_cast<uintptr_t>(B) & 15) == 0 && (d.ldb & 3) == 0;
+
+    __shared__ float As[WBK][WBM + WPAD];
+    __shared__ float Bs[WBK][WBN + WPAD];
+
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wm = w >> 2, wn = w & 3;
+    f4_t acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
+
+    // slab k0 .. k0 + 31: thread t holds A rows m0 + 4 (t % 16) .. + 3 at k0 + t / 16, and
+    // four runs of B: chunk c = t + 512 q covers k0 + c / 64, columns n0 + 4 (c % 64) .. + 3
+    const int ak = t >> 4, ai = (t & 15) * 4;
+    f4_t ra, rb[4];
+    auto fetch = [&](int k0) {
+        const int kk = k0 + ak;
+        const int nva = kk < d.K ? min(4, d.M - (m0 + ai)) : 0;
+        ra = load4_f32<TA>(A, (long)(m0 + ai) + (long)kk * d.lda, nva, vecA);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = t + WTH * q, bk = k0 + (c >> 6), bn = n0 + (c & 63) * 4;
+            const int nvb = bk < d.K ? min(4, d.N - bn) : 0;
+            rb[q] = load4_f32<TB>(B, (long)bn + (long)bk * d.ldb, nvb, vecB);
+        }
+    };
+    auto stage = [&]() {
+        *reinterpret_cast<f4_t*>(&As[ak][ai]) = ra;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = t + WTH * q;
+            *reinterpret_cast<f4_t*>(&Bs[c >> 6][(c & 63) * 4]) = rb[q];
+        }
+    };
+    const int nk = (d.K + WBK - 1) / WBK;
+    fetch(0);
+    stage();
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) fetch((kt + 1) * WBK);
+        // A operand: lane holds row (lane % 16), K value lane / 16 of the 4-deep step;
+        // B operand: column (lane % 16), the same K value.
+#pragma unroll
+        for (int k4 = 0; k4 < WBK / 4; ++k4) {
+            const int krow = k4 * 4 + (lane >> 4);
+            float a[2], b[4];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) a[i] = As[krow][wm * 32 + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[krow][wn * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+        if (kt + 1 < nk) {
+            stage();
+            __syncthreads();
+        }
+    }
+    // D[i][j] of a 16x16 FP32 block sits in lane j + 16*(i/4), element i%4: four
+    // consecutive rows of one column of C per lane
+    const bool vecC = beta == 0.0 && (reinterpret_cast<uintptr_t>(d.C) & 15) == 0 && (d.ldc & 1) == 0;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) {
+            const int row = m0 + wm * 32 + bi * 16 + (lane >> 4) * 4;
+            const int col = n0 + wn * 64 + bj * 16 + (lane & 15);
+            if (col >= d.N) continue;
+            double* c = d.C + (long)row + (long)col * d.ldc;
+            if (vecC && row + 3 < d.M) {
+                typedef double d2_t __attribute__((ext_vector_type(2)));
+                *reinterpret_cast<d2_t*>(c) = d2_t{alpha * (double)acc[bi][bj][0], alpha * (double)acc[bi][bj][1]};
+                *reinterpret_cast<d2_t*>(c + 2) = d2_t{alpha * (double)acc[bi][bj][2], alpha * (double)acc[bi][bj][3]};
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (row + v < d.M) {
+                        double val = alpha * (double)acc[bi][bj][v];
+                        if (beta != 0.0) val += beta * c[v];
+                        c[v] = val;
+                    }
+            }
+        }
+}
+
 template <typename TA, typename TB>
 static void launch_f32(const GemmDesc* descs, int count, int maxM, int maxN, bool ta, bool tb, double alpha,
                        double beta, hipStream_t s) {
+    if (!ta && tb && maxN > GBN) {
+        // projections of candidate blocks wider than one 64-column tile: wide tiles
+        const int wt = ((maxM + WBM - 1) / WBM) * ((maxN + WBN - 1) / WBN);
+        for (int base = 0; base < count; base += 65535) {
+            const int n = count - base < 65535 ? count - base : 65535;
+            hipLaunchKernelGGL((gemm_f32_wide_kernel<TA, TB>), dim3(wt, n), dim3(WTH), 0, s, descs, base, alpha, beta);
+        }
+        return;
+    }
     const int tiles = ((maxM + GBM - 1) / GBM) * ((maxN + GBN - 1) / GBN);
     for (int base = 0; base < count; base += 65535) {
         const int n = count - base < 65535 ? count - base : 65535;

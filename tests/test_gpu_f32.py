@@ -69,6 +69,26 @@ def test_gemm_f32_matches_rounded_product(cm, M, N, K, ta, tb):
         assert np.max(np.abs(out - exact)) > 1e3 * 2.0 ** -52 * np.max(np.abs(A) @ np.abs(B))
 
 
+@pytest.mark.parametrize("M,N,K", [(64, 300, 1024), (65, 257, 33), (128, 512, 96), (62, 66, 8)])
+@pytest.mark.parametrize("beta", [0.0, -0.5])
+def test_gemm_f32_wide_tiles(cm, M, N, K, beta):
+    """The projection layout (op(A) = A, op(B) = B^T) with more than 64 columns runs on
+    64 x 256 tiles: ragged tiles in M, N and K, vector and element-wise loads (leading
+    dimensions with and without 16-byte rows), and the vector store of C when beta = 0."""
+    rng = np.random.default_rng(M * 5 + N * 11 + K + (7 if beta else 0))
+    A = rng.standard_normal((M, K)) * np.exp(rng.uniform(-3, 3, (M, K)))
+    B = rng.standard_normal((K, N)).astype(np.float32).astype(np.float64)
+    say(f"gemm_f32 wide tiles M={M} N={N} K={K} beta={beta}")
+    At = torch.from_numpy(A.T.copy()).cuda().t()  # column-major, lda = M
+    Bt = torch.from_numpy(B.astype(np.float32).T.copy()).cuda().t()  # B^T stored N x K, ldb = N
+    C0 = rng.standard_normal((M, N))
+    C = torch.from_numpy(C0.T.copy()).cuda().t()
+    out = cm.cmsvd_gemm_f32(At, Bt, C=C, alpha=0.75, beta=beta).cpu().numpy()
+    ref = 0.75 * (lowprec.round_f32(A) @ B) + beta * C0
+    tol = 0.75 * (K + 2) * U32 * 1.01 * (np.abs(A) @ np.abs(B)) + 1e-15 * np.abs(ref)
+    assert np.all(np.abs(out - ref) <= tol + 1e-300)
+
+
 def kyfan(st, B, r, elem):
     """sum_{i<=r} sigma_i of [[0, S D], [D^T S, 0]] with D = elem (rho x k, an elementwise
     bound on the error of Y = U^T B)."""
