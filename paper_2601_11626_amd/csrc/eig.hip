@@ -1879,60 +1879,124 @@ __global__ void __launch_bounds__(ET) sym_vectors_kernel(const VecDesc* __restri
     }
     __syncthreads();
 
-    // (2) Gram-Schmidt in descending-eigenvalue order, two passes (CGS2).  The dot
-    // products and updates keep 8 independent loads and partial sums in flight.
-    for (int q = 0; q < nk; ++q) {
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int qq = t; qq < q; qq += ET) {
-                double sp[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                int i = 0;
-                for (; i + 8 <= n; i += 8) {
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) sp[u] = fma(at(4, i + u, qq), at(4, i + u, q), sp[u]);
-                }
-                for (; i < n; ++i) sp[0] = fma(at(4, i, qq), at(4, i, q), sp[0]);
-                coef[qq] = ((sp[0] + sp[1]) + (sp[2] + sp[3])) + ((sp[4] + sp[5]) + (sp[6] + sp[7]));
-            }
-            __syncthreads();
-            for (int i = t; i < n; i += ET) {
-                double vp8[8] = {at(4, i, q), 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                int qq = 0;
-                for (; qq + 8 <= q; qq += 8) {
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) vp8[u] = fma(-coef[qq + u], at(4, i, qq + u), vp8[u]);
-                }
-                for (; qq < q; ++qq) vp8[0] = fma(-coef[qq], at(4, i, qq), vp8[0]);
-                at(4, i, q) = ((vp8[0] + vp8[1]) + (vp8[2] + vp8[3])) + ((vp8[4] + vp8[5]) + (vp8[6] + vp8[7]));
-            }
-            __syncthreads();
-        }
-        double part = 0.0;
-        for (int i = t; i < n; i += ET) part += at(4, i, q) * at(4, i, q);
-        const double nrm = sqrt(block_sum(part, red));
-        const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-        for (int i = t; i < n; i += ET) at(4, i, q) *= inv;
-        __syncthreads();
-    }
-
-    if (D.skip_bt) {
+    // With every iterate in LDS (rows of n + 1 doubles, so that the lanes of a column
+    // read fall on different banks), Gram-Schmidt and the back-transformation read no
+    // global memory; otherwise the iterates stay in the scratch and the reflectors are
+    // applied to LDS panels of them.
+    const int ldx = n + 1;
+    const long hdr_d = 16L + ((nk + 15) / 16) * 16;  // red + coef
+    const bool in_lds = (hdr_d + (long)nk * ldx + n) * 8 <= LDS_BYTES;
+    if (in_lds) {
         for (int el = t; el < nk * n; el += ET) {
-            const int i = el % n, q = el / n;
-            D.Z[(long)i + (long)q * D.ldz] = at(4, i, q);
+            const int q = el / n, i = el % n;
+            X[(size_t)q * ldx + i] = at(4, i, q);
         }
-        return;
+        __syncthreads();
+        // (2) Gram-Schmidt in descending-eigenvalue order, two passes (CGS2): each
+        // coefficient is split over four lanes (a quarter of the rows each, summed by
+        // DPP), each row's update keeps four partial sums
+        for (int q = 0; q < nk; ++q) {
+            double* xq = X + (size_t)q * ldx;
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int base = 0; base < q; base += ET / 4) {
+                    const int c = base + (t >> 2), part = t & 3;
+                    double sp = 0.0;
+                    if (c < q) {
+                        const double* xc = X + (size_t)c * ldx;
+                        for (int i = part; i < n; i += 4) sp = fma(xc[i], xq[i], sp);
+                    }
+                    sp += dpp_move<0xB1>(sp);
+                    sp += dpp_move<0x4E>(sp);
+                    if (c < q && part == 0) coef[c] = sp;
+                }
+                __syncthreads();
+                for (int i = t; i < n; i += ET) {
+                    double a0 = xq[i], a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                    int c = 0;
+                    for (; c + 4 <= q; c += 4) {
+                        a0 = fma(-coef[c], X[(size_t)c * ldx + i], a0);
+                        a1 = fma(-coef[c + 1], X[(size_t)(c + 1) * ldx + i], a1);
+                        a2 = fma(-coef[c + 2], X[(size_t)(c + 2) * ldx + i], a2);
+                        a3 = fma(-coef[c + 3], X[(size_t)(c + 3) * ldx + i], a3);
+                    }
+                    for (; c < q; ++c) a0 = fma(-coef[c], X[(size_t)c * ldx + i], a0);
+                    xq[i] = (a0 + a1) + (a2 + a3);
+                }
+                __syncthreads();
+            }
+            double part = 0.0;
+            for (int i = t; i < n; i += ET) part += xq[i] * xq[i];
+            const double nrm = sqrt(block_sum(part, red));
+            const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+            for (int i = t; i < n; i += ET) xq[i] *= inv;
+            __syncthreads();
+        }
+        if (D.skip_bt) {
+            for (int el = t; el < nk * n; el += ET) {
+                const int i = el % n, q = el / n;
+                D.Z[(long)i + (long)q * D.ldz] = X[(size_t)q * ldx + i];
+            }
+            return;
+        }
+    } else {
+        // (2) Gram-Schmidt in descending-eigenvalue order, two passes (CGS2).  The dot
+        // products and updates keep 8 independent loads and partial sums in flight.
+        for (int q = 0; q < nk; ++q) {
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int qq = t; qq < q; qq += ET) {
+                    double sp[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                    int i = 0;
+                    for (; i + 8 <= n; i += 8) {
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) sp[u] = fma(at(4, i + u, qq), at(4, i + u, q), sp[u]);
+                    }
+                    for (; i < n; ++i) sp[0] = fma(at(4, i, qq), at(4, i, q), sp[0]);
+                    coef[qq] = ((sp[0] + sp[1]) + (sp[2] + sp[3])) + ((sp[4] + sp[5]) + (sp[6] + sp[7]));
+                }
+                __syncthreads();
+                for (int i = t; i < n; i += ET) {
+                    double vp8[8] = {at(4, i, q), 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                    int qq = 0;
+                    for (; qq + 8 <= q; qq += 8) {
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) vp8[u] = fma(-coef[qq + u], at(4, i, qq + u), vp8[u]);
+                    }
+                    for (; qq < q; ++qq) vp8[0] = fma(-coef[qq], at(4, i, qq), vp8[0]);
+                    at(4, i, q) = ((vp8[0] + vp8[1]) + (vp8[2] + vp8[3])) + ((vp8[4] + vp8[5]) + (vp8[6] + vp8[7]));
+                }
+                __syncthreads();
+            }
+            double part = 0.0;
+            for (int i = t; i < n; i += ET) part += at(4, i, q) * at(4, i, q);
+            const double nrm = sqrt(block_sum(part, red));
+            const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+            for (int i = t; i < n; i += ET) at(4, i, q) *= inv;
+            __syncthreads();
+        }
+
+        if (D.skip_bt) {
+            for (int el = t; el < nk * n; el += ET) {
+                const int i = el % n, q = el / n;
+                D.Z[(long)i + (long)q * D.ldz] = at(4, i, q);
+            }
+            return;
+        }
     }
 
-    // (3) back-transformation z = H_0 H_1 ... H_{n-3} x, vectors in LDS panels
-    const long hdr = (16L + ((nk + 15) / 16) * 16) * 8 + (long)n * 8;  // red + coef + v_j
-    const int nv = (int)((LDS_BYTES - hdr) / ((long)n * 8));
+    // (3) back-transformation z = H_0 H_1 ... H_{n-3} x: all vectors at once when they
+    // are in LDS, else in LDS panels loaded from the scratch
+    const int ldp = in_lds ? ldx : n;
+    const long hdr = hdr_d * 8 + (long)n * 8;  // red + coef + v_j
+    const int nv = in_lds ? nk : (int)((LDS_BYTES - hdr) / ((long)n * 8));
     const int panel = nv < nk ? (nv > 0 ? nv : 1) : nk;
-    double* vj = X + (size_t)panel * n;  // n doubles
+    double* vj = X + (size_t)panel * ldp;  // n doubles
     for (int q0 = 0; q0 < nk; q0 += panel) {
         const int pq = (nk - q0) < panel ? (nk - q0) : panel;
-        for (int el = t; el < pq * n; el += ET) {
-            const int i = el % n, qq = el / n;
-            X[(size_t)qq * n + i] = at(4, i, q0 + qq);
-        }
+        if (!in_lds)
+            for (int el = t; el < pq * n; el += ET) {
+                const int i = el % n, qq = el / n;
+                X[(size_t)qq * ldp + i] = at(4, i, q0 + qq);
+            }
         __syncthreads();
         for (int j = n - 3; j >= 0; --j) {
             const double tj = D.tau[j];
@@ -1944,7 +2008,7 @@ __global__ void __launch_bounds__(ET) sym_vectors_kernel(const VecDesc* __restri
                 const int qq = base + (t >> 3), part = t & 7;
                 double s = 0.0;
                 if (qq < pq) {
-                    const double* x = X + (size_t)qq * n;
+                    const double* x = X + (size_t)qq * ldp;
                     for (int i = j + 1 + part; i < n; i += 8) s = fma(vj[i], x[i], s);
                 }
                 s = sum_lanes8(s);
@@ -1953,13 +2017,13 @@ __global__ void __launch_bounds__(ET) sym_vectors_kernel(const VecDesc* __restri
             __syncthreads();
             for (int el = t; el < pq * (n - j - 1); el += ET) {
                 const int qq = el / (n - j - 1), i = j + 1 + el % (n - j - 1);
-                X[(size_t)qq * n + i] -= coef[qq] * vj[i];
+                X[(size_t)qq * ldp + i] -= coef[qq] * vj[i];
             }
             __syncthreads();
         }
         for (int el = t; el < pq * n; el += ET) {
             const int i = el % n, qq = el / n;
-            D.Z[(long)i + (long)(q0 + qq) * D.ldz] = X[(size_t)qq * n + i];
+            D.Z[(long)i + (long)(q0 + qq) * D.ldz] = X[(size_t)qq * ldp + i];
         }
         __syncthreads();
     }
