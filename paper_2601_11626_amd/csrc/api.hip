@@ -705,6 +705,9 @@ struct CommitJob {
     // Optional: the block energy ||B||_F^2 (double-double, device) when the caller has
     // it already; otherwise the pipeline computes it.
     const double* nb_in = nullptr;
+    // Optional, for r_in == 0: the block's Gram B^T B (k x k FP64, ld k, device) when the
+    // caller has it already; it is copied in place of the first CholeskyQR Gram.
+    const double* G_in = nullptr;
 };
 
 cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
@@ -776,7 +779,7 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
     // descriptor tables
     std::vector<NormDesc> nd;
     std::vector<const double*> pnb(J);
-    std::vector<CopyDesc> cd(J);
+    std::vector<CopyDesc> cd(J), gcd;  // block -> Rt copies; given Grams -> G1
     GemmGroup gP, gR1, gP2, gR2, gG1, gQ1, gG2, gQr, gF, gS, gU1, gU2a, gU2b;
     gP.tb = true;                        // P = Ut * Bt^T
     gR1.ta = true; gR1.alpha = -1.0; gR1.beta = 1.0;   // Rt -= P^T Ut
@@ -815,7 +818,8 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
             gP2.push(GemmDesc{c.U, D(q.Rt), D(q.P2), c.r_in, k, m, c.ldu, (long)k, (long)c.r_in});
             gR2.push(GemmDesc{D(q.P2), c.U, D(q.Rt), k, m, c.r_in, (long)c.r_in, c.ldu, (long)k});
         }
-        gG1.push(GemmDesc{D(q.Rt), D(q.Rt), D(q.G1), k, k, m, (long)k, (long)k, (long)k});
+        if (c.r_in == 0 && c.G_in) gcd.push_back(CopyDesc{c.G_in, k, k, (long)k, 0, D(q.G1), (long)k});
+        else gG1.push(GemmDesc{D(q.Rt), D(q.Rt), D(q.G1), k, k, m, (long)k, (long)k, (long)k});
         ch1[j] = CholDesc{k, D(q.G1), (long)k, D(q.Li1), (long)k, (h->chol_c > 0.0 ? h->chol_c : (double)k) * EPS,
                           pnb[j], nullptr};
         gQ1.push(GemmDesc{D(q.Li1), D(q.Rt), D(q.Q1), k, m, k, (long)k, (long)k, (long)k});
@@ -872,7 +876,7 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
         cp2.build(ch2, scr);  // runs after cp1 is done with the scratch
     }
     Stage stg;
-    size_t o_nd = stg.add(nd), o_cd = stg.add(cd);
+    size_t o_nd = stg.add(nd), o_cd = stg.add(cd), o_gcd = stg.add(gcd);
     cp1.stage(stg);
     cp2.stage(stg);
     std::vector<FinDesc> fdk;
@@ -904,6 +908,7 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
     run_gemm(h, gR2, db);
     for (int j = 0; j < J; ++j)
         if (jobs[j].r_in > 0) add_f64(D(o[j].P2), D(o[j].P), (long)jobs[j].r_in * o[j].k, s);
+    if (!gcd.empty()) copy_f64_batched(reinterpret_cast<const CopyDesc*>(db + o_gcd), (int)gcd.size(), maxrows, s);
     run_gemm(h, gG1, db);
     cp1.run(h, db);
     run_gemm(h, gQ1, db);
@@ -2566,6 +2571,9 @@ static cmsvd_status merge_errors_run(cmsvd_ctx* h, const cmsvd_block* blocks, in
                 const int i = anchors[a];
                 jobs.push_back(CommitJob{(int)m, nullptr, (long)r, nullptr, 0, blocks[i], (int)r, K(o_U[a]), ldu_a,
                                          K(o_S[a]), K(o_acc[a]), nullptr});
+                // the norm and Gram of the block, computed above for the evaluation
+                jobs.back().nb_in = K(o_n[cslot[i]]);
+                if (o_g[cslot[i]] != (size_t)-1 && o_g[cslot[i]] != o_n[cslot[i]]) jobs.back().G_in = K(o_g[cslot[i]]);
             }
             st = commit_batched(h, jobs);
             if (st != CMSVD_OK) return st;
