@@ -115,6 +115,9 @@ def _pmc_rows(path):
 # the headline's dominant launch: the register-resident tridiagonalisation of the split
 # evaluation (n = 320: 10 tile rows of 32), whose bisection runs in tri_bisect_kernel
 EIG_KERNEL = "sym_eig_reg_kernel<2, 512, 5, 5, 10, true>"
+# the four-wave kernel that finishes cores of order 161..320 on their trailing matrix
+TAIL_KERNEL = "sym_eig_reg_kernel<2, 256, 4, 0, 5, true>"
+TAIL_ORDER = 160
 
 
 def pmc_summary(fetch_csv, write_csv, copy_mib, kernel=EIG_KERNEL):
@@ -1010,19 +1013,29 @@ def main():
                    "max_rel_diff_vs_batched": lib_dev}
         log(f"library: {lib_rate:.1f} merges/s over {len(sample)} pairs")
 
-    # dominant stage and its roofline position
+    # dominant stage and its roofline position.  Cores of order 161..320 are
+    # tridiagonalised for n - 160 column steps by EIG_KERNEL; the trailing 160 x 160
+    # matrix goes to TAIL_KERNEL (stage core_tail).  Each is priced at the (4/3) n^3 of
+    # the part of the reduction it does.
+    n_core = r + k
+    nt = TAIL_ORDER if TAIL_ORDER < n_core <= 320 else 0
     flops = {
         "projection": 2.0 * r * k * m * npairs * args.steps,
-        "core_eig": (4.0 / 3.0) * float(r + k) ** 3 * npairs * args.steps,
+        "core_eig": (4.0 / 3.0) * (float(n_core) ** 3 - float(nt) ** 3) * npairs * args.steps,
+        "core_tail": (4.0 / 3.0) * float(nt) ** 3 * npairs * args.steps,
     }
-    timed = {n: stages[n][0] for n in ("commit", "projection", "core_eig", "core_bisect")}
+    timed = {n: stages[n][0] for n in ("commit", "projection", "core_eig", "core_bisect", "core_tail")}
     dom = max(timed, key=timed.get)
     roof = None
-    if dom in flops and timed[dom] > 0:
+    if dom in flops and timed[dom] > 0 and not (dom == "projection" and args.projection != "f64"):
         ach = flops[dom] / (timed[dom] * 1e-3) / 1e12
+        label = {"core_eig": EIG_KERNEL + (f" (tridiagonalisation, first n - {nt} steps)" if nt else
+                                           " (tridiagonalisation)"),
+                 "core_tail": TAIL_KERNEL + f" (trailing {nt} x {nt})",
+                 "projection": "gemm_f64_kernel (Y = U^T B)"}[dom]
         roof = {
-            "kernel": (EIG_KERNEL + " (tridiagonalisation)") if dom == "core_eig" else "gemm_f64_kernel (Y = U^T B)",
-            "bound": "alu" if dom == "core_eig" else "mfma",
+            "kernel": label,
+            "bound": "mfma" if dom == "projection" else "alu",
             "achieved": round(ach, 3),
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
@@ -1035,8 +1048,17 @@ def main():
         roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": None, "traffic": None}
 
-    if roof.get("achieved") is not None:
+    if roof.get("achieved") is not None and dom in ("core_eig", "projection"):
         roof["traffic"] = measured_traffic(EIG_KERNEL if dom == "core_eig" else "gemm_f64_kernel", npairs)
+
+    # the trailing tridiagonalisation against the same FP64 vector peak
+    tail_roof = None
+    if timed["core_tail"] > 0:
+        ach = flops["core_tail"] / (timed["core_tail"] * 1e-3) / 1e12
+        tail_roof = {"kernel": TAIL_KERNEL + f" (trailing {nt} x {nt})", "bound": "alu", "achieved": round(ach, 3),
+                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4),
+                     "launches": int(stages["core_tail"][1]),
+                     "avg_launch_ms": round(timed["core_tail"] / max(stages["core_tail"][1], 1), 3)}
 
     # the projection GEMMs against the matrix-core peak of their own operand type
     proj_roof = None
@@ -1100,6 +1122,7 @@ def main():
         "library": library,
         "stages_ms_per_step": {n: round(stages[n][0] / args.steps, 3) for n in stages},
         "roofline": roof,
+        "tail_roofline": tail_roof,
         "projection_roofline": proj_roof,
         "cpu_baseline": cpu,
         "parity": parity,

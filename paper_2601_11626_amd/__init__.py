@@ -93,7 +93,7 @@ EXPORTS = ("cmsvd_create", "cmsvd_destroy", "cmsvd_set_stream", "cmsvd_last_erro
 
 PROJECTIONS = {"f64": 0, "bf16": 1, "bf16x3": 2, "f32": 3}  # cmsvd_projection
 
-STAGES = ("norms_grams", "commit", "projection", "core_eig", "core_bisect")
+STAGES = ("norms_grams", "commit", "projection", "core_eig", "core_bisect", "core_tail")
 
 
 def _check(status: int):

@@ -104,6 +104,9 @@ struct Stage {
 
 }  // namespace
 
+// timed pipeline stages (cmsvd_profile)
+enum { ST_PREP = 0, ST_COMMIT = 1, ST_PROJ = 2, ST_CORE = 3, ST_BISECT = 4, ST_TAIL = 5, NSTAGE = 6 };
+
 struct cmsvd_ctx {
     hipStream_t stream = nullptr;
     int device = 0;
@@ -173,7 +176,7 @@ struct cmsvd_ctx {
     int64_t panel_cols = 0;      // cmsvd_update(_batch): widest block appended in one step (0: any)
     // stage timing
     bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> marks[5];
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> marks[NSTAGE];
     std::vector<hipEvent_t> pool;
 };
 
@@ -313,8 +316,6 @@ struct DevBuf {
         if (p) dev_free(h, p);
     }
 };
-
-enum { ST_PREP = 0, ST_COMMIT = 1, ST_PROJ = 2, ST_CORE = 3, ST_BISECT = 4, NSTAGE = 5 };
 
 hipEvent_t take_event(cmsvd_ctx* h) {
     hipEvent_t e = nullptr;
@@ -968,9 +969,13 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
         rmax = std::max(rmax, j.r);
     }
     const int nmax = rmax + kmax;
-    // chunk so that the projection buffers stay within ~8 GiB
-    const size_t per = (size_t)rmax * kmax * 8;
-    size_t chunk = std::max<size_t>(1, ((size_t)8 << 30) / std::max<size_t>(per, 1));
+    // Register-resident cores above the tail order hand their trailing matrix over to the
+    // four-wave kernel (two problems per CU) after n - tail column steps.
+    const int tail = sym_eig_tail_order();
+    const bool hand = sym_eig_split(nmax) && !(kmax == 1 && rmax <= 256);
+    // chunk so that the projection buffers and trailing matrices stay within ~16 GiB
+    const size_t per = (size_t)rmax * kmax * 8 + (hand ? (size_t)tail * tail * 8 : 0);
+    size_t chunk = std::max<size_t>(1, ((size_t)16 << 30) / std::max<size_t>(per, 1));
     chunk = std::min(chunk, total);
     const int nslots = (int)std::min<size_t>(chunk, (size_t)h->ncu);
     for (size_t b0 = 0; b0 < total; b0 += chunk) {
@@ -981,6 +986,10 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
         const size_t eig_off = pl.add(sym_eig_workspace_doubles(nmax, nslots) * 8);
         const size_t tri = sym_eig_tri_doubles(nmax);
         const size_t tri_off = pl.add(nj * tri * 8);  // tridiagonals of the split evaluation
+        size_t nhand = 0;
+        if (hand)
+            for (size_t i = 0; i < nj; ++i) nhand += jobs[b0 + i].r + jobs[b0 + i].B.cols > tail ? 1 : 0;
+        const size_t at_off = pl.add(nhand * (size_t)tail * tail * 8);  // trailing matrices
         cmsvd_status st = ensure(h, h->ws, h->ws_cap, pl.off);
         if (st != CMSVD_OK) return st;
         char* W = h->ws;
@@ -989,6 +998,7 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
         g32.bf32 = true;
         g32.prec = g64.prec = proj_prec(h);
         std::vector<EigDesc> ed(nj);
+        size_t ihand = 0;
         for (size_t i = 0; i < nj; ++i) {
             const EvalJob& j = jobs[b0 + i];
             const int k = (int)j.B.cols;
@@ -1010,6 +1020,11 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
             e.out_rel = j.rel;
             e.d = reinterpret_cast<double*>(W + tri_off) + i * tri;
             e.e = e.d + tri / 2;
+            if (hand && e.n > tail) {
+                e.jsplit = e.n - tail;
+                e.At = reinterpret_cast<double*>(W + at_off) + (size_t)ihand++ * tail * tail;
+                e.ldt = tail;
+            }
             ed[i] = e;
         }
         // The eigen kernels take problems in a grid-stride order, so problems next to each
@@ -1033,10 +1048,24 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
                 ed.swap(grouped);
             }
         }
+        // the trailing problems, in the (grouped) order of their full problems
+        std::vector<EigDesc> et;
+        for (const EigDesc& e : ed)
+            if (e.jsplit > 0) {
+                EigDesc t2{};
+                t2.n = e.n - e.jsplit;
+                t2.nkeep = e.nkeep;
+                t2.Y = e.At;
+                t2.ldy = e.ldt;
+                t2.d = e.d + e.jsplit;
+                t2.e = e.e + e.jsplit;
+                et.push_back(t2);
+            }
         Stage stg;
         g32.off = stg.add(g32.d);
         g64.off = stg.add(g64.d);
         const size_t o_ed = stg.add(ed);
+        const size_t o_et = stg.add(et);
         char* db = nullptr;
         st = upload(h, stg, &db);
         if (st != CMSVD_OK) return st;
@@ -1052,6 +1081,10 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
             else
                 sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), (int)nj, nmax, 2,
                                 reinterpret_cast<double*>(W + eig_off), nslots, h->stream, eig_threads(h, nmax));
+        }
+        if (!et.empty()) {
+            StageMark mark(h, ST_TAIL);
+            sym_eig_tail_batched(reinterpret_cast<const EigDesc*>(db + o_et), (int)et.size(), h->stream);
         }
         if (!(kmax == 1 && rmax <= 256) && sym_eig_split(nmax)) {
             StageMark mark(h, ST_BISECT);

@@ -736,8 +736,10 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
         // trailing tiles applying the update of step j-1 and forming A v_j, while the
         // owners of column j+1 publish it; (W) w_j, column j+1 with the update of
         // step j, the norm partials for step j+1, and v_j kept as the previous
-        // vector.  Three barriers per step.
-        for (int j = 0; j + 1 < n; ++j) {
+        // vector.  Three barriers per step.  In mode 2 with D.jsplit > 0 the loop
+        // stops after jsplit steps and hands the trailing matrix over.
+        const int jend = (MODE == 2 && D.jsplit > 0) ? D.jsplit : n - 1;
+        for (int j = 0; j < jend; ++j) {
             const int Cj = j >> 5;
             // (H) redundantly in every wave
             double xn2 = 0.0;
@@ -890,9 +892,71 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
         if (MODE == 2) {
             // evaluation split in two launches: the tridiagonal goes to the problem's
             // slot (D.d, D.e) and tri_bisect_kernel finishes the evaluation
-            for (int i = t; i < n; i += RT) {
-                D.d[i] = dd[i];
-                if (i < n - 1) D.e[i] = ee[i];
+            if (D.jsplit > 0) {
+                // Hand-over after jend steps: d, e up to jend - 1, and the trailing
+                // matrix M = A[jend:, jend:] with the update of step jend - 1 applied
+                // (still pending in the tiles; v and w of that step are in vp, wp).
+                // Its first column is column jend as (W) left it in dd and xv.
+                const int nt = n - jend, Cj = jend >> 5;
+                const long ldt = D.ldt;
+                double* M = D.At;
+                for (int i = t; i < jend; i += RT) {
+                    D.d[i] = dd[i];
+                    D.e[i] = ee[i];
+                }
+                for (int a = t; a < nt; a += RT) {
+                    const double x = a == 0 ? dd[jend] : xv[jend + a];
+                    M[a] = x;
+                    M[(long)a * ldt] = x;
+                }
+                // every other element from the lower triangle of the active tiles,
+                // written to both triangles of M
+                auto put = [&](int gi, int gc, double a) {
+                    if (gc > jend && gi >= gc && gi < n) {
+                        double x = fma(-vp[gi], wp[gc], a);
+                        x = fma(-wp[gi], vp[gc], x);
+                        M[(long)(gi - jend) + (long)(gc - jend) * ldt] = x;
+                        M[(long)(gc - jend) + (long)(gi - jend) * ldt] = x;
+                    }
+                };
+#pragma unroll
+                for (int sl = 0; sl < NSLOT; ++sl) {
+                    const int code = __builtin_amdgcn_readfirstlane(geo[w * NSLOT + sl]);
+                    if (code >= 0 && (code & 255) >= Cj) {
+                        const int R = code >> 8, C = code & 255;
+#pragma unroll
+                        for (int s = 0; s < 4; ++s)
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                put(R * TILE + 4 * ly + s, C * TILE + 4 * lx + q, rt[sl][s * 4 + q]);
+                    }
+                }
+                {
+                    const int al = __builtin_amdgcn_readfirstlane(geo[RW * NSLOT + Cj * RW + w]);
+                    const int cl = Cj > c0 ? Cj : c0;
+                    int f = al >> 8, k = al & 255;
+                    int R = cl, C = cl;
+                    while (f > R - cl) {
+                        f -= R - cl + 1;
+                        ++R;
+                    }
+                    C = cl + f;
+                    for (; k > 0; --k) {
+                        const double* tp = lt + (size_t)lds_tile_index(R, C, c0, TL) * TILE_EL;
+                        for (int s = 0; s < 4; ++s)
+                            for (int q = 0; q < 4; ++q)
+                                put(R * TILE + 4 * ly + s, C * TILE + 4 * lx + q, tp[((4 * s + q) << 6) + lane]);
+                        if (++C > R) {
+                            ++R;
+                            C = cl;
+                        }
+                    }
+                }
+            } else {
+                for (int i = t; i < n; i += RT) {
+                    D.d[i] = dd[i];
+                    if (i < n - 1) D.e[i] = ee[i];
+                }
             }
             __syncthreads();
             continue;
@@ -1653,6 +1717,16 @@ int sym_eig_nmax() {
 bool sym_eig_split(int nmax) {
     const int T = (nmax + TILE - 1) / TILE;
     return nmax > SN && T > THIN_TMAX && T <= REG_TMAX;
+}
+
+int sym_eig_tail_order() { return THIN_TMAX * TILE; }
+
+void sym_eig_tail_batched(const EigDesc* d_descs, int count, hipStream_t s) {
+    if (count <= 0) return;
+    const size_t lds = (size_t)THIN_LDS_DOUBLES * 8;
+    const int grid = count < 2048 ? count : 2048;
+    hipLaunchKernelGGL((sym_eig_reg_kernel<2, 256, THIN_NSLOT, 0, THIN_TMAX, true>), dim3(grid), dim3(256), lds, s,
+                       d_descs, count);
 }
 
 void tri_bisect_batched(const EigDesc* d_descs, int count, int nmax, hipStream_t s) {

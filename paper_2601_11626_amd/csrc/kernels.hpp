@@ -56,6 +56,13 @@ struct EigDesc {
     long ldv;
     double* tau;      // n
     double* sum_top;  // 2 doubles: (hi, lo) of the sum of the kept eigenvalues
+    // mode 2, register-resident orders above 160: jsplit > 0 stops the tridiagonalisation
+    // after jsplit column steps; d and e then hold entries 0 .. jsplit - 1 and the
+    // trailing matrix (order n - jsplit, with every earlier step applied) is written to
+    // At (column-major, ld ldt, both triangles) for sym_eig_tail_batched
+    double* At;
+    long ldt;
+    int jsplit;
 };
 
 // Tridiagonalisation + bisection.  mode 0: evaluation (writes out_err/out_rel);
@@ -72,6 +79,12 @@ size_t sym_eig_workspace_doubles(int nmax, int nslots);
 // Scratch doubles per problem for the tridiagonal of mode 2 (d at 0, e at half of it).
 size_t sym_eig_tri_doubles(int nmax);
 bool sym_eig_split(int nmax);
+// Order of the trailing matrix that a mode-2 tridiagonalisation of order n above it
+// hands over (jsplit = n - sym_eig_tail_order()), and the tridiagonalisation of those
+// trailing matrices: descriptors with n1 = 0, Y = At (ld ldt), d and e pointing at
+// entry jsplit of the full problem's; four waves per problem, two problems per CU.
+int sym_eig_tail_order();
+void sym_eig_tail_batched(const EigDesc* d_descs, int count, hipStream_t s);
 void tri_bisect_batched(const EigDesc* d_descs, int count, int nmax, hipStream_t s);
 // Doubles of global scratch one workgroup slot of sym_eig_batched needs for order nmax
 // (0 when the kernel chosen for that order keeps every tile on chip).

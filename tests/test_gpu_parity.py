@@ -226,6 +226,28 @@ def test_merge_errors_rotated_groups_full_shape(cm):
         assert_est(err[p], err_o[p], nm, f"pair {p}")
 
 
+def test_merge_errors_across_the_tail_handover(cm):
+    """Cores of order 161..320 are tridiagonalised for n - 160 steps by the eight-wave
+    kernel and finished on the trailing 160 x 160 matrix by the four-wave kernel; one
+    call mixes orders on both sides of the hand-over (160, 161, 162, 192, 193, 224, 288,
+    319, 320: ragged tiles and a trailing matrix starting inside a tile)."""
+    rng = np.random.default_rng(77)
+    m, r = 400, 40
+    Q = workloads.orthonormal(rng, m, 30)
+    widths = [120, 121, 122, 152, 153, 184, 248, 279, 280]
+    anchors = [Q @ rng.standard_normal((30, 90)) + 0.05 * rng.standard_normal((m, 90)) for _ in range(2)]
+    cands = [Q[:, :20] @ rng.standard_normal((20, k)) + 0.1 * rng.standard_normal((m, k)) for k in widths]
+    blocks = anchors + cands
+    pairs = [(a, 2 + c) for a in range(2) for c in range(len(cands))]
+    say(f"merge_errors across the tail hand-over: orders {[r + k for k in widths]}")
+    err_o, _ = oracle.merge_errors(blocks, pairs, r, nthreads=8)
+    err, _ = cm.cmsvd_merge_errors(dev_tensors(blocks), pairs, r)
+    err = err.cpu().numpy()
+    for p, (i, j) in enumerate(pairs):
+        nm = math.sqrt(oracle.frob2(blocks[i]) + oracle.frob2(blocks[j]))
+        assert_est(err[p], err_o[p], nm, f"pair {(i, j)} order {r + blocks[j].shape[1]}")
+
+
 def test_shared_subspace_zero_and_nan(cm):
     say("edge: shared subspace, NaN")
     rng = np.random.default_rng(3)
