@@ -971,10 +971,10 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
     const int nmax = rmax + kmax;
     // Register-resident cores above the tail order hand their trailing matrix over to the
     // four-wave kernel (two problems per CU) after n - tail column steps.
-    const int tail = sym_eig_tail_order();
+    const int tail = sym_eig_tail_order(), tail2 = sym_eig_tail2_order();
     const bool hand = sym_eig_split(nmax) && !(kmax == 1 && rmax <= 256);
     // chunk so that the projection buffers and trailing matrices stay within ~16 GiB
-    const size_t per = (size_t)rmax * kmax * 8 + (hand ? (size_t)tail * tail * 8 : 0);
+    const size_t per = (size_t)rmax * kmax * 8 + (hand ? (size_t)(tail * tail + tail2 * tail2) * 8 : 0);
     size_t chunk = std::max<size_t>(1, ((size_t)16 << 30) / std::max<size_t>(per, 1));
     chunk = std::min(chunk, total);
     const int nslots = (int)std::min<size_t>(chunk, (size_t)h->ncu);
@@ -989,7 +989,8 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
         size_t nhand = 0;
         if (hand)
             for (size_t i = 0; i < nj; ++i) nhand += jobs[b0 + i].r + jobs[b0 + i].B.cols > tail ? 1 : 0;
-        const size_t at_off = pl.add(nhand * (size_t)tail * tail * 8);  // trailing matrices
+        const size_t at_off = pl.add(nhand * (size_t)tail * tail * 8);    // trailing matrices
+        const size_t at2_off = pl.add(nhand * (size_t)tail2 * tail2 * 8);  // and theirs
         cmsvd_status st = ensure(h, h->ws, h->ws_cap, pl.off);
         if (st != CMSVD_OK) return st;
         char* W = h->ws;
@@ -1048,8 +1049,9 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
                 ed.swap(grouped);
             }
         }
-        // the trailing problems, in the (grouped) order of their full problems
-        std::vector<EigDesc> et;
+        // the trailing problems, in the (grouped) order of their full problems, and
+        // their own trailing problems of order tail2
+        std::vector<EigDesc> et, et2;
         for (const EigDesc& e : ed)
             if (e.jsplit > 0) {
                 EigDesc t2{};
@@ -1059,13 +1061,26 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
                 t2.ldy = e.ldt;
                 t2.d = e.d + e.jsplit;
                 t2.e = e.e + e.jsplit;
+                if (t2.n > tail2) {
+                    t2.jsplit = t2.n - tail2;
+                    t2.At = reinterpret_cast<double*>(W + at2_off) + et2.size() * (size_t)tail2 * tail2;
+                    t2.ldt = tail2;
+                    EigDesc t3{};
+                    t3.n = tail2;
+                    t3.nkeep = e.nkeep;
+                    t3.Y = t2.At;
+                    t3.ldy = tail2;
+                    t3.d = t2.d + t2.jsplit;
+                    t3.e = t2.e + t2.jsplit;
+                    et2.push_back(t3);
+                }
                 et.push_back(t2);
             }
         Stage stg;
         g32.off = stg.add(g32.d);
         g64.off = stg.add(g64.d);
         const size_t o_ed = stg.add(ed);
-        const size_t o_et = stg.add(et);
+        const size_t o_et = stg.add(et), o_et2 = stg.add(et2);
         char* db = nullptr;
         st = upload(h, stg, &db);
         if (st != CMSVD_OK) return st;
@@ -1085,6 +1100,7 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
         if (!et.empty()) {
             StageMark mark(h, ST_TAIL);
             sym_eig_tail_batched(reinterpret_cast<const EigDesc*>(db + o_et), (int)et.size(), h->stream);
+            sym_eig_tail2_batched(reinterpret_cast<const EigDesc*>(db + o_et2), (int)et2.size(), h->stream);
         }
         if (!(kmax == 1 && rmax <= 256) && sym_eig_split(nmax)) {
             StageMark mark(h, ST_BISECT);

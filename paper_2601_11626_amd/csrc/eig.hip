@@ -1315,6 +1315,13 @@ __global__ void __launch_bounds__(64 * SWV) sym_eig_small_kernel(const EigDesc* 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (MODE == 2) {
+            // the trailing part of a larger problem: its tridiagonal only
+            if (lane < n) D.d[lane] = dd[lane];
+            if (lane < n - 1) D.e[lane] = es[lane];
+            __builtin_amdgcn_wave_barrier();
+            continue;
+        }
 
         // ---- multisection bisection for the nkeep largest eigenvalues ----
         double glo = INFINITY, ghi = -INFINITY, em = 0.0;
@@ -1720,6 +1727,7 @@ bool sym_eig_split(int nmax) {
 }
 
 int sym_eig_tail_order() { return THIN_TMAX * TILE; }
+int sym_eig_tail2_order() { return SN; }
 
 void sym_eig_tail_batched(const EigDesc* d_descs, int count, hipStream_t s) {
     if (count <= 0) return;
@@ -1727,6 +1735,13 @@ void sym_eig_tail_batched(const EigDesc* d_descs, int count, hipStream_t s) {
     const int grid = count < 2048 ? count : 2048;
     hipLaunchKernelGGL((sym_eig_reg_kernel<2, 256, THIN_NSLOT, 0, THIN_TMAX, true>), dim3(grid), dim3(256), lds, s,
                        d_descs, count);
+}
+
+void sym_eig_tail2_batched(const EigDesc* d_descs, int count, hipStream_t s) {
+    if (count <= 0) return;
+    int grid = (count + SWV - 1) / SWV;
+    if (grid > 16384) grid = 16384;
+    hipLaunchKernelGGL((sym_eig_small_kernel<2, SN>), dim3(grid), dim3(64 * SWV), 0, s, d_descs, count);
 }
 
 void tri_bisect_batched(const EigDesc* d_descs, int count, int nmax, hipStream_t s) {

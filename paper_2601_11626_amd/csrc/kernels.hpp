@@ -85,6 +85,11 @@ bool sym_eig_split(int nmax);
 // entry jsplit of the full problem's; four waves per problem, two problems per CU.
 int sym_eig_tail_order();
 void sym_eig_tail_batched(const EigDesc* d_descs, int count, hipStream_t s);
+// The same hand-over one level down: the four-wave kernel, given jsplit = n -
+// sym_eig_tail2_order(), leaves a trailing matrix of that order (64) to the one-wave
+// kernel (one problem per wavefront, up to 16 per CU), which writes its tridiagonal.
+int sym_eig_tail2_order();
+void sym_eig_tail2_batched(const EigDesc* d_descs, int count, hipStream_t s);
 void tri_bisect_batched(const EigDesc* d_descs, int count, int nmax, hipStream_t s);
 // Doubles of global scratch one workgroup slot of sym_eig_batched needs for order nmax
 // (0 when the kernel chosen for that order keeps every tile on chip).
