@@ -115,11 +115,12 @@ def _pmc_rows(path):
 # the headline's dominant launch: the register-resident tridiagonalisation of the split
 # evaluation (n = 320: 10 tile rows of 32), whose bisection runs in tri_bisect_kernel
 EIG_KERNEL = "sym_eig_reg_kernel<2, 512, 5, 5, 10, true>"
-# the kernels that finish cores of order 161..320 on their trailing matrices: four
-# waves from order 160 down to 64, then one wave per problem
-TAIL_KERNEL = "sym_eig_reg_kernel<2, 256, 4, 0, 5, true>"
-TAIL2_KERNEL = "sym_eig_small_kernel<2, 64>"
-TAIL_ORDER = 160
+# the kernels that finish cores of order 193..320 on their trailing matrices: four waves
+# from order 192 down to 160 (register and LDS tiles) and down to 64 (register tiles),
+# then one wave per problem
+TAIL_KERNELS = ("sym_eig_reg_kernel<2, 256, 4, 3, 6, true> (192 -> 160)",
+                "sym_eig_reg_kernel<2, 256, 4, 0, 5, true> (160 -> 64)", "sym_eig_small_kernel<2, 64> (64)")
+TAIL_ORDER = 192
 
 
 def pmc_summary(fetch_csv, write_csv, copy_mib, kernel=EIG_KERNEL):
@@ -1015,10 +1016,10 @@ def main():
                    "max_rel_diff_vs_batched": lib_dev}
         log(f"library: {lib_rate:.1f} merges/s over {len(sample)} pairs")
 
-    # dominant stage and its roofline position.  Cores of order 161..320 are
-    # tridiagonalised for n - 160 column steps by EIG_KERNEL; the trailing 160 x 160
-    # matrix goes to TAIL_KERNEL (stage core_tail).  Each is priced at the (4/3) n^3 of
-    # the part of the reduction it does.
+    # dominant stage and its roofline position.  Cores of order 193..320 are
+    # tridiagonalised for n - 192 column steps by EIG_KERNEL; the trailing 192 x 192
+    # matrix goes to the TAIL_KERNELS (stage core_tail).  Each stage is priced at the
+    # (4/3) n^3 of the part of the reduction it does.
     n_core = r + k
     nt = TAIL_ORDER if TAIL_ORDER < n_core <= 320 else 0
     flops = {
@@ -1033,7 +1034,7 @@ def main():
         ach = flops[dom] / (timed[dom] * 1e-3) / 1e12
         label = {"core_eig": EIG_KERNEL + (f" (tridiagonalisation, first n - {nt} steps)" if nt else
                                            " (tridiagonalisation)"),
-                 "core_tail": f"{TAIL_KERNEL} + {TAIL2_KERNEL} (trailing {nt} x {nt})",
+                 "core_tail": f"trailing {nt} x {nt}: " + " + ".join(TAIL_KERNELS),
                  "projection": "gemm_f64_kernel (Y = U^T B)"}[dom]
         roof = {
             "kernel": label,
@@ -1057,7 +1058,7 @@ def main():
     tail_roof = None
     if timed["core_tail"] > 0:
         ach = flops["core_tail"] / (timed["core_tail"] * 1e-3) / 1e12
-        tail_roof = {"kernel": f"{TAIL_KERNEL} (trailing {nt} x {nt} down to 64) + {TAIL2_KERNEL} (trailing 64 x 64)",
+        tail_roof = {"kernel": f"trailing {nt} x {nt}: " + " + ".join(TAIL_KERNELS),
                      "bound": "alu", "achieved": round(ach, 3),
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4),
                      "launches": int(stages["core_tail"][1]),

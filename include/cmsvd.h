@@ -452,11 +452,12 @@ cmsvd_status cmsvd_graph_stats(cmsvd_handle handle, int64_t* captures, int64_t* 
    initialisation and state updates), 2 = projection GEMM Y = U^T B of candidate
    evaluation, 3 = core eigenvalue kernel of candidate evaluation (tridiagonalisation,
    and for all but cores of order 161..320 also bisection and the plug-in error; one
-   launch per evaluation chunk; cores of order 161..320 stop here after n - 160 column
+   launch per evaluation chunk; cores of order 193..320 stop here after n - 192 column
    steps), 4 = the bisection kernel that finishes the evaluation of cores of order
    161..320 (eigenvalues of their tridiagonals, plug-in error), 5 = the
-   tridiagonalisation of the trailing 160 x 160 matrices that cores of order 161..320
-   hand over (four wavefronts per problem, two problems per compute unit).
+   tridiagonalisation of the trailing 192 x 192 matrices that cores of order 193..320
+   hand over (three launches: four wavefronts per problem down to order 160 and to 64,
+   then one wavefront per problem; two or more problems per compute unit).
    cmsvd_profile_read synchronises the handle's stream, writes for each of the 6
    stages the summed milliseconds and the number of bracketed launches, and resets
    the counters.  ms and count are HOST arrays of 6 entries. */

@@ -971,10 +971,13 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
     const int nmax = rmax + kmax;
     // Register-resident cores above the tail order hand their trailing matrix over to the
     // four-wave kernel (two problems per CU) after n - tail column steps.
-    const int tail = sym_eig_tail_order(), tail2 = sym_eig_tail2_order();
+    int lvo[8];
+    const int nlv = sym_eig_tail_levels(lvo);
+    const int tail = lvo[0];
     const bool hand = sym_eig_split(nmax) && !(kmax == 1 && rmax <= 256);
-    // chunk so that the projection buffers and trailing matrices stay within ~16 GiB
-    const size_t per = (size_t)rmax * kmax * 8 + (hand ? (size_t)(tail * tail + tail2 * tail2) * 8 : 0);
+    // chunk so that the projection buffers and trailing matrices stay within ~16 GiB (each
+    // level overwrites the trailing matrix it read with the one it hands over)
+    const size_t per = (size_t)rmax * kmax * 8 + (hand ? (size_t)tail * tail * 8 : 0);
     size_t chunk = std::max<size_t>(1, ((size_t)16 << 30) / std::max<size_t>(per, 1));
     chunk = std::min(chunk, total);
     const int nslots = (int)std::min<size_t>(chunk, (size_t)h->ncu);
@@ -989,8 +992,7 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
         size_t nhand = 0;
         if (hand)
             for (size_t i = 0; i < nj; ++i) nhand += jobs[b0 + i].r + jobs[b0 + i].B.cols > tail ? 1 : 0;
-        const size_t at_off = pl.add(nhand * (size_t)tail * tail * 8);    // trailing matrices
-        const size_t at2_off = pl.add(nhand * (size_t)tail2 * tail2 * 8);  // and theirs
+        const size_t at_off = pl.add(nhand * (size_t)tail * tail * 8);  // trailing matrices
         cmsvd_status st = ensure(h, h->ws, h->ws_cap, pl.off);
         if (st != CMSVD_OK) return st;
         char* W = h->ws;
@@ -1049,38 +1051,37 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
                 ed.swap(grouped);
             }
         }
-        // the trailing problems, in the (grouped) order of their full problems, and
-        // their own trailing problems of order tail2
-        std::vector<EigDesc> et, et2;
-        for (const EigDesc& e : ed)
-            if (e.jsplit > 0) {
+        // the trailing problems of every hand-over level, in the (grouped) order of their
+        // full problems; a level reads its matrix into tiles before it writes the next
+        // level's into the same slot
+        std::vector<std::vector<EigDesc>> lv((size_t)nlv);
+        for (const EigDesc& e : ed) {
+            if (e.jsplit <= 0) continue;
+            EigDesc cur = e;
+            for (int l = 0; l < nlv; ++l) {
                 EigDesc t2{};
-                t2.n = e.n - e.jsplit;
+                t2.n = cur.n - cur.jsplit;
                 t2.nkeep = e.nkeep;
-                t2.Y = e.At;
-                t2.ldy = e.ldt;
-                t2.d = e.d + e.jsplit;
-                t2.e = e.e + e.jsplit;
-                if (t2.n > tail2) {
-                    t2.jsplit = t2.n - tail2;
-                    t2.At = reinterpret_cast<double*>(W + at2_off) + et2.size() * (size_t)tail2 * tail2;
-                    t2.ldt = tail2;
-                    EigDesc t3{};
-                    t3.n = tail2;
-                    t3.nkeep = e.nkeep;
-                    t3.Y = t2.At;
-                    t3.ldy = tail2;
-                    t3.d = t2.d + t2.jsplit;
-                    t3.e = t2.e + t2.jsplit;
-                    et2.push_back(t3);
+                t2.Y = cur.At;
+                t2.ldy = cur.ldt;
+                t2.d = cur.d + cur.jsplit;
+                t2.e = cur.e + cur.jsplit;
+                if (l + 1 < nlv && t2.n > lvo[l + 1]) {
+                    t2.jsplit = t2.n - lvo[l + 1];
+                    t2.At = cur.At;
+                    t2.ldt = lvo[l + 1];
                 }
-                et.push_back(t2);
+                lv[(size_t)l].push_back(t2);
+                if (t2.jsplit <= 0) break;
+                cur = t2;
             }
+        }
         Stage stg;
         g32.off = stg.add(g32.d);
         g64.off = stg.add(g64.d);
         const size_t o_ed = stg.add(ed);
-        const size_t o_et = stg.add(et), o_et2 = stg.add(et2);
+        std::vector<size_t> o_lv((size_t)nlv);
+        for (int l = 0; l < nlv; ++l) o_lv[(size_t)l] = stg.add(lv[(size_t)l]);
         char* db = nullptr;
         st = upload(h, stg, &db);
         if (st != CMSVD_OK) return st;
@@ -1097,10 +1098,11 @@ cmsvd_status eval_batched(cmsvd_ctx* h, const std::vector<EvalJob>& jobs, int m)
                 sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), (int)nj, nmax, 2,
                                 reinterpret_cast<double*>(W + eig_off), nslots, h->stream, eig_threads(h, nmax));
         }
-        if (!et.empty()) {
+        if (!lv[0].empty()) {
             StageMark mark(h, ST_TAIL);
-            sym_eig_tail_batched(reinterpret_cast<const EigDesc*>(db + o_et), (int)et.size(), h->stream);
-            sym_eig_tail2_batched(reinterpret_cast<const EigDesc*>(db + o_et2), (int)et2.size(), h->stream);
+            for (int l = 0; l < nlv; ++l)
+                sym_eig_tail_batched(reinterpret_cast<const EigDesc*>(db + o_lv[(size_t)l]), (int)lv[(size_t)l].size(), l,
+                                     h->stream);
         }
         if (!(kmax == 1 && rmax <= 256) && sym_eig_split(nmax)) {
             StageMark mark(h, ST_BISECT);

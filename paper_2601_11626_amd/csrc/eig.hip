@@ -1726,22 +1726,40 @@ bool sym_eig_split(int nmax) {
     return nmax > SN && T > THIN_TMAX && T <= REG_TMAX;
 }
 
-int sym_eig_tail_order() { return THIN_TMAX * TILE; }
-int sym_eig_tail2_order() { return SN; }
+// Trailing matrices of order up to 192: four waves, 15 register tiles (4 slots per wave)
+// and the last three tile columns (6 tiles) in LDS; 66 KB of LDS, so two problems share
+// a CU.
+constexpr int MID_TMAX = 6;
+constexpr int MID_RTL = 3;
+constexpr int MID_LDS_DOUBLES = 7 * MID_TMAX * TILE + 4 * MID_TMAX * TILE + 16 + MID_RTL * (MID_RTL + 1) / 2 * TILE_EL +
+                                (4 * THIN_NSLOT + 4 * MID_TMAX + 1) / 2;
+static_assert(2 * MID_LDS_DOUBLES * 8 <= LDS_BYTES, "two trailing problems must share a CU");
 
-void sym_eig_tail_batched(const EigDesc* d_descs, int count, hipStream_t s) {
-    if (count <= 0) return;
-    const size_t lds = (size_t)THIN_LDS_DOUBLES * 8;
-    const int grid = count < 2048 ? count : 2048;
-    hipLaunchKernelGGL((sym_eig_reg_kernel<2, 256, THIN_NSLOT, 0, THIN_TMAX, true>), dim3(grid), dim3(256), lds, s,
-                       d_descs, count);
+int sym_eig_tail_levels(int* orders) {
+    orders[0] = MID_TMAX * TILE;   // 192: four waves, register and LDS tiles
+    orders[1] = THIN_TMAX * TILE;  // 160: four waves, register tiles only
+    orders[2] = SN;                // 64: one wave per problem
+    return 3;
 }
 
-void sym_eig_tail2_batched(const EigDesc* d_descs, int count, hipStream_t s) {
+void sym_eig_tail_batched(const EigDesc* d_descs, int count, int level, hipStream_t s) {
     if (count <= 0) return;
-    int grid = (count + SWV - 1) / SWV;
-    if (grid > 16384) grid = 16384;
-    hipLaunchKernelGGL((sym_eig_small_kernel<2, SN>), dim3(grid), dim3(64 * SWV), 0, s, d_descs, count);
+    if (level == 0) {
+        const size_t lds = (size_t)MID_LDS_DOUBLES * 8;
+        lds_limit((const void*)sym_eig_reg_kernel<2, 256, THIN_NSLOT, MID_RTL, MID_TMAX, true>, (int)lds);
+        const int grid = count < 2048 ? count : 2048;
+        hipLaunchKernelGGL((sym_eig_reg_kernel<2, 256, THIN_NSLOT, MID_RTL, MID_TMAX, true>), dim3(grid), dim3(256), lds,
+                           s, d_descs, count);
+    } else if (level == 1) {
+        const size_t lds = (size_t)THIN_LDS_DOUBLES * 8;
+        const int grid = count < 2048 ? count : 2048;
+        hipLaunchKernelGGL((sym_eig_reg_kernel<2, 256, THIN_NSLOT, 0, THIN_TMAX, true>), dim3(grid), dim3(256), lds, s,
+                           d_descs, count);
+    } else {
+        int grid = (count + SWV - 1) / SWV;
+        if (grid > 16384) grid = 16384;
+        hipLaunchKernelGGL((sym_eig_small_kernel<2, SN>), dim3(grid), dim3(64 * SWV), 0, s, d_descs, count);
+    }
 }
 
 void tri_bisect_batched(const EigDesc* d_descs, int count, int nmax, hipStream_t s) {

@@ -79,17 +79,15 @@ size_t sym_eig_workspace_doubles(int nmax, int nslots);
 // Scratch doubles per problem for the tridiagonal of mode 2 (d at 0, e at half of it).
 size_t sym_eig_tri_doubles(int nmax);
 bool sym_eig_split(int nmax);
-// Order of the trailing matrix that a mode-2 tridiagonalisation of order n above it
-// hands over (jsplit = n - sym_eig_tail_order()), and the tridiagonalisation of those
-// trailing matrices: descriptors with n1 = 0, Y = At (ld ldt), d and e pointing at
-// entry jsplit of the full problem's; four waves per problem, two problems per CU.
-int sym_eig_tail_order();
-void sym_eig_tail_batched(const EigDesc* d_descs, int count, hipStream_t s);
-// The same hand-over one level down: the four-wave kernel, given jsplit = n -
-// sym_eig_tail2_order(), leaves a trailing matrix of that order (64) to the one-wave
-// kernel (one problem per wavefront, up to 16 per CU), which writes its tridiagonal.
-int sym_eig_tail2_order();
-void sym_eig_tail2_batched(const EigDesc* d_descs, int count, hipStream_t s);
+// Hand-over levels of the evaluation's tridiagonalisation.  A mode-2 problem of order n
+// above orders[0] stops after n - orders[0] steps (jsplit) and writes its trailing matrix;
+// level l tridiagonalises trailing matrices of order orders[l] (descriptors with n1 = 0,
+// Y = At, d and e pointing at the entries of the full problem that follow) and, except
+// the last level, hands its own trailing matrix of order orders[l + 1] over the same way.
+// Levels: order 192 (four waves, register and LDS tiles), 160 (four waves, register
+// tiles), 64 (one wave per problem); two or more problems share a CU at every level.
+int sym_eig_tail_levels(int* orders);
+void sym_eig_tail_batched(const EigDesc* d_descs, int count, int level, hipStream_t s);
 void tri_bisect_batched(const EigDesc* d_descs, int count, int nmax, hipStream_t s);
 // Doubles of global scratch one workgroup slot of sym_eig_batched needs for order nmax
 // (0 when the kernel chosen for that order keeps every tile on chip).

@@ -227,10 +227,11 @@ def test_merge_errors_rotated_groups_full_shape(cm):
 
 
 def test_merge_errors_across_the_tail_handover(cm):
-    """Cores of order 161..320 are tridiagonalised for n - 160 steps by the eight-wave
-    kernel and finished on the trailing 160 x 160 matrix by the four-wave kernel; one
-    call mixes orders on both sides of the hand-over (160, 161, 162, 192, 193, 224, 288,
-    319, 320: ragged tiles and a trailing matrix starting inside a tile)."""
+    """Cores of order 193..320 are tridiagonalised for n - 192 steps by the eight-wave
+    kernel and finished on the trailing 192 x 192 matrix by the four-wave kernels (down
+    to order 160, then to 64) and the one-wave kernel; one call mixes orders on both
+    sides of the hand-overs (160, 161, 162, 192, 193, 224, 288, 319, 320: no hand-over,
+    a single step before it, ragged tiles and trailing matrices starting inside a tile)."""
     rng = np.random.default_rng(77)
     m, r = 400, 40
     Q = workloads.orthonormal(rng, m, 30)
