@@ -711,6 +711,8 @@ struct CommitJob {
     const double* G_in = nullptr;
 };
 
+int eig_threads(const cmsvd_ctx* h, int64_t n);
+
 cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
     const int J = (int)jobs.size();
     if (J == 0) return CMSVD_OK;
@@ -919,7 +921,9 @@ cmsvd_status commit_batched(cmsvd_ctx* h, const std::vector<CommitJob>& jobs) {
     run_gemm(h, gF, db);
     assemble_kt_batched(reinterpret_cast<const KtDesc*>(db + o_kd), J, nmax, s);
     run_gemm(h, gS, db);
-    sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), J, nmax, 1, D(eig_off), nslots, s);
+    // the workgroup size the autotuner measured for this order bucket (evaluations of
+    // the same orders), else the default
+    sym_eig_batched(reinterpret_cast<const EigDesc*>(db + o_ed), J, nmax, 1, D(eig_off), nslots, s, eig_threads(h, nmax));
     bp.run(h, db);
     run_gemm(h, gU1, db);
     run_gemm(h, gU2a, db);
