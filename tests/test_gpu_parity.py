@@ -249,6 +249,31 @@ def test_merge_errors_across_the_tail_handover(cm):
         assert_est(err[p], err_o[p], nm, f"pair {(i, j)} order {r + blocks[j].shape[1]}")
 
 
+def test_degenerate_candidates_across_the_hand_over(cm):
+    """Order-320 cores (r = 64, k = 256) whose tridiagonalisation meets zero reflectors
+    before and after the hand-over: an all-zero candidate, a candidate inside the
+    anchor's span, a rank-10 candidate, and one holding a NaN."""
+    rng = np.random.default_rng(91)
+    m, r, k = 400, 64, 256
+    anchor = rng.standard_normal((m, 96)) * np.linspace(2.0, 0.05, 96)
+    U = np.linalg.svd(anchor, full_matrices=False)[0][:, :r]
+    cands = [np.zeros((m, k)), U @ rng.standard_normal((r, k)),
+             rng.standard_normal((m, 10)) @ rng.standard_normal((10, k))]
+    blocks = [anchor] + cands
+    pairs = [(0, 1), (0, 2), (0, 3)]
+    say("merge_errors degenerate candidates at order 320")
+    err_o, _ = oracle.merge_errors(blocks, pairs, r, nthreads=8)
+    err, _ = cm.cmsvd_merge_errors(dev_tensors(blocks), pairs, r)
+    err = err.cpu().numpy()
+    for p_, (i, j) in enumerate(pairs):
+        nm = math.sqrt(oracle.frob2(blocks[i]) + oracle.frob2(blocks[j]))
+        assert_est(err[p_], err_o[p_], nm, f"pair {(i, j)}")
+    bad = rng.standard_normal((m, k))
+    bad[17, 200] = np.nan
+    err2, _ = cm.cmsvd_merge_errors(dev_tensors([anchor, bad]), [(0, 1)], r)
+    assert np.isnan(err2.cpu().numpy()[0])
+
+
 def test_shared_subspace_zero_and_nan(cm):
     say("edge: shared subspace, NaN")
     rng = np.random.default_rng(3)
