@@ -529,13 +529,20 @@ __device__ __forceinline__ void tile_step(double (&a)[16], int R, int C, const d
     }
 }
 
+// Vector index -> LDS position.  In the shared-vector kernels (SW) two doubles of
+// padding follow every sixteen: the eight 4-element groups that the lanes of one tile
+// read (32 bytes apart) then fall on distinct LDS banks instead of pairing up.
+template <bool SW>
+__device__ __forceinline__ int vpos(int i) { return SW ? i + 2 * (i >> 4) : i; }
+
 // The same tile update for row-owned passes: the row partials are accumulated into
 // racc (per lane, rows 4ly..4ly+3 of the tile row) instead of being reduced per tile;
 // flush_rows reduces and publishes them once per tile row.
+template <bool SW>
 __device__ __forceinline__ void tile_step_racc(double (&a)[16], int R, int C, const double* __restrict__ vc,
                                                const double* __restrict__ vp, const double* __restrict__ wp,
                                                double* pww, int ly, int lx, double (&racc)[4]) {
-    const int gi0 = R * TILE + 4 * ly, gc0 = C * TILE + 4 * lx;
+    const int gi0 = vpos<SW>(R * TILE + 4 * ly), gc0 = vpos<SW>(C * TILE + 4 * lx);
     double vq[4], wq[4], cq[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -568,10 +575,11 @@ __device__ __forceinline__ void tile_step_racc(double (&a)[16], int R, int C, co
 // The same step on a tile held in LDS (plane order: element s*4 + q of lane at
 // tp[(s*4 + q) * 64 + lane]), one of its four rows at a time, so that only four of its
 // elements occupy registers beside the resident tiles (more would spill those).
+template <bool SW>
 __device__ __forceinline__ void tile_step_lds(double* tp, int lane, int R, int C, const double* __restrict__ vc,
                                               const double* __restrict__ vp, const double* __restrict__ wp,
                                               double* pww, int ly, int lx, double (&racc)[4]) {
-    const int gi0 = R * TILE + 4 * ly, gc0 = C * TILE + 4 * lx;
+    const int gi0 = vpos<SW>(R * TILE + 4 * ly), gc0 = vpos<SW>(C * TILE + 4 * lx);
     double vq[4], wq[4], cq[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -606,11 +614,12 @@ __device__ __forceinline__ void tile_step_lds(double* tp, int lane, int R, int C
     }
 }
 
+template <bool SW>
 __device__ __forceinline__ void flush_rows(int R, double (&racc)[4], double* pww, int ly, int lx) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const double v = sum_lanes8(racc[s]);
-        if (lx == s) unsafeAtomicAdd(&pww[R * TILE + 4 * ly + s], v);
+        if (lx == s) unsafeAtomicAdd(&pww[vpos<SW>(R * TILE + 4 * ly) + s], v);
         racc[s] = 0.0;
     }
 }
@@ -620,33 +629,45 @@ __device__ __forceinline__ int lds_tile_index(int R, int C, int c0, int TL) {
     return cc * TL - (cc * (cc - 1)) / 2 + (rr - cc);
 }
 
-constexpr int REG_NP = REG_TMAX * TILE;                                  // vector stride (fixed layout)
-constexpr int REG_PWL = RW * REG_NP;                                     // per-wave partials
-// geo: RW*NSLOT slot codes, then per tile column c the LDS-tile share of every wave
-// ((first << 8) | count, RW * REG_TMAX ints)
-constexpr int REG_GEO_INTS = RW * NSLOT + RW * REG_TMAX;
-constexpr int REG_LDS_DOUBLES = 7 * REG_NP + REG_PWL + 16 + RTL * (RTL + 1) / 2 * TILE_EL + REG_GEO_INTS / 2;
+constexpr int REG_NP = REG_TMAX * TILE;  // vector length (fixed layout)
+
+// LDS of the register kernels, in doubles, in the kernel's order: xv (np); vc, vp, wp, xn
+// (np, padded by vpos in the shared-vector kernels); the partials of A v (one padded
+// vector with SHV, else one vector per wave); dd, ee (np); 16 for the reductions; the
+// LDS tiles (the last rtl tile columns); the geometry ints: rw*nslot slot codes, then per
+// tile column c the LDS-tile share of every wave ((first << 8) | count, rw*tmax).
+__host__ __device__ constexpr int reg_npp(int tmax, bool shv) { return shv ? tmax * TILE + tmax * TILE / 8 : tmax * TILE; }
+__host__ __device__ constexpr int reg_lds_doubles(int rw, int nslot, int rtl, int tmax, bool shv) {
+    return 3 * tmax * TILE + 4 * reg_npp(tmax, shv) + (shv ? reg_npp(tmax, shv) : rw * tmax * TILE) + 16 +
+           rtl * (rtl + 1) / 2 * TILE_EL + (rw * nslot + rw * tmax + 1) / 2;
+}
+constexpr int REG_LDS_DOUBLES = reg_lds_doubles(RW, NSLOT, RTL, REG_TMAX, false);
+constexpr int REG_LDS_DOUBLES_SHV = reg_lds_doubles(RW, NSLOT, RTL, REG_TMAX, true);
 static_assert(REG_LDS_DOUBLES * 8 <= LDS_BYTES, "register-resident eigen kernel exceeds the LDS");
+static_assert(REG_LDS_DOUBLES_SHV <= REG_LDS_DOUBLES, "the shared-vector layout is the smaller one");
 // Thin cores (65..160): 256 threads, 4 slots per wave (16 >= 15 tiles), no LDS tiles.
 constexpr int THIN_TMAX = 5;
 constexpr int THIN_NSLOT = 4;
-constexpr int THIN_LDS_DOUBLES = 7 * THIN_TMAX * TILE + 4 * THIN_TMAX * TILE + 16 + (4 * THIN_NSLOT + 4 * THIN_TMAX + 1) / 2;
+constexpr int THIN_LDS_DOUBLES = reg_lds_doubles(4, THIN_NSLOT, 0, THIN_TMAX, false);
+constexpr int THIN_LDS_DOUBLES_SHV = reg_lds_doubles(4, THIN_NSLOT, 0, THIN_TMAX, true);
 
-// SHV: the waves accumulate A v into one shared vector (pw[0, NP)) instead of a vector
-// each; the dot with v is then formed after the second barrier (every wave, over all
-// indices), (W) reads one partial per index, and the vector is cleared in (H).
+// SHV: the waves accumulate A v into one shared vector (pw) instead of a vector each;
+// the dot with v is then formed after the second barrier (every wave, over all
+// indices), (W) reads one partial per index, and the vector is cleared in (H).  The
+// vectors read per tile position (vc, vp, wp, xn, pw) are laid out by vpos<SHV>.
 template <int MODE, int RT_, int NSLOT_, int RTL_, int TMAX_, bool SHV = false>
 __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_reg_kernel(const EigDesc* __restrict__ descs,
                                                                                  int count) {
     constexpr int RT = RT_, RW = RT_ / 64, NSLOT = NSLOT_, RTL = RTL_;
-    constexpr int NP = TMAX_ * TILE, PWL = RW * NP;
+    constexpr int NP = TMAX_ * TILE, NPP = reg_npp(TMAX_, SHV), PWL = SHV ? NPP : RW * NP;
+    static_assert(!SHV || MODE == 2, "the shared-vector layout has no room for the bisection's brackets");
     extern __shared__ double lds[];
     double* xv = lds;           // current column below the diagonal (later e^2)
     double* vc = xv + NP;       // Householder vector v_j of the current step
-    double* vp = vc + NP;       // v of the previous step
-    double* wp = vp + NP;       // w of the previous step
-    double* xn = wp + NP;       // next column as held in the register tiles
-    double* pw = xn + NP;       // RW per-wave partials of A v (PWL doubles)
+    double* vp = vc + NPP;      // v of the previous step
+    double* wp = vp + NPP;      // w of the previous step
+    double* xn = wp + NPP;      // next column as held in the register tiles
+    double* pw = xn + NPP;      // partials of A v (PWL doubles)
     double* dd = pw + PWL;
     double* ee = dd + NP;
     double* red = ee + NP;      // 16: per-wave dots (0..7), per-wave norm partials (8..15)
@@ -721,7 +742,9 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
             xv[i] = i >= 1 ? x : 0.0;
             dd[i] = i == 0 ? x : 0.0;
             if (i >= 2) part += x * x;
-            vc[i] = vp[i] = wp[i] = xn[i] = ee[i] = 0.0;
+            const int pi = vpos<SHV>(i);
+            vc[pi] = vp[pi] = wp[pi] = xn[pi] = 0.0;
+            ee[i] = 0.0;
         }
         for (int i = t; i < PWL; i += RT) pw[i] = 0.0;
         part = wave_sum(part);
@@ -762,8 +785,9 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
             if (MODE == 1 && D.V)
                 for (int i = j + 2 + t; i < n; i += RT) D.V[(long)i + (long)j * D.ldv] = tau != 0.0 ? xv[i] * scale : 0.0;
             for (int i = t; i < npad; i += RT) {
-                vc[i] = (tau == 0.0 || i <= j || i >= n) ? 0.0 : (i == j + 1 ? 1.0 : xv[i] * scale);
-                if (SHV && i > j) pw[i] = 0.0;
+                const int pi = vpos<SHV>(i);
+                vc[pi] = (tau == 0.0 || i <= j || i >= n) ? 0.0 : (i == j + 1 ? 1.0 : xv[i] * scale);
+                if (SHV && i > j) pw[pi] = 0.0;
             }
             __syncthreads();  // #1
             // (P) register tiles, then this wave's share of the LDS tiles.  Row
@@ -784,12 +808,12 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                 if (code >= 0 && (code & 255) >= Cj) {
                     const int R = code >> 8, C = code & 255;
                     if (R != curR) {
-                        if (curR >= 0) flush_rows(curR, racc, pww, ly, lx);
+                        if (curR >= 0) flush_rows<SHV>(curR, racc, pww, ly, lx);
                         curR = R;
                     }
-                    tile_step_racc(rt[sl], R, C, vc, vp, wp, pww, ly, lx, racc);
+                    tile_step_racc<SHV>(rt[sl], R, C, vc, vp, wp, pww, ly, lx, racc);
                     if (C == Cn && lx == (cn >> 2)) {
-                        double* xo = xn + R * TILE + 4 * ly;
+                        double* xo = xn + vpos<SHV>(R * TILE + 4 * ly);
                         switch (cn & 3) {  // uniform across the wave
                             case 0: xo[0] = rt[sl][0]; xo[1] = rt[sl][4]; xo[2] = rt[sl][8]; xo[3] = rt[sl][12]; break;
                             case 1: xo[0] = rt[sl][1]; xo[1] = rt[sl][5]; xo[2] = rt[sl][9]; xo[3] = rt[sl][13]; break;
@@ -812,10 +836,10 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                 C = cl + f;
                 for (; k > 0; --k) {
                     if (R != curR) {
-                        if (curR >= 0) flush_rows(curR, racc, pww, ly, lx);
+                        if (curR >= 0) flush_rows<SHV>(curR, racc, pww, ly, lx);
                         curR = R;
                     }
-                    tile_step_lds(lt + (size_t)lds_tile_index(R, C, c0, TL) * TILE_EL, lane, R, C, vc, vp, wp, pww, ly,
+                    tile_step_lds<SHV>(lt + (size_t)lds_tile_index(R, C, c0, TL) * TILE_EL, lane, R, C, vc, vp, wp, pww, ly,
                                   lx, racc);
                     if (++C > R) {
                         ++R;
@@ -823,7 +847,7 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                     }
                 }
             }
-            if (curR >= 0) flush_rows(curR, racc, pww, ly, lx);
+            if (curR >= 0) flush_rows<SHV>(curR, racc, pww, ly, lx);
             double dsum = 0.0;
             if (!SHV) {
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -839,7 +863,7 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
             // itself; those partials are never cleared (row j+1 is dead from here on).
             if (SHV) {
                 double dp = 0.0;
-                for (int i = j + 1 + lane; i < n; i += 64) dp += pw[i] * vc[i];
+                for (int i = j + 1 + lane; i < n; i += 64) dp += pw[vpos<SHV>(i)] * vc[vpos<SHV>(i)];
                 dsum = wave_sum(dp);
             } else {
 #pragma unroll
@@ -847,27 +871,28 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
             }
             const double K = -0.5 * tau * tau * dsum;
             double p1 = 0.0;
-            if (SHV) p1 = pw[j + 1];
+            if (SHV) p1 = pw[vpos<SHV>(j + 1)];
             else {
 #pragma unroll
                 for (int q = 0; q < RW; ++q) p1 += pw[q * NP + j + 1];
             }
-            const double v1 = vc[j + 1];
+            const double v1 = vc[vpos<SHV>(j + 1)];
             const double w1 = tau * p1 + K * v1;
             part = 0.0;
             for (int i = t; i < npad; i += RT) {
+                const int pi = vpos<SHV>(i);
                 double wi = 0.0;
                 if (i >= j + 1 && i < n) {
                     double acc = 0.0;
-                    if (SHV) acc = pw[i];
+                    if (SHV) acc = pw[pi];
                     else {
 #pragma unroll
                         for (int q = 0; q < RW; ++q) acc += pw[q * NP + i];
                     }
-                    wi = tau * acc + K * vc[i];
-                    const double base = Cn < c0 ? xn[i]
+                    wi = tau * acc + K * vc[pi];
+                    const double base = Cn < c0 ? xn[pi]
                                                 : lt[(size_t)lds_tile_index(i >> 5, Cn, c0, TL) * TILE_EL + tile_off(i & 31, cn)];
-                    double x = fma(-vc[i], w1, base);
+                    double x = fma(-vc[pi], w1, base);
                     x = fma(-wi, v1, x);
                     if (i == j + 1) dd[j + 1] = x;
                     else {
@@ -879,8 +904,8 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
 #pragma unroll
                     for (int q = 0; q < RW; ++q) pw[q * NP + i] = 0.0;
                 }
-                wp[i] = wi;
-                vp[i] = vc[i];
+                wp[pi] = wi;
+                vp[pi] = vc[pi];
             }
             part = wave_sum(part);
             if (SHV) {
@@ -913,8 +938,9 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                 // written to both triangles of M
                 auto put = [&](int gi, int gc, double a) {
                     if (gc > jend && gi >= gc && gi < n) {
-                        double x = fma(-vp[gi], wp[gc], a);
-                        x = fma(-wp[gi], vp[gc], x);
+                        const int pi = vpos<SHV>(gi), pc = vpos<SHV>(gc);
+                        double x = fma(-vp[pi], wp[pc], a);
+                        x = fma(-wp[pi], vp[pc], x);
                         M[(long)(gi - jend) + (long)(gc - jend) * ldt] = x;
                         M[(long)(gc - jend) + (long)(gi - jend) * ldt] = x;
                     }
@@ -1731,8 +1757,7 @@ bool sym_eig_split(int nmax) {
 // a CU.
 constexpr int MID_TMAX = 6;
 constexpr int MID_RTL = 3;
-constexpr int MID_LDS_DOUBLES = 7 * MID_TMAX * TILE + 4 * MID_TMAX * TILE + 16 + MID_RTL * (MID_RTL + 1) / 2 * TILE_EL +
-                                (4 * THIN_NSLOT + 4 * MID_TMAX + 1) / 2;
+constexpr int MID_LDS_DOUBLES = reg_lds_doubles(4, THIN_NSLOT, MID_RTL, MID_TMAX, true);
 static_assert(2 * MID_LDS_DOUBLES * 8 <= LDS_BYTES, "two trailing problems must share a CU");
 
 int sym_eig_tail_levels(int* orders) {
@@ -1751,7 +1776,7 @@ void sym_eig_tail_batched(const EigDesc* d_descs, int count, int level, hipStrea
         hipLaunchKernelGGL((sym_eig_reg_kernel<2, 256, THIN_NSLOT, MID_RTL, MID_TMAX, true>), dim3(grid), dim3(256), lds,
                            s, d_descs, count);
     } else if (level == 1) {
-        const size_t lds = (size_t)THIN_LDS_DOUBLES * 8;
+        const size_t lds = (size_t)THIN_LDS_DOUBLES_SHV * 8;
         const int grid = count < 2048 ? count : 2048;
         hipLaunchKernelGGL((sym_eig_reg_kernel<2, 256, THIN_NSLOT, 0, THIN_TMAX, true>), dim3(grid), dim3(256), lds, s,
                            d_descs, count);
@@ -1816,7 +1841,7 @@ void sym_eig_batched(const EigDesc* d_descs, int count, int nmax, int mode, doub
         return;
     }
     if (T <= REG_TMAX) {
-        const size_t lds = (size_t)REG_LDS_DOUBLES * 8;
+        const size_t lds = (size_t)(split ? REG_LDS_DOUBLES_SHV : REG_LDS_DOUBLES) * 8;
         const int grid = count < nslots ? count : nslots;
         if (split) {
             // the evaluation's tridiagonalisation sums A v in one shared vector: 10 % faster
