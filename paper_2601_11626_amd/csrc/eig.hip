@@ -535,6 +535,17 @@ __device__ __forceinline__ void tile_step(double (&a)[16], int R, int C, const d
 template <bool SW>
 __device__ __forceinline__ int vpos(int i) { return SW ? i + 2 * (i >> 4) : i; }
 
+// Four consecutive doubles of a vector as two 16-byte LDS loads: the groups read per
+// tile start at even positions of 16-byte aligned vectors, and the loads' 16-bit
+// offsets let one address reach all three vectors.
+__device__ __forceinline__ void ld4(const double* p, double (&o)[4]) {
+    const double2 x = reinterpret_cast<const double2*>(p)[0], y = reinterpret_cast<const double2*>(p)[1];
+    o[0] = x.x;
+    o[1] = x.y;
+    o[2] = y.x;
+    o[3] = y.y;
+}
+
 // The same tile update for row-owned passes: the row partials are accumulated into
 // racc (per lane, rows 4ly..4ly+3 of the tile row) instead of being reduced per tile;
 // flush_rows reduces and publishes them once per tile row.
@@ -543,17 +554,17 @@ __device__ __forceinline__ void tile_step_racc(double (&a)[16], int R, int C, co
                                                const double* __restrict__ vp, const double* __restrict__ wp,
                                                double* pww, int ly, int lx, double (&racc)[4]) {
     const int gi0 = vpos<SW>(R * TILE + 4 * ly), gc0 = vpos<SW>(C * TILE + 4 * lx);
-    double vq[4], wq[4], cq[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        vq[q] = vp[gc0 + q];
-        wq[q] = wp[gc0 + q];
-        cq[q] = vc[gc0 + q];
-    }
+    double vq[4], wq[4], cq[4], vr4[4], wr4[4], cr4[4];
+    ld4(vp + gc0, vq);
+    ld4(wp + gc0, wq);
+    ld4(vc + gc0, cq);
+    ld4(vp + gi0, vr4);
+    ld4(wp + gi0, wr4);
+    ld4(vc + gi0, cr4);
     double cp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        const double vr = vp[gi0 + s], wr = wp[gi0 + s], cr = vc[gi0 + s];
+        const double vr = vr4[s], wr = wr4[s], cr = cr4[s];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             double x = fma(-vr, wq[q], a[s * 4 + q]);
@@ -580,20 +591,20 @@ __device__ __forceinline__ void tile_step_lds(double* tp, int lane, int R, int C
                                               const double* __restrict__ vp, const double* __restrict__ wp,
                                               double* pww, int ly, int lx, double (&racc)[4]) {
     const int gi0 = vpos<SW>(R * TILE + 4 * ly), gc0 = vpos<SW>(C * TILE + 4 * lx);
-    double vq[4], wq[4], cq[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        vq[q] = vp[gc0 + q];
-        wq[q] = wp[gc0 + q];
-        cq[q] = vc[gc0 + q];
-    }
+    double vq[4], wq[4], cq[4], vr4[4], wr4[4], cr4[4];
+    ld4(vp + gc0, vq);
+    ld4(wp + gc0, wq);
+    ld4(vc + gc0, cq);
+    ld4(vp + gi0, vr4);
+    ld4(wp + gi0, wr4);
+    ld4(vc + gi0, cr4);
     double cp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         double a[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) a[q] = tp[((4 * s + q) << 6) + lane];
-        const double vr = vp[gi0 + s], wr = wp[gi0 + s], cr = vc[gi0 + s];
+        const double vr = vr4[s], wr = wr4[s], cr = cr4[s];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             double x = fma(-vr, wq[q], a[q]);
@@ -614,14 +625,20 @@ __device__ __forceinline__ void tile_step_lds(double* tp, int lane, int R, int C
     }
 }
 
+// Publishes the row partials of tile row R (four per lane) and clears them.  A
+// transpose-reduce over the eight lanes of a row group (lx): each stage keeps half of
+// the values and exchanges the other half with the partner lane, so that lane lx ends
+// with row 2*bit2(lx) + bit1(lx) summed over the group; the lanes with even lx add it.
 template <bool SW>
 __device__ __forceinline__ void flush_rows(int R, double (&racc)[4], double* pww, int ly, int lx) {
+    const bool b2 = (lx & 4) != 0, b1 = (lx & 2) != 0;
+    const double u0 = (b2 ? racc[2] : racc[0]) + dpp_move<0x141>(b2 ? racc[0] : racc[2]);  // partner lx ^ 7
+    const double u1 = (b2 ? racc[3] : racc[1]) + dpp_move<0x141>(b2 ? racc[1] : racc[3]);
+    double v = (b1 ? u1 : u0) + dpp_move<0x4E>(b1 ? u0 : u1);                             // partner lx ^ 2
+    v += dpp_move<0xB1>(v);                                                                 // partner lx ^ 1
+    if ((lx & 1) == 0) unsafeAtomicAdd(&pww[vpos<SW>(R * TILE + 4 * ly) + (lx >> 1)], v);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const double v = sum_lanes8(racc[s]);
-        if (lx == s) unsafeAtomicAdd(&pww[vpos<SW>(R * TILE + 4 * ly) + s], v);
-        racc[s] = 0.0;
-    }
+    for (int s = 0; s < 4; ++s) racc[s] = 0.0;
 }
 
 __device__ __forceinline__ int lds_tile_index(int R, int C, int c0, int TL) {
@@ -661,7 +678,7 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
     constexpr int RT = RT_, RW = RT_ / 64, NSLOT = NSLOT_, RTL = RTL_;
     constexpr int NP = TMAX_ * TILE, NPP = reg_npp(TMAX_, SHV), PWL = SHV ? NPP : RW * NP;
     static_assert(!SHV || MODE == 2, "the shared-vector layout has no room for the bisection's brackets");
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) double lds[];
     double* xv = lds;           // current column below the diagonal (later e^2)
     double* vc = xv + NP;       // Householder vector v_j of the current step
     double* vp = vc + NPP;      // v of the previous step
