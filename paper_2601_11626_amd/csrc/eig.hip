@@ -529,6 +529,15 @@ __device__ __forceinline__ void tile_step(double (&a)[16], int R, int C, const d
     }
 }
 
+// 0.0 formed where it is used.  In the column loops of the register kernels the
+// compiler otherwise keeps one zero register pair for the whole loop, spills it under
+// register pressure, and reloads it from scratch at each store of a zero.
+__device__ __forceinline__ double fresh_zero() {
+    double z;
+    asm volatile("v_mov_b64 %0, 0" : "=v"(z));
+    return z;
+}
+
 // Vector index -> LDS position.  In the shared-vector kernels (SW) two doubles of
 // padding follow every sixteen: the eight 4-element groups that the lanes of one tile
 // read (32 bytes apart) then fall on distinct LDS banks instead of pairing up.
@@ -678,6 +687,7 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
     constexpr int RT = RT_, RW = RT_ / 64, NSLOT = NSLOT_, RTL = RTL_;
     constexpr int NP = TMAX_ * TILE, NPP = reg_npp(TMAX_, SHV), PWL = SHV ? NPP : RW * NP;
     static_assert(!SHV || MODE == 2, "the shared-vector layout has no room for the bisection's brackets");
+    static_assert(RT_ >= TMAX_ * TILE, "(H) and (W) form one vector element per thread");
     extern __shared__ __align__(16) double lds[];
     double* xv = lds;           // current column below the diagonal (later e^2)
     double* vc = xv + NP;       // Householder vector v_j of the current step
@@ -789,6 +799,7 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                 for (int q = 0; q < RW; ++q) xn2 += red[8 + q];
             }
             const double alpha = xv[j + 1];
+            const double xvt = xv[t < NP ? t : 0];  // this thread's element, loaded with the others
             double tau = 0.0, beta = alpha, scale = 0.0;
             if (xn2 > 0.0) {
                 beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
@@ -801,17 +812,17 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
             }
             if (MODE == 1 && D.V)
                 for (int i = j + 2 + t; i < n; i += RT) D.V[(long)i + (long)j * D.ldv] = tau != 0.0 ? xv[i] * scale : 0.0;
-            for (int i = t; i < npad; i += RT) {
-                const int pi = vpos<SHV>(i);
-                vc[pi] = (tau == 0.0 || i <= j || i >= n) ? 0.0 : (i == j + 1 ? 1.0 : xv[i] * scale);
-                if (SHV && i > j) pw[pi] = 0.0;
+            if (t < npad) {  // one element per thread (RT >= NP)
+                const int i = t, pi = vpos<SHV>(i);
+                vc[pi] = (tau == 0.0 || i <= j || i >= n) ? 0.0 : (i == j + 1 ? 1.0 : xvt * scale);
+                if (SHV && i > j) pw[pi] = fresh_zero();
             }
             __syncthreads();  // #1
             // (P) register tiles, then this wave's share of the LDS tiles.  Row
             // partials accumulate while consecutive tiles stay in one tile row.
             const int Cn = (j + 1) >> 5, cn = (j + 1) & 31;
             double* pww = SHV ? pw : pw + w * NP;
-            if (SHV && t == 0) red[8] = 0.0;  // every wave read it in (H); (W) adds to it
+            if (SHV && t == 0) red[8] = fresh_zero();  // every wave read it in (H); (W) adds to it
             // the wave's slot codes and LDS share, read together (one LDS wait)
             int codes[NSLOT];
 #pragma unroll
@@ -870,7 +881,17 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 double dp = 0.0;
-                for (int i = j + 1 + lane; i < n; i += 64) dp += pww[i] * vc[i];
+                constexpr int NU = (NP + 63) / 64;
+                double pa[NU], pb[NU];
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {  // unconditional loads, all issued before the first use
+                    const int i = j + 1 + lane + 64 * u, ic = i < n ? i : 0;
+                    pa[u] = pww[ic];
+                    pb[u] = vc[ic];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < NU; ++u) dp += j + 1 + lane + 64 * u < n ? pa[u] * pb[u] : 0.0;
                 dp = wave_sum(dp);
                 if (lane == 0) red[w] = dp;
             }
@@ -878,15 +899,20 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
             // (W) p = tau A v, w = p - (tau/2)(p.v) v; column j+1 of A - v w^T - w v^T.
             // Every thread needs w_{j+1} and v_{j+1}, so it forms them from the partials
             // itself; those partials are never cleared (row j+1 is dead from here on).
-            if (SHV) {
-                double dp = 0.0;
-                for (int i = j + 1 + lane; i < n; i += 64) dp += pw[vpos<SHV>(i)] * vc[vpos<SHV>(i)];
-                dsum = wave_sum(dp);
-            } else {
+            // Thread t forms element i = t (RT >= NP); its operands are loaded before
+            // the reductions so that their latency overlaps them.
+            const int i = t, pi = vpos<SHV>(i);
+            const bool act = i >= j + 1 && i < n;
+            double acc = 0.0, vci = 0.0, base = 0.0;
+            if (act) {
+                if (SHV) acc = pw[pi];
+                else {
 #pragma unroll
-                for (int q = 0; q < RW; ++q) dsum += red[q];
+                    for (int q = 0; q < RW; ++q) acc += pw[q * NP + i];
+                }
+                vci = vc[pi];
+                base = Cn < c0 ? xn[pi] : lt[(size_t)lds_tile_index(i >> 5, Cn, c0, TL) * TILE_EL + tile_off(i & 31, cn)];
             }
-            const double K = -0.5 * tau * tau * dsum;
             double p1 = 0.0;
             if (SHV) p1 = pw[vpos<SHV>(j + 1)];
             else {
@@ -894,22 +920,32 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                 for (int q = 0; q < RW; ++q) p1 += pw[q * NP + j + 1];
             }
             const double v1 = vc[vpos<SHV>(j + 1)];
+            if (SHV) {
+                double dp = 0.0;
+                constexpr int NU = (NP + 63) / 64;
+                double pa[NU], pb[NU];
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {  // unconditional loads, all issued before the first use
+                    const int iu = j + 1 + lane + 64 * u, pu = vpos<SHV>(iu < n ? iu : 0);
+                    pa[u] = pw[pu];
+                    pb[u] = vc[pu];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < NU; ++u) dp += j + 1 + lane + 64 * u < n ? pa[u] * pb[u] : 0.0;
+                dsum = wave_sum(dp);
+            } else {
+#pragma unroll
+                for (int q = 0; q < RW; ++q) dsum += red[q];
+            }
+            const double K = -0.5 * tau * tau * dsum;
             const double w1 = tau * p1 + K * v1;
             part = 0.0;
-            for (int i = t; i < npad; i += RT) {
-                const int pi = vpos<SHV>(i);
+            if (i < npad) {
                 double wi = 0.0;
-                if (i >= j + 1 && i < n) {
-                    double acc = 0.0;
-                    if (SHV) acc = pw[pi];
-                    else {
-#pragma unroll
-                        for (int q = 0; q < RW; ++q) acc += pw[q * NP + i];
-                    }
-                    wi = tau * acc + K * vc[pi];
-                    const double base = Cn < c0 ? xn[pi]
-                                                : lt[(size_t)lds_tile_index(i >> 5, Cn, c0, TL) * TILE_EL + tile_off(i & 31, cn)];
-                    double x = fma(-vc[pi], w1, base);
+                if (act) {
+                    wi = tau * acc + K * vci;
+                    double x = fma(-vci, w1, base);
                     x = fma(-wi, v1, x);
                     if (i == j + 1) dd[j + 1] = x;
                     else {
@@ -922,7 +958,7 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                     for (int q = 0; q < RW; ++q) pw[q * NP + i] = 0.0;
                 }
                 wp[pi] = wi;
-                vp[pi] = vc[pi];
+                vp[pi] = vci;  // v vanishes outside [j + 1, n)
             }
             part = wave_sum(part);
             if (SHV) {
