@@ -729,21 +729,55 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
         if (SHV && t == 0) red[8] = 0.0;
         __syncthreads();
         // For each tile column c (the step's leading column), the active LDS tiles
-        // (columns >= max(c, c0)) in row-major order, handed out so that every wave
-        // ends up with about the same number of active tiles.
+        // (columns >= max(c, c0)) in row-major order, handed out in contiguous shares
+        // that balance a load model of the step: a register tile costs 5 units, an LDS
+        // tile 8 (it also moves its elements through LDS).  Each LDS tile goes to the
+        // SIMD with the least load (waves w and w + 4 share one), and there to the
+        // wave with the least load, a younger wave (w >= 4, which loses issue
+        // arbitration to the older one) counted 30 % heavier.
         if (t < T) {
             const int c = t, cl = c > c0 ? c : c0, mL = T - cl, NL = mL * (mL + 1) / 2;
-            int tot = NL;
-            for (int g = 0; g < RW * NSLOT; ++g) tot += (geo[g] >= 0 && (geo[g] & 255) >= c) ? 1 : 0;
-            const int target = (tot + RW - 1) / RW;
-            int first = 0;
+            int load[RW], k[RW];
+#pragma unroll
             for (int ww = 0; ww < RW; ++ww) {
                 int rc = 0;
                 for (int sl = 0; sl < NSLOT; ++sl) rc += (geo[ww * NSLOT + sl] >= 0 && (geo[ww * NSLOT + sl] & 255) >= c) ? 1 : 0;
-                int k = target - rc;
-                k = k < 0 ? 0 : (k > NL - first ? NL - first : k);
-                geo[RW * NSLOT + c * RW + ww] = (first << 8) | k;
-                first += k;
+                load[ww] = 5 * rc;
+                k[ww] = 0;
+            }
+            for (int m = 0; m < NL; ++m) {
+                int bs = 0, bl = 0x7fffffff;
+#pragma unroll
+                for (int sd = 0; sd < (RW < 4 ? RW : 4); ++sd) {
+                    int l = 0;
+#pragma unroll
+                    for (int ww = sd; ww < RW; ww += 4) l += load[ww];
+                    if (l < bl) {
+                        bl = l;
+                        bs = sd;
+                    }
+                }
+                int bw = bs, be = 0x7fffffff;
+#pragma unroll
+                for (int ww = 0; ww < RW; ++ww) {
+                    const int e = ww >= 4 ? load[ww] * 13 : load[ww] * 10;
+                    if ((ww & 3) == bs && e < be) {
+                        be = e;
+                        bw = ww;
+                    }
+                }
+#pragma unroll
+                for (int ww = 0; ww < RW; ++ww)
+                    if (ww == bw) {
+                        load[ww] += 8;
+                        ++k[ww];
+                    }
+            }
+            int first = 0;
+#pragma unroll
+            for (int ww = 0; ww < RW; ++ww) {
+                geo[RW * NSLOT + c * RW + ww] = (first << 8) | k[ww];
+                first += k[ww];
             }
         }
         double rt[NSLOT][16];
