@@ -634,6 +634,77 @@ __device__ __forceinline__ void tile_step_lds(double* tp, int lane, int R, int C
     }
 }
 
+// The two steps above with the row values v, w, v_j of the tile row given by the
+// caller, which loads them once per tile row (kernels with registers to spare).
+template <bool SW>
+__device__ __forceinline__ void tile_step_racc_rows(double (&a)[16], int R, int C, const double* __restrict__ vc,
+                                               const double* __restrict__ vp, const double* __restrict__ wp,
+                                               double* pww, int ly, int lx, double (&racc)[4],
+        const double (&vr4)[4], const double (&wr4)[4], const double (&cr4)[4]) {
+    const int gc0 = vpos<SW>(C * TILE + 4 * lx);
+    double vq[4], wq[4], cq[4];
+    ld4(vp + gc0, vq);
+    ld4(wp + gc0, wq);
+    ld4(vc + gc0, cq);
+    double cp[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const double vr = vr4[s], wr = wr4[s], cr = cr4[s];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double x = fma(-vr, wq[q], a[s * 4 + q]);
+            x = fma(-wr, vq[q], x);
+            a[s * 4 + q] = x;
+            racc[s] = fma(x, cq[q], racc[s]);
+            cp[q] = fma(x, cr, cp[q]);
+        }
+    }
+    if (R != C) {
+        const double s01 = add_swap32(cp[0], cp[1]);
+        const double s23 = add_swap32(cp[2], cp[3]);
+        double t = add_swap16(s01, s23);
+        t += dpp_move<0x128>(t);
+        if ((ly & 1) == 0) unsafeAtomicAdd(&pww[gc0 + (ly >> 2) + 2 * ((ly >> 1) & 1)], t);
+    }
+}
+
+template <bool SW>
+__device__ __forceinline__ void tile_step_lds_rows(double* tp, int lane, int R, int C, const double* __restrict__ vc,
+                                              const double* __restrict__ vp, const double* __restrict__ wp,
+                                              double* pww, int ly, int lx, double (&racc)[4],
+        const double (&vr4)[4], const double (&wr4)[4], const double (&cr4)[4]) {
+    const int gc0 = vpos<SW>(C * TILE + 4 * lx);
+    double vq[4], wq[4], cq[4];
+    ld4(vp + gc0, vq);
+    ld4(wp + gc0, wq);
+    ld4(vc + gc0, cq);
+    double cp[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        double a[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = tp[((4 * s + q) << 6) + lane];
+        const double vr = vr4[s], wr = wr4[s], cr = cr4[s];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double x = fma(-vr, wq[q], a[q]);
+            x = fma(-wr, vq[q], x);
+            a[q] = x;
+            racc[s] = fma(x, cq[q], racc[s]);
+            cp[q] = fma(x, cr, cp[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tp[((4 * s + q) << 6) + lane] = a[q];
+    }
+    if (R != C) {
+        const double s01 = add_swap32(cp[0], cp[1]);
+        const double s23 = add_swap32(cp[2], cp[3]);
+        double t = add_swap16(s01, s23);
+        t += dpp_move<0x128>(t);
+        if ((ly & 1) == 0) unsafeAtomicAdd(&pww[gc0 + (ly >> 2) + 2 * ((ly >> 1) & 1)], t);
+    }
+}
+
 // Publishes the row partials of tile row R (four per lane) and clears them.  A
 // transpose-reduce over the eight lanes of a row group (lx): each stage keeps half of
 // the values and exchanges the other half with the partner lane, so that lane lx ends
@@ -863,6 +934,10 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
             for (int sl = 0; sl < NSLOT; ++sl) codes[sl] = geo[w * NSLOT + sl];
             const int al_v = geo[RW * NSLOT + Cj * RW + w];
             double racc[4] = {0.0, 0.0, 0.0, 0.0};
+            // v, w and v_j over the rows of the current tile row, kept across its tiles in
+            // the four-wave kernels (the eight-wave kernel has no registers to spare)
+            constexpr bool ROWC = RW == 4;
+            double rv[ROWC ? 4 : 1], rw[ROWC ? 4 : 1], rcv[ROWC ? 4 : 1];
             int curR = -1;
 #pragma unroll
             for (int sl = 0; sl < NSLOT; ++sl) {
@@ -872,8 +947,15 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                     if (R != curR) {
                         if (curR >= 0) flush_rows<SHV>(curR, racc, pww, ly, lx);
                         curR = R;
+                        if constexpr (ROWC) {
+                            const int gi0 = vpos<SHV>(R * TILE + 4 * ly);
+                            ld4(vp + gi0, rv);
+                            ld4(wp + gi0, rw);
+                            ld4(vc + gi0, rcv);
+                        }
                     }
-                    tile_step_racc<SHV>(rt[sl], R, C, vc, vp, wp, pww, ly, lx, racc);
+                    if constexpr (ROWC) tile_step_racc_rows<SHV>(rt[sl], R, C, vc, vp, wp, pww, ly, lx, racc, rv, rw, rcv);
+                    else tile_step_racc<SHV>(rt[sl], R, C, vc, vp, wp, pww, ly, lx, racc);
                     if (C == Cn && lx == (cn >> 2)) {
                         double* xo = xn + vpos<SHV>(R * TILE + 4 * ly);
                         switch (cn & 3) {  // uniform across the wave
@@ -900,9 +982,19 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                     if (R != curR) {
                         if (curR >= 0) flush_rows<SHV>(curR, racc, pww, ly, lx);
                         curR = R;
+                        if constexpr (ROWC) {
+                            const int gi0 = vpos<SHV>(R * TILE + 4 * ly);
+                            ld4(vp + gi0, rv);
+                            ld4(wp + gi0, rw);
+                            ld4(vc + gi0, rcv);
+                        }
                     }
-                    tile_step_lds<SHV>(lt + (size_t)lds_tile_index(R, C, c0, TL) * TILE_EL, lane, R, C, vc, vp, wp, pww, ly,
-                                  lx, racc);
+                    if constexpr (ROWC)
+                        tile_step_lds_rows<SHV>(lt + (size_t)lds_tile_index(R, C, c0, TL) * TILE_EL, lane, R, C, vc, vp, wp,
+                                                pww, ly, lx, racc, rv, rw, rcv);
+                    else
+                        tile_step_lds<SHV>(lt + (size_t)lds_tile_index(R, C, c0, TL) * TILE_EL, lane, R, C, vc, vp, wp, pww, ly,
+                                           lx, racc);
                     if (++C > R) {
                         ++R;
                         C = cl;
