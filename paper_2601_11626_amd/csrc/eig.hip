@@ -729,13 +729,14 @@ __device__ __forceinline__ int lds_tile_index(int R, int C, int c0, int TL) {
 constexpr int REG_NP = REG_TMAX * TILE;  // vector length (fixed layout)
 
 // LDS of the register kernels, in doubles, in the kernel's order: xv (np); vc, vp, wp, xn
-// (np, padded by vpos in the shared-vector kernels); the partials of A v (one padded
-// vector with SHV, else one vector per wave); dd, ee (np); 16 for the reductions; the
+// (np, padded by vpos in the shared-vector kernels); the partials of A v (one vector per
+// wave; with SHV two padded partial vectors and the second unscaled-column buffer,
+// see the kernel); dd, ee (np); 16 for the reductions; the
 // LDS tiles (the last rtl tile columns); the geometry ints: rw*nslot slot codes, then per
 // tile column c the LDS-tile share of every wave ((first << 8) | count, rw*tmax).
 __host__ __device__ constexpr int reg_npp(int tmax, bool shv) { return shv ? tmax * TILE + tmax * TILE / 8 : tmax * TILE; }
 __host__ __device__ constexpr int reg_lds_doubles(int rw, int nslot, int rtl, int tmax, bool shv) {
-    return 3 * tmax * TILE + 4 * reg_npp(tmax, shv) + (shv ? reg_npp(tmax, shv) : rw * tmax * TILE) + 16 +
+    return 3 * tmax * TILE + 4 * reg_npp(tmax, shv) + (shv ? 3 * reg_npp(tmax, shv) : rw * tmax * TILE) + 16 +
            rtl * (rtl + 1) / 2 * TILE_EL + (rw * nslot + rw * tmax + 1) / 2;
 }
 constexpr int REG_LDS_DOUBLES = reg_lds_doubles(RW, NSLOT, RTL, REG_TMAX, false);
@@ -748,15 +749,21 @@ constexpr int THIN_NSLOT = 4;
 constexpr int THIN_LDS_DOUBLES = reg_lds_doubles(4, THIN_NSLOT, 0, THIN_TMAX, false);
 constexpr int THIN_LDS_DOUBLES_SHV = reg_lds_doubles(4, THIN_NSLOT, 0, THIN_TMAX, true);
 
-// SHV: the waves accumulate A v into one shared vector (pw) instead of a vector each;
-// the dot with v is then formed after the second barrier (every wave, over all
-// indices), (W) reads one partial per index, and the vector is cleared in (H).  The
-// vectors read per tile position (vc, vp, wp, xn, pw) are laid out by vpos<SHV>.
+// SHV: the waves accumulate the products into one shared vector instead of a vector
+// each, and a step has two barriers instead of three: the tiles multiply by the
+// unscaled column below its first subdiagonal element (x, zero elsewhere) instead of
+// by v, so no barrier is needed between the Householder scalars and the tile pass.
+// (W) assembles A v = A e_{j+1} + scale A x from the published column j + 1 and the
+// products, and by symmetry v^T A v = A_{j+1,j+1} + 2 scale (A x)_{j+1} + scale^2 x^T A x.
+// The unscaled column, the products and the norm accumulator alternate between two
+// buffers by step parity, so (W) prepares the next step's while every wave may still
+// read this step's.  The vectors read per tile position (x, vp, wp, xn, the products)
+// are laid out by vpos<SHV>.
 template <int MODE, int RT_, int NSLOT_, int RTL_, int TMAX_, bool SHV = false>
 __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_reg_kernel(const EigDesc* __restrict__ descs,
                                                                                  int count) {
     constexpr int RT = RT_, RW = RT_ / 64, NSLOT = NSLOT_, RTL = RTL_;
-    constexpr int NP = TMAX_ * TILE, NPP = reg_npp(TMAX_, SHV), PWL = SHV ? NPP : RW * NP;
+    constexpr int NP = TMAX_ * TILE, NPP = reg_npp(TMAX_, SHV), PWL = SHV ? 3 * NPP : RW * NP;
     static_assert(!SHV || MODE == 2, "the shared-vector layout has no room for the bisection's brackets");
     static_assert(RT_ >= TMAX_ * TILE, "(H) and (W) form one vector element per thread");
     extern __shared__ __align__(16) double lds[];
@@ -766,6 +773,7 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
     double* wp = vp + NPP;      // w of the previous step
     double* xn = wp + NPP;      // next column as held in the register tiles
     double* pw = xn + NPP;      // partials of A v (PWL doubles)
+    double* xs1 = pw + 2 * NPP;  // SHV: unscaled column of odd steps (vc holds the even steps')
     double* dd = pw + PWL;
     double* ee = dd + NP;
     double* red = ee + NP;      // 16: per-wave dots (0..7), per-wave norm partials (8..15)
@@ -797,7 +805,7 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
             }
             geo[t] = code;
         }
-        if (SHV && t == 0) red[8] = 0.0;
+        if (SHV && t == 0) red[8] = red[9] = 0.0;
         __syncthreads();
         // For each tile column c (the step's leading column), the active LDS tiles
         // (columns >= max(c, c0)) in row-major order, handed out in contiguous shares
@@ -875,7 +883,8 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
             dd[i] = i == 0 ? x : 0.0;
             if (i >= 2) part += x * x;
             const int pi = vpos<SHV>(i);
-            vc[pi] = vp[pi] = wp[pi] = xn[pi] = 0.0;
+            vp[pi] = wp[pi] = xn[pi] = 0.0;
+            vc[pi] = SHV && i >= 2 ? x : 0.0;
             ee[i] = 0.0;
         }
         for (int i = t; i < PWL; i += RT) pw[i] = 0.0;
@@ -896,38 +905,52 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
         const int jend = (MODE == 2 && D.jsplit > 0) ? D.jsplit : n - 1;
         for (int j = 0; j < jend; ++j) {
             const int Cj = j >> 5;
-            // (H) redundantly in every wave
-            double xn2 = 0.0;
-            if (SHV) xn2 = red[8];
-            else {
+            const int b = j & 1;  // SHV buffer parity
+            double tau = 0.0, beta = 0.0, scale = 0.0;
+            if constexpr (!SHV) {
+                // (H) redundantly in every wave
+                double xn2 = 0.0;
 #pragma unroll
                 for (int q = 0; q < RW; ++q) xn2 += red[8 + q];
-            }
-            const double alpha = xv[j + 1];
-            const double xvt = xv[t < NP ? t : 0];  // this thread's element, loaded with the others
-            double tau = 0.0, beta = alpha, scale = 0.0;
-            if (xn2 > 0.0) {
-                beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-                tau = (beta - alpha) / beta;
-                scale = 1.0 / (alpha - beta);
-            }
-            if (t == 0) {
+                const double alpha = xv[j + 1];
+                const double xvt = xv[t < NP ? t : 0];  // this thread's element, loaded with the others
+                beta = alpha;
+                if (xn2 > 0.0) {
+                    beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+                    tau = (beta - alpha) / beta;
+                    scale = 1.0 / (alpha - beta);
+                }
+                if (t == 0) {
+                    ee[j] = beta;
+                    if (MODE == 1 && D.tau) D.tau[j] = tau;
+                }
+                if (MODE == 1 && D.V)
+                    for (int i = j + 2 + t; i < n; i += RT) D.V[(long)i + (long)j * D.ldv] = tau != 0.0 ? xv[i] * scale : 0.0;
+                if (t < npad) {  // one element per thread (RT >= NP)
+                    const int i = t;
+                    vc[i] = (tau == 0.0 || i <= j || i >= n) ? 0.0 : (i == j + 1 ? 1.0 : xvt * scale);
+                }
+                __syncthreads();  // #1
+            } else if (t == RT - 1) {
+                // the Householder scalars, by one thread of the last wave (the others go
+                // straight to their tiles); (W) reads tau and scale from red[10], red[11]
+                const double xn2 = red[8 + b];
+                const double alpha = xv[j + 1];
+                beta = alpha;
+                if (xn2 > 0.0) {
+                    beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+                    tau = (beta - alpha) / beta;
+                    scale = 1.0 / (alpha - beta);
+                }
                 ee[j] = beta;
-                if (MODE == 1 && D.tau) D.tau[j] = tau;
+                red[10] = tau;
+                red[11] = scale;
             }
-            if (MODE == 1 && D.V)
-                for (int i = j + 2 + t; i < n; i += RT) D.V[(long)i + (long)j * D.ldv] = tau != 0.0 ? xv[i] * scale : 0.0;
-            if (t < npad) {  // one element per thread (RT >= NP)
-                const int i = t, pi = vpos<SHV>(i);
-                vc[pi] = (tau == 0.0 || i <= j || i >= n) ? 0.0 : (i == j + 1 ? 1.0 : xvt * scale);
-                if (SHV && i > j) pw[pi] = fresh_zero();
-            }
-            __syncthreads();  // #1
             // (P) register tiles, then this wave's share of the LDS tiles.  Row
             // partials accumulate while consecutive tiles stay in one tile row.
             const int Cn = (j + 1) >> 5, cn = (j + 1) & 31;
-            double* pww = SHV ? pw : pw + w * NP;
-            if (SHV && t == 0) red[8] = fresh_zero();  // every wave read it in (H); (W) adds to it
+            double* pww = SHV ? pw + b * NPP : pw + w * NP;  // products of this step
+            const double* vcx = SHV && b ? xs1 : vc;         // the vector the tiles multiply by
             // the wave's slot codes and LDS share, read together (one LDS wait)
             int codes[NSLOT];
 #pragma unroll
@@ -951,11 +974,11 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                             const int gi0 = vpos<SHV>(R * TILE + 4 * ly);
                             ld4(vp + gi0, rv);
                             ld4(wp + gi0, rw);
-                            ld4(vc + gi0, rcv);
+                            ld4(vcx + gi0, rcv);
                         }
                     }
-                    if constexpr (ROWC) tile_step_racc_rows<SHV>(rt[sl], R, C, vc, vp, wp, pww, ly, lx, racc, rv, rw, rcv);
-                    else tile_step_racc<SHV>(rt[sl], R, C, vc, vp, wp, pww, ly, lx, racc);
+                    if constexpr (ROWC) tile_step_racc_rows<SHV>(rt[sl], R, C, vcx, vp, wp, pww, ly, lx, racc, rv, rw, rcv);
+                    else tile_step_racc<SHV>(rt[sl], R, C, vcx, vp, wp, pww, ly, lx, racc);
                     if (C == Cn && lx == (cn >> 2)) {
                         double* xo = xn + vpos<SHV>(R * TILE + 4 * ly);
                         switch (cn & 3) {  // uniform across the wave
@@ -986,15 +1009,15 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                             const int gi0 = vpos<SHV>(R * TILE + 4 * ly);
                             ld4(vp + gi0, rv);
                             ld4(wp + gi0, rw);
-                            ld4(vc + gi0, rcv);
+                            ld4(vcx + gi0, rcv);
                         }
                     }
                     if constexpr (ROWC)
-                        tile_step_lds_rows<SHV>(lt + (size_t)lds_tile_index(R, C, c0, TL) * TILE_EL, lane, R, C, vc, vp, wp,
+                        tile_step_lds_rows<SHV>(lt + (size_t)lds_tile_index(R, C, c0, TL) * TILE_EL, lane, R, C, vcx, vp, wp,
                                                 pww, ly, lx, racc, rv, rw, rcv);
                     else
-                        tile_step_lds<SHV>(lt + (size_t)lds_tile_index(R, C, c0, TL) * TILE_EL, lane, R, C, vc, vp, wp, pww, ly,
-                                           lx, racc);
+                        tile_step_lds<SHV>(lt + (size_t)lds_tile_index(R, C, c0, TL) * TILE_EL, lane, R, C, vcx, vp, wp, pww,
+                                           ly, lx, racc);
                     if (++C > R) {
                         ++R;
                         C = cl;
@@ -1022,48 +1045,27 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                 if (lane == 0) red[w] = dp;
             }
             __syncthreads();  // #2
+            if constexpr (!SHV) {
             // (W) p = tau A v, w = p - (tau/2)(p.v) v; column j+1 of A - v w^T - w v^T.
             // Every thread needs w_{j+1} and v_{j+1}, so it forms them from the partials
             // itself; those partials are never cleared (row j+1 is dead from here on).
             // Thread t forms element i = t (RT >= NP); its operands are loaded before
             // the reductions so that their latency overlaps them.
-            const int i = t, pi = vpos<SHV>(i);
+            const int i = t;
             const bool act = i >= j + 1 && i < n;
             double acc = 0.0, vci = 0.0, base = 0.0;
             if (act) {
-                if (SHV) acc = pw[pi];
-                else {
 #pragma unroll
-                    for (int q = 0; q < RW; ++q) acc += pw[q * NP + i];
-                }
-                vci = vc[pi];
-                base = Cn < c0 ? xn[pi] : lt[(size_t)lds_tile_index(i >> 5, Cn, c0, TL) * TILE_EL + tile_off(i & 31, cn)];
+                for (int q = 0; q < RW; ++q) acc += pw[q * NP + i];
+                vci = vc[i];
+                base = Cn < c0 ? xn[i] : lt[(size_t)lds_tile_index(i >> 5, Cn, c0, TL) * TILE_EL + tile_off(i & 31, cn)];
             }
             double p1 = 0.0;
-            if (SHV) p1 = pw[vpos<SHV>(j + 1)];
-            else {
 #pragma unroll
-                for (int q = 0; q < RW; ++q) p1 += pw[q * NP + j + 1];
-            }
-            const double v1 = vc[vpos<SHV>(j + 1)];
-            if (SHV) {
-                double dp = 0.0;
-                constexpr int NU = (NP + 63) / 64;
-                double pa[NU], pb[NU];
+            for (int q = 0; q < RW; ++q) p1 += pw[q * NP + j + 1];
+            const double v1 = vc[j + 1];
 #pragma unroll
-                for (int u = 0; u < NU; ++u) {  // unconditional loads, all issued before the first use
-                    const int iu = j + 1 + lane + 64 * u, pu = vpos<SHV>(iu < n ? iu : 0);
-                    pa[u] = pw[pu];
-                    pb[u] = vc[pu];
-                }
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int u = 0; u < NU; ++u) dp += j + 1 + lane + 64 * u < n ? pa[u] * pb[u] : 0.0;
-                dsum = wave_sum(dp);
-            } else {
-#pragma unroll
-                for (int q = 0; q < RW; ++q) dsum += red[q];
-            }
+            for (int q = 0; q < RW; ++q) dsum += red[q];
             const double K = -0.5 * tau * tau * dsum;
             const double w1 = tau * p1 + K * v1;
             part = 0.0;
@@ -1079,17 +1081,83 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                         if (i >= j + 3) part += x * x;
                     }
                 }
-                if (!SHV && i >= j + 2) {
+                if (i >= j + 2) {
 #pragma unroll
                     for (int q = 0; q < RW; ++q) pw[q * NP + i] = 0.0;
                 }
-                wp[pi] = wi;
-                vp[pi] = vci;  // v vanishes outside [j + 1, n)
+                wp[i] = wi;
+                vp[i] = vci;  // v vanishes outside [j + 1, n)
             }
             part = wave_sum(part);
-            if (SHV) {
-                if (lane == 0) unsafeAtomicAdd(&red[8], part);
-            } else if (lane == 0) red[8 + w] = part;
+            if (lane == 0) red[8 + w] = part;
+            } else {
+            // (W) with the products y = A x of the unscaled column x (zero up to j + 1):
+            // A v = A e_{j+1} + scale y, where A e_{j+1} is the column j + 1 the tile owners
+            // published (base); v^T A v = A_{j+1,j+1} + 2 scale y_{j+1} + scale^2 x^T y;
+            // p = tau A v, w = p - (tau/2)(p.v) v; column j+1 of A - v w^T - w v^T.
+            // Thread t forms element i = t (RT >= NP); its operands are loaded before
+            // the reductions so that their latency overlaps them.  It also prepares the
+            // next step's buffers at its index: the unscaled column (zero at j + 1 and
+            // j + 2) and cleared products.
+            const int i = t, pi = vpos<SHV>(i), nb = b ^ 1;
+            double* xsn = nb ? xs1 : vc;
+            double* pwn = pw + nb * NPP;
+            const bool act = i >= j + 1 && i < n;
+            double yi = 0.0, xi = 0.0, base = 0.0;
+            if (act) {
+                yi = pww[pi];
+                xi = vcx[pi];
+                base = Cn < c0 ? xn[pi] : lt[(size_t)lds_tile_index(i >> 5, Cn, c0, TL) * TILE_EL + tile_off(i & 31, cn)];
+            }
+            const int p1i = vpos<SHV>(j + 1);
+            tau = red[10];
+            scale = red[11];
+            const double y1 = pww[p1i];
+            const double a11 = Cn < c0 ? xn[p1i]
+                                       : lt[(size_t)lds_tile_index((j + 1) >> 5, Cn, c0, TL) * TILE_EL + tile_off((j + 1) & 31, cn)];
+            double dp = 0.0;
+            {
+                constexpr int NU = (NP + 63) / 64;
+                double pa[NU], pb[NU];
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {  // unconditional loads, all issued before the first use
+                    const int iu = j + 2 + lane + 64 * u, pu = vpos<SHV>(iu < n ? iu : 0);
+                    pa[u] = pww[pu];
+                    pb[u] = vcx[pu];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < NU; ++u) dp += j + 2 + lane + 64 * u < n ? pa[u] * pb[u] : 0.0;
+            }
+            const double xy = wave_sum(dp);
+            const double v1 = tau != 0.0 ? 1.0 : 0.0;
+            const double p1 = fma(scale, y1, a11);
+            dsum = fma(scale * scale, xy, fma(2.0 * scale, y1, a11));
+            const double K = -0.5 * tau * tau * dsum;
+            const double w1 = tau * p1 + K * v1;
+            part = 0.0;
+            if (i < npad) {
+                double wi = 0.0, vi = 0.0;
+                if (act) {
+                    vi = tau == 0.0 ? 0.0 : (i == j + 1 ? 1.0 : scale * xi);
+                    wi = tau * fma(scale, yi, base) + K * vi;
+                    double x = fma(-vi, w1, base);
+                    x = fma(-wi, v1, x);
+                    if (i == j + 1) dd[j + 1] = x;
+                    else {
+                        xv[i] = x;
+                        if (i >= j + 3) part += x * x;
+                    }
+                    xsn[pi] = i >= j + 3 ? x : 0.0;
+                    pwn[pi] = fresh_zero();
+                }
+                wp[pi] = wi;
+                vp[pi] = vi;
+            }
+            if (t == 0) red[8 + b] = fresh_zero();  // every wave read it at the start of this step
+            part = wave_sum(part);
+            if (lane == 0) unsafeAtomicAdd(&red[8 + nb], part);
+            }
             __syncthreads();  // #3
         }
         __syncthreads();
