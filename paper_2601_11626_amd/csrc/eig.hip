@@ -463,12 +463,11 @@ __global__ void __launch_bounds__(NT) sym_eig_kernel(const EigDesc* __restrict__
 // Register-resident variant for n <= 320 (at most 10 tile rows).
 //
 // 512 threads (8 waves, two per SIMD).  The trailing (up to) 5 tile columns live in
-// LDS as above; every other lower tile (at most 40) lives permanently in the VGPRs
-// of one wave (wave w owns tiles w, w+8, ... in column-major tile order, 5 slots), so
-// the reduction never touches global memory.  One column step costs three barriers:
-// the Householder scalars are recomputed redundantly by every wave, and each wave
-// contracts its own partial A v with v before the cross-wave combine.
-// Bisection is a multisection with 512 / nkeep probes per eigenvalue per round.
+// LDS; every other lower tile (at most 40) lives permanently in the VGPRs of one wave
+// (a contiguous row-major chunk of 5 slots per wave), so the reduction never touches
+// global memory.  A column step costs three barriers (two in the shared-vector
+// kernels, see the kernel).  Bisection is a multisection with 512 / nkeep probes per
+// eigenvalue per round.
 // ---------------------------------------------------------------------------
 constexpr int RT = 512;
 constexpr int RW = RT / 64;
