@@ -899,8 +899,9 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
         // trailing tiles applying the update of step j-1 and forming A v_j, while the
         // owners of column j+1 publish it; (W) w_j, column j+1 with the update of
         // step j, the norm partials for step j+1, and v_j kept as the previous
-        // vector.  Three barriers per step.  In mode 2 with D.jsplit > 0 the loop
-        // stops after jsplit steps and hands the trailing matrix over.
+        // vector.  Three barriers per step; two in the shared-vector kernels, where (H)
+        // shrinks to the Householder scalars (see above).  In mode 2 with D.jsplit > 0
+        // the loop stops after jsplit steps and hands the trailing matrix over.
         const int jend = (MODE == 2 && D.jsplit > 0) ? D.jsplit : n - 1;
         for (int j = 0; j < jend; ++j) {
             const int Cj = j >> 5;
