@@ -1099,11 +1099,12 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
             // the reductions so that their latency overlaps them.  It also prepares the
             // next step's buffers at its index: the unscaled column (zero at j + 1 and
             // j + 2) and cleared products.
-            // In the eight-wave kernel the elements are rotated by four tile rows: the rows
-            // that stay active longest go to the older waves 0-2, and the first 128 rows,
-            // which retire as the steps advance, to waves 3 and 4 (a younger wave loses
-            // issue to the older one on its SIMD).
-            const int i = RW == 8 && t < NP ? (t + 128) % NP : t, pi = vpos<SHV>(i), nb = b ^ 1;
+            // In the eight-wave kernel the elements are rotated by two tile rows: the rows
+            // that stay active longest go to waves 1-3, and the first 128 rows, which retire
+            // as the steps advance, to waves 4 and 0, which share a SIMD (a younger wave
+            // loses issue to the older one on its SIMD, so neither of that pair is slowed
+            // by a busy sibling).
+            const int i = RW == 8 && t < NP ? (t + 64) % NP : t, pi = vpos<SHV>(i), nb = b ^ 1;
             double* xsn = nb ? xs1 : vc;
             double* pwn = pw + nb * NPP;
             const bool act = i >= j + 1 && i < n;
