@@ -820,7 +820,7 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
             for (int ww = 0; ww < RW; ++ww) {
                 int rc = 0;
                 for (int sl = 0; sl < NSLOT; ++sl) rc += (geo[ww * NSLOT + sl] >= 0 && (geo[ww * NSLOT + sl] & 255) >= c) ? 1 : 0;
-                load[ww] = 5 * rc;
+                load[ww] = 5 * rc + (SHV && ww == RW - 1 ? 5 : 0);  // the last wave also forms the norm
                 k[ww] = 0;
             }
             for (int m = 0; m < NL; ++m) {
@@ -931,10 +931,19 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                     vc[i] = (tau == 0.0 || i <= j || i >= n) ? 0.0 : (i == j + 1 ? 1.0 : xvt * scale);
                 }
                 __syncthreads();  // #1
-            } else if (t == RT - 1) {
-                // the Householder scalars, by one thread of the last wave (the others go
-                // straight to their tiles); (W) reads tau and scale from red[10], red[11]
-                const double xn2 = red[8 + b];
+            } else if (w == RW - 1) {
+                // the Householder scalars, by the last wave (the others go straight to their
+                // tiles): the norm of the unscaled column from its buffer, then tau and scale
+                // for (W) in red[10], red[11]
+                const double* xsb = b ? xs1 : vc;
+                double sq = 0.0;
+#pragma unroll
+                for (int u = 0; u < (NP + 63) / 64; ++u) {
+                    const int iu = lane + 64 * u;
+                    const double x = iu < NP ? xsb[vpos<SHV>(iu)] : 0.0;
+                    sq = fma(x, x, sq);
+                }
+                const double xn2 = wave_sum(sq);
                 const double alpha = xv[j + 1];
                 beta = alpha;
                 if (xn2 > 0.0) {
@@ -942,9 +951,11 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                     tau = (beta - alpha) / beta;
                     scale = 1.0 / (alpha - beta);
                 }
-                ee[j] = beta;
-                red[10] = tau;
-                red[11] = scale;
+                if (lane == 63) {
+                    ee[j] = beta;
+                    red[10] = tau;
+                    red[11] = scale;
+                }
             }
             // (P) register tiles, then this wave's share of the LDS tiles.  Row
             // partials accumulate while consecutive tiles stay in one tile row.
@@ -1149,19 +1160,13 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                     double x = fma(-vi, w1, base);
                     x = fma(-wi, v1, x);
                     if (i == j + 1) dd[j + 1] = x;
-                    else {
-                        xv[i] = x;
-                        if (i >= j + 3) part += x * x;
-                    }
+                    else xv[i] = x;
                     xsn[pi] = i >= j + 3 ? x : 0.0;
                     pwn[pi] = fresh_zero();
                 }
                 wp[pi] = wi;
                 vp[pi] = vi;
             }
-            if (t == 0) red[8 + b] = fresh_zero();  // every wave read it at the start of this step
-            part = wave_sum(part);
-            if (lane == 0) unsafeAtomicAdd(&red[8 + nb], part);
             }
             __syncthreads();  // #3
         }
