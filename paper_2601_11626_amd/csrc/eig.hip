@@ -812,7 +812,7 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
         // tile 8 (it also moves its elements through LDS).  Each LDS tile goes to the
         // SIMD with the least load (waves w and w + 4 share one), and there to the
         // wave with the least load, a younger wave (w >= 4, which loses issue
-        // arbitration to the older one) counted 30 % heavier.
+        // arbitration to the older one) counted 40 % heavier.
         if (t < T) {
             const int c = t, cl = c > c0 ? c : c0, mL = T - cl, NL = mL * (mL + 1) / 2;
             int load[RW], k[RW];
@@ -820,7 +820,7 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
             for (int ww = 0; ww < RW; ++ww) {
                 int rc = 0;
                 for (int sl = 0; sl < NSLOT; ++sl) rc += (geo[ww * NSLOT + sl] >= 0 && (geo[ww * NSLOT + sl] & 255) >= c) ? 1 : 0;
-                load[ww] = 5 * rc + (SHV && ww == RW - 1 ? 5 : 0);  // the last wave also forms the norm
+                load[ww] = 5 * rc + (SHV && ww == RW - 1 ? 8 : 0);  // the last wave also forms the norm
                 k[ww] = 0;
             }
             for (int m = 0; m < NL; ++m) {
@@ -838,7 +838,7 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
                 int bw = bs, be = 0x7fffffff;
 #pragma unroll
                 for (int ww = 0; ww < RW; ++ww) {
-                    const int e = ww >= 4 ? load[ww] * 13 : load[ww] * 10;
+                    const int e = ww >= 4 ? load[ww] * 14 : load[ww] * 10;
                     if ((ww & 3) == bs && e < be) {
                         be = e;
                         bw = ww;
