@@ -754,9 +754,10 @@ constexpr int THIN_LDS_DOUBLES_SHV = reg_lds_doubles(4, THIN_NSLOT, 0, THIN_TMAX
 // by v, so no barrier is needed between the Householder scalars and the tile pass.
 // (W) assembles A v = A e_{j+1} + scale A x from the published column j + 1 and the
 // products, and by symmetry v^T A v = A_{j+1,j+1} + 2 scale (A x)_{j+1} + scale^2 x^T A x.
-// The unscaled column, the products and the norm accumulator alternate between two
-// buffers by step parity, so (W) prepares the next step's while every wave may still
-// read this step's.  The vectors read per tile position (x, vp, wp, xn, the products)
+// The unscaled column and the products alternate between two buffers by step parity,
+// so (W) prepares the next step's while every wave may still read this step's; the
+// wave that forms the Householder scalars also forms the column's norm from that
+// buffer.  The vectors read per tile position (x, vp, wp, xn, the products)
 // are laid out by vpos<SHV>.
 template <int MODE, int RT_, int NSLOT_, int RTL_, int TMAX_, bool SHV = false>
 __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_reg_kernel(const EigDesc* __restrict__ descs,
@@ -804,7 +805,6 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
             }
             geo[t] = code;
         }
-        if (SHV && t == 0) red[8] = red[9] = 0.0;
         __syncthreads();
         // For each tile column c (the step's leading column), the active LDS tiles
         // (columns >= max(c, c0)) in row-major order, handed out in contiguous shares
@@ -887,12 +887,12 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
             ee[i] = 0.0;
         }
         for (int i = t; i < PWL; i += RT) pw[i] = 0.0;
-        part = wave_sum(part);
-        if (SHV) {
-            // one norm accumulator (red[8]) for all waves; it was zeroed before the
-            // geometry barrier above
-            if (lane == 0) unsafeAtomicAdd(&red[8], part);
-        } else if (lane == 0) red[8 + w] = part;
+        // the per-wave norm partials of column 0 (the shared-vector kernels form each
+        // column's norm in the scalar wave instead)
+        if (!SHV) {
+            part = wave_sum(part);
+            if (lane == 0) red[8 + w] = part;
+        }
         __syncthreads();
 
         // Step j: (H) Householder vector v_j of column j; (P) one pass over the
