@@ -794,14 +794,30 @@ __global__ void __launch_bounds__(RT_, 1024 / RT_ > 1 ? 512 / RT_ : 1) sym_eig_r
         const int cs = (ngl + RW - 1) / RW;
         if (t < RW * NSLOT) {
             const int ww = t / NSLOT, sl = t % NSLOT;
-            int g = ww * cs + sl, code = -1;
-            if (sl < cs && g < ngl) {
-                int R = 0;
-                while (g >= (R + 1 < c0 ? R + 1 : c0)) {
-                    g -= (R + 1 < c0 ? R + 1 : c0);
-                    ++R;
+            int code = -1;
+            if constexpr (RW == 4 && RTL == 0 && SHV) {
+                // The register-only trailing kernel retires whole tile columns as it goes:
+                // its tiles are dealt round-robin to the waves from the last tile column
+                // backwards, so that every wave keeps a share of the columns still active.
+                int g = sl * RW + ww;
+                if (g < ngl)
+                    for (int C = c0 - 1; C >= 0; --C) {
+                        if (g < T - C) {
+                            code = ((C + g) << 8) | C;
+                            break;
+                        }
+                        g -= T - C;
+                    }
+            } else {
+                int g = ww * cs + sl;
+                if (sl < cs && g < ngl) {
+                    int R = 0;
+                    while (g >= (R + 1 < c0 ? R + 1 : c0)) {
+                        g -= (R + 1 < c0 ? R + 1 : c0);
+                        ++R;
+                    }
+                    code = (R << 8) | g;
                 }
-                code = (R << 8) | g;
             }
             geo[t] = code;
         }
